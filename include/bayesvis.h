@@ -1,0 +1,200 @@
+/*
+ * bayesvis.h -- C ABI of the MI355X (gfx950) visibility / chi^2 / HMC library.
+ *
+ * What is computed (Kern 2025, "A Differentiable, End-to-End Forward Model
+ * for 21 cm Cosmology"):
+ *
+ *   sky        I(p, nu) = sum_lm Y(p, lm) a(lm, nu)            Sec. 3.2, eq. fg_harmonic_matrix
+ *              Y = real orthonormal spherical harmonics with integer l,
+ *              column l*l + l + m, no Condon-Shortley phase  (App. A, eq. sht_ortho)
+ *   RIME       V_ij(nu, t) = dOmega sum_p B(p, nu, t) I(p, nu)
+ *                            exp(-2 pi i nu b_ij . s_p(t) / c)  Sec. 2.1, eq. rime_discrete
+ *              pixels fixed on the celestial sphere, so s_p and the beam move
+ *              with time (eq. rime_matrix: one design matrix per time);
+ *              evaluated once per redundant baseline vector (Sec. 3.1)
+ *   beam       B = exp(-theta^2 / 2 sigma^2) above the horizon, 0 below,
+ *              sigma = F (nu_ref / nu) / (2 sqrt(2 ln 2)); F = FWHM at nu_ref (rad)
+ *   gains      m_ij = g_i conj(g_j) V_ij                       Sec. 2.1 (gain terms)
+ *   chi^2      sum |d - m|^2 / sigma_n^2                       Sec. 2.3, eq. likelihood
+ *   gradients  of chi^2 w.r.t. a, g, F (replacing reverse-mode AD, Sec. 2.3)
+ *   HMC        diagonal-mass leapfrog + Metropolis             Sec. 4.2, App. B
+ *
+ * Conventions
+ *   - complex numbers are interleaved float pairs (vis_c64);
+ *   - the gradient w.r.t. a complex quantity z is dL/dRe z + i dL/dIm z;
+ *   - layouts (row-major):  alm[n_freq][n_modes] float,
+ *       gains[n_freq][n_ant] vis_c64, vis/data[n_time][n_freq][n_bl] vis_c64,
+ *     with physical baselines (i, j), i < j, in lexicographic order and
+ *     b_ij = r_i - r_j;
+ *   - pixel grid: n_z rings uniform in z = sin(dec), centres
+ *     z_j = -1 + (j + 1/2) 2 / n_z; n_phi columns alpha_k = (k + 1/2) 2 pi / n_phi;
+ *     pixel p = j n_phi + k; dOmega = 4 pi / (n_z n_phi);
+ *   - topocentric frame E, N, U; hour angle H = LST - alpha.
+ *
+ * Memory ownership
+ *   The caller allocates every device buffer, including each object's
+ *   workspace (query its size first).  The library never calls hipMalloc;
+ *   objects sub-allocate inside the workspace they are given, which must
+ *   stay allocated and untouched until the object is destroyed.  Inputs are
+ *   never modified; outputs are overwritten.  Handles are host objects owned
+ *   by the library (freed by the matching *_destroy).
+ *
+ * Streams
+ *   `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Work is stream-ordered and asynchronous; no entry point synchronises the
+ *   host except the *_create calls (which upload tables) and hmc_poll.
+ *   Evaluations on one field use the field's scratch space: calls on the
+ *   same field must be ordered on one stream (calls on different fields may
+ *   run concurrently).
+ *
+ * Errors
+ *   Every entry point returns a vis_status; nothing is thrown or aborted
+ *   across the ABI.  On a non-zero status, vis_last_error() returns a
+ *   thread-local message.  Device-side faults surface as VIS_EDEVICE from a
+ *   later call.
+ */
+#ifndef BAYESVIS_H
+#define BAYESVIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VIS_OK = 0,
+  VIS_EINVAL = -1,     /* bad argument, shape or descriptor */
+  VIS_ENOMEM = -2,     /* workspace / arena too small */
+  VIS_EDEVICE = -3,    /* HIP runtime error */
+  VIS_EAGAIN = -4,     /* resource busy: retry later (serving admission) */
+  VIS_ENOTFOUND = -5,  /* unknown chain id */
+  VIS_ENUMERIC = -6    /* non-finite value detected */
+} vis_status;
+
+typedef enum {
+  VIS_FP32 = 1,        /* FP32 MFMA synthesis, FP32 fringe */
+  VIS_BF16X3 = 2,      /* synthesis as bf16 hi/lo split products on MFMA, FP32 accumulate */
+  VIS_FP16X3 = 3       /* synthesis as fp16 hi/lo split products (scaled lo), FP32 accumulate */
+} vis_precision;
+
+typedef struct { float re, im; } vis_c64;
+
+typedef struct vis_basis vis_basis;
+typedef struct vis_field vis_field;
+
+/* ---------------------------------------------------------------- basis --
+ * Y(p, lm) on the equal-area grid for 0 <= l <= lmax, generated on the GPU
+ * from a normalised Legendre recurrence (App. A: the normalisation is
+ * carried through the recurrence so high orders do not overflow).
+ * Any field with a smaller lmax uses the leading (lmax'+1)^2 columns.
+ * storage: bit 0 = FP32 copy (needed by VIS_FP32 fields), bit 1 = bf16
+ * hi/lo copy (VIS_BF16X3), bit 2 = fp16 hi/lo copy (VIS_FP16X3).            */
+typedef struct {
+  int32_t grid_nz, grid_nphi;
+  int32_t lmax;
+  uint32_t storage;
+} vis_basis_desc;
+
+vis_status vis_basis_workspace_bytes(const vis_basis_desc* desc, size_t* bytes);
+vis_status vis_basis_create(const vis_basis_desc* desc, void* workspace_dev, size_t bytes,
+                            void* stream, vis_basis** out);
+vis_status vis_basis_destroy(vis_basis* basis);
+
+/* ---------------------------------------------------------------- field --
+ * One observation.  Antennas sit on a 2-D lattice (Sec. 3.1: a hexagonal
+ * array): r_i = ant_lattice[i][0] e1 + ant_lattice[i][1] e2, with e1, e2
+ * ENU vectors in metres whose U components are 0 (coplanar array).  Two
+ * physical baselines are redundant when their integer lattice differences
+ * agree up to sign; the canonical representative has its first non-zero
+ * lattice coordinate positive.  All descriptor arrays are host memory and
+ * are copied; the caller may free them after vis_field_create returns.
+ * Limits: 2 <= n_ant <= 1024, lattice differences |dn| <= 16, n_freq and
+ * n_time in [1, 4096], lmax <= basis lmax.
+ * VIS_EINVAL: antennas sharing a site, non-coplanar basis, sizes out of range.  */
+typedef struct {
+  int32_t n_ant;
+  const int32_t* ant_lattice;        /* [n_ant][2] */
+  double lattice_e1_m[3];
+  double lattice_e2_m[3];
+  int32_t n_freq;
+  const double* freq_hz;             /* [n_freq] */
+  int32_t n_time;
+  const double* lst_rad;             /* [n_time] */
+  double latitude_rad;
+  int32_t lmax;
+  double beam_ref_hz;                /* nu_ref of the beam-width law */
+  int32_t precision;                 /* vis_precision */
+} vis_field_desc;
+
+typedef struct {
+  int32_t n_ant, n_bl, n_ubl, n_freq, n_time, n_pix, n_modes;
+  int32_t n_pix_visible;             /* pixels above the horizon at some time */
+  int32_t lattice_extent;            /* max |dn| over baselines */
+  int32_t precision;
+  double d_omega;
+  double fwd_macs;                   /* complex x real MACs of one fringe pass:
+                                        sum over (u, t) of visible pixels x n_freq */
+} vis_field_info;
+
+vis_status vis_field_workspace_bytes(const vis_basis* basis, const vis_field_desc* desc,
+                                     size_t* bytes);
+vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc,
+                            void* workspace_dev, size_t bytes, void* stream, vis_field** out);
+vis_status vis_field_get_info(const vis_field* field, vis_field_info* info);
+vis_status vis_field_destroy(vis_field* field);
+
+/* ---------------------------------------------------------- evaluation --
+ * vis_forward: model visibilities m = g_i conj(g_j) V_ij            (Sec. 2.1)
+ *   alm   device [n_freq][n_modes] float
+ *   gains device [n_freq][n_ant] vis_c64
+ *   fwhm  device pointer to one float, F in radians
+ *   vis   device [n_time][n_freq][n_bl] vis_c64 (output)                  */
+vis_status vis_forward(const vis_field* field, const float* alm, const vis_c64* gains,
+                       const float* fwhm, vis_c64* vis, void* stream);
+
+/* vis_adjoint: gradients of a real scalar L given its cotangent with respect
+ * to the model visibilities, dvis = dL/dRe m + i dL/dIm m (device, same
+ * layout as vis).  Outputs (device): grad_alm [n_freq][n_modes],
+ * grad_gains [n_freq][n_ant], grad_fwhm (one float).  This is the transpose
+ * of the linearised forward model (Sec. 2.3: the gradient that reverse-mode
+ * AD would give), evaluated by recomputing fringe tiles.                   */
+vis_status vis_adjoint(const vis_field* field, const float* alm, const vis_c64* gains,
+                       const float* fwhm, const vis_c64* dvis, float* grad_alm,
+                       vis_c64* grad_gains, float* grad_fwhm, void* stream);
+
+/* chi2_and_grad: chi^2 = sum |d - m|^2 / sigma_n^2 (Sec. 2.3, eq. likelihood,
+ * diagonal noise of Sec. 3.5 with variance sigma_n^2 per real component)
+ * and its gradient.  chi2 is a device double accumulated in FP64.
+ * data device [n_time][n_freq][n_bl] vis_c64; other pointers as above.
+ * Any output pointer except chi2 may be NULL to skip the adjoint entirely
+ * (then only the forward and chi^2 run).                                    */
+vis_status chi2_and_grad(const vis_field* field, const vis_c64* data, float sigma_n,
+                         const float* alm, const vis_c64* gains, const float* fwhm,
+                         double* chi2, float* grad_alm, vis_c64* grad_gains,
+                         float* grad_fwhm, void* stream);
+
+/* ------------------------------------------------------------ profiling --
+ * Optional per-field kernel timing: when enabled, every kernel the field
+ * launches is bracketed by a pair of hipEvents on the launch stream and its
+ * elapsed time is added to a per-kernel-name total when read.  Reading
+ * synchronises with the recorded events.  Used to report the launch
+ * duration of the dominant kernel; off by default (no events recorded).   */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} vis_kernel_time;
+
+vis_status vis_profile_enable(vis_field* field, int32_t enable);
+vis_status vis_profile_read(vis_field* field, vis_kernel_time* out, int32_t max, int32_t* n_out,
+                            int32_t reset);
+
+const char* vis_last_error(void);
+const char* vis_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BAYESVIS_H */

@@ -1,0 +1,83 @@
+// Evaluation entry points of the C ABI: vis_forward, vis_adjoint, chi2_and_grad.
+// Each is a fixed stream-ordered sequence of kernel launches; nothing returns
+// to the host.
+#include "objects.hpp"
+
+using namespace bv;
+
+namespace {
+
+void check_field(const vis_field* f) {
+  BV_REQUIRE(f != nullptr, VIS_EINVAL, "null field");
+}
+
+void forward_core(const vis_field* f, const float* alm, const float* fwhm, hipStream_t s) {
+  launch_synth_fwd(f, alm, f->scr.img, s);
+  launch_fringe_fwd(f, f->scr.img, fwhm, f->scr.vu, s);
+}
+
+void adjoint_tail(const vis_field* f, const float* fwhm, float* grad_alm, float2* grad_gains,
+                  float* grad_fwhm, bool with_chi2, double* chi2, hipStream_t s) {
+  launch_reduce_grads(f, with_chi2, f->scr.chi_part, chi2, f->scr.g_part, grad_gains,
+                      f->scr.f_part, nullptr, s);
+  launch_fringe_adj(f, f->scr.img, fwhm, f->scr.w, f->scr.dimg, f->scr.f_part, s);
+  if (grad_fwhm != nullptr)
+    launch_reduce_grads(f, false, nullptr, nullptr, nullptr, nullptr, f->scr.f_part, grad_fwhm, s);
+  if (grad_alm != nullptr) launch_synth_adj(f, f->scr.dimg, grad_alm, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+vis_status vis_forward(const vis_field* f, const float* alm, const vis_c64* gains,
+                       const float* fwhm, vis_c64* vis, void* stream) {
+  return guarded([&] {
+    check_field(f);
+    BV_REQUIRE(alm && gains && fwhm && vis, VIS_EINVAL, "null device pointer");
+    hipStream_t s = as_stream(stream);
+    forward_core(f, alm, fwhm, s);
+    launch_gains(f, kGainFwd, f->scr.vu, reinterpret_cast<const float2*>(gains), nullptr, 0.f,
+                 reinterpret_cast<float2*>(vis), nullptr, nullptr, nullptr, s);
+  });
+}
+
+vis_status vis_adjoint(const vis_field* f, const float* alm, const vis_c64* gains,
+                       const float* fwhm, const vis_c64* dvis, float* grad_alm,
+                       vis_c64* grad_gains, float* grad_fwhm, void* stream) {
+  return guarded([&] {
+    check_field(f);
+    BV_REQUIRE(alm && gains && fwhm && dvis, VIS_EINVAL, "null device pointer");
+    BV_REQUIRE(grad_alm && grad_gains && grad_fwhm, VIS_EINVAL, "null gradient output");
+    hipStream_t s = as_stream(stream);
+    forward_core(f, alm, fwhm, s);
+    launch_gains(f, kGainAdj, f->scr.vu, reinterpret_cast<const float2*>(gains),
+                 reinterpret_cast<const float2*>(dvis), 0.f, nullptr, nullptr, f->scr.w,
+                 f->scr.g_part, s);
+    adjoint_tail(f, fwhm, grad_alm, reinterpret_cast<float2*>(grad_gains), grad_fwhm, false,
+                 nullptr, s);
+  });
+}
+
+vis_status chi2_and_grad(const vis_field* f, const vis_c64* data, float sigma_n, const float* alm,
+                         const vis_c64* gains, const float* fwhm, double* chi2, float* grad_alm,
+                         vis_c64* grad_gains, float* grad_fwhm, void* stream) {
+  return guarded([&] {
+    check_field(f);
+    BV_REQUIRE(data && alm && gains && fwhm && chi2, VIS_EINVAL, "null device pointer");
+    BV_REQUIRE(sigma_n > 0.f && sigma_n < 3.0e38f, VIS_EINVAL, "sigma_n must be positive and finite");
+    hipStream_t s = as_stream(stream);
+    forward_core(f, alm, fwhm, s);
+    launch_gains(f, kGainChi2, f->scr.vu, reinterpret_cast<const float2*>(gains),
+                 reinterpret_cast<const float2*>(data), sigma_n, nullptr, f->scr.chi_part,
+                 f->scr.w, f->scr.g_part, s);
+    const bool any_grad = grad_alm || grad_gains || grad_fwhm;
+    if (!any_grad) {
+      launch_reduce_grads(f, true, f->scr.chi_part, chi2, nullptr, nullptr, nullptr, nullptr, s);
+      return;
+    }
+    adjoint_tail(f, fwhm, grad_alm, reinterpret_cast<float2*>(grad_gains), grad_fwhm, true, chi2, s);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,578 @@
+// Basis (Y) generation and field set-up: geometry tables computed once per
+// observation in FP64 on the host ("cached mode": coordinate transforms are
+// prepared once and reused by every evaluation), then uploaded.
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "objects.hpp"
+
+namespace bv {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+void clear_error() { g_err[0] = '\0'; }
+
+// ------------------------------------------------------------- profiler --
+hipEvent_t Profiler::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  BV_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Profiler::drain() {
+  for (auto& r : pending) {
+    BV_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    BV_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    auto& t = totals[r.name];
+    t.first += 1;
+    t.second += ms;
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+}
+
+Profiler::~Profiler() {
+  for (auto& r : pending) {
+    (void)hipEventSynchronize(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+ProfScope::ProfScope(Profiler* p_, const char* n, hipStream_t s) : p(p_), name(n), st(s) {
+  if (p && p->on) {
+    a = p->get();
+    BV_HIP(hipEventRecord(a, st));
+  }
+}
+
+ProfScope::~ProfScope() {
+  if (a != nullptr) {
+    hipEvent_t b = nullptr;
+    try {
+      b = p->get();
+    } catch (...) {
+      p->pool.push_back(a);
+      return;
+    }
+    if (hipEventRecord(b, st) == hipSuccess) {
+      p->pending.push_back(Profiler::Rec{name, a, b});
+      if (p->pending.size() > 4096) {
+        try { p->drain(); } catch (...) {}
+      }
+    } else {
+      p->pool.push_back(a);
+      p->pool.push_back(b);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- basis --
+// Normalised associated Legendre values lambda_lm(z) = sqrt((2l+1)/(4 pi)
+// (l-m)!/(l+m)!) P_l^m(z) (no Condon-Shortley phase), stored triangular
+// [l(l+1)/2 + m].  Built column by column in m: the diagonal from
+// lambda_mm = sqrt((2m+1)/(2m)) sqrt(1-z^2) lambda_{m-1,m-1}, then upward in l
+// with the three-term recurrence whose coefficients keep every value
+// normalised (no factorials are ever formed, App. A).
+static void legendre_ring(int lmax, double z, double* out) {
+  const double s = std::sqrt(std::max(0.0, 1.0 - z * z));
+  double diag = 1.0 / std::sqrt(4.0 * kPi);
+  for (int m = 0; m <= lmax; ++m) {
+    if (m > 0) diag *= std::sqrt((2.0 * m + 1.0) / (2.0 * m)) * s;
+    double prev2 = 0.0, prev1 = diag;
+    out[m * (m + 1) / 2 + m] = diag;
+    for (int l = m + 1; l <= lmax; ++l) {
+      const double ll = l, mm = m;
+      const double a = std::sqrt((4.0 * ll * ll - 1.0) / (ll * ll - mm * mm));
+      const double b = (l - 1 > m)
+                           ? std::sqrt(((ll - 1) * (ll - 1) - mm * mm) / (4.0 * (ll - 1) * (ll - 1) - 1.0))
+                           : 0.0;
+      const double cur = a * (z * prev1 - b * prev2);
+      out[l * (l + 1) / 2 + m] = cur;
+      prev2 = prev1;
+      prev1 = cur;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_make_basis(int nphi, int n_modes, int kpad, int ntri,
+                                                    const double* __restrict__ lam,
+                                                    const double* __restrict__ trig,  // [nphi][2*(lmax+1)]
+                                                    int lmax, float* y32, __hip_bfloat16* ybh,
+                                                    __hip_bfloat16* ybl, _Float16* yhh, _Float16* yhl) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (c >= kpad) return;
+  const int j = p / nphi, k = p - j * nphi;
+  double y = 0.0;
+  if (c < n_modes) {
+    int l = static_cast<int>(sqrtf(static_cast<float>(c)));
+    while ((l + 1) * (l + 1) <= c) ++l;
+    while (l * l > c) --l;
+    const int m = c - l * l - l;
+    const int am = m < 0 ? -m : m;
+    const double lv = lam[static_cast<size_t>(j) * ntri + l * (l + 1) / 2 + am];
+    const double* tr = trig + static_cast<size_t>(k) * 2 * (lmax + 1);
+    if (m == 0) y = lv;
+    else if (m > 0) y = 1.4142135623730951 * lv * tr[2 * am];
+    else y = 1.4142135623730951 * lv * tr[2 * am + 1];
+  }
+  const size_t o = static_cast<size_t>(p) * kpad + c;
+  if (y32) y32[o] = static_cast<float>(y);
+  if (ybh) {
+    const __hip_bfloat16 h = __float2bfloat16(static_cast<float>(y));
+    ybh[o] = h;
+    ybl[o] = __float2bfloat16(static_cast<float>(y - static_cast<double>(__bfloat162float(h))));
+  }
+  if (yhh) {
+    const _Float16 h = static_cast<_Float16>(static_cast<float>(y));
+    yhh[o] = h;
+    yhl[o] = static_cast<_Float16>(static_cast<float>((y - static_cast<double>(static_cast<float>(h))) * 2048.0));
+  }
+}
+
+static void carve_basis(vis_basis* b, Carver& cv) {
+  const size_t n = static_cast<size_t>(b->n_pix) * b->kpad;
+  b->y32 = (b->storage & 1u) ? cv.take<float>(n) : nullptr;
+  b->ybh = (b->storage & 2u) ? cv.take<__hip_bfloat16>(n) : nullptr;
+  b->ybl = (b->storage & 2u) ? cv.take<__hip_bfloat16>(n) : nullptr;
+  b->yhh = (b->storage & 4u) ? cv.take<_Float16>(n) : nullptr;
+  b->yhl = (b->storage & 4u) ? cv.take<_Float16>(n) : nullptr;
+  // staging tables for the generator (Legendre values per ring, cos/sin per column)
+  b->lam = cv.take<double>(static_cast<size_t>(b->nz) * (b->lmax + 1) * (b->lmax + 2) / 2);
+  b->trig = cv.take<double>(static_cast<size_t>(b->nphi) * 2 * (b->lmax + 1));
+}
+
+static void basis_shape(const vis_basis_desc* d, vis_basis* b) {
+  BV_REQUIRE(d != nullptr, VIS_EINVAL, "null basis descriptor");
+  BV_REQUIRE(d->grid_nz >= 2 && d->grid_nz <= 8192 && d->grid_nphi >= 4 && d->grid_nphi <= 16384,
+             VIS_EINVAL, "grid %d x %d out of range", d->grid_nz, d->grid_nphi);
+  BV_REQUIRE(d->lmax >= 0 && d->lmax <= 512, VIS_EINVAL, "lmax %d out of range [0, 512]", d->lmax);
+  BV_REQUIRE(d->storage != 0 && (d->storage & ~7u) == 0, VIS_EINVAL, "bad storage flags 0x%x",
+             d->storage);
+  b->nz = d->grid_nz;
+  b->nphi = d->grid_nphi;
+  b->lmax = d->lmax;
+  b->n_pix = d->grid_nz * d->grid_nphi;
+  b->n_modes = (d->lmax + 1) * (d->lmax + 1);
+  b->kpad = static_cast<int>(round_up(b->n_modes, 64));
+  b->storage = d->storage;
+}
+
+// ---------------------------------------------------------------- field --
+struct HostGeometry {
+  std::vector<std::pair<int, int>> ubl;  // canonical (n1, n2), sorted
+  std::vector<int> bl_i, bl_j, bl_u, bl_sign;
+  int extent = 0;
+  std::vector<int> vpix;                 // visible pixel indices
+  int nv_pad = 0;
+  std::vector<double> p1, p2;            // [t][nv_pad]
+  std::vector<float> th2;                // [t][nv_pad]
+  std::vector<int> tlo, thi;             // per chunk
+  std::vector<int> tchunk_off, tchunk;   // CSR per time
+  double vis_pix_time = 0.0;             // sum over t of visible pixel count
+};
+
+static void validate_field(const vis_basis* basis, const vis_field_desc* d) {
+  BV_REQUIRE(basis != nullptr && d != nullptr, VIS_EINVAL, "null basis or field descriptor");
+  BV_REQUIRE(d->n_ant >= 2 && d->n_ant <= 1024, VIS_EINVAL, "n_ant %d out of range [2, 1024]",
+             d->n_ant);
+  BV_REQUIRE(d->ant_lattice && d->freq_hz && d->lst_rad, VIS_EINVAL, "null descriptor array");
+  BV_REQUIRE(d->n_freq >= 1 && d->n_freq <= 4096, VIS_EINVAL, "n_freq %d out of range", d->n_freq);
+  BV_REQUIRE(d->n_time >= 1 && d->n_time <= 4096, VIS_EINVAL, "n_time %d out of range", d->n_time);
+  BV_REQUIRE(d->lmax >= 0 && d->lmax <= basis->lmax, VIS_EINVAL,
+             "field lmax %d exceeds the basis lmax %d", d->lmax, basis->lmax);
+  BV_REQUIRE(d->lattice_e1_m[2] == 0.0 && d->lattice_e2_m[2] == 0.0, VIS_EINVAL,
+             "lattice basis must be horizontal (U = 0): the array is assumed coplanar");
+  const double cross = d->lattice_e1_m[0] * d->lattice_e2_m[1] - d->lattice_e1_m[1] * d->lattice_e2_m[0];
+  BV_REQUIRE(std::fabs(cross) > 1e-9, VIS_EINVAL, "lattice basis vectors are parallel");
+  for (int f = 0; f < d->n_freq; ++f)
+    BV_REQUIRE(std::isfinite(d->freq_hz[f]) && d->freq_hz[f] > 0.0, VIS_EINVAL,
+               "frequency %d is not positive", f);
+  for (int t = 0; t < d->n_time; ++t)
+    BV_REQUIRE(std::isfinite(d->lst_rad[t]), VIS_EINVAL, "lst %d not finite", t);
+  BV_REQUIRE(std::isfinite(d->latitude_rad) && std::fabs(d->latitude_rad) <= kPi / 2, VIS_EINVAL,
+             "latitude out of range");
+  BV_REQUIRE(d->beam_ref_hz > 0.0, VIS_EINVAL, "beam_ref_hz must be positive");
+  BV_REQUIRE(d->precision == VIS_FP32 || d->precision == VIS_BF16X3 || d->precision == VIS_FP16X3,
+             VIS_EINVAL, "unknown precision %d", d->precision);
+  const uint32_t need = d->precision == VIS_FP32 ? 1u : d->precision == VIS_BF16X3 ? 2u : 4u;
+  BV_REQUIRE((basis->storage & need) != 0, VIS_EINVAL,
+             "the basis was created without the storage this precision needs");
+}
+
+static HostGeometry build_geometry(const vis_basis* basis, const vis_field_desc* d) {
+  HostGeometry g;
+  const int na = d->n_ant;
+  // baselines (i < j), lattice differences, canonical sign
+  std::map<std::pair<int, int>, int> index;
+  std::vector<std::pair<int, int>> canon;
+  for (int i = 0; i < na; ++i)
+    for (int j = i + 1; j < na; ++j) {
+      int a = d->ant_lattice[2 * i] - d->ant_lattice[2 * j];
+      int b = d->ant_lattice[2 * i + 1] - d->ant_lattice[2 * j + 1];
+      BV_REQUIRE(a != 0 || b != 0, VIS_EINVAL, "antennas %d and %d share a lattice site", i, j);
+      int s = 1;
+      if (!(a > 0 || (a == 0 && b > 0))) { a = -a; b = -b; s = -1; }
+      g.bl_i.push_back(i);
+      g.bl_j.push_back(j);
+      g.bl_sign.push_back(s);
+      canon.emplace_back(a, b);
+      index[{a, b}] = 0;
+      g.extent = std::max(g.extent, std::max(std::abs(a), std::abs(b)));
+    }
+  BV_REQUIRE(g.extent <= kMaxExtent, VIS_EINVAL, "lattice extent %d exceeds %d", g.extent, kMaxExtent);
+  int u = 0;
+  for (auto& kv : index) { kv.second = u++; g.ubl.push_back(kv.first); }
+  for (auto& c : canon) g.bl_u.push_back(index[c]);
+
+  // directions of every pixel at every time
+  const int nz = basis->nz, nphi = basis->nphi, npix = basis->n_pix, nt = d->n_time;
+  const double cphi = std::cos(d->latitude_rad), sphi = std::sin(d->latitude_rad);
+  std::vector<double> E(static_cast<size_t>(nt) * npix), N(E.size()), U(E.size());
+  std::vector<char> ever(npix, 0);
+  for (int t = 0; t < nt; ++t)
+    for (int j = 0; j < nz; ++j) {
+      const double z = -1.0 + (j + 0.5) * 2.0 / nz;
+      const double cd = std::sqrt(std::max(0.0, 1.0 - z * z)), sd = z;
+      for (int k = 0; k < nphi; ++k) {
+        const double alpha = (k + 0.5) * 2.0 * kPi / nphi;
+        const double h = d->lst_rad[t] - alpha;
+        const double ch = std::cos(h), sh = std::sin(h);
+        const size_t o = static_cast<size_t>(t) * npix + j * nphi + k;
+        E[o] = -cd * sh;
+        N[o] = cphi * sd - sphi * cd * ch;
+        U[o] = sphi * sd + cphi * cd * ch;
+        if (U[o] > 0.0) ever[j * nphi + k] = 1;
+      }
+    }
+  for (int p = 0; p < npix; ++p)
+    if (ever[p]) g.vpix.push_back(p);
+  BV_REQUIRE(!g.vpix.empty(), VIS_EINVAL, "no pixel is above the horizon at any time");
+  const int nv = static_cast<int>(g.vpix.size());
+  g.nv_pad = static_cast<int>(round_up(nv, kChunk));
+  const int nchunks = g.nv_pad / kChunk;
+  g.p1.assign(static_cast<size_t>(nt) * g.nv_pad, 0.0);
+  g.p2.assign(g.p1.size(), 0.0);
+  g.th2.assign(g.p1.size(), kBelowHorizon);
+  g.tlo.assign(nchunks, nt);
+  g.thi.assign(nchunks, -1);
+  std::vector<std::vector<int>> active(nt);
+  const double* e1 = d->lattice_e1_m;
+  const double* e2 = d->lattice_e2_m;
+  for (int t = 0; t < nt; ++t) {
+    for (int c = 0; c < nchunks; ++c) {
+      bool any = false;
+      for (int q = 0; q < kChunk; ++q) {
+        const int k = c * kChunk + q;
+        if (k >= nv) break;
+        const size_t o = static_cast<size_t>(t) * npix + g.vpix[k];
+        const size_t w = static_cast<size_t>(t) * g.nv_pad + k;
+        g.p1[w] = (e1[0] * E[o] + e1[1] * N[o]) / kCLight;
+        g.p2[w] = (e2[0] * E[o] + e2[1] * N[o]) / kCLight;
+        if (U[o] > 0.0) {
+          const double th = std::acos(std::min(1.0, U[o]));
+          g.th2[w] = static_cast<float>(th * th);
+          any = true;
+          g.vis_pix_time += 1.0;
+        }
+      }
+      if (any) {
+        active[t].push_back(c);
+        g.tlo[c] = std::min(g.tlo[c], t);
+        g.thi[c] = std::max(g.thi[c], t);
+      }
+    }
+  }
+  g.tchunk_off.push_back(0);
+  for (int t = 0; t < nt; ++t) {
+    for (int c : active[t]) g.tchunk.push_back(c);
+    g.tchunk_off.push_back(static_cast<int>(g.tchunk.size()));
+  }
+  return g;
+}
+
+static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
+  const size_t nt = f->n_time, nfq = f->n_freq, nvp = f->nv_pad;
+  auto& T = f->tab;
+  T.freq = cv.take<double>(nfq);
+  T.vpix = cv.take<int>(nvp);
+  T.p1 = cv.take<double>(nt * nvp);
+  T.p2 = cv.take<double>(nt * nvp);
+  T.th2 = cv.take<float>(nt * nvp);
+  T.chunk_t = cv.take<int2>(f->n_chunks);
+  T.tchunk_off = cv.take<int>(nt + 1);
+  T.tchunk = cv.take<int>(std::max(1, n_tchunk));
+  T.bl_ant = cv.take<int2>(f->n_bl);
+  T.bl_u = cv.take<int>(f->n_bl);
+  T.u_off = cv.take<int>(f->n_ubl + 1);
+  T.u_list = cv.take<int>(f->n_bl);
+  T.a_off = cv.take<int>(f->n_ant + 1);
+  T.a_list = cv.take<int>(2 * static_cast<size_t>(f->n_bl));
+  T.ubl_nm = cv.take<int2>(f->n_ubl);
+  T.ulut = cv.take<int>(static_cast<size_t>(f->extent + 1) * (2 * f->extent + 1));
+  auto& S = f->scr;
+  const size_t kpad = f->basis->kpad;
+  S.img = cv.take<float>(nfq * nvp);
+  S.dimg = cv.take<float>(nfq * nvp);
+  S.vu = cv.take<float2>(nt * nfq * f->n_ubl);
+  S.w = cv.take<float2>(nt * nfq * f->n_ubl);
+  S.chi_part = cv.take<double>(nt * nfq);
+  S.g_part = cv.take<float2>(nt * nfq * f->n_ant);
+  S.f_part = cv.take<float>(nfq * f->n_chunks);
+  S.a_part = cv.take<float>(static_cast<size_t>(f->asplit) * nfq * kpad);
+}
+
+static int choose_asplit(int n_freq, int kpad, int nv_pad) {
+  const int tiles = ceil_div(n_freq, 64) * (kpad / 64);
+  int s = std::max(1, ceil_div(1024, tiles));
+  s = std::min(s, std::max(1, nv_pad / 512));
+  return std::min(s, 64);
+}
+
+static void fill_shape(vis_field* f, const vis_basis* basis, const vis_field_desc* d,
+                       const HostGeometry& g) {
+  f->basis = basis;
+  f->n_ant = d->n_ant;
+  f->n_bl = static_cast<int>(g.bl_i.size());
+  f->n_ubl = static_cast<int>(g.ubl.size());
+  f->n_freq = d->n_freq;
+  f->n_time = d->n_time;
+  f->lmax = d->lmax;
+  f->n_modes = (d->lmax + 1) * (d->lmax + 1);
+  f->nv = static_cast<int>(g.vpix.size());
+  f->nv_pad = g.nv_pad;
+  f->n_chunks = g.nv_pad / kChunk;
+  f->n_tchunk = static_cast<int>(g.tchunk.size());
+  f->extent = g.extent;
+  f->precision = d->precision;
+  f->d_omega = 4.0 * kPi / basis->n_pix;
+  f->beam_ref_hz = d->beam_ref_hz;
+  f->fwd_macs = g.vis_pix_time * f->n_ubl * d->n_freq;
+  f->asplit = choose_asplit(d->n_freq, basis->kpad, g.nv_pad);
+}
+
+template <class T>
+static void up(T* dst, const std::vector<T>& src, hipStream_t st) {
+  if (!src.empty())
+    BV_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+}  // namespace bv
+
+using namespace bv;
+
+extern "C" {
+
+const char* vis_last_error(void) { return g_err; }
+const char* vis_version(void) { return "bayesvis 0.1 (gfx950)"; }
+
+vis_status vis_basis_workspace_bytes(const vis_basis_desc* desc, size_t* bytes) {
+  return guarded([&] {
+    BV_REQUIRE(bytes != nullptr, VIS_EINVAL, "null output");
+    vis_basis b;
+    basis_shape(desc, &b);
+    Carver cv;
+    carve_basis(&b, cv);
+    *bytes = cv.used;
+  });
+}
+
+vis_status vis_basis_create(const vis_basis_desc* desc, void* ws, size_t bytes, void* stream,
+                            vis_basis** out) {
+  vis_basis* b = nullptr;
+  vis_status st = guarded([&] {
+    BV_REQUIRE(out != nullptr && ws != nullptr, VIS_EINVAL, "null workspace or output");
+    b = new vis_basis();
+    basis_shape(desc, b);
+    Carver cv{static_cast<char*>(ws), bytes, 0};
+    carve_basis(b, cv);
+    const int ntri = (b->lmax + 1) * (b->lmax + 2) / 2;
+    std::vector<double> lam(static_cast<size_t>(b->nz) * ntri), trig(static_cast<size_t>(b->nphi) * 2 * (b->lmax + 1));
+    for (int j = 0; j < b->nz; ++j) legendre_ring(b->lmax, -1.0 + (j + 0.5) * 2.0 / b->nz, &lam[static_cast<size_t>(j) * ntri]);
+    for (int k = 0; k < b->nphi; ++k) {
+      const double alpha = (k + 0.5) * 2.0 * kPi / b->nphi;
+      for (int m = 0; m <= b->lmax; ++m) {
+        trig[static_cast<size_t>(k) * 2 * (b->lmax + 1) + 2 * m] = std::cos(m * alpha);
+        trig[static_cast<size_t>(k) * 2 * (b->lmax + 1) + 2 * m + 1] = std::sin(m * alpha);
+      }
+    }
+    hipStream_t s = as_stream(stream);
+    double* dlam = b->lam;
+    double* dtrig = b->trig;
+    BV_HIP(hipMemcpyAsync(dlam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    BV_HIP(hipMemcpyAsync(dtrig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    dim3 grid(ceil_div(b->kpad, 256), b->n_pix);
+    k_make_basis<<<grid, 256, 0, s>>>(b->nphi, b->n_modes, b->kpad, ntri, dlam, dtrig, b->lmax,
+                                      b->y32, b->ybh, b->ybl, b->yhh, b->yhl);
+    check_launch("k_make_basis");
+    BV_HIP(hipStreamSynchronize(s));
+    *out = b;
+  });
+  if (st != VIS_OK) delete b;
+  return st;
+}
+
+vis_status vis_basis_destroy(vis_basis* basis) {
+  delete basis;
+  return VIS_OK;
+}
+
+vis_status vis_field_workspace_bytes(const vis_basis* basis, const vis_field_desc* desc,
+                                     size_t* bytes) {
+  return guarded([&] {
+    BV_REQUIRE(bytes != nullptr, VIS_EINVAL, "null output");
+    validate_field(basis, desc);
+    HostGeometry g = build_geometry(basis, desc);
+    vis_field f;
+    fill_shape(&f, basis, desc, g);
+    Carver cv;
+    carve_field(&f, cv, f.n_tchunk);
+    *bytes = cv.used;
+  });
+}
+
+vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, void* ws,
+                            size_t bytes, void* stream, vis_field** out) {
+  vis_field* f = nullptr;
+  vis_status st = guarded([&] {
+    BV_REQUIRE(out != nullptr && ws != nullptr, VIS_EINVAL, "null workspace or output");
+    validate_field(basis, desc);
+    HostGeometry g = build_geometry(basis, desc);
+    f = new vis_field();
+    fill_shape(f, basis, desc, g);
+    Carver cv{static_cast<char*>(ws), bytes, 0};
+    carve_field(f, cv, f->n_tchunk);
+    hipStream_t s = as_stream(stream);
+    const int nchunks = f->n_chunks;
+    std::vector<double> freq(desc->freq_hz, desc->freq_hz + desc->n_freq);
+    std::vector<int> vpix(g.vpix);
+    vpix.resize(g.nv_pad, 0);
+    std::vector<int2> chunk_t(nchunks);
+    for (int c = 0; c < nchunks; ++c) chunk_t[c] = make_int2(g.tlo[c], g.thi[c]);
+    std::vector<int2> bl_ant(f->n_bl);
+    std::vector<int> bl_u(f->n_bl);
+    for (int k = 0; k < f->n_bl; ++k) {
+      bl_ant[k] = make_int2(g.bl_i[k], g.bl_j[k]);
+      bl_u[k] = g.bl_sign[k] > 0 ? g.bl_u[k] : ~g.bl_u[k];
+    }
+    std::vector<int> u_off(f->n_ubl + 1, 0), u_list(f->n_bl);
+    for (int k = 0; k < f->n_bl; ++k) u_off[g.bl_u[k] + 1]++;
+    for (int u = 0; u < f->n_ubl; ++u) u_off[u + 1] += u_off[u];
+    {
+      std::vector<int> fill(u_off.begin(), u_off.end() - 1);
+      for (int k = 0; k < f->n_bl; ++k) u_list[fill[g.bl_u[k]]++] = (k << 1) | (g.bl_sign[k] < 0);
+    }
+    std::vector<int> a_off(f->n_ant + 1, 0), a_list(2 * static_cast<size_t>(f->n_bl));
+    for (int k = 0; k < f->n_bl; ++k) { a_off[g.bl_i[k] + 1]++; a_off[g.bl_j[k] + 1]++; }
+    for (int a = 0; a < f->n_ant; ++a) a_off[a + 1] += a_off[a];
+    {
+      std::vector<int> fill(a_off.begin(), a_off.end() - 1);
+      for (int k = 0; k < f->n_bl; ++k) {
+        a_list[fill[g.bl_i[k]]++] = (k << 1) | 0;
+        a_list[fill[g.bl_j[k]]++] = (k << 1) | 1;
+      }
+    }
+    const int D = f->extent;
+    std::vector<int2> ubl_nm(f->n_ubl);
+    std::vector<int> ulut(static_cast<size_t>(D + 1) * (2 * D + 1), -1);
+    for (int u = 0; u < f->n_ubl; ++u) {
+      ubl_nm[u] = make_int2(g.ubl[u].first, g.ubl[u].second);
+      ulut[g.ubl[u].first * (2 * D + 1) + g.ubl[u].second + D] = u;
+    }
+    auto& T = f->tab;
+    up(T.freq, freq, s);
+    up(T.vpix, vpix, s);
+    up(T.p1, g.p1, s);
+    up(T.p2, g.p2, s);
+    up(T.th2, g.th2, s);
+    up(T.chunk_t, chunk_t, s);
+    up(T.tchunk_off, g.tchunk_off, s);
+    up(T.tchunk, g.tchunk, s);
+    up(T.bl_ant, bl_ant, s);
+    up(T.bl_u, bl_u, s);
+    up(T.u_off, u_off, s);
+    up(T.u_list, u_list, s);
+    up(T.a_off, a_off, s);
+    up(T.a_list, a_list, s);
+    up(T.ubl_nm, ubl_nm, s);
+    up(T.ulut, ulut, s);
+    // the padded tail of the sky scratch must stay finite (it is multiplied by a zero beam)
+    BV_HIP(hipMemsetAsync(f->scr.img, 0, sizeof(float) * f->n_freq * f->nv_pad, s));
+    BV_HIP(hipStreamSynchronize(s));
+    *out = f;
+  });
+  if (st != VIS_OK) delete f;
+  return st;
+}
+
+vis_status vis_field_get_info(const vis_field* f, vis_field_info* info) {
+  return guarded([&] {
+    BV_REQUIRE(f != nullptr && info != nullptr, VIS_EINVAL, "null argument");
+    info->n_ant = f->n_ant;
+    info->n_bl = f->n_bl;
+    info->n_ubl = f->n_ubl;
+    info->n_freq = f->n_freq;
+    info->n_time = f->n_time;
+    info->n_pix = f->basis->n_pix;
+    info->n_modes = f->n_modes;
+    info->n_pix_visible = f->nv;
+    info->lattice_extent = f->extent;
+    info->precision = f->precision;
+    info->d_omega = f->d_omega;
+    info->fwd_macs = f->fwd_macs;
+  });
+}
+
+vis_status vis_field_destroy(vis_field* f) {
+  delete f;
+  return VIS_OK;
+}
+
+vis_status vis_profile_enable(vis_field* f, int32_t enable) {
+  return guarded([&] {
+    BV_REQUIRE(f != nullptr, VIS_EINVAL, "null field");
+    f->prof.on = enable != 0;
+  });
+}
+
+vis_status vis_profile_read(vis_field* f, vis_kernel_time* out, int32_t max, int32_t* n_out,
+                            int32_t reset) {
+  return guarded([&] {
+    BV_REQUIRE(f != nullptr && n_out != nullptr && (out != nullptr || max == 0), VIS_EINVAL,
+               "null argument");
+    f->prof.drain();
+    int n = 0;
+    for (auto& kv : f->prof.totals) {
+      if (n >= max) break;
+      snprintf(out[n].name, sizeof(out[n].name), "%s", kv.first.c_str());
+      out[n].launches = kv.second.first;
+      out[n].total_ms = kv.second.second;
+      ++n;
+    }
+    *n_out = n;
+    if (reset) f->prof.totals.clear();
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+// Per-antenna gains, residual, chi^2 and the gradient bookkeeping that links
+// physical baselines to the unique-baseline fringe kernels.
+//
+// Sec. 2.1: m_ij = g_i conj(g_j) V_ij with V_ij = V_u (b_ij = b_u) or
+// conj(V_u) (b_ij = -b_u) for a real sky and beam (Sec. 3.1: unique
+// baselines are broadcast to the physical ones).
+// Sec. 2.3, eq. likelihood: chi^2 = sum |d - m|^2 / sigma_n^2 (FP64 total).
+// With the cotangent c = dL/dRe m + i dL/dIm m (c = -2 (d - m) / sigma_n^2 for
+// chi^2):
+//   omega_u = sum_{ij -> +u} conj(c_ij) G_ij + sum_{ij -> -u} c_ij conj(G_ij)
+//     (the coefficients of the adjoint fringe pass; G_ij = g_i conj(g_j));
+//   dL/dg_a = sum_{(a, j)} c_aj g_j conj(V_aj) + sum_{(i, a)} conj(c_ia) g_i V_ia.
+// One 256-thread block per (t, nu) keeps the gains and unique visibilities of
+// that slice in LDS; every reduction runs in a fixed order.
+#include "objects.hpp"
+
+namespace bv {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+
+struct GainArgs {
+  int mode, nt, nf, nbl, nubl, nant;
+  float inv_sig2;
+  const int2* bl_ant;
+  const int* bl_u;
+  const int* u_off;
+  const int* u_list;
+  const int* a_off;
+  const int* a_list;
+  const float2* vu;
+  const float2* gains;
+  const float2* din;
+  float2* vis_out;
+  double* chi_part;
+  float2* w;
+  float2* g_part;
+};
+
+__global__ void __launch_bounds__(256) k_gains(GainArgs a) {
+  extern __shared__ float2 sm[];
+  float2* g = sm;              // [nant]
+  float2* v = sm + a.nant;     // [nubl]
+  __shared__ double red[256];
+  const int f = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
+  const size_t slice = static_cast<size_t>(t) * a.nf + f;
+  for (int i = tid; i < a.nant; i += 256) g[i] = a.gains[static_cast<size_t>(f) * a.nant + i];
+  for (int u = tid; u < a.nubl; u += 256) v[u] = a.vu[slice * a.nubl + u];
+  __syncthreads();
+  const float2* din = a.din + slice * a.nbl;
+  auto vis_of = [&](int k) {
+    const int u = a.bl_u[k];
+    return u >= 0 ? v[u] : conjf2(v[~u]);
+  };
+  auto gprod = [&](int k) {
+    const int2 ij = a.bl_ant[k];
+    return cmul(g[ij.x], conjf2(g[ij.y]));
+  };
+  // cotangent of baseline k
+  auto cot = [&](int k) {
+    if (a.mode == kGainAdj) return din[k];
+    const float2 m = cmul(gprod(k), vis_of(k));
+    const float2 r = make_float2(din[k].x - m.x, din[k].y - m.y);
+    return make_float2(-2.f * a.inv_sig2 * r.x, -2.f * a.inv_sig2 * r.y);
+  };
+  if (a.mode == kGainFwd) {
+    float2* out = a.vis_out + slice * a.nbl;
+    for (int k = tid; k < a.nbl; k += 256) out[k] = cmul(gprod(k), vis_of(k));
+    return;
+  }
+  if (a.mode == kGainChi2) {
+    double acc = 0.0;
+    for (int k = tid; k < a.nbl; k += 256) {
+      const float2 m = cmul(gprod(k), vis_of(k));
+      const double rx = static_cast<double>(din[k].x) - m.x;
+      const double ry = static_cast<double>(din[k].y) - m.y;
+      acc += rx * rx + ry * ry;
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) a.chi_part[slice] = red[0] * static_cast<double>(a.inv_sig2);
+  }
+  for (int u = tid; u < a.nubl; u += 256) {
+    float2 om = make_float2(0.f, 0.f);
+    for (int e = a.u_off[u]; e < a.u_off[u + 1]; ++e) {
+      const int code = a.u_list[e];
+      const int k = code >> 1;
+      const float2 c = cot(k), G = gprod(k);
+      const float2 term = (code & 1) ? cmul(c, conjf2(G)) : cmul(conjf2(c), G);
+      om.x += term.x;
+      om.y += term.y;
+    }
+    a.w[slice * a.nubl + u] = om;
+  }
+  for (int ant = tid; ant < a.nant; ant += 256) {
+    float2 s = make_float2(0.f, 0.f);
+    for (int e = a.a_off[ant]; e < a.a_off[ant + 1]; ++e) {
+      const int code = a.a_list[e];
+      const int k = code >> 1;
+      const int2 ij = a.bl_ant[k];
+      const float2 c = cot(k), vk = vis_of(k);
+      const float2 term = (code & 1) ? cmul(cmul(conjf2(c), g[ij.x]), vk)
+                                     : cmul(cmul(c, g[ij.y]), conjf2(vk));
+      s.x += term.x;
+      s.y += term.y;
+    }
+    a.g_part[slice * a.nant + ant] = s;
+  }
+}
+
+// grad_gains[f][a] = sum_t g_part[t][f][a]; block (nblk-1) also totals chi^2
+// and dL/dF in FP64.
+__global__ void __launch_bounds__(256)
+k_reduce_grads(int nt, int nf, int nant, int nfpart, int with_chi2, const double* __restrict__ chi_part,
+               double* chi2, const float2* __restrict__ g_part, float2* grad_gains,
+               const float* __restrict__ f_part, float* grad_fwhm) {
+  const int tid = threadIdx.x;
+  if (blockIdx.x + 1 < gridDim.x) {
+    const int idx = blockIdx.x * 256 + tid;
+    if (idx >= nf * nant || grad_gains == nullptr) return;
+    float2 s = make_float2(0.f, 0.f);
+    for (int t = 0; t < nt; ++t) {
+      const float2 v = g_part[static_cast<size_t>(t) * nf * nant + idx];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    grad_gains[idx] = s;
+    return;
+  }
+  __shared__ double red[256];
+  if (with_chi2) {
+    double acc = 0.0;
+    for (int i = tid; i < nt * nf; i += 256) acc += chi_part[i];
+    red[tid] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) *chi2 = red[0];
+    __syncthreads();
+  }
+  if (grad_fwhm != nullptr) {
+    double acc = 0.0;
+    for (int i = tid; i < nfpart; i += 256) acc += f_part[i];
+    red[tid] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) *grad_fwhm = static_cast<float>(red[0]);
+  }
+}
+
+void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const float2* gains,
+                  const float2* din, float sigma_n, float2* vis_out, double* chi_part, float2* w,
+                  float2* g_part, hipStream_t st) {
+  GainArgs a;
+  a.mode = mode;
+  a.nt = f->n_time;
+  a.nf = f->n_freq;
+  a.nbl = f->n_bl;
+  a.nubl = f->n_ubl;
+  a.nant = f->n_ant;
+  a.inv_sig2 = sigma_n > 0.f ? 1.0f / (sigma_n * sigma_n) : 0.f;
+  a.bl_ant = f->tab.bl_ant;
+  a.bl_u = f->tab.bl_u;
+  a.u_off = f->tab.u_off;
+  a.u_list = f->tab.u_list;
+  a.a_off = f->tab.a_off;
+  a.a_list = f->tab.a_list;
+  a.vu = vu;
+  a.gains = gains;
+  a.din = din;
+  a.vis_out = vis_out;
+  a.chi_part = chi_part;
+  a.w = w;
+  a.g_part = g_part;
+  const size_t lds = sizeof(float2) * (f->n_ant + f->n_ubl);
+  BV_REQUIRE(lds <= 48 * 1024, VIS_EINVAL, "field too large for the gains pass LDS budget");
+  dim3 grid(f->n_freq, f->n_time);
+  ProfScope ps(&f->prof, "k_gains", st);
+  k_gains<<<grid, 256, lds, st>>>(a);
+  check_launch("k_gains");
+}
+
+void launch_reduce_grads(const vis_field* f, bool with_chi2, const double* chi_part, double* chi2,
+                         const float2* g_part, float2* grad_gains, const float* f_part,
+                         float* grad_fwhm, hipStream_t st) {
+  const int nblk = ceil_div(static_cast<long>(f->n_freq) * f->n_ant, 256) + 1;
+  ProfScope ps(&f->prof, "k_reduce_grads", st);
+  k_reduce_grads<<<nblk, 256, 0, st>>>(f->n_time, f->n_freq, f->n_ant, f->n_freq * f->n_chunks,
+                                       with_chi2 ? 1 : 0, chi_part, chi2, g_part, grad_gains,
+                                       f_part, grad_fwhm);
+  check_launch("k_reduce_grads");
+}
+
+}  // namespace bv

@@ -1,0 +1,126 @@
+// Internal layouts of the basis and field objects and the launchers that
+// operate on them.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_bf16.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace bv {
+
+// Per-field kernel timer: a pair of hipEvents around each launch while on.
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<long long, double>> totals;
+  hipEvent_t get();
+  void drain();   // waits for pending events and folds them into totals
+  ~Profiler();
+};
+
+// Brackets one kernel launch when the field's profiler is on.
+struct ProfScope {
+  Profiler* p;
+  const char* name;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(Profiler* p_, const char* n, hipStream_t s);
+  ~ProfScope();
+};
+
+}  // namespace bv
+
+struct vis_basis {
+  int nz = 0, nphi = 0, lmax = 0;
+  int n_pix = 0, n_modes = 0;
+  int kpad = 0;                    // row stride of Y (modes rounded up to 64), zero-filled tail
+  uint32_t storage = 0;
+  float* y32 = nullptr;            // [n_pix][kpad] FP32
+  __hip_bfloat16* ybh = nullptr;   // [n_pix][kpad] bf16 hi part
+  __hip_bfloat16* ybl = nullptr;   // [n_pix][kpad] bf16 lo part (y - hi)
+  _Float16* yhh = nullptr;         // [n_pix][kpad] fp16 hi part
+  _Float16* yhl = nullptr;         // [n_pix][kpad] fp16 lo part, scaled by 2^11
+  double* lam = nullptr;           // generator staging: normalised Legendre per ring
+  double* trig = nullptr;          // generator staging: cos / sin (m alpha) per column
+};
+
+namespace bv {
+
+// Per-evaluation scratch of one field (device).
+struct FieldScratch {
+  float* img = nullptr;            // [n_freq][nv_pad] sky at visible pixels
+  float* dimg = nullptr;           // [n_freq][nv_pad] dL/dI
+  float2* vu = nullptr;            // [n_time][n_freq][n_ubl] gain-free unique visibilities
+  float2* w = nullptr;             // [n_time][n_freq][n_ubl] collapsed adjoint coefficients
+  double* chi_part = nullptr;      // [n_time * n_freq]
+  float2* g_part = nullptr;        // [n_time][n_freq][n_ant]
+  float* f_part = nullptr;         // [n_freq * n_chunks]
+  float* a_part = nullptr;         // [split][n_freq][kpad] split-K partials of dL/da
+};
+
+// Immutable device tables of one field.
+struct FieldTables {
+  double* freq = nullptr;          // [n_freq] Hz
+  int* vpix = nullptr;             // [nv_pad] pixel index of each visible slot
+  double* p1 = nullptr;            // [n_time][nv_pad] (e1 . s) / c, seconds
+  double* p2 = nullptr;            // [n_time][nv_pad] (e2 . s) / c
+  float* th2 = nullptr;            // [n_time][nv_pad] zenith angle^2, kBelowHorizon if U <= 0
+  int2* chunk_t = nullptr;         // [n_chunks] first / last time the chunk is visible
+  int* tchunk_off = nullptr;       // [n_time + 1] CSR of chunks active at each time
+  int* tchunk = nullptr;           // [sum] chunk indices
+  int2* bl_ant = nullptr;          // [n_bl] (i, j)
+  int* bl_u = nullptr;             // [n_bl] unique index, negative-encoded sign: u or ~u
+  int* u_off = nullptr;            // [n_ubl + 1] CSR unique -> physical
+  int* u_list = nullptr;           // [n_bl] (bl << 1) | (sign < 0)
+  int* a_off = nullptr;            // [n_ant + 1] CSR antenna -> baselines
+  int* a_list = nullptr;           // [2 n_bl] (bl << 1) | role (0: antenna is i, 1: is j)
+  int2* ubl_nm = nullptr;          // [n_ubl] lattice (n1, n2), canonical
+  int* ulut = nullptr;             // [(D+1) * (2D+1)] unique index of (n1, n2) or -1
+};
+
+}  // namespace bv
+
+struct vis_field {
+  const vis_basis* basis = nullptr;
+  int n_ant = 0, n_bl = 0, n_ubl = 0, n_freq = 0, n_time = 0;
+  int n_modes = 0, lmax = 0;
+  int nv = 0, nv_pad = 0, n_chunks = 0, n_tchunk = 0;
+  int extent = 0;                  // D = max |n1|, |n2|
+  int precision = VIS_FP32;
+  int asplit = 1;                  // split-K factor of the adjoint synthesis
+  double d_omega = 0.0;
+  double beam_ref_hz = 150e6;
+  double fwd_macs = 0.0;
+  bv::FieldTables tab;
+  bv::FieldScratch scr;
+  mutable bv::Profiler prof;
+};
+
+namespace bv {
+
+// ---- launchers (stream-ordered, no host sync) ----------------------------
+void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStream_t st);
+void launch_synth_adj(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st);
+void launch_fringe_fwd(const vis_field* f, const float* img, const float* fwhm, float2* vu,
+                       hipStream_t st);
+void launch_fringe_adj(const vis_field* f, const float* img, const float* fwhm, const float2* w,
+                       float* dimg, float* f_part, hipStream_t st);
+
+enum GainMode { kGainFwd = 0, kGainChi2 = 1, kGainAdj = 2 };
+void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const float2* gains,
+                  const float2* data_or_dvis, float sigma_n, float2* vis_out, double* chi_part,
+                  float2* w, float2* g_part, hipStream_t st);
+void launch_reduce_grads(const vis_field* f, bool with_chi2, const double* chi_part,
+                         double* chi2, const float2* g_part, float2* grad_gains,
+                         const float* f_part, float* grad_fwhm, hipStream_t st);
+
+}  // namespace bv

@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances.  FP32 visibilities: per-channel normwise relative error <= 1e-5
+(the stated FP32 bar).  Gradients: the chi^2 gradient is built from the
+residual r = d - m; at the truth |r| ~ 1% of |m|, so an FP32 error of 1e-5
+|m| in m is ~1e-3 of r.  Gradients are therefore compared at a point where
+the residual is ~10-30% of the model (a_lm scaled by 1.2), where the same
+FP32 error is <~1e-4 of r; the bound used is 2e-4 normwise.  chi^2 itself is
+an FP64 sum of FP32 terms: relative bound 1e-4 at that point.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_07090_amd import workload as w
+from oracle import model
+from tests.gpu_common import chan_rel_err, rel_norm, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vis():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_07090_amd import vis as v
+    return v
+
+
+def _setup(vis, cfg, precision=1, basis=None):
+    say("setup", cfg.name, "precision", precision)
+    if basis is None:
+        basis = vis.basis_for(cfg, storage=vis.STORAGE_FOR[precision])
+    fld = vis.Field.from_config(basis, cfg, precision)
+    d = w.draw(cfg)
+    return basis, fld, d
+
+
+def _dev_params(d, cfg, alm_scale=1.0):
+    alm = torch.tensor(d.alm * alm_scale, dtype=torch.float32, device="cuda")
+    g = torch.tensor(d.gains, dtype=torch.complex64, device="cuda")
+    fw = torch.tensor([w.fwhm_ref_rad(cfg)], dtype=torch.float32, device="cuda")
+    return alm, g, fw
+
+
+@pytest.fixture(scope="module")
+def c0(vis):
+    cfg = w.C0
+    basis, fld, d = _setup(vis, cfg)
+    of = model.Field(cfg)
+    m_true, sig, data = model.make_data(of, d)
+    return cfg, basis, fld, d, of, m_true, sig, data
+
+
+def test_field_info_c0(c0):
+    cfg, basis, fld, d, of, *_ = c0
+    assert fld.n_bl == 120 and fld.n_ubl == 24 and fld.info.lattice_extent == 3
+    # algorithmic MACs = unique baselines x pixels above the horizon x channels, summed over time
+    nvis = int(np.sum(of.up))
+    assert fld.fwd_macs == 24 * nvis * cfg.n_freq
+
+
+def test_forward_c0(vis, c0):
+    cfg, basis, fld, d, of, m_true, sig, data = c0
+    alm, g, fw = _dev_params(d, cfg)
+    say("vis_forward c0")
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    err = chan_rel_err(m, m_true)
+    say("c0 per-channel rel err", err)
+    assert np.all(err <= 1e-5)
+
+
+def test_forward_deterministic(vis, c0):
+    cfg, basis, fld, d, *_ = c0
+    alm, g, fw = _dev_params(d, cfg)
+    a = vis.forward(fld, alm, g, fw)
+    b = vis.forward(fld, alm, g, fw)
+    assert torch.equal(a, b)
+
+
+def test_chi2_and_grad_c0(vis, c0):
+    cfg, basis, fld, d, of, m_true, sig, data = c0
+    alm, g, fw = _dev_params(d, cfg, alm_scale=1.2)
+    say("chi2_and_grad c0")
+    x2, ga, gg, gf = vis.chi2_and_grad(fld, torch.tensor(data, dtype=torch.complex64, device="cuda"),
+                                       sig, alm, g, fw)
+    rx2, rga, rgg, rgf = model.chi2_and_grad(of, data, sig, d.alm * 1.2, d.gains, w.fwhm_ref_rad(cfg))
+    say("chi2", float(x2), rx2, "gF", float(gf), rgf)
+    assert abs(float(x2) - rx2) <= 1e-4 * rx2
+    e_a = rel_norm(ga.cpu().numpy(), rga)
+    e_g = rel_norm(gg.cpu().numpy(), rgg)
+    say("grad errs", e_a, e_g)
+    assert e_a <= 2e-4 and e_g <= 2e-4
+    assert abs(float(gf) - rgf) <= 2e-4 * abs(rgf)
+
+
+def test_chi2_only_matches(vis, c0):
+    cfg, basis, fld, d, of, m_true, sig, data = c0
+    alm, g, fw = _dev_params(d, cfg, alm_scale=1.2)
+    dd = torch.tensor(data, dtype=torch.complex64, device="cuda")
+    a = vis.chi2_and_grad(fld, dd, sig, alm, g, fw, grads=True)[0]
+    b = vis.chi2_and_grad(fld, dd, sig, alm, g, fw, grads=False)[0]
+    assert float(a) == float(b)
+
+
+def test_adjoint_matches_oracle_c0(vis, c0):
+    cfg, basis, fld, d, of, *_ = c0
+    rng = np.random.default_rng(7)
+    y = rng.normal(size=(cfg.n_time, cfg.n_freq, fld.n_bl)) + 1j * rng.normal(
+        size=(cfg.n_time, cfg.n_freq, fld.n_bl))
+    alm, g, fw = _dev_params(d, cfg)
+    say("vis_adjoint c0")
+    ga, gg, gf = vis.adjoint(fld, alm, g, fw, torch.tensor(y, dtype=torch.complex64, device="cuda"))
+    rga, rgg, rgf = model.adjoint(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), y)
+    assert rel_norm(ga.cpu().numpy(), rga) <= 2e-5
+    assert rel_norm(gg.cpu().numpy(), rgg) <= 2e-5
+    assert abs(float(gf) - rgf) <= 2e-5 * abs(rgf)
+
+
+def test_gpu_adjoint_dot(vis, c0):
+    """Re<y, A x> = <x, A^T y> for the GPU forward/adjoint pair (a -> m linear)."""
+    cfg, basis, fld, d, *_ = c0
+    rng = np.random.default_rng(8)
+    x = torch.tensor(rng.normal(size=d.alm.shape), dtype=torch.float32, device="cuda")
+    y = torch.tensor(rng.normal(size=(cfg.n_time, cfg.n_freq, fld.n_bl)) * (1 + 1j),
+                     dtype=torch.complex64, device="cuda")
+    _, g, fw = _dev_params(d, cfg)
+    ax = vis.forward(fld, x, g, fw)
+    ga, _, _ = vis.adjoint(fld, x, g, fw, y)
+    lhs = float(torch.sum(y.real.double() * ax.real.double() + y.imag.double() * ax.imag.double()))
+    rhs = float(torch.sum(x.double() * ga.double()))
+    scale = float(torch.linalg.vector_norm(ax.abs().double()) * torch.linalg.vector_norm(y.abs().double()))
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("side", [3, 7])
+def test_forward_hex_sides(vis, side):
+    """Other lattice extents (D = 4 and D = 12: two MFMA tiles per side)."""
+    cfg = w.scaled(w.C0, array="hex", array_size=side, n_freq=3, n_time=3,
+                   freq_lo_hz=120e6, freq_hi_hz=130e6, grid_nz=32, grid_nphi=96, lmax=12)
+    basis, fld, d = _setup(vis, cfg)
+    of = model.Field(cfg)
+    alm, g, fw = _dev_params(d, cfg)
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    ref = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg))
+    assert np.all(chan_rel_err(m, ref) <= 1e-5)
+    y = np.random.default_rng(1).normal(size=ref.shape) * (1 + 0.5j)
+    ga, gg, gf = vis.adjoint(fld, alm, g, fw, torch.tensor(y, dtype=torch.complex64, device="cuda"))
+    rga, rgg, rgf = model.adjoint(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), y)
+    assert rel_norm(ga.cpu().numpy(), rga) <= 2e-5
+    assert rel_norm(gg.cpu().numpy(), rgg) <= 2e-5
+
+
+def test_lmax_prefix_of_larger_basis(vis):
+    """A field with lmax below the basis lmax uses the leading columns of Y."""
+    cfg = w.scaled(w.C0, lmax=9, n_freq=2, n_time=2)
+    big = vis.Basis(cfg.grid_nz, cfg.grid_nphi, 20, 1)
+    basis, fld, d = _setup(vis, cfg, basis=big)
+    of = model.Field(cfg)
+    alm, g, fw = _dev_params(d, cfg)
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    ref = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg))
+    assert np.all(chan_rel_err(m, ref) <= 1e-5)
+
+
+def test_degenerate_two_antennas_one_channel_one_time(vis):
+    cfg = w.C0
+    basis = vis.Basis(32, 96, 20, 1)
+    e = w.lattice_basis(cfg)
+    fld = vis.Field(basis, [[0, 0], [1, 0]], e[0], e[1], [150e6], [0.3], w.latitude_rad(cfg), 20)
+    assert fld.n_bl == 1 and fld.n_ubl == 1
+    d = w.draw(w.scaled(w.C0, n_freq=1))
+    alm = torch.tensor(d.alm, dtype=torch.float32, device="cuda")
+    g = torch.ones((1, 2), dtype=torch.complex64, device="cuda")
+    fw = torch.tensor([w.fwhm_ref_rad(cfg)], dtype=torch.float32, device="cuda")
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    # oracle: the same two antennas by direct sum over all pixels
+    from oracle import rime, sky
+    dec, ra = sky.pixel_dec_ra(32, 96)
+    enu = rime.enu_directions(dec, ra, np.array([0.3]), w.latitude_rad(cfg))
+    img = sky.synthesize(32, 96, 20, d.alm)
+    wgt = (4 * math.pi / 3072) * rime.beam(enu, np.array([150e6]), w.fwhm_ref_rad(cfg), 150e6) * img[None]
+    ref = rime.vis_direct(-e[:1], enu, wgt, np.array([150e6]))
+    assert np.abs(m - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+def test_invalid_inputs_raise(vis, c0):
+    cfg, basis, fld, d, *_ = c0
+    alm, g, fw = _dev_params(d, cfg)
+    with pytest.raises(ValueError):
+        vis.forward(fld, alm[:, :-1].contiguous(), g, fw)
+    with pytest.raises(TypeError):
+        vis.forward(fld, alm.double(), g, fw)
+    with pytest.raises(vis.VisError):
+        e = w.lattice_basis(cfg)
+        vis.Field(basis, [[0, 0], [0, 0]], e[0], e[1], [150e6], [0.0], -0.5, 5)
+    with pytest.raises(vis.VisError):
+        e = w.lattice_basis(cfg)
+        vis.Field(basis, [[0, 0], [1, 0]], e[0], e[1], [150e6], [0.0], -0.5, 30)  # lmax > basis
+
+
+@pytest.fixture(scope="module")
+def c1(vis):
+    cfg = w.C1
+    basis, fld, d = _setup(vis, cfg)
+    return cfg, basis, fld, d
+
+
+C1_CHANS = [0, 37]
+
+
+def test_forward_c1_sampled_channels(vis, c1):
+    """Full C1 size (61 dishes, 49152 px, lmax 100, 64 ch, 60 t) in the benchmarked
+    launch configuration; the oracle computes channels 0 and 37 over all times."""
+    cfg, basis, fld, d = c1
+    alm, g, fw = _dev_params(d, cfg)
+    say("vis_forward c1")
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    of = model.Field(cfg)
+    ref = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), chans=C1_CHANS)
+    err = chan_rel_err(m[:, C1_CHANS], ref)
+    say("c1 per-channel rel err", err)
+    assert np.all(err <= 1e-5)
+
+
+def test_grad_c1_sampled_channel(vis, c1):
+    """chi^2 gradient of one C1 channel: every term of channel f's gradient
+    depends only on channel f's data, so the oracle evaluates that channel alone."""
+    cfg, basis, fld, d = c1
+    f = 37
+    of = model.Field(cfg)
+    ref_m = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), chans=[f])
+    sig = model.noise_sigma(cfg, ref_m)
+    data_f = ref_m + sig * math.sqrt(2) * d.noise_unit[:, [f], :]
+    data = np.zeros((cfg.n_time, cfg.n_freq, fld.n_bl), dtype=np.complex64)
+    data[:, f] = data_f[:, 0]
+    alm, g, fw = _dev_params(d, cfg, alm_scale=1.2)
+    say("chi2_and_grad c1")
+    x2, ga, gg, gf = vis.chi2_and_grad(fld, torch.tensor(data, device="cuda"), sig, alm, g, fw)
+    rx2, rga, rgg, rgf = model.chi2_and_grad(of, data_f, sig, d.alm * 1.2, d.gains,
+                                             w.fwhm_ref_rad(cfg), chans=[f])
+    e_a = rel_norm(ga[f].cpu().numpy(), rga[0])
+    e_g = rel_norm(gg[f].cpu().numpy(), rgg[0])
+    say("c1 grad errs", e_a, e_g)
+    assert e_a <= 2e-4 and e_g <= 2e-4
