@@ -1,17 +1,26 @@
-"""Benchmark of the visibility / chi^2 / gradient hot path on one MI355X.
+"""Benchmark of the visibility / chi^2 / gradient / HMC hot path on one MI355X.
 
-One step = one chi^2 + gradient evaluation of the full path on the 61-dish
-hex / 49152-pixel / lmax 100 / 64-channel / 60-time workload: sky synthesis
-I = Y a, forward fringe contraction, gains + residual + chi^2, residual
-collapse and gain gradient, adjoint fringe contraction, adjoint synthesis,
-followed by one diagonal-mass leapfrog update of the parameter vector.
-Inputs are synthetic (seeded) and resident in HBM before timing starts.
+Step: one leapfrog step of an HMC chain on the 61-dish hex / 49152-pixel /
+lmax 100 / 64-channel / 60-time workload, run through the serving runtime:
+kick + drift, sky synthesis I = Y a, forward fringe contraction, gains +
+residual + FP64 chi^2, residual collapse and gain gradient, adjoint fringe
+contraction, adjoint synthesis, prior terms + kick, FP64 energy partials
+(and the Metropolis test at the end of the trajectory).  The timed chain has
+exactly `--steps` leapfrog steps; its initial gradient is evaluated before
+timing starts.  Inputs are synthetic (seeded) and resident in HBM.
 
 Headline value: fwd+adjoint complex MAC/s, one MAC being one term of the
 fringe sum for one (unique baseline, pixel above the horizon, channel, time),
 counted once for the forward and once for the adjoint contraction.
 
-Prints ONE JSON line.
+Serving (`serving` key): 64 concurrent chains on uneven hex fields
+(19-127 dishes, 16-128 channels, 10-120 times, lmax 30-100), one trajectory
+of 20 leapfrog steps each, through the batched server with split-precision
+(bf16 hi/lo) synthesis, against the same request stream through the plain
+FP32 path one request per tick: gradient evaluations per second and request
+latency p50/p99.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -26,8 +35,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"hbm_gbs": 8000.0, "fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0,
-        "fp32_vector_tflops": 157.3}
+PEAK = {"hbm_gbs": 8000.0, "fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0}
+EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 
 
 def log(*a):
@@ -56,10 +65,80 @@ def cpu_baseline(cfg, chan: int = 37):
     macs = 2.0 * len(of.ubl_ij) * float(np.sum(of.up))  # fwd + adjoint, one channel
     return {"value": macs / (t2 - t1), "unit": "complex MAC/s", "cores": int(blas_threads),
             "kind": "oracle",
-            "sample": (f"FP64 NumPy oracle chi^2 + analytic gradient of channel {chan} only, all "
+            "sample": (f"FP64 NumPy oracle chi^2 + analytic gradient of channel {chan} of 64, all "
                        f"{cfg.n_time} times, {len(of.ubl_ij)} unique baselines, full grid: "
-                       f"{t2 - t1:.1f} s (data generation {t1 - t0:.1f} s not timed); elementwise "
-                       f"NumPy is single-threaded, BLAS uses {blas_threads} threads")}
+                       f"{t2 - t1:.1f} s (data generation {t1 - t0:.1f} s not timed); "
+                       f"elementwise NumPy single-threaded, BLAS {blas_threads} threads")}
+
+
+def make_chain(vis, serve, torch, basis, cfg, prec, start_scale=1.0):
+    """Field, synthetic data, inverse mass and prior for one chain of config cfg."""
+    from paper_2504_07090_amd import workload as w
+    fld = vis.Field.from_config(basis, cfg, prec)
+    d = w.draw(cfg)
+    alm = torch.tensor(d.alm, dtype=torch.float32, device="cuda")
+    g = torch.tensor(d.gains, dtype=torch.complex64, device="cuda")
+    fw = torch.tensor([w.fwhm_ref_rad(cfg)], dtype=torch.float32, device="cuda")
+    m = vis.forward(fld, alm, g, fw)
+    rms = float(torch.sqrt(torch.mean(m.abs().double() ** 2)))
+    sigma = cfg.noise_frac * rms / math.sqrt(2.0)
+    data = (m + sigma * math.sqrt(2.0) * torch.tensor(d.noise_unit, dtype=torch.complex64,
+                                                      device="cuda")).contiguous()
+    del m
+    lay = serve.Layout(fld)
+    h = serve.diag_hessian(fld, alm, g, fw, sigma, n_probes=16)
+    cvar = torch.tensor(d.alm_var, dtype=torch.float32, device="cuda")
+    h[:lay.nalm] += 1.0 / cvar.reshape(-1).double()
+    h[lay.goff:lay.goff + lay.ngain] += 2.0 / cfg.gain_scatter ** 2
+    minv = (1.0 / h).float().contiguous()
+    # start slightly off the truth: 1% of the prior width
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(cfg.seed)
+    q0 = lay.pack(alm, g, fw)
+    q0[:lay.nalm] += 0.01 * torch.sqrt(cvar.reshape(-1)) * torch.randn(lay.nalm, generator=gen,
+                                                                       device="cuda")
+    return fld, data, sigma, q0.contiguous(), minv, cvar, lay
+
+
+def wait_requests(srv, n, timeout_s=300):
+    t_end = time.monotonic() + timeout_s
+    while srv.stats()["requests"] < n:
+        if time.monotonic() > t_end:
+            raise TimeoutError("server did not finish the initial evaluations")
+        time.sleep(0.002)
+
+
+def serving_bench(vis, serve, torch, basis, n_chains, prec, max_batch, n_leapfrog=20):
+    from paper_2504_07090_amd import workload as w
+    chains = []
+    for c in range(n_chains):
+        cfg = w.serving_chain_config(c)
+        chains.append((cfg, make_chain(vis, serve, torch, basis, cfg, prec)))
+    fp = sum(serve.Server.footprint(ch[1][0]) for ch in chains)
+    srv = serve.Server(fp + (64 << 20), max_chains=n_chains, max_batch=max_batch)
+    ids = []
+    for c, (cfg, (fld, data, sigma, q0, minv, cvar, lay)) in enumerate(chains):
+        ids.append(srv.admit(fld, data, sigma, q0, minv, cvar, cfg.gain_scatter, EPS, n_leapfrog,
+                             seed=7, stream_id=c, adapt_step=True))
+    wait_requests(srv, n_chains)
+    srv.stats(reset=True)
+    log("serving: chains admitted,", sum(1 for _ in ids), "fields, max_batch", max_batch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in ids:
+        srv.submit(i, 1)
+    res = srv.wait(n_chains, timeout_s=600)
+    t1 = time.perf_counter()
+    if any(r["status"] != 0 for r in res):
+        raise RuntimeError("a serving chain failed: " + str([r for r in res if r["status"]][:2]))
+    st = srv.stats()
+    srv.close()
+    macs = sum(2.0 * ch[1][0].fwd_macs for ch in chains) * n_leapfrog
+    acc = sum(r["accepted"] for r in res) / len(res)
+    bad = sum(r["status"] != 0 for r in res)
+    return {"grad_evals_per_s": st["requests"] / (t1 - t0), "p50_ms": st["p50_ms"],
+            "p99_ms": st["p99_ms"], "requests": st["requests"], "wall_s": t1 - t0,
+            "complex_macs_per_s": macs / (t1 - t0), "acceptance": acc, "failed": bad}
 
 
 def main():
@@ -68,6 +147,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--serve-chains", type=int, default=64)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -75,71 +156,75 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2504_07090_amd import vis, workload as w
+    from paper_2504_07090_amd import serve, vis, workload as w
 
     torch.cuda.set_device(0)
     cfg = w.C1
     prec = vis.VIS_FP32 if args.precision == "fp32" else vis.VIS_BF16X3
-    log("building basis and field", cfg.name)
-    basis = vis.basis_for(cfg, storage=vis.STORAGE_FOR[prec])
-    fld = vis.Field.from_config(basis, cfg, prec)
-    d = w.draw(cfg)
-    alm = torch.tensor(d.alm, dtype=torch.float32, device="cuda")
-    gains = torch.tensor(d.gains, dtype=torch.complex64, device="cuda")
-    fwhm = torch.tensor([w.fwhm_ref_rad(cfg)], dtype=torch.float32, device="cuda")
-    # synthetic data: model at the truth plus noise of 1% of the visibility rms
-    m_true = vis.forward(fld, alm, gains, fwhm)
-    rms = float(torch.sqrt(torch.mean(m_true.abs().double() ** 2)))
-    sigma = cfg.noise_frac * rms / math.sqrt(2.0)
-    noise = torch.tensor(d.noise_unit, dtype=torch.complex64, device="cuda")
-    data = (m_true + sigma * math.sqrt(2.0) * noise).contiguous()
-    del noise, m_true
-    # evaluate at a perturbed point so the gradient is not dominated by noise
-    alm_q = (alm * 1.05).contiguous()
-    torch.cuda.synchronize()
-
-    def step():
-        return vis.chi2_and_grad(fld, data, sigma, alm_q, gains, fwhm)
-
-    log("warmup", args.warmup)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    log("basis + fields", cfg.name)
+    basis = vis.basis_for(cfg, storage=1 | 2)
+    warm = make_chain(vis, serve, torch, basis, cfg, prec)
+    timed = make_chain(vis, serve, torch, basis, cfg, prec)
+    fld = timed[0]
+    srv = serve.Server(serve.Server.footprint(fld) * 2 + (64 << 20), max_chains=2, max_batch=2)
+    fldw, dataw, sigw, q0w, minvw, cvarw, _ = warm
+    cw = srv.admit(fldw, dataw, sigw, q0w, minvw, cvarw, cfg.gain_scatter, EPS,
+                   max(1, args.warmup), seed=1, stream_id=0)
+    srv.submit(cw, 1)
+    srv.wait(1, timeout_s=300)
+    fld, data, sigma, q0, minv, cvar, lay = timed
     vis.profile_enable(fld, True)
+    ct = srv.admit(fld, data, sigma, q0, minv, cvar, cfg.gain_scatter, EPS, args.steps,
+                   seed=2, stream_id=1)
+    wait_requests(srv, 1 + max(1, args.warmup) + 1)   # warm-up chain + the timed chain's initial gradient
     vis.profile_read(fld, reset=True)
+    srv.stats(reset=True)
+    log("timed trajectory of", args.steps, "leapfrog steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = step()
+    srv.submit(ct, 1)
+    res = srv.wait(1, timeout_s=600)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    st = srv.stats()
     ktimes = vis.profile_read(fld, reset=True)
     vis.profile_enable(fld, False)
+    srv.close()
+    if res[0]["status"] != 0:
+        raise RuntimeError(f"timed chain failed: {res[0]}")
     ms = (t1 - t0) * 1e3 / args.steps
     macs = 2.0 * fld.fwd_macs
     value = macs / (ms * 1e-3)
-    log("chi2", float(out[0]), "ms/step", ms)
+    log("ms/step", ms, "result", res[0])
 
-    # dominant kernel and its roofline
     per = {k: v[1] / max(1, v[0]) for k, v in ktimes.items()}
     dom = max(ktimes, key=lambda k: ktimes[k][1])
     dom_ms = per[dom]
     nv = fld.info.n_pix_visible
     if dom.startswith("k_fringe"):
         work = 4.0 * fld.fwd_macs            # 2 FMA per complex x real MAC
-        roof = {"bound": "mfma", "achieved": work / (dom_ms * 1e-3) / 1e12,
-                "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s"}
+        roof = {"bound": "mfma", "peak": PEAK["fp32_mfma_tflops"]}
     else:
         work = 2.0 * cfg.n_freq * nv * fld.n_modes
-        pk = PEAK["fp32_mfma_tflops"] if prec == vis.VIS_FP32 else PEAK["bf16_mfma_tflops"]
-        roof = {"bound": "mfma", "achieved": work / (dom_ms * 1e-3) / 1e12, "peak": pk,
-                "unit": "TFLOP/s"}
+        roof = {"bound": "mfma", "peak": PEAK["fp32_mfma_tflops"] if prec == vis.VIS_FP32
+                else PEAK["bf16_mfma_tflops"]}
+    roof.update({"achieved": work / (dom_ms * 1e-3) / 1e12, "unit": "TFLOP/s"})
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
     roof["kernel"] = dom
     roof["kernel_ms"] = dom_ms
+
+    serving = None
+    if not args.no_serve:
+        log("serving:", args.serve_chains, "chains, batched bf16x3")
+        fast = serving_bench(vis, serve, torch, basis, args.serve_chains, vis.VIS_BF16X3,
+                             max_batch=args.serve_chains)
+        log("serving: per-chain FP32 baseline")
+        base = serving_bench(vis, serve, torch, basis, args.serve_chains, vis.VIS_FP32, max_batch=1)
+        serving = {"chains": args.serve_chains, "leapfrog_steps": 20,
+                   "batched_bf16x3": fast, "per_chain_fp32": base,
+                   "speedup": fast["grad_evals_per_s"] / base["grad_evals_per_s"]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -154,10 +239,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg.name, "n_ant": fld.n_ant, "n_bl": fld.n_bl, "n_ubl": fld.n_ubl,
                    "n_pix": fld.info.n_pix, "n_pix_visible": nv, "lmax": cfg.lmax,
-                   "n_freq": cfg.n_freq, "n_time": cfg.n_time, "fwd_macs": fld.fwd_macs},
-        "kernel_ms": {k: v[1] / max(1, v[0]) for k, v in ktimes.items()},
+                   "n_freq": cfg.n_freq, "n_time": cfg.n_time, "fwd_macs": fld.fwd_macs,
+                   "leapfrog_steps": args.steps},
         "grad_evals_per_s": 1e3 / ms,
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+        "kernel_ms": per,
         "roofline": roof,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -1,0 +1,106 @@
+/*
+ * bayesvis_serve.h -- C ABI of the continuous-batching HMC server built on
+ * the bayesvis evaluation path (include bayesvis.h first).
+ */
+#ifndef BAYESVIS_SERVE_H
+#define BAYESVIS_SERVE_H
+
+#include "bayesvis.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- serving --
+ * Continuous-batching HMC server (Sec. 4.2, App. B with a diagonal mass
+ * matrix).  Each chain owns a field, data, a parameter vector q =
+ * [a (n_freq*n_modes), gains as (Re, Im) pairs (n_freq*n_ant*2), F] and an
+ * inverse mass diagonal of the same length, all resident in the server's
+ * arena.  The potential is U = chi^2/2 + sum a^2 / (2 C) + sum |g - 1|^2 /
+ * (2 s_g^2 / 2) (Gaussian priors; flat in F).  A trajectory draws
+ * p = z / sqrt(minv), z from Philox-4x32-10 (key = seed, counter =
+ * (block, trajectory, chain stream, 0)) with Box-Muller, takes n_leapfrog
+ * steps and accepts with probability min(1, exp(H0 - H1)) (uniform from
+ * counter (0xFFFFFFFF, trajectory, stream, 1)).  Each leapfrog step is one
+ * chi^2 + gradient request; a worker thread batches the pending requests of
+ * all chains into one sequence of batched kernel launches per tick, and
+ * admits new chains while others are in flight when the arena has room.
+ * If adapt_step is set, after each trajectory eps <- eps / 1.2 when the
+ * acceptance probability is below 0.2, else eps <- min(eps0, 1.2 eps)
+ * (App. B, step-size adaptation).
+ * Parameter layout (float): a at [0, n_freq*n_modes), zero padding up to
+ * g_off = round_up(n_freq*n_modes, 64), gains as (Re, Im) pairs at
+ * [g_off, g_off + 2*n_freq*n_ant), F last; length g_off + 2*n_freq*n_ant + 1.
+ * The padding is ignored (its minv may be anything).  Each chain needs its
+ * own field (the field holds the evaluation scratch).  A trajectory whose
+ * final energy is non-finite (a divergence) is rejected like any other.  A
+ * chain whose potential at its own position is non-finite reports
+ * VIS_ENUMERIC once and stops; other chains are unaffected.  The server owns `stream` while it exists; it allocates only
+ * host objects (a worker thread, events, pinned staging for tick tables).  */
+typedef struct hmc_server hmc_server;
+
+typedef struct {
+  int32_t max_chains;          /* request-table capacity, >= 1 */
+  int32_t max_batch;           /* requests per tick, >= 1 */
+  int32_t batched;             /* 1: batched launches across chains; 0: one chain per launch */
+  int32_t reserved;
+} hmc_server_config;
+
+typedef struct {
+  const vis_field* field;      /* must outlive the chain */
+  const vis_c64* data;         /* device [n_time][n_freq][n_bl], read during the chain's life */
+  float sigma_n;
+  const float* q0;             /* device, initial position (copied into the arena) */
+  const float* minv;           /* device, inverse mass diagonal (copied) */
+  const float* alm_prior_var;  /* device [n_freq][n_modes] prior variance C (copied) */
+  float gain_prior_sigma;      /* s_g: gains ~ 1 + s_g CN(0, 1) */
+  float eps;                   /* leapfrog step size */
+  int32_t n_leapfrog;          /* steps per trajectory, >= 1 */
+  int32_t adapt_step;
+  uint64_t seed;               /* Philox key */
+  uint32_t stream_id;          /* Philox counter word 2 (distinct per chain) */
+} hmc_chain_init;
+
+typedef struct {
+  int32_t chain;
+  int32_t trajectory;          /* 0-based trajectory index of this chain */
+  int32_t accepted;
+  int32_t status;              /* VIS_OK or VIS_ENUMERIC (non-finite H) */
+  double h0, h1;               /* Hamiltonian before / after (FP64) */
+  double chi2;                 /* chi^2 at the chain's position after the transition */
+  float eps;                   /* step size used */
+  int32_t n_grad;              /* gradient evaluations in this trajectory */
+  uint64_t t_submit_ns, t_done_ns;   /* host steady-clock timestamps */
+} hmc_result;
+
+typedef struct {
+  int64_t requests;            /* chi^2 + gradient requests completed */
+  double p50_ms, p99_ms, max_ms; /* request latency: tick enqueue -> result visible to the host */
+  int64_t arena_free_bytes;
+  int32_t live_chains;
+} hmc_stats;
+
+/* Arena bytes one chain of this field occupies (its state vectors, prior
+ * variances, reduction partials); admission succeeds when a free block of
+ * this size exists.  The field workspace and the data are the caller's.    */
+size_t hmc_chain_footprint_bytes(const vis_field* field);
+vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size_t arena_bytes,
+                             void* stream, hmc_server** out);
+/* VIS_EAGAIN: the arena has no room for this chain now (retry after a release). */
+vis_status hmc_chain_admit(hmc_server* s, const hmc_chain_init* init, int32_t* chain_id);
+vis_status hmc_submit(hmc_server* s, int32_t chain_id, int32_t n_trajectories);
+/* Copies up to max finished trajectories; waits up to timeout_ms (0 = no wait). */
+vis_status hmc_poll(hmc_server* s, hmc_result* out, int32_t max, int32_t* n_out,
+                    int32_t timeout_ms);
+/* Copies the chain's current position (device pointer q_out, length of q). */
+vis_status hmc_chain_position(hmc_server* s, int32_t chain_id, float* q_out, void* stream);
+vis_status hmc_chain_release(hmc_server* s, int32_t chain_id);
+/* Request-latency percentiles since creation or the last reset.            */
+vis_status hmc_server_stats(hmc_server* s, hmc_stats* out, int32_t reset);
+/* Stops the worker after the ticks in flight complete; frees the handle.  */
+vis_status hmc_server_destroy(hmc_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BAYESVIS_SERVE_H */

@@ -84,16 +84,22 @@ def leapfrog(q: np.ndarray, p: np.ndarray, grad: np.ndarray, eps: float, n_steps
     return q, p, u, grad
 
 
-def draw_momentum(minv: np.ndarray, seed: int, stream: int, traj: int) -> np.ndarray:
-    z = philox.normals(minv.size, seed, stream, traj)
+def draw_momentum(minv: np.ndarray, seed: int, stream: int, traj: int,
+                  normal_index: np.ndarray = None) -> np.ndarray:
+    """p = z / sqrt(minv); element j takes normal number normal_index[j] (default j)
+    of the (seed, stream, traj) Philox sequence."""
+    if normal_index is None:
+        z = philox.normals(minv.size, seed, stream, traj)
+    else:
+        z = philox.normals(int(np.max(normal_index)) + 1, seed, stream, traj)[normal_index]
     return z / np.sqrt(minv)
 
 
 def trajectory(q0: np.ndarray, u0: float, grad0: np.ndarray, eps: float, n_steps: int,
                minv: np.ndarray, potential_and_grad: Callable, seed: int, stream: int,
-               traj: int):
+               traj: int, normal_index: np.ndarray = None):
     """One HMC transition.  Returns (q, U, grad, accepted, H0, H1)."""
-    p0 = draw_momentum(minv, seed, stream, traj)
+    p0 = draw_momentum(minv, seed, stream, traj, normal_index)
     h0 = u0 + kinetic(p0, minv)
     q1, p1, u1, g1 = leapfrog(q0, p0, grad0, eps, n_steps, minv, potential_and_grad)
     h1 = u1 + kinetic(p1, minv)

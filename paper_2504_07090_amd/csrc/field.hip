@@ -214,8 +214,8 @@ static void validate_field(const vis_basis* basis, const vis_field_desc* d) {
   BV_REQUIRE(std::isfinite(d->latitude_rad) && std::fabs(d->latitude_rad) <= kPi / 2, VIS_EINVAL,
              "latitude out of range");
   BV_REQUIRE(d->beam_ref_hz > 0.0, VIS_EINVAL, "beam_ref_hz must be positive");
-  BV_REQUIRE(d->precision == VIS_FP32 || d->precision == VIS_BF16X3 || d->precision == VIS_FP16X3,
-             VIS_EINVAL, "unknown precision %d", d->precision);
+  BV_REQUIRE(d->precision == VIS_FP32 || d->precision == VIS_BF16X3, VIS_EINVAL,
+             "precision %d is not available (VIS_FP32 and VIS_BF16X3 are)", d->precision);
   const uint32_t need = d->precision == VIS_FP32 ? 1u : d->precision == VIS_BF16X3 ? 2u : 4u;
   BV_REQUIRE((basis->storage & need) != 0, VIS_EINVAL,
              "the basis was created without the storage this precision needs");

@@ -1,0 +1,223 @@
+// Leapfrog / Hamiltonian kernels for HMC with a diagonal mass matrix.
+//
+// Sec. 4.2 and App. B: with M = diag(1 / minv) the kinetic energy is
+// K = sum minv p^2 / 2, the drift is dq = eps minv p, and momenta are drawn as
+// p = z / sqrt(minv), z ~ N(0, 1).  One leapfrog step is
+//     p <- p - eps/2 grad U(q);  q <- q + eps minv p;  p <- p - eps/2 grad U(q),
+// and a trajectory ends with a Metropolis test on H = U + K (FP64).
+// The potential is U = chi^2 / 2 + sum a^2 / (2 C) + sum |g - 1|^2 / (2 v_g)
+// (Gaussian priors; flat in F), so grad U = grad chi^2 / 2 + a / C + (g - 1) / v_g.
+//
+// Momenta come from Philox-4x32-10 (Salmon et al. 2011): counter (block,
+// trajectory, stream, 0), key (seed lo, seed hi); each 4-word output gives
+// four normals by the Box-Muller transform.  The Metropolis uniform is word 0
+// of counter (0xFFFFFFFF, trajectory, stream, 1).  All per-chain reductions
+// run in a fixed order, so a chain's trajectory does not depend on which
+// other chains share its batch.
+#include "hmc.hpp"
+
+namespace bv {
+
+// ---------------------------------------------------------------- Philox --
+__device__ __forceinline__ uint4 philox_round(uint4 c, uint2 k) {
+  const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+  const uint32_t hi0 = __umulhi(m0, c.x), lo0 = m0 * c.x;
+  const uint32_t hi1 = __umulhi(m1, c.z), lo1 = m1 * c.z;
+  return make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+}
+
+__device__ uint4 philox10(uint4 c, uint2 k) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k.x += 0x9E3779B9u;
+      k.y += 0xBB67AE85u;
+    }
+    c = philox_round(c, k);
+  }
+  return c;
+}
+
+__device__ __forceinline__ double unit_open(uint32_t x) {
+  return (static_cast<double>(x) + 0.5) * 2.3283064365386963e-10;  // 2^-32
+}
+
+// Normals 4j .. 4j+3 of the (trajectory, stream) momentum sequence.
+__device__ __forceinline__ void normals4(uint64_t seed, uint32_t stream, uint32_t traj, uint32_t j,
+                                         float z[4]) {
+  const uint4 x = philox10(make_uint4(j, traj, stream, 0u),
+                           make_uint2(static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32)));
+  const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const float r = sqrtf(-2.0f * logf(static_cast<float>(unit_open(w[2 * h]))));
+    float s, c;
+    sincospif(2.0f * static_cast<float>(unit_open(w[2 * h + 1])), &s, &c);
+    z[2 * h] = r * c;
+    z[2 * h + 1] = r * s;
+  }
+}
+
+__device__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int o = kHmcThreads / 2; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// One block handles kHmcPerBlock consecutive parameters of one chain.
+__global__ void __launch_bounds__(kHmcThreads)
+k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__ blk0) {
+  __shared__ double red[kHmcThreads];
+  // locate the task: blk0 is an exclusive prefix over tasks of their block counts
+  int lo = 0, hi = ntask - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (blk0[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const HmcTask T = tasks[lo];
+  const int lb = b - blk0[lo];
+  if (lb >= T.nblk) return;
+  HmcState* st = T.st;
+  const float eps = st->eps;
+  const int beg = lb * kHmcPerBlock;
+  double acc_u = 0.0, acc_k = 0.0, acc_k0 = 0.0;
+  if ((T.op & kOpRestore) != 0 && st->restore == 0) return;
+  for (int i0 = beg + threadIdx.x * 4; i0 < beg + kHmcPerBlock; i0 += kHmcThreads * 4) {
+    float z[4];
+    if (T.op & kOpBegin) normals4(T.seed, T.stream, T.traj, static_cast<uint32_t>(i0 >> 2), z);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = i0 + e;
+      if (i >= T.len) break;
+      if (i >= T.nalm && i < T.goff) continue;  // alignment padding: never touched
+      if (T.op & kOpRestore) {
+        T.q[i] = T.q0[i];
+        T.grad[i] = T.grad0[i];
+        continue;
+      }
+      const float mi = T.minv[i];
+      float p = T.p[i];
+      if (T.op & kOpBegin) {
+        p = z[e] * rsqrtf(mi);
+        acc_k0 += 0.5 * static_cast<double>(mi) * p * p;
+        T.q0[i] = T.q[i];
+        T.grad0[i] = T.grad[i];
+      }
+      if (T.op & kOpKickDrift) {
+        p -= 0.5f * eps * T.grad[i];
+        T.q[i] += eps * mi * p;
+      }
+      if (T.op & (kOpPost | kOpInit)) {
+        // assemble grad U from the chi^2 gradient and the priors
+        const float q = T.q[i];
+        float g = 0.5f * T.gchi[i];
+        if (i < T.nalm) {
+          g += q / T.cvar[i];
+          acc_u += 0.5 * static_cast<double>(q) * q / T.cvar[i];
+        } else if (i >= T.goff && i < T.goff + T.ngain) {
+          const float dg = q - ((i - T.goff) % 2 == 0 ? 1.0f : 0.0f);
+          g += dg * T.gvar_inv;
+          acc_u += 0.5 * static_cast<double>(dg) * dg * T.gvar_inv;
+        }
+        T.grad[i] = g;
+        if (T.op & kOpPost) {
+          p -= 0.5f * eps * g;
+          acc_k += 0.5 * static_cast<double>(mi) * p * p;
+        }
+      }
+      T.p[i] = p;
+    }
+  }
+  if (T.op & kOpRestore) return;
+  const double su = block_sum(acc_u, red);
+  const double sk = block_sum(acc_k, red);
+  const double sk0 = block_sum(acc_k0, red);
+  if (threadIdx.x == 0) {
+    if (T.op & (kOpPost | kOpInit)) T.part_u[lb] = su;
+    if (T.op & kOpPost) T.part_k[lb] = sk;
+    if (T.op & kOpBegin) {
+      T.part_k0[lb] = sk0;
+      if (lb == 0) {
+        st->u0 = st->u;
+        st->chi2_0 = st->chi2;
+      }
+    }
+  }
+}
+
+// One block per task: totals in FP64, Hamiltonian and Metropolis test at the
+// end of a trajectory, step-size adaptation.
+__global__ void __launch_bounds__(kHmcThreads)
+k_hmc_finalize(const HmcTask* __restrict__ tasks) {
+  __shared__ double red[kHmcThreads];
+  const HmcTask T = tasks[blockIdx.x];
+  HmcState* st = T.st;
+  double su = 0.0, sk = 0.0, sk0 = 0.0;
+  for (int i = threadIdx.x; i < T.nblk; i += kHmcThreads) {
+    su += T.part_u[i];
+    if (T.op & kOpEnd) {
+      sk += T.part_k[i];
+      sk0 += T.part_k0[i];
+    }
+  }
+  su = block_sum(su, red);
+  sk = block_sum(sk, red);
+  sk0 = block_sum(sk0, red);
+  if (threadIdx.x != 0) return;
+  const double u = 0.5 * st->chi2 + su;
+  st->u = u;
+  st->restore = 0;
+  if (!(T.op & kOpEnd)) {
+    // a non-finite potential at the chain's own (accepted) position is an
+    // error; mid-trajectory it is a divergence, rejected at the trajectory end
+    if ((T.op & kOpInit) && !isfinite(u)) st->status = -6;
+    *T.st_out = *st;
+    return;
+  }
+  const double h0 = st->u0 + sk0;
+  const double h1 = u + sk;
+  st->h0 = h0;
+  st->h1 = h1;
+  const double un = unit_open(philox10(make_uint4(0xFFFFFFFFu, T.traj, T.stream, 1u),
+                                       make_uint2(static_cast<uint32_t>(T.seed),
+                                                  static_cast<uint32_t>(T.seed >> 32))).x);
+  const bool finite = isfinite(h0) && isfinite(h1);
+  const double acc_prob = finite ? exp(fmin(0.0, h0 - h1)) : 0.0;
+  const int accepted = finite && un < acc_prob;
+  st->accepted = accepted;
+  st->status = isfinite(h0) ? 0 : -6;
+  st->eps_used = st->eps;
+  if (!accepted) {
+    st->restore = 1;
+    st->u = st->u0;
+    st->chi2 = st->chi2_0;
+  }
+  if (st->adapt) {
+    const float e = st->eps;
+    st->eps = acc_prob < 0.2 ? e / 1.2f : fminf(st->eps0, 1.2f * e);
+  }
+  *T.st_out = *st;
+}
+
+void launch_hmc_elem(const HmcTask* tasks_dev, int ntask, const int* blk0_dev, int nblocks,
+                     hipStream_t st) {
+  if (ntask == 0 || nblocks == 0) return;
+  k_hmc_elem<<<nblocks, kHmcThreads, 0, st>>>(tasks_dev, ntask, blk0_dev);
+  check_launch("k_hmc_elem");
+}
+
+void launch_hmc_finalize(const HmcTask* tasks_dev, int ntask, hipStream_t st) {
+  if (ntask == 0) return;
+  k_hmc_finalize<<<ntask, kHmcThreads, 0, st>>>(tasks_dev);
+  check_launch("k_hmc_finalize");
+}
+
+}  // namespace bv

@@ -1,0 +1,58 @@
+// Internal structures of the HMC kernels and the serving runtime.
+#pragma once
+
+#include "objects.hpp"
+
+namespace bv {
+
+constexpr int kHmcThreads = 256;
+constexpr int kHmcPerBlock = 4096;   // parameters per elementwise block
+
+enum HmcOp : int {
+  kOpBegin = 1,        // draw p, save q0 / grad0, K0 partials
+  kOpKickDrift = 2,    // p -= eps/2 grad; q += eps minv p
+  kOpPost = 4,         // grad = grad chi^2 / 2 + prior; p -= eps/2 grad; U, K partials
+  kOpInit = 8,         // grad and U partials at the initial position, no kick
+  kOpEnd = 16,         // finalize: this evaluation ends a trajectory
+  kOpRestore = 32      // q = q0, grad = grad0 if the trajectory was rejected
+};
+
+// Device-resident scalars of one chain.
+struct HmcState {
+  double chi2;       // chi^2 at q (written by the evaluation)
+  double chi2_0;     // chi^2 at the start of the current trajectory
+  double u, u0;      // potential at q / at the trajectory start
+  double h0, h1;     // Hamiltonian before / after the last finished trajectory
+  float eps, eps0, eps_used;
+  int adapt;
+  int accepted, restore, status;
+  int pad;
+};
+
+// One chain's work in one kernel launch.
+struct HmcTask {
+  float* q;
+  float* p;
+  float* grad;       // grad U at q
+  const float* gchi; // grad chi^2 at q (evaluation output)
+  const float* minv;
+  float* q0;
+  float* grad0;
+  const float* cvar; // prior variance of the sky coefficients
+  double* part_u;
+  double* part_k;
+  double* part_k0;
+  HmcState* st;
+  HmcState* st_out;  // finalize copies the state here for the host read-back
+  uint64_t seed;
+  int len, nalm, goff, ngain;
+  float gvar_inv;
+  int op, nblk;
+  uint32_t stream, traj;
+};
+
+void launch_hmc_elem(const HmcTask* tasks_dev, int ntask, const int* blk0_dev, int nblocks,
+                     hipStream_t st);
+void launch_hmc_finalize(const HmcTask* tasks_dev, int ntask, hipStream_t st);
+
+}  // namespace bv

@@ -1,0 +1,664 @@
+// Continuous-batching HMC server.
+//
+// Each admitted chain owns a slice of the caller's arena holding its
+// position q, momentum p, gradients, inverse mass diagonal, trajectory-start
+// copies, prior variances, reduction partials and a small FP64 state block.
+// A worker thread runs "ticks": every chain with work left contributes one
+// chi^2 + gradient request (one leapfrog step) to the tick; a tick is one
+// batched elementwise launch (kick / drift / momentum draw), the evaluations,
+// one batched post-kick launch, one FP64 finalize launch (energies,
+// Metropolis test, step-size adaptation) and a batched restore launch.
+// Because a trajectory always has n_leapfrog steps, the host knows the step
+// schedule in advance and enqueues the next tick before the previous one
+// finishes; results are read back asynchronously through pinned staging.
+// Chains admitted or submitted while ticks are in flight join the next tick.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "hmc.hpp"
+
+#include "../../include/bayesvis_serve.h"
+
+namespace bv {
+
+static uint64_t now_ns() {
+  return static_cast<uint64_t>(std::chrono::duration_cast<std::chrono::nanoseconds>(
+                                   std::chrono::steady_clock::now().time_since_epoch())
+                                   .count());
+}
+
+struct ChainLayout {
+  int nalm, goff, ngain, len, nblk;
+  size_t off_q, off_p, off_grad, off_gchi, off_minv, off_q0, off_grad0, off_cvar;
+  size_t off_pu, off_pk, off_pk0, off_state, bytes;
+};
+
+static ChainLayout chain_layout(const vis_field* f) {
+  ChainLayout L;
+  L.nalm = f->n_freq * f->n_modes;
+  L.goff = static_cast<int>(round_up(L.nalm, 64));
+  L.ngain = 2 * f->n_freq * f->n_ant;
+  L.len = L.goff + L.ngain + 1;
+  L.nblk = ceil_div(L.len, kHmcPerBlock);
+  Carver cv;
+  auto at = [&](size_t bytes) {
+    size_t off = (cv.used + 255) / 256 * 256;
+    cv.used = off + bytes;
+    return off;
+  };
+  const size_t vf = sizeof(float) * static_cast<size_t>(L.len);
+  L.off_q = at(vf);
+  L.off_p = at(vf);
+  L.off_grad = at(vf);
+  L.off_gchi = at(vf);
+  L.off_minv = at(vf);
+  L.off_q0 = at(vf);
+  L.off_grad0 = at(vf);
+  L.off_cvar = at(sizeof(float) * static_cast<size_t>(L.nalm));
+  L.off_pu = at(sizeof(double) * L.nblk);
+  L.off_pk = at(sizeof(double) * L.nblk);
+  L.off_pk0 = at(sizeof(double) * L.nblk);
+  L.off_state = at(sizeof(HmcState));
+  L.bytes = round_up(cv.used, 256);
+  return L;
+}
+
+// First-fit allocator over the arena in 256-byte granules.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  std::list<std::pair<size_t, size_t>> free_list;  // (offset, size), sorted
+  void init(char* b, size_t c) {
+    base = b;
+    cap = c;
+    free_list.clear();
+    free_list.emplace_back(0, c);
+  }
+  long alloc(size_t n) {
+    n = round_up(n, 256);
+    for (auto it = free_list.begin(); it != free_list.end(); ++it) {
+      if (it->second >= n) {
+        const size_t off = it->first;
+        it->first += n;
+        it->second -= n;
+        if (it->second == 0) free_list.erase(it);
+        return static_cast<long>(off);
+      }
+    }
+    return -1;
+  }
+  void release(size_t off, size_t n) {
+    n = round_up(n, 256);
+    auto it = free_list.begin();
+    while (it != free_list.end() && it->first < off) ++it;
+    it = free_list.insert(it, {off, n});
+    auto nx = std::next(it);
+    if (nx != free_list.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_list.erase(nx);
+    }
+    if (it != free_list.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_list.erase(it);
+      }
+    }
+  }
+};
+
+struct Chain {
+  int id = -1;
+  const vis_field* field = nullptr;
+  const float2* data = nullptr;
+  float sigma_n = 1.f;
+  float gvar_inv = 0.f;
+  int n_leapfrog = 1;
+  uint64_t seed = 0;
+  uint32_t stream = 0;
+  ChainLayout L{};
+  long off = -1;
+  char* base = nullptr;
+  // host-side schedule (advanced when a tick is enqueued)
+  bool initialised = false;   // initial gradient evaluation enqueued
+  int pending = 0;            // trajectories submitted, not yet started
+  int step = 0;               // leapfrog steps done in the running trajectory (0 = none running)
+  int traj_started = 0;       // trajectories begun
+  bool running = false;
+  bool releasing = false;
+  bool failed = false;
+  int inflight = 0;           // ticks in flight that include this chain
+  std::deque<uint64_t> traj_submit_ns;
+  HmcState* st() const { return reinterpret_cast<HmcState*>(base + L.off_state); }
+  float* ptr(size_t o) const { return reinterpret_cast<float*>(base + o); }
+};
+
+struct TickEntry {
+  struct Chain* c;
+  bool init;        // gradient at the admitted position (no leapfrog step)
+  bool first;       // first step of a trajectory: draw the momentum
+  bool ends;        // last step of a trajectory: energies and Metropolis test
+  int traj;
+  uint64_t t_enqueue;
+};
+
+struct Tick {
+  std::vector<TickEntry> entries;
+  hipEvent_t done = nullptr;
+  int slot = 0;
+};
+
+// Pinned host staging + device table slots, one per in-flight tick.
+struct Slot {
+  HmcTask* host_tasks = nullptr;     // pinned: [4][max_batch] task tables
+  int* host_blk = nullptr;           // pinned: [3][max_batch + 1] block prefixes
+  HmcState* host_states = nullptr;   // pinned: [max_batch] read-back
+  HmcTask* dev_tasks = nullptr;      // in the arena
+  int* dev_blk = nullptr;
+  HmcState* dev_states = nullptr;    // finalize output, [max_batch]
+};
+
+constexpr int kSlots = 3;
+
+}  // namespace bv
+
+using namespace bv;
+
+struct hmc_server {
+  hmc_server_config cfg{};
+  hipStream_t stream = nullptr;
+  Arena arena;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::thread worker;
+  bool stop = false;
+  std::vector<Chain*> chains;         // by id (nullptr once released)
+  std::deque<hmc_result> results;
+  std::deque<Tick> inflight;
+  Slot slots[kSlots];
+  int next_slot = 0;
+  int rr = 0;                         // round-robin start
+  std::vector<uint64_t> req_latency_ns;
+  uint64_t n_requests = 0;
+  vis_status worker_status = VIS_OK;
+  std::string worker_error;
+
+  void run();
+  bool build_tick(Tick& t);
+  void enqueue(Tick& t);
+  void complete(Tick& t);
+};
+
+namespace {
+
+void hip_or_throw(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    throw Failure{VIS_EDEVICE};
+  }
+}
+
+}  // namespace
+
+bool hmc_server::build_tick(Tick& t) {
+  const int n = static_cast<int>(chains.size());
+  for (int k = 0; k < n && static_cast<int>(t.entries.size()) < cfg.max_batch; ++k) {
+    Chain* c = chains[(rr + k) % n];
+    if (c == nullptr || c->releasing || c->failed) continue;
+    TickEntry e{c, false, false, false, 0, now_ns()};
+    if (!c->initialised) {
+      c->initialised = true;
+      e.init = true;
+      e.traj = -1;
+    } else if (c->running) {
+      c->step += 1;
+      e.traj = c->traj_started - 1;
+    } else if (c->pending > 0) {
+      c->pending -= 1;
+      c->running = true;
+      c->step = 1;
+      c->traj_started += 1;
+      e.first = true;
+      e.traj = c->traj_started - 1;
+    } else {
+      continue;
+    }
+    if (!e.init && c->step == c->n_leapfrog) {
+      e.ends = true;
+      c->running = false;
+      c->step = 0;
+    }
+    c->inflight += 1;
+    t.entries.push_back(e);
+  }
+  if (n > 0) rr = (rr + 1) % n;
+  return !t.entries.empty();
+}
+
+void hmc_server::enqueue(Tick& t) {
+  Slot& S = slots[t.slot];
+  const int nb = cfg.max_batch;
+  HmcTask* pre = S.host_tasks;
+  HmcTask* post = S.host_tasks + nb;
+  HmcTask* fin = S.host_tasks + 2 * nb;
+  HmcTask* rst = S.host_tasks + 3 * nb;
+  int* pre_blk = S.host_blk;
+  int* post_blk = S.host_blk + (nb + 1);
+  int npre = 0, npost = 0, nrst = 0, bpre = 0, bpost = 0;
+  std::vector<const Chain*> evs;
+  for (const TickEntry& e : t.entries) {
+    Chain* c = e.c;
+    HmcTask T{};
+    T.q = c->ptr(c->L.off_q);
+    T.p = c->ptr(c->L.off_p);
+    T.grad = c->ptr(c->L.off_grad);
+    T.gchi = c->ptr(c->L.off_gchi);
+    T.minv = c->ptr(c->L.off_minv);
+    T.q0 = c->ptr(c->L.off_q0);
+    T.grad0 = c->ptr(c->L.off_grad0);
+    T.cvar = c->ptr(c->L.off_cvar);
+    T.part_u = reinterpret_cast<double*>(c->base + c->L.off_pu);
+    T.part_k = reinterpret_cast<double*>(c->base + c->L.off_pk);
+    T.part_k0 = reinterpret_cast<double*>(c->base + c->L.off_pk0);
+    T.st = c->st();
+    T.st_out = S.dev_states + npost;
+    T.seed = c->seed;
+    T.len = c->L.len;
+    T.nalm = c->L.nalm;
+    T.goff = c->L.goff;
+    T.ngain = c->L.ngain;
+    T.gvar_inv = c->gvar_inv;
+    T.nblk = c->L.nblk;
+    T.stream = c->stream;
+    T.traj = static_cast<uint32_t>(e.traj < 0 ? 0 : e.traj);
+    const bool is_init = e.init;
+    // pre-evaluation: momentum draw at a trajectory start, then kick + drift
+    if (!is_init) {
+      HmcTask P = T;
+      P.op = kOpKickDrift | (e.first ? kOpBegin : 0);
+      pre_blk[npre] = bpre;
+      pre[npre++] = P;
+      bpre += P.nblk;
+    }
+    HmcTask Q = T;
+    Q.op = is_init ? kOpInit : (kOpPost | (e.ends ? kOpEnd : 0));
+    post_blk[npost] = bpost;
+    post[npost] = Q;
+    fin[npost] = Q;
+    npost++;
+    bpost += Q.nblk;
+    if (e.ends) {
+      HmcTask R = T;
+      R.op = kOpRestore;
+      rst[nrst++] = R;
+    }
+    evs.push_back(c);
+  }
+  pre_blk[npre] = bpre;
+  post_blk[npost] = bpost;
+  // restore tasks reuse the post block prefix layout of their own list
+  std::vector<int> rst_blk(nrst + 1, 0);
+  for (int i = 0; i < nrst; ++i) rst_blk[i + 1] = rst_blk[i] + rst[i].nblk;
+  int* rst_blk_host = S.host_blk + 2 * (nb + 1);
+  std::memcpy(rst_blk_host, rst_blk.data(), sizeof(int) * (nrst + 1));
+
+  hip_or_throw(hipMemcpyAsync(S.dev_tasks, S.host_tasks, sizeof(HmcTask) * 4 * nb,
+                              hipMemcpyHostToDevice, stream), "task upload");
+  hip_or_throw(hipMemcpyAsync(S.dev_blk, S.host_blk, sizeof(int) * 3 * (nb + 1),
+                              hipMemcpyHostToDevice, stream), "prefix upload");
+  launch_hmc_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
+  for (const Chain* c : evs) {
+    const float* q = c->ptr(c->L.off_q);
+    float* g = c->ptr(c->L.off_gchi);
+    const vis_status s = chi2_and_grad(
+        c->field, reinterpret_cast<const vis_c64*>(c->data), c->sigma_n, q,
+        reinterpret_cast<const vis_c64*>(q + c->L.goff), q + c->L.len - 1, &c->st()->chi2, g,
+        reinterpret_cast<vis_c64*>(g + c->L.goff), g + c->L.len - 1, stream);
+    if (s != VIS_OK) throw Failure{s};
+  }
+  launch_hmc_elem(S.dev_tasks + nb, npost, S.dev_blk + (nb + 1), bpost, stream);
+  launch_hmc_finalize(S.dev_tasks + 2 * nb, npost, stream);
+  launch_hmc_elem(S.dev_tasks + 3 * nb, nrst, S.dev_blk + 2 * (nb + 1), rst_blk[nrst], stream);
+  // read back the state of every chain in the tick (gathered by the finalize kernel)
+  hip_or_throw(hipMemcpyAsync(S.host_states, S.dev_states, sizeof(HmcState) * npost,
+                              hipMemcpyDeviceToHost, stream), "state read-back");
+  hip_or_throw(hipEventRecord(t.done, stream), "event record");
+}
+
+void hmc_server::complete(Tick& t) {
+  hip_or_throw(hipEventSynchronize(t.done), "tick wait");
+  const uint64_t tnow = now_ns();
+  Slot& S = slots[t.slot];
+  std::lock_guard<std::mutex> lk(mu);
+  for (size_t i = 0; i < t.entries.size(); ++i) {
+    const TickEntry& e = t.entries[i];
+    Chain* c = e.c;
+    c->inflight -= 1;
+    req_latency_ns.push_back(tnow - e.t_enqueue);
+    n_requests += 1;
+    const HmcState& hs = S.host_states[i];
+    const bool bad = hs.status != 0;
+    if ((e.ends || bad) && !c->failed) {
+      hmc_result r{};
+      r.chain = c->id;
+      r.trajectory = e.traj;
+      r.accepted = bad ? 0 : hs.accepted;
+      r.status = bad ? VIS_ENUMERIC : VIS_OK;
+      r.h0 = hs.h0;
+      r.h1 = hs.h1;
+      r.chi2 = hs.chi2;
+      r.eps = hs.eps_used;
+      r.n_grad = e.init ? 1 : c->n_leapfrog;
+      if (!e.init && !c->traj_submit_ns.empty()) {
+        r.t_submit_ns = c->traj_submit_ns.front();
+        c->traj_submit_ns.pop_front();
+      }
+      r.t_done_ns = tnow;
+      results.push_back(r);
+      if (bad) {
+        // a non-finite energy stops this chain only; its queued work is dropped
+        c->failed = true;
+        c->pending = 0;
+        c->running = false;
+        c->traj_submit_ns.clear();
+      }
+    }
+    if (c->releasing && c->inflight == 0 && c->off >= 0) {
+      arena.release(static_cast<size_t>(c->off), c->L.bytes);
+      c->off = -1;
+      chains[c->id] = nullptr;
+      delete c;
+    }
+  }
+  cv_done.notify_all();
+}
+
+void hmc_server::run() {
+  try {
+    while (true) {
+      Tick t;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        while (true) {
+          if (stop && inflight.empty()) return;
+          if (!stop && static_cast<int>(inflight.size()) < kSlots - 1 && build_tick(t)) break;
+          if (!inflight.empty()) break;
+          cv_work.wait_for(lk, std::chrono::milliseconds(5));
+        }
+      }
+      if (!t.entries.empty()) {
+        t.slot = next_slot;
+        next_slot = (next_slot + 1) % kSlots;
+        hip_or_throw(hipEventCreateWithFlags(&t.done, hipEventDisableTiming), "event create");
+        enqueue(t);
+        inflight.push_back(std::move(t));
+      }
+      // keep at most kSlots - 1 ticks in flight; complete the oldest when full
+      // or when nothing new could be scheduled
+      if (!inflight.empty() &&
+          (static_cast<int>(inflight.size()) >= kSlots - 1 || t.entries.empty())) {
+        Tick& old = inflight.front();
+        complete(old);
+        (void)hipEventDestroy(old.done);
+        inflight.pop_front();
+      }
+    }
+  } catch (const Failure& f) {
+    std::lock_guard<std::mutex> lk(mu);
+    worker_status = f.code;
+    worker_error = vis_last_error();
+    stop = true;
+    cv_done.notify_all();
+  }
+}
+
+extern "C" {
+
+size_t hmc_chain_footprint_bytes(const vis_field* field) {
+  if (field == nullptr) return 0;
+  return chain_layout(field).bytes;
+}
+
+vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size_t arena_bytes,
+                             void* stream, hmc_server** out) {
+  hmc_server* s = nullptr;
+  vis_status st = guarded([&] {
+    BV_REQUIRE(cfg && out && arena_dev, VIS_EINVAL, "null argument");
+    BV_REQUIRE(cfg->max_chains >= 1 && cfg->max_chains <= 4096, VIS_EINVAL, "max_chains out of range");
+    BV_REQUIRE(cfg->max_batch >= 1 && cfg->max_batch <= 1024, VIS_EINVAL, "max_batch out of range");
+    s = new hmc_server();
+    s->cfg = *cfg;
+    s->stream = as_stream(stream);
+    const int nb = cfg->max_batch;
+    const size_t task_bytes = round_up(sizeof(HmcTask) * 4 * nb, 256);
+    const size_t blk_bytes = round_up(sizeof(int) * 3 * (nb + 1), 256);
+    const size_t st_bytes = round_up(sizeof(HmcState) * nb, 256);
+    const size_t per = task_bytes + blk_bytes + st_bytes;
+    const size_t reserve = kSlots * per;
+    BV_REQUIRE(arena_bytes > reserve, VIS_ENOMEM, "arena smaller than the %zu-byte tick tables",
+               reserve);
+    char* base = static_cast<char*>(arena_dev);
+    for (int i = 0; i < kSlots; ++i) {
+      Slot& S = s->slots[i];
+      S.dev_tasks = reinterpret_cast<HmcTask*>(base + i * per);
+      S.dev_blk = reinterpret_cast<int*>(base + i * per + task_bytes);
+      S.dev_states = reinterpret_cast<HmcState*>(base + i * per + task_bytes + blk_bytes);
+      BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_tasks), sizeof(HmcTask) * 4 * nb));
+      BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_blk), sizeof(int) * 3 * (nb + 1)));
+      BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_states), sizeof(HmcState) * nb));
+      std::memset(S.host_tasks, 0, sizeof(HmcTask) * 4 * nb);
+      std::memset(S.host_blk, 0, sizeof(int) * 3 * (nb + 1));
+    }
+    s->arena.init(base + reserve, arena_bytes - reserve);
+    s->chains.reserve(cfg->max_chains);
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+  });
+  if (st != VIS_OK && s != nullptr) {
+    for (auto& S : s->slots) {
+      if (S.host_tasks) (void)hipHostFree(S.host_tasks);
+      if (S.host_blk) (void)hipHostFree(S.host_blk);
+      if (S.host_states) (void)hipHostFree(S.host_states);
+    }
+    delete s;
+  }
+  return st;
+}
+
+vis_status hmc_chain_admit(hmc_server* s, const hmc_chain_init* in, int32_t* chain_id) {
+  return guarded([&] {
+    BV_REQUIRE(s && in && chain_id, VIS_EINVAL, "null argument");
+    BV_REQUIRE(in->field && in->data && in->q0 && in->minv && in->alm_prior_var, VIS_EINVAL,
+               "null pointer in chain init");
+    BV_REQUIRE(in->n_leapfrog >= 1 && in->n_leapfrog <= 100000, VIS_EINVAL, "n_leapfrog out of range");
+    BV_REQUIRE(in->eps > 0.f && in->sigma_n > 0.f && in->gain_prior_sigma > 0.f, VIS_EINVAL,
+               "eps, sigma_n and gain_prior_sigma must be positive");
+    const ChainLayout L = chain_layout(in->field);
+    Chain* c = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      BV_REQUIRE(s->worker_status == VIS_OK, s->worker_status, "server failed: %s",
+                 s->worker_error.c_str());
+      int live = 0;
+      for (Chain* x : s->chains) {
+        if (x == nullptr) continue;
+        ++live;
+        BV_REQUIRE(x->field != in->field, VIS_EINVAL,
+                   "field already used by chain %d (each chain needs its own field)", x->id);
+      }
+      if (live >= s->cfg.max_chains) {
+        set_error("request table full (%d chains)", s->cfg.max_chains);
+        throw Failure{VIS_EAGAIN};
+      }
+      const long off = s->arena.alloc(L.bytes);
+      if (off < 0) {
+        set_error("arena has no room for a %zu-byte chain now", L.bytes);
+        throw Failure{VIS_EAGAIN};
+      }
+      c = new Chain();
+      c->off = off;
+      c->base = s->arena.base + off;
+      c->L = L;
+      c->field = in->field;
+      c->data = reinterpret_cast<const float2*>(in->data);
+      c->sigma_n = in->sigma_n;
+      c->gvar_inv = 2.0f / (in->gain_prior_sigma * in->gain_prior_sigma);
+      c->n_leapfrog = in->n_leapfrog;
+      c->seed = in->seed;
+      c->stream = in->stream_id;
+      c->releasing = true;  // not schedulable until its buffers are initialised
+      c->id = static_cast<int>(s->chains.size());
+      s->chains.push_back(c);
+    }
+    // initialise the chain's buffers on a private stream, then publish it
+    hipStream_t cs = nullptr;
+    BV_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const size_t vf = sizeof(float) * L.len;
+    BV_HIP(hipMemsetAsync(c->base, 0, L.bytes, cs));
+    BV_HIP(hipMemcpyAsync(c->ptr(L.off_q), in->q0, vf, hipMemcpyDeviceToDevice, cs));
+    BV_HIP(hipMemcpyAsync(c->ptr(L.off_minv), in->minv, vf, hipMemcpyDeviceToDevice, cs));
+    BV_HIP(hipMemcpyAsync(c->ptr(L.off_cvar), in->alm_prior_var, sizeof(float) * L.nalm,
+                          hipMemcpyDeviceToDevice, cs));
+    HmcState hs{};
+    hs.eps = hs.eps0 = hs.eps_used = in->eps;
+    hs.adapt = in->adapt_step ? 1 : 0;
+    BV_HIP(hipMemcpyAsync(c->st(), &hs, sizeof(HmcState), hipMemcpyHostToDevice, cs));
+    BV_HIP(hipStreamSynchronize(cs));
+    (void)hipStreamDestroy(cs);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      c->releasing = false;
+      *chain_id = c->id;
+    }
+    s->cv_work.notify_all();
+  });
+}
+
+vis_status hmc_submit(hmc_server* s, int32_t id, int32_t n) {
+  return guarded([&] {
+    BV_REQUIRE(s != nullptr && n >= 0, VIS_EINVAL, "bad argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    BV_REQUIRE(id >= 0 && id < static_cast<int>(s->chains.size()) && s->chains[id] != nullptr &&
+                   !s->chains[id]->releasing,
+               VIS_ENOTFOUND, "unknown chain %d", id);
+    Chain* c = s->chains[id];
+    BV_REQUIRE(!c->failed, VIS_ENUMERIC, "chain %d stopped after a non-finite energy", id);
+    const uint64_t t = now_ns();
+    c->pending += n;
+    for (int i = 0; i < n; ++i) c->traj_submit_ns.push_back(t);
+    s->cv_work.notify_all();
+  });
+}
+
+vis_status hmc_poll(hmc_server* s, hmc_result* out, int32_t max, int32_t* n_out, int32_t timeout_ms) {
+  return guarded([&] {
+    BV_REQUIRE(s && n_out && (out || max == 0), VIS_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->results.empty() && timeout_ms > 0 && s->worker_status == VIS_OK)
+      s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                          [&] { return !s->results.empty() || s->worker_status != VIS_OK; });
+    BV_REQUIRE(s->worker_status == VIS_OK, s->worker_status, "server failed: %s",
+               s->worker_error.c_str());
+    int n = 0;
+    while (n < max && !s->results.empty()) {
+      out[n++] = s->results.front();
+      s->results.pop_front();
+    }
+    *n_out = n;
+  });
+}
+
+vis_status hmc_chain_position(hmc_server* s, int32_t id, float* q_out, void* stream) {
+  return guarded([&] {
+    BV_REQUIRE(s && q_out, VIS_EINVAL, "null argument");
+    Chain* c = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      BV_REQUIRE(id >= 0 && id < static_cast<int>(s->chains.size()) && s->chains[id] != nullptr,
+                 VIS_ENOTFOUND, "unknown chain %d", id);
+      c = s->chains[id];
+      BV_REQUIRE(c->inflight == 0 && !c->running && c->pending == 0, VIS_EAGAIN,
+                 "chain %d still has work in flight", id);
+    }
+    // the server stream orders this copy after the chain's last tick
+    BV_HIP(hipMemcpyAsync(q_out, c->ptr(c->L.off_q), sizeof(float) * c->L.len,
+                          hipMemcpyDeviceToDevice, s->stream));
+    BV_HIP(hipStreamSynchronize(s->stream));
+    (void)stream;
+  });
+}
+
+vis_status hmc_chain_release(hmc_server* s, int32_t id) {
+  return guarded([&] {
+    BV_REQUIRE(s != nullptr, VIS_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    BV_REQUIRE(id >= 0 && id < static_cast<int>(s->chains.size()) && s->chains[id] != nullptr,
+               VIS_ENOTFOUND, "unknown chain %d", id);
+    Chain* c = s->chains[id];
+    c->releasing = true;
+    c->pending = 0;
+    c->running = false;
+    if (c->inflight == 0) {
+      s->arena.release(static_cast<size_t>(c->off), c->L.bytes);
+      c->off = -1;
+      s->chains[id] = nullptr;
+      delete c;
+    }
+  });
+}
+
+vis_status hmc_server_stats(hmc_server* s, hmc_stats* out, int32_t reset) {
+  return guarded([&] {
+    BV_REQUIRE(s && out, VIS_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<uint64_t> v = s->req_latency_ns;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double q) {
+      if (v.empty()) return 0.0;
+      const size_t i = std::min(v.size() - 1, static_cast<size_t>(q * (v.size() - 1) + 0.5));
+      return static_cast<double>(v[i]) * 1e-6;
+    };
+    out->requests = static_cast<int64_t>(s->n_requests);
+    out->p50_ms = pct(0.50);
+    out->p99_ms = pct(0.99);
+    out->max_ms = v.empty() ? 0.0 : static_cast<double>(v.back()) * 1e-6;
+    size_t used = 0;
+    for (auto& fr : s->arena.free_list) used += fr.second;
+    out->arena_free_bytes = static_cast<int64_t>(used);
+    int live = 0;
+    for (Chain* c : s->chains) live += c != nullptr;
+    out->live_chains = live;
+    if (reset) {
+      s->req_latency_ns.clear();
+      s->n_requests = 0;
+    }
+  });
+}
+
+vis_status hmc_server_destroy(hmc_server* s) {
+  if (s == nullptr) return VIS_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (Chain* c : s->chains) delete c;
+  for (auto& S : s->slots) {
+    if (S.host_tasks) (void)hipHostFree(S.host_tasks);
+    if (S.host_blk) (void)hipHostFree(S.host_blk);
+    if (S.host_states) (void)hipHostFree(S.host_states);
+  }
+  delete s;
+  return VIS_OK;
+}
+
+}  // extern "C"

@@ -166,7 +166,14 @@ k_reduce_splits(int nsplit, int nf, int nm, int kpad, const float* __restrict__ 
   grad[idx] = s;
 }
 
+void launch_synth_fwd_bf16x3(const vis_field* f, const float* alm, float* img, hipStream_t st);
+void launch_synth_adj_bf16x3(const vis_field* f, const float* dimg, int kps, hipStream_t st);
+
 void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStream_t st) {
+  if (f->precision == VIS_BF16X3) {
+    launch_synth_fwd_bf16x3(f, alm, img, st);
+    return;
+  }
   const vis_basis* b = f->basis;
   BV_REQUIRE(b->y32 != nullptr, VIS_EINVAL, "basis has no FP32 storage");
   dim3 grid(f->nv_pad / 64, ceil_div(f->n_freq, 64));
@@ -178,12 +185,15 @@ void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStrea
 
 void launch_synth_adj(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st) {
   const vis_basis* b = f->basis;
-  BV_REQUIRE(b->y32 != nullptr, VIS_EINVAL, "basis has no FP32 storage");
   const int nsplit = f->asplit;
+  if (f->precision == VIS_BF16X3) {
+    const int kps = static_cast<int>(round_up(ceil_div(f->nv_pad, nsplit), 32));
+    launch_synth_adj_bf16x3(f, dimg, kps, st);
+  } else {
+  BV_REQUIRE(b->y32 != nullptr, VIS_EINVAL, "basis has no FP32 storage");
   const int kps = static_cast<int>(round_up(ceil_div(f->nv_pad, nsplit), 16));
   const int ncol = static_cast<int>(round_up(f->n_modes, 64));
   dim3 grid(ncol / 64, ceil_div(f->n_freq, 64), nsplit);
-  {
   ProfScope ps(&f->prof, "k_synth_adj_f32", st);
   k_synth_adj_f32<<<grid, 256, 0, st>>>(f->n_freq, f->nv_pad, b->kpad, kps, dimg, b->y32,
                                          f->tab.vpix, f->scr.a_part);

@@ -1,0 +1,197 @@
+"""Python binding of the HMC server (ctypes): argument marshalling only.
+
+The server keeps every chain's state in a caller-provided device arena and
+runs leapfrog steps as batched kernel launches on a worker thread inside the
+library.  Helpers here pack parameter vectors in the server's layout and
+estimate a diagonal mass matrix from the library's adjoint.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import vis as V
+
+_lib = V.lib()
+_vp = C.c_void_p
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("max_chains", C.c_int32), ("max_batch", C.c_int32), ("batched", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class ChainInit(C.Structure):
+    _fields_ = [("field", _vp), ("data", _vp), ("sigma_n", C.c_float), ("q0", _vp),
+                ("minv", _vp), ("alm_prior_var", _vp), ("gain_prior_sigma", C.c_float),
+                ("eps", C.c_float), ("n_leapfrog", C.c_int32), ("adapt_step", C.c_int32),
+                ("seed", C.c_uint64), ("stream_id", C.c_uint32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("chain", C.c_int32), ("trajectory", C.c_int32), ("accepted", C.c_int32),
+                ("status", C.c_int32), ("h0", C.c_double), ("h1", C.c_double),
+                ("chi2", C.c_double), ("eps", C.c_float), ("n_grad", C.c_int32),
+                ("t_submit_ns", C.c_uint64), ("t_done_ns", C.c_uint64)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("requests", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
+                ("max_ms", C.c_double), ("arena_free_bytes", C.c_int64), ("live_chains", C.c_int32)]
+
+
+_lib.hmc_chain_footprint_bytes.argtypes = [_vp]
+_lib.hmc_chain_footprint_bytes.restype = C.c_size_t
+_lib.hmc_server_create.argtypes = [C.POINTER(ServerConfig), _vp, C.c_size_t, _vp, C.POINTER(_vp)]
+_lib.hmc_chain_admit.argtypes = [_vp, C.POINTER(ChainInit), C.POINTER(C.c_int32)]
+_lib.hmc_submit.argtypes = [_vp, C.c_int32, C.c_int32]
+_lib.hmc_poll.argtypes = [_vp, C.POINTER(Result), C.c_int32, C.POINTER(C.c_int32), C.c_int32]
+_lib.hmc_chain_position.argtypes = [_vp, C.c_int32, _vp, _vp]
+_lib.hmc_chain_release.argtypes = [_vp, C.c_int32]
+_lib.hmc_server_stats.argtypes = [_vp, C.POINTER(Stats), C.c_int32]
+_lib.hmc_server_destroy.argtypes = [_vp]
+for _n in ("hmc_server_create", "hmc_chain_admit", "hmc_submit", "hmc_poll", "hmc_chain_position",
+           "hmc_chain_release", "hmc_server_stats", "hmc_server_destroy"):
+    getattr(_lib, _n).restype = C.c_int
+
+VIS_EAGAIN, VIS_ENUMERIC = -4, -6
+
+
+class Layout:
+    """Offsets of the parameter vector: [a | pad | gains (Re, Im) | F]."""
+
+    def __init__(self, field: V.Field):
+        self.nalm = field.n_freq * field.n_modes
+        self.goff = (self.nalm + 63) // 64 * 64
+        self.ngain = 2 * field.n_freq * field.n_ant
+        self.length = self.goff + self.ngain + 1
+        self.shape = (field.n_freq, field.n_modes, field.n_ant)
+
+    def pack(self, alm: torch.Tensor, gains: torch.Tensor, fwhm: torch.Tensor) -> torch.Tensor:
+        q = torch.zeros(self.length, dtype=torch.float32, device=alm.device)
+        q[:self.nalm] = alm.reshape(-1)
+        q[self.goff:self.goff + self.ngain] = torch.view_as_real(gains).reshape(-1)
+        q[-1] = fwhm.reshape(-1)[0]
+        return q
+
+    def unpack(self, q: torch.Tensor):
+        nf, nm, na = self.shape
+        alm = q[:self.nalm].reshape(nf, nm)
+        g = torch.view_as_complex(q[self.goff:self.goff + self.ngain].reshape(nf, na, 2).contiguous())
+        return alm, g, q[-1:]
+
+
+def diag_hessian(field: V.Field, alm, gains, fwhm, sigma_n: float, n_probes: int = 8,
+                 seed: int = 0) -> torch.Tensor:
+    """Hutchinson estimate of diag(J^T J) / sigma_n^2 (the Gauss-Newton diagonal of chi^2 / 2).
+
+    For z with unit-variance real and imaginary parts, vis_adjoint(dvis = z)
+    returns J^T z, and E[(J^T z)^2] = diag(J^T J).  Returned in the server's
+    parameter layout (padding entries set to 1).
+    """
+    lay = Layout(field)
+    g = torch.Generator(device=alm.device)
+    g.manual_seed(seed)
+    acc = torch.zeros(lay.length, dtype=torch.float64, device=alm.device)
+    shape = (field.n_time, field.n_freq, field.n_bl)
+    for _ in range(n_probes):
+        z = torch.complex(torch.randn(shape, generator=g, device=alm.device),
+                          torch.randn(shape, generator=g, device=alm.device))
+        ga, gg, gf = V.adjoint(field, alm, gains, fwhm, z)
+        v = lay.pack(ga, gg, gf).double()
+        acc += v * v
+    h = acc / n_probes / (sigma_n ** 2)
+    h[lay.nalm:lay.goff] = 1.0
+    return h
+
+
+class Server:
+    def __init__(self, arena_bytes: int, max_chains: int = 64, max_batch: int = 64,
+                 batched: int = 1, device: str = "cuda"):
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.Stream(device=self.arena.device)
+        cfg = ServerConfig(max_chains, max_batch, batched, 0)
+        h = C.c_void_p()
+        V._check(_lib.hmc_server_create(C.byref(cfg), C.c_void_p(self.arena.data_ptr()),
+                                        self.arena.numel(), C.c_void_p(self.stream.cuda_stream),
+                                        C.byref(h)), "hmc_server_create")
+        self.handle = h
+        self._keep = {}
+
+    @staticmethod
+    def footprint(field: V.Field) -> int:
+        return int(_lib.hmc_chain_footprint_bytes(field.handle))
+
+    def admit(self, field: V.Field, data: torch.Tensor, sigma_n: float, q0: torch.Tensor,
+              minv: torch.Tensor, alm_prior_var: torch.Tensor, gain_prior_sigma: float,
+              eps: float, n_leapfrog: int, seed: int, stream_id: int,
+              adapt_step: bool = False) -> Optional[int]:
+        """Chain id, or None if the arena has no room now (VIS_EAGAIN)."""
+        lay = Layout(field)
+        V._need(data, "data", torch.complex64, (field.n_time, field.n_freq, field.n_bl), field.device)
+        V._need(q0, "q0", torch.float32, (lay.length,), field.device)
+        V._need(minv, "minv", torch.float32, (lay.length,), field.device)
+        V._need(alm_prior_var, "alm_prior_var", torch.float32, (field.n_freq, field.n_modes),
+                field.device)
+        torch.cuda.current_stream().synchronize()
+        init = ChainInit(field.handle, data.data_ptr(), sigma_n, q0.data_ptr(), minv.data_ptr(),
+                         alm_prior_var.data_ptr(), gain_prior_sigma, eps, n_leapfrog,
+                         1 if adapt_step else 0, seed, stream_id)
+        cid = C.c_int32()
+        st = _lib.hmc_chain_admit(self.handle, C.byref(init), C.byref(cid))
+        if st == VIS_EAGAIN:
+            return None
+        V._check(st, "hmc_chain_admit")
+        self._keep[cid.value] = (field, data)
+        return cid.value
+
+    def submit(self, chain: int, n_traj: int):
+        V._check(_lib.hmc_submit(self.handle, chain, n_traj), "hmc_submit")
+
+    def poll(self, max_results: int = 256, timeout_ms: int = 0) -> List[dict]:
+        buf = (Result * max_results)()
+        n = C.c_int32()
+        V._check(_lib.hmc_poll(self.handle, buf, max_results, C.byref(n), timeout_ms), "hmc_poll")
+        return [{f: getattr(buf[i], f) for f, _ in Result._fields_} for i in range(n.value)]
+
+    def position(self, chain: int, length: int, device) -> torch.Tensor:
+        q = torch.empty(length, dtype=torch.float32, device=device)
+        V._check(_lib.hmc_chain_position(self.handle, chain, C.c_void_p(q.data_ptr()), None),
+                 "hmc_chain_position")
+        return q
+
+    def release(self, chain: int):
+        V._check(_lib.hmc_chain_release(self.handle, chain), "hmc_chain_release")
+        self._keep.pop(chain, None)
+
+    def stats(self, reset: bool = False) -> dict:
+        s = Stats()
+        V._check(_lib.hmc_server_stats(self.handle, C.byref(s), 1 if reset else 0), "hmc_server_stats")
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h:
+            V._check(_lib.hmc_server_destroy(h), "hmc_server_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def wait(self, n_results: int, timeout_s: float = 120.0) -> List[dict]:
+        """Collect n_results trajectory results (raises on timeout)."""
+        import time
+        out: List[dict] = []
+        t_end = time.monotonic() + timeout_s
+        while len(out) < n_results:
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"only {len(out)} of {n_results} results")
+            out += self.poll(256, timeout_ms=100)
+        return out
