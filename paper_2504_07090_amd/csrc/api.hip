@@ -20,7 +20,7 @@ void adjoint_tail(const vis_field* f, const float* fwhm, float* grad_alm, float2
                   float* grad_fwhm, bool with_chi2, double* chi2, hipStream_t s) {
   launch_reduce_grads(f, with_chi2, f->scr.chi_part, chi2, f->scr.g_part, grad_gains,
                       f->scr.f_part, nullptr, s);
-  launch_fringe_adj(f, f->scr.img, fwhm, f->scr.w, f->scr.dimg, f->scr.f_part, s);
+  launch_fringe_adj(f, f->scr.img, fwhm, f->scr.gco, f->scr.dimg, f->scr.f_part, s);
   if (grad_fwhm != nullptr)
     launch_reduce_grads(f, false, nullptr, nullptr, nullptr, nullptr, f->scr.f_part, grad_fwhm, s);
   if (grad_alm != nullptr) launch_synth_adj(f, f->scr.dimg, grad_alm, s);
@@ -52,7 +52,7 @@ vis_status vis_adjoint(const vis_field* f, const float* alm, const vis_c64* gain
     hipStream_t s = as_stream(stream);
     forward_core(f, alm, fwhm, s);
     launch_gains(f, kGainAdj, f->scr.vu, reinterpret_cast<const float2*>(gains),
-                 reinterpret_cast<const float2*>(dvis), 0.f, nullptr, nullptr, f->scr.w,
+                 reinterpret_cast<const float2*>(dvis), 0.f, nullptr, nullptr, f->scr.gco,
                  f->scr.g_part, s);
     adjoint_tail(f, fwhm, grad_alm, reinterpret_cast<float2*>(grad_gains), grad_fwhm, false,
                  nullptr, s);
@@ -70,7 +70,7 @@ vis_status chi2_and_grad(const vis_field* f, const vis_c64* data, float sigma_n,
     forward_core(f, alm, fwhm, s);
     launch_gains(f, kGainChi2, f->scr.vu, reinterpret_cast<const float2*>(gains),
                  reinterpret_cast<const float2*>(data), sigma_n, nullptr, f->scr.chi_part,
-                 f->scr.w, f->scr.g_part, s);
+                 f->scr.gco, f->scr.g_part, s);
     const bool any_grad = grad_alm || grad_gains || grad_fwhm;
     if (!any_grad) {
       launch_reduce_grads(f, true, f->scr.chi_part, chi2, nullptr, nullptr, nullptr, nullptr, s);

@@ -336,11 +336,12 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
   S.img = cv.take<float>(nfq * nvp);
   S.dimg = cv.take<float>(nfq * nvp);
   S.vu = cv.take<float2>(nt * nfq * f->n_ubl);
-  S.w = cv.take<float2>(nt * nfq * f->n_ubl);
+  S.gco = cv.take<float>(nt * nfq * static_cast<size_t>(f->gstride));
   S.chi_part = cv.take<double>(nt * nfq);
   S.g_part = cv.take<float2>(nt * nfq * f->n_ant);
   S.f_part = cv.take<float>(nfq * f->n_chunks);
-  S.a_part = cv.take<float>(static_cast<size_t>(f->asplit) * nfq * kpad);
+  S.a_part = cv.take<float>(std::max(static_cast<size_t>(f->asplit) * nfq * kpad,
+                                     static_cast<size_t>(f->fsplit) * nfq * nvp));
 }
 
 static int choose_asplit(int n_freq, int kpad, int nv_pad) {
@@ -365,11 +366,19 @@ static void fill_shape(vis_field* f, const vis_basis* basis, const vis_field_des
   f->n_chunks = g.nv_pad / kChunk;
   f->n_tchunk = static_cast<int>(g.tchunk.size());
   f->extent = g.extent;
+  f->dtile = fringe_tile_extent(g.extent);
+  f->gstride = adj_coef_stride(f->dtile);
   f->precision = d->precision;
   f->d_omega = 4.0 * kPi / basis->n_pix;
   f->beam_ref_hz = d->beam_ref_hz;
   f->fwd_macs = g.vis_pix_time * f->n_ubl * d->n_freq;
   f->asplit = choose_asplit(d->n_freq, basis->kpad, g.nv_pad);
+  {
+    // forward synthesis: enough (pixel tile x mode split) blocks for ~4 per CU
+    const int tiles = ceil_div(d->n_freq, 64) * (g.nv_pad / 64);
+    const int nm = (d->lmax + 1) * (d->lmax + 1);
+    f->fsplit = std::max(1, std::min(ceil_div(1024, tiles), std::max(1, nm / 512)));
+  }
 }
 
 template <class T>

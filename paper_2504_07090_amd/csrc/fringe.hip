@@ -25,7 +25,7 @@
 // stays at the FP32 rounding level of a number below one cycle times D.
 //
 // The adjoint (transpose over the reals) of the same map, for coefficients
-// omega_u = dL/dRe V_u - i dL/dIm V_u... (see the gains pass) is
+// omega_u = dL/dRe V_u - i dL/dIm V_u (formed by the gains pass), is
 //     Z_p = sum_u Re[omega_u alpha^n1 beta^n2]
 //         = sum_{r,c} A[r][p] G[r][c] Bb[p][c] + axis terms,
 // with G built from omega(n, +m), omega(n, -m); it runs as the GEMM
@@ -47,9 +47,17 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// sin and cos of 2 pi x for |x| <= 1/2
+// sin and cos of 2 pi x for |x| <= 1/2.  The argument is already reduced to
+// one turn in FP64, so the hardware transcendental units (which take their
+// argument in turns) are used directly; BV_ACCURATE_TRIG selects the
+// correctly-rounded library routine instead.
 __device__ __forceinline__ void sincos_rev(float x, float& s, float& c) {
+#ifdef BV_ACCURATE_TRIG
   sincospif(2.0f * x, &s, &c);
+#else
+  s = __builtin_amdgcn_sinf(x);
+  c = __builtin_amdgcn_cosf(x);
+#endif
 }
 
 // Reduced phase of nu * p in cycles, in [-1/2, 1/2], formed in FP64.
@@ -70,14 +78,45 @@ template <int D>
 struct Tile {
   static constexpr int RT = (2 * D + 15) / 16;  // 16-wide MFMA tiles per side
   static constexpr int W = 16 * RT;             // padded side
-  static constexpr int PITCH = W + 17;          // odd-ish LDS pitch (floats)
+  static constexpr int PITCH = W + 1;           // LDS row pitch (floats): conflict-free rows
 };
+
+// Geometry of one (time, visible pixel) entry.
+struct Geo {
+  double p1, p2;
+  float th2;
+};
+
+// Powers alpha^n (n = 1..D) and beta^m w (m = 1..D) of one pixel into its LDS
+// rows, zero padding up to W; visit(n, alpha^n, beta^n w) sees every power
+// while it is still in registers.
+template <int D, int W, class Visit>
+__device__ __forceinline__ void write_powers(float* arow, float* brow, float c1, float s1, float c2,
+                                             float s2, float w, Visit visit) {
+  float ar = c1, ai = -s1;
+  float br = c2 * w, bi = -s2 * w;
+#pragma unroll
+  for (int n = 0; n < D; ++n) {
+    arow[2 * n] = ar;
+    arow[2 * n + 1] = ai;
+    brow[2 * n] = br;
+    brow[2 * n + 1] = bi;
+    visit(n, ar, ai, br, bi);
+    const float nar = ar * c1 + ai * s1;  // (ar + i ai)(c1 - i s1)
+    const float nai = ai * c1 - ar * s1;
+    const float nbr = br * c2 + bi * s2;
+    const float nbi = bi * c2 - br * s2;
+    ar = nar; ai = nai; br = nbr; bi = nbi;
+  }
+#pragma unroll
+  for (int r = 2 * D; r < W; ++r) { arow[r] = 0.f; brow[r] = 0.f; }
+}
 
 // ------------------------------------------------------------------ forward --
 // One wavefront per (t, nu); loops over the pixel chunks visible at t.
 template <int D>
 __global__ void __launch_bounds__(64)
-k_fringe_fwd(int nf, int nt, int nvp, int nubl, int dr, float d_omega, double beam_ref,
+k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
              const double* __restrict__ freq, const double* __restrict__ P1,
              const double* __restrict__ P2, const float* __restrict__ TH2,
              const int* __restrict__ tchunk_off, const int* __restrict__ tchunk,
@@ -100,44 +139,45 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, int dr, float d_omega, double be
   for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < RT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  float axr[D], axi[D], bxr[D], bxi[D];  // per-lane partial sums of alpha^n S and beta^m S
+  // per-lane partial sums of alpha^n S and beta^m S (the axis baselines)
+  float axr[D], axi[D], bxr[D], bxi[D];
 #pragma unroll
   for (int n = 0; n < D; ++n) axr[n] = axi[n] = bxr[n] = bxi[n] = 0.f;
 
   const int cbeg = tchunk_off[t], cend = tchunk_off[t + 1];
   float* arow = As + lane * PITCH;
   float* brow = Bs + lane * PITCH;
+  const double* p1t = P1 + static_cast<size_t>(t) * nvp;
+  const double* p2t = P2 + static_cast<size_t>(t) * nvp;
+  const float* tht = TH2 + static_cast<size_t>(t) * nvp;
+  const float* imf = img + static_cast<size_t>(f) * nvp;
+  // software pipeline: the next chunk's inputs are in flight while this one computes
+  double np1 = 0.0, np2 = 0.0;
+  float nth = 0.f, nim = 0.f;
+  if (cbeg < cend) {
+    const int k = tchunk[cbeg] * kChunk + lane;
+    np1 = p1t[k]; np2 = p2t[k]; nth = tht[k]; nim = imf[k];
+  }
   for (int ci = cbeg; ci < cend; ++ci) {
-    const int k = tchunk[ci] * kChunk + lane;
-    const size_t g = static_cast<size_t>(t) * nvp + k;
-    const float x1 = reduced_cycles(nu, P1[g]);
-    const float x2 = reduced_cycles(nu, P2[g]);
-    const float th2 = TH2[g];
-    const float s = d_omega * exp2f(-th2 * kb) * img[static_cast<size_t>(f) * nvp + k];
+    const double p1 = np1, p2 = np2;
+    const float th2 = nth, iv = nim;
+    if (ci + 1 < cend) {
+      const int k = tchunk[ci + 1] * kChunk + lane;
+      np1 = p1t[k]; np2 = p2t[k]; nth = tht[k]; nim = imf[k];
+    }
+    const float x1 = reduced_cycles(nu, p1);
+    const float x2 = reduced_cycles(nu, p2);
+    const float s = d_omega * exp2f(-th2 * kb) * iv;
     float s1, c1, s2, c2;
     sincos_rev(x1, s1, c1);
     sincos_rev(x2, s2, c2);
-    // alpha^n and beta^m S, n, m = 1..D
-    float ar = c1, ai = -s1;
-    float br = c2 * s, bi = -s2 * s;
-#pragma unroll
-    for (int n = 0; n < D; ++n) {
-      arow[2 * n] = ar;
-      arow[2 * n + 1] = ai;
-      brow[2 * n] = br;
-      brow[2 * n + 1] = bi;
-      axr[n] += ar * s;
-      axi[n] += ai * s;
-      bxr[n] += br;
-      bxi[n] += bi;
-      const float nar = ar * c1 + ai * s1;      // (ar + i ai)(c1 - i s1)
-      const float nai = ai * c1 - ar * s1;
-      const float nbr = br * c2 + bi * s2;
-      const float nbi = bi * c2 - br * s2;
-      ar = nar; ai = nai; br = nbr; bi = nbi;
-    }
-#pragma unroll
-    for (int r = 2 * D; r < W; ++r) { arow[r] = 0.f; brow[r] = 0.f; }
+    write_powers<D, W>(arow, brow, c1, s1, c2, s2, s,
+                       [&](int n, float ar, float ai, float br, float bi) {
+                         axr[n] += ar * s;
+                         axi[n] += ai * s;
+                         bxr[n] += br;
+                         bxi[n] += bi;
+                       });
     wave_sync();
 #pragma unroll 4
     for (int q = 0; q < 16; ++q) {
@@ -154,7 +194,6 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, int dr, float d_omega, double be
     }
     wave_sync();
   }
-  // reduce the axis sums over the wavefront
 #pragma unroll
   for (int n = 0; n < D; ++n) {
 #pragma unroll
@@ -165,7 +204,7 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, int dr, float d_omega, double be
       bxi[n] += __shfl_xor(bxi[n], o);
     }
   }
-  // P tile to LDS (reuse As as a W x W matrix), axis sums after it
+  // P tile to LDS (reuse As as a W x W matrix), axis sums in Bs
   float* P = As;
 #pragma unroll
   for (int i = 0; i < RT; ++i)
@@ -201,22 +240,23 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, int dr, float d_omega, double be
     }
     out[u] = v;
   }
-  (void)dr;
 }
 
 // ------------------------------------------------------------------ adjoint --
 // One wavefront per (nu, chunk of 64 visible pixels); loops over the times at
-// which the chunk is above the horizon.  w[t][nu][u] holds omega_u.
+// which the chunk is above the horizon.  gco[t][nu] holds the coefficient
+// matrix in MFMA A-operand order followed by the axis coefficients.
 template <int D>
 __global__ void __launch_bounds__(64)
-k_fringe_adj(int nf, int nt, int nvp, int nchunks, int nubl, int dr, float d_omega,
-             double beam_ref, const double* __restrict__ freq, const double* __restrict__ P1,
+k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, double beam_ref,
+             const double* __restrict__ freq, const double* __restrict__ P1,
              const double* __restrict__ P2, const float* __restrict__ TH2,
-             const int2* __restrict__ chunk_t, const int* __restrict__ ulut,
-             const float* __restrict__ img, const float* __restrict__ fwhm,
-             const float2* __restrict__ w, float* __restrict__ dimg, float* __restrict__ f_part) {
+             const int2* __restrict__ chunk_t, const float* __restrict__ img,
+             const float* __restrict__ fwhm, const float* __restrict__ gco,
+             float* __restrict__ dimg, float* __restrict__ f_part) {
   using T = Tile<D>;
   constexpr int RT = T::RT, W = T::W, PITCH = T::PITCH;
+  constexpr int NMAT = RT * RT * 256;
   __shared__ float As[64 * PITCH];
   __shared__ float Bs[64 * PITCH];
   const int lane = threadIdx.x;
@@ -231,67 +271,41 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int nubl, int dr, float d_ome
   const int k = chunk * kChunk + lane;
   const float ival = img[static_cast<size_t>(f) * nvp + k];
   const int2 tr = chunk_t[chunk];
-  const int lw = 2 * dr + 1;
   float acc_i = 0.f, acc_f = 0.f;
   float* arow = As + lane * PITCH;
   float* brow = Bs + lane * PITCH;
-
+  const size_t gst = static_cast<size_t>(nf) * gstride;
+  // software pipeline over t
+  double np1 = P1[static_cast<size_t>(tr.x) * nvp + k];
+  double np2 = P2[static_cast<size_t>(tr.x) * nvp + k];
+  float nth = TH2[static_cast<size_t>(tr.x) * nvp + k];
   for (int t = tr.x; t <= tr.y; ++t) {
-    const float2* wt = w + (static_cast<size_t>(t) * nf + f) * nubl;
-    const size_t g = static_cast<size_t>(t) * nvp + k;
-    const float x1 = reduced_cycles(nu, P1[g]);
-    const float x2 = reduced_cycles(nu, P2[g]);
-    const float th2 = TH2[g];
-    const float bm = exp2f(-th2 * kb);
-    float s1, c1, s2, c2;
-    sincos_rev(x1, s1, c1);
-    sincos_rev(x2, s2, c2);
-    float ar = c1, ai = -s1, br = c2, bi = -s2;
-    float zax = 0.f;
-#pragma unroll
-    for (int n = 0; n < D; ++n) {
-      arow[2 * n] = ar;
-      arow[2 * n + 1] = ai;
-      brow[2 * n] = br;
-      brow[2 * n + 1] = bi;
-      if (n < dr) {
-        const int ua = ulut[(n + 1) * lw + dr];        // (n+1, 0)
-        const int ub = ulut[0 * lw + (n + 1) + dr];    // (0, n+1)
-        if (ua >= 0) { const float2 o = wt[ua]; zax += o.x * ar - o.y * ai; }
-        if (ub >= 0) { const float2 o = wt[ub]; zax += o.x * br - o.y * bi; }
-      }
-      const float nar = ar * c1 + ai * s1;
-      const float nai = ai * c1 - ar * s1;
-      const float nbr = br * c2 + bi * s2;
-      const float nbi = bi * c2 - br * s2;
-      ar = nar; ai = nai; br = nbr; bi = nbi;
+    const double p1 = np1, p2 = np2;
+    const float th2 = nth;
+    if (t < tr.y) {
+      const size_t g = static_cast<size_t>(t + 1) * nvp + k;
+      np1 = P1[g]; np2 = P2[g]; nth = TH2[g];
     }
-#pragma unroll
-    for (int r = 2 * D; r < W; ++r) { arow[r] = 0.f; brow[r] = 0.f; }
-    // coefficient matrix in the MFMA A layout: G[r][c], r = 16 i + (lane & 15),
-    // c = 16 kt + 4 s + (lane >> 4)
-    float gco[RT][RT][4];
+    const float* G = gco + t * gst + static_cast<size_t>(f) * gstride;
+    f4 gv[RT][RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int kt = 0; kt < RT; ++kt)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int r = 16 * i + (lane & 15), c = 16 * kt + 4 * s + (lane >> 4);
-          const int n = (r >> 1) + 1, m = (c >> 1) + 1;
-          float v = 0.f;
-          if (n <= dr && m <= dr) {
-            const int up = ulut[n * lw + m + dr], um = ulut[n * lw - m + dr];
-            const float2 op = up >= 0 ? wt[up] : make_float2(0.f, 0.f);
-            const float2 om = um >= 0 ? wt[um] : make_float2(0.f, 0.f);
-            const int pr = r & 1, pc = c & 1;
-            if (pr == 0 && pc == 0) v = op.x + om.x;
-            else if (pr == 1 && pc == 1) v = om.x - op.x;
-            else if (pr == 0 && pc == 1) v = om.y - op.y;
-            else v = -op.y - om.y;
-          }
-          gco[i][kt][s] = v;
-        }
+        gv[i][kt] = *reinterpret_cast<const f4*>(G + ((i * RT + kt) * 64 + lane) * 4);
+    const float bm = exp2f(-th2 * kb);
+    const float x1 = reduced_cycles(nu, p1);
+    const float x2 = reduced_cycles(nu, p2);
+    float s1, c1, s2, c2;
+    sincos_rev(x1, s1, c1);
+    sincos_rev(x2, s2, c2);
+    // axis terms: sum_n Re[omega(n,0) alpha^n] + Re[omega(0,n) beta^n]
+    float zax = 0.f;
+    write_powers<D, W>(arow, brow, c1, s1, c2, s2, 1.0f,
+                       [&](int n, float ar, float ai, float br, float bi) {
+                         const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 4 * n);
+                         zax += ax[0] * ar - ax[1] * ai + ax[2] * br - ax[3] * bi;
+                       });
     wave_sync();
     float zcore = 0.f;
 #pragma unroll
@@ -305,7 +319,7 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int nubl, int dr, float d_ome
         for (int kt = 0; kt < RT; ++kt)
 #pragma unroll
           for (int s = 0; s < 4; ++s)
-            tacc = mfma4(gco[i][kt][s], Bs[px * PITCH + 16 * kt + 4 * s + (lane >> 4)], tacc);
+            tacc = mfma4(gv[i][kt][s], Bs[px * PITCH + 16 * kt + 4 * s + (lane >> 4)], tacc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) zp += As[px * PITCH + 16 * i + 4 * (lane >> 4) + r] * tacc[r];
       }
@@ -331,22 +345,22 @@ static void fwd_d(const vis_field* f, const float* img, const float* fwhm, float
   const int nblk = static_cast<int>(round_up(static_cast<long>(f->n_freq) * f->n_time, 8));
   const auto& T = f->tab;
   ProfScope ps(&f->prof, "k_fringe_fwd", st);
-  k_fringe_fwd<D><<<nblk, 64, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_ubl, f->extent,
+  k_fringe_fwd<D><<<nblk, 64, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_ubl,
                                        static_cast<float>(f->d_omega), f->beam_ref_hz, T.freq, T.p1,
                                        T.p2, T.th2, T.tchunk_off, T.tchunk, T.ubl_nm, img, fwhm, vu);
   check_launch("k_fringe_fwd");
 }
 
 template <int D>
-static void adj_d(const vis_field* f, const float* img, const float* fwhm, const float2* w,
+static void adj_d(const vis_field* f, const float* img, const float* fwhm, const float* gco,
                   float* dimg, float* f_part, hipStream_t st) {
   const int nblk = static_cast<int>(round_up(static_cast<long>(f->n_freq) * f->n_chunks, 8));
   const auto& T = f->tab;
   ProfScope ps(&f->prof, "k_fringe_adj", st);
-  k_fringe_adj<D><<<nblk, 64, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_chunks, f->n_ubl,
-                                       f->extent, static_cast<float>(f->d_omega), f->beam_ref_hz,
-                                       T.freq, T.p1, T.p2, T.th2, T.chunk_t, T.ulut, img, fwhm, w,
-                                       dimg, f_part);
+  BV_REQUIRE(f->dtile == D, VIS_EINVAL, "internal: adjoint tile mismatch");
+  k_fringe_adj<D><<<nblk, 64, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_chunks, f->gstride,
+                                       static_cast<float>(f->d_omega), f->beam_ref_hz, T.freq, T.p1,
+                                       T.p2, T.th2, T.chunk_t, img, fwhm, gco, dimg, f_part);
   check_launch("k_fringe_adj");
 }
 
@@ -368,9 +382,13 @@ void launch_fringe_fwd(const vis_field* f, const float* img, const float* fwhm, 
 #undef BV_CALL_FWD
 }
 
-void launch_fringe_adj(const vis_field* f, const float* img, const float* fwhm, const float2* w,
+int fringe_tile_extent(int e) {
+  return e <= 2 ? 2 : e <= 4 ? 4 : e <= 6 ? 6 : e <= 8 ? 8 : e <= 12 ? 12 : 16;
+}
+
+void launch_fringe_adj(const vis_field* f, const float* img, const float* fwhm, const float* gco,
                        float* dimg, float* f_part, hipStream_t st) {
-#define BV_CALL_ADJ(DD) adj_d<DD>(f, img, fwhm, w, dimg, f_part, st)
+#define BV_CALL_ADJ(DD) adj_d<DD>(f, img, fwhm, gco, dimg, f_part, st)
   BV_DISPATCH_EXTENT(f->extent, BV_CALL_ADJ);
 #undef BV_CALL_ADJ
 }

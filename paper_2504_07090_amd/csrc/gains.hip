@@ -8,7 +8,8 @@
 // With the cotangent c = dL/dRe m + i dL/dIm m (c = -2 (d - m) / sigma_n^2 for
 // chi^2):
 //   omega_u = sum_{ij -> +u} conj(c_ij) G_ij + sum_{ij -> -u} c_ij conj(G_ij)
-//     (the coefficients of the adjoint fringe pass; G_ij = g_i conj(g_j));
+//     (G_ij = g_i conj(g_j)), from which the coefficients of the adjoint fringe
+//     pass are laid out directly in that kernel's MFMA operand order;
 //   dL/dg_a = sum_{(a, j)} c_aj g_j conj(V_aj) + sum_{(i, a)} conj(c_ia) g_i V_ia.
 // One 256-thread block per (t, nu) keeps the gains and unique visibilities of
 // that slice in LDS; every reduction runs in a fixed order.
@@ -35,14 +36,17 @@ struct GainArgs {
   const float2* din;
   float2* vis_out;
   double* chi_part;
-  float2* w;
+  float* gco;
   float2* g_part;
+  const int* ulut;
+  int dr, dtile, rt, gstride;
 };
 
 __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
   extern __shared__ float2 sm[];
   float2* g = sm;              // [nant]
   float2* v = sm + a.nant;     // [nubl]
+  float2* om = v + a.nubl;     // [nubl] collapsed coefficients omega_u
   __shared__ double red[256];
   const int f = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
   const size_t slice = static_cast<size_t>(t) * a.nf + f;
@@ -87,16 +91,16 @@ __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
     if (tid == 0) a.chi_part[slice] = red[0] * static_cast<double>(a.inv_sig2);
   }
   for (int u = tid; u < a.nubl; u += 256) {
-    float2 om = make_float2(0.f, 0.f);
+    float2 o = make_float2(0.f, 0.f);
     for (int e = a.u_off[u]; e < a.u_off[u + 1]; ++e) {
       const int code = a.u_list[e];
       const int k = code >> 1;
       const float2 c = cot(k), G = gprod(k);
       const float2 term = (code & 1) ? cmul(c, conjf2(G)) : cmul(conjf2(c), G);
-      om.x += term.x;
-      om.y += term.y;
+      o.x += term.x;
+      o.y += term.y;
     }
-    a.w[slice * a.nubl + u] = om;
+    om[u] = o;
   }
   for (int ant = tid; ant < a.nant; ant += 256) {
     float2 s = make_float2(0.f, 0.f);
@@ -111,6 +115,43 @@ __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
       s.y += term.y;
     }
     a.g_part[slice * a.nant + ant] = s;
+  }
+  __syncthreads();
+  // Adjoint coefficients.  Entry ((i * rt + kt) * 64 + l) * 4 + s holds
+  // G[r][c], r = 16 i + (l & 15), c = 16 kt + 4 s + (l >> 4), with
+  // r = 2 (n - 1) + (Re / Im of alpha^n), c = 2 (m - 1) + (Re / Im of beta^m):
+  //   G = w+r + w-r (Re Re), w-r - w+r (Im Im), w-i - w+i (Re Im), -w+i - w-i (Im Re),
+  // w+- = omega(n, +-m).  After rt*rt*256 entries follow, for n = 1..dtile,
+  // (omega(n, 0).re, omega(n, 0).im, omega(0, n).re, omega(0, n).im).
+  const int lw = 2 * a.dr + 1;
+  auto omega = [&](int n1, int n2) {
+    if (n1 > a.dr || n2 > a.dr || n2 < -a.dr) return make_float2(0.f, 0.f);
+    const int u = a.ulut[n1 * lw + n2 + a.dr];
+    return u >= 0 ? om[u] : make_float2(0.f, 0.f);
+  };
+  float* G = a.gco + slice * a.gstride;
+  const int nmat = a.rt * a.rt * 256;
+  for (int e = tid; e < a.gstride; e += 256) {
+    float val = 0.f;
+    if (e < nmat) {
+      const int s4 = e & 3, l = (e >> 2) & 63, blk = e >> 8;
+      const int i = blk / a.rt, kt = blk - i * a.rt;
+      const int r = 16 * i + (l & 15), c = 16 * kt + 4 * s4 + (l >> 4);
+      const int n = (r >> 1) + 1, m = (c >> 1) + 1;
+      if (n <= a.dtile && m <= a.dtile) {
+        const float2 wp = omega(n, m), wm = omega(n, -m);
+        const int pr = r & 1, pc = c & 1;
+        if (pr == 0 && pc == 0) val = wp.x + wm.x;
+        else if (pr == 1 && pc == 1) val = wm.x - wp.x;
+        else if (pr == 0 && pc == 1) val = wm.y - wp.y;
+        else val = -wp.y - wm.y;
+      }
+    } else if (e < nmat + 4 * a.dtile) {
+      const int idx = e - nmat, n = idx / 4 + 1, comp = idx & 3;
+      const float2 w0 = comp < 2 ? omega(n, 0) : omega(0, n);
+      val = (comp & 1) ? w0.y : w0.x;
+    }
+    G[e] = val;
   }
 }
 
@@ -160,7 +201,7 @@ k_reduce_grads(int nt, int nf, int nant, int nfpart, int with_chi2, const double
 }
 
 void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const float2* gains,
-                  const float2* din, float sigma_n, float2* vis_out, double* chi_part, float2* w,
+                  const float2* din, float sigma_n, float2* vis_out, double* chi_part, float* gco,
                   float2* g_part, hipStream_t st) {
   GainArgs a;
   a.mode = mode;
@@ -181,9 +222,14 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
   a.din = din;
   a.vis_out = vis_out;
   a.chi_part = chi_part;
-  a.w = w;
+  a.gco = gco;
   a.g_part = g_part;
-  const size_t lds = sizeof(float2) * (f->n_ant + f->n_ubl);
+  a.ulut = f->tab.ulut;
+  a.dr = f->extent;
+  a.dtile = f->dtile;
+  a.rt = fringe_tiles(f->dtile);
+  a.gstride = f->gstride;
+  const size_t lds = sizeof(float2) * (f->n_ant + 2 * f->n_ubl);
   BV_REQUIRE(lds <= 48 * 1024, VIS_EINVAL, "field too large for the gains pass LDS budget");
   dim3 grid(f->n_freq, f->n_time);
   ProfScope ps(&f->prof, "k_gains", st);

@@ -60,11 +60,12 @@ struct FieldScratch {
   float* img = nullptr;            // [n_freq][nv_pad] sky at visible pixels
   float* dimg = nullptr;           // [n_freq][nv_pad] dL/dI
   float2* vu = nullptr;            // [n_time][n_freq][n_ubl] gain-free unique visibilities
-  float2* w = nullptr;             // [n_time][n_freq][n_ubl] collapsed adjoint coefficients
+  float* gco = nullptr;            // [n_time][n_freq][gstride] adjoint coefficients, MFMA layout
   double* chi_part = nullptr;      // [n_time * n_freq]
   float2* g_part = nullptr;        // [n_time][n_freq][n_ant]
   float* f_part = nullptr;         // [n_freq * n_chunks]
-  float* a_part = nullptr;         // [split][n_freq][kpad] split-K partials of dL/da
+  float* a_part = nullptr;         // split-K partials: [asplit][n_freq][kpad] of dL/da,
+                                   // or [fsplit][n_freq][nv_pad] of the sky
 };
 
 // Immutable device tables of one field.
@@ -95,8 +96,11 @@ struct vis_field {
   int n_modes = 0, lmax = 0;
   int nv = 0, nv_pad = 0, n_chunks = 0, n_tchunk = 0;
   int extent = 0;                  // D = max |n1|, |n2|
+  int dtile = 0;                   // compile-time extent of the fringe kernels (>= extent)
+  int gstride = 0;                 // floats per (t, nu) of the adjoint coefficient table
   int precision = VIS_FP32;
   int asplit = 1;                  // split-K factor of the adjoint synthesis
+  int fsplit = 1;                  // split-K factor of the FP32 forward synthesis
   double d_omega = 0.0;
   double beam_ref_hz = 150e6;
   double fwd_macs = 0.0;
@@ -112,13 +116,22 @@ void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStrea
 void launch_synth_adj(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st);
 void launch_fringe_fwd(const vis_field* f, const float* img, const float* fwhm, float2* vu,
                        hipStream_t st);
-void launch_fringe_adj(const vis_field* f, const float* img, const float* fwhm, const float2* w,
+void launch_fringe_adj(const vis_field* f, const float* img, const float* fwhm, const float* gco,
                        float* dimg, float* f_part, hipStream_t st);
+
+// Extent instantiated by the fringe kernels for a lattice extent D, and the
+// layout of the adjoint coefficient table that the gains pass writes.
+int fringe_tile_extent(int extent);
+inline int fringe_tiles(int dtile) { return (2 * dtile + 15) / 16; }
+inline int adj_coef_stride(int dtile) {
+  const int rt = fringe_tiles(dtile);
+  return static_cast<int>(round_up(rt * rt * 256 + 4 * dtile, 64));
+}
 
 enum GainMode { kGainFwd = 0, kGainChi2 = 1, kGainAdj = 2 };
 void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const float2* gains,
                   const float2* data_or_dvis, float sigma_n, float2* vis_out, double* chi_part,
-                  float2* w, float2* g_part, hipStream_t st);
+                  float* gco, float2* g_part, hipStream_t st);
 void launch_reduce_grads(const vis_field* f, bool with_chi2, const double* chi_part,
                          double* chi2, const float2* g_part, float2* grad_gains,
                          const float* f_part, float* grad_fwhm, hipStream_t st);

@@ -23,17 +23,20 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// img[f][k] = sum_{c < nm} alm[f][c] Y[vpix[k]][c]
-// Block tile 64 (f) x 64 (k), K step 16, 4 waves as 2 x 2 sub-tiles of 32 x 32.
+// part[s][f][k] = sum_{c in split s, c < nm} alm[f][c] Y[vpix[k]][c]
+// Block tile 64 (f) x 64 (k), K step 32, 4 waves as 2 x 2 sub-tiles of 32 x 32;
+// the mode range is split over blockIdx.z so the grid fills the chip, and the
+// splits are summed in a fixed order afterwards.
 __global__ void __launch_bounds__(256)
-k_synth_fwd_f32(int nf, int nm, int nvp, int kpad, const float* __restrict__ alm,
-                const float* __restrict__ Y, const int* __restrict__ vpix, float* __restrict__ img) {
-  __shared__ float As[2][64][17];
-  __shared__ float Bs[2][64][17];
+k_synth_fwd_f32(int nf, int nm, int nvp, int kpad, int kps, const float* __restrict__ alm,
+                const float* __restrict__ Y, const int* __restrict__ vpix, float* __restrict__ part) {
+  __shared__ float As[2][64][33];
+  __shared__ float Bs[2][64][33];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
+  const int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64, split = blockIdx.z;
+  const int kbeg = split * kps, kend = min(nm, kbeg + kps);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int lr = tid >> 2, lk = (tid & 3) * 4;
+  const int lr = tid >> 2, lk = (tid & 3) * 8;
   const int arow = m0 + lr;
   const float* yrow = Y + static_cast<size_t>(vpix[n0 + lr]) * kpad;
   const float* arow_p = alm + static_cast<size_t>(arow) * nm;
@@ -42,29 +45,32 @@ k_synth_fwd_f32(int nf, int nm, int nvp, int kpad, const float* __restrict__ alm
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  float ra[4];
-  f4 rb;
-  const int ksteps = (nm + 15) / 16;
+  float ra[8];
+  f4 rb0, rb1;
+  const int ksteps = (kend - kbeg + 31) / 32;
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const int c = k0 + lk + q;
-      ra[q] = (arow < nf && c < nm) ? arow_p[c] : 0.f;
+      ra[q] = (arow < nf && c < kend) ? arow_p[c] : 0.f;
     }
-    rb = *reinterpret_cast<const f4*>(yrow + k0 + lk);
+    rb0 = *reinterpret_cast<const f4*>(yrow + k0 + lk);
+    rb1 = *reinterpret_cast<const f4*>(yrow + k0 + lk + 4);
   };
-  gload(0);
+  if (ksteps > 0) gload(kbeg);
   for (int s = 0; s < ksteps; ++s) {
     const int buf = s & 1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       As[buf][lr][lk + q] = ra[q];
-      Bs[buf][lr][lk + q] = rb[q];
+      As[buf][lr][lk + 4 + q] = ra[4 + q];
+      Bs[buf][lr][lk + q] = rb0[q];
+      Bs[buf][lr][lk + 4 + q] = rb1[q];
     }
     __syncthreads();
-    if (s + 1 < ksteps) gload((s + 1) * 16);
+    if (s + 1 < ksteps) gload(kbeg + (s + 1) * 32);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
+    for (int kk = 0; kk < 8; ++kk) {
       float a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = As[buf][wm + 16 * i + (lane & 15)][4 * kk + (lane >> 4)];
@@ -76,6 +82,7 @@ k_synth_fwd_f32(int nf, int nm, int nvp, int kpad, const float* __restrict__ alm
         for (int j = 0; j < 2; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
     }
   }
+  float* out = part + static_cast<size_t>(split) * nf * nvp;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -84,8 +91,18 @@ k_synth_fwd_f32(int nf, int nm, int nvp, int kpad, const float* __restrict__ alm
       for (int r = 0; r < 4; ++r) {
         const int f = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
         const int k = n0 + wn + 16 * j + (lane & 15);
-        if (f < nf) img[static_cast<size_t>(f) * nvp + k] = acc[i][j][r];
+        if (f < nf) out[static_cast<size_t>(f) * nvp + k] = acc[i][j][r];
       }
+}
+
+// img[f][k] = sum_s part[s][f][k], fixed order over s.
+__global__ void __launch_bounds__(256)
+k_sum_fwd_splits(int nsplit, long n, const float* __restrict__ part, float* __restrict__ img) {
+  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  float s = 0.f;
+  for (int q = 0; q < nsplit; ++q) s += part[q * n + idx];
+  img[idx] = s;
 }
 
 // part[s][f][c] = sum_{k in split s} dimg[f][k] Y[vpix[k]][c]
@@ -176,11 +193,19 @@ void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStrea
   }
   const vis_basis* b = f->basis;
   BV_REQUIRE(b->y32 != nullptr, VIS_EINVAL, "basis has no FP32 storage");
-  dim3 grid(f->nv_pad / 64, ceil_div(f->n_freq, 64));
-  ProfScope ps(&f->prof, "k_synth_fwd_f32", st);
-  k_synth_fwd_f32<<<grid, 256, 0, st>>>(f->n_freq, f->n_modes, f->nv_pad, b->kpad, alm, b->y32,
-                                         f->tab.vpix, img);
-  check_launch("k_synth_fwd_f32");
+  const int nsplit = f->fsplit;
+  const int kps = static_cast<int>(round_up(ceil_div(f->n_modes, nsplit), 32));
+  dim3 grid(f->nv_pad / 64, ceil_div(f->n_freq, 64), nsplit);
+  {
+    ProfScope ps(&f->prof, "k_synth_fwd_f32", st);
+    k_synth_fwd_f32<<<grid, 256, 0, st>>>(f->n_freq, f->n_modes, f->nv_pad, b->kpad, kps, alm,
+                                           b->y32, f->tab.vpix, f->scr.a_part);
+    check_launch("k_synth_fwd_f32");
+  }
+  const long n = static_cast<long>(f->n_freq) * f->nv_pad;
+  ProfScope ps(&f->prof, "k_sum_fwd_splits", st);
+  k_sum_fwd_splits<<<ceil_div(n, 256), 256, 0, st>>>(nsplit, n, f->scr.a_part, img);
+  check_launch("k_sum_fwd_splits");
 }
 
 void launch_synth_adj(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st) {
