@@ -126,7 +126,8 @@ def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=
     flds = [f if prec == vis.VIS_FP32 else vis.Field.from_config(basis, cfg, prec)
             for (cfg, f, *_rest) in inputs]
     fp = sum(serve.Server.footprint(f) for f in flds)
-    srv = serve.Server(fp + (64 << 20), max_chains=n_chains, max_batch=max_batch)
+    srv = serve.Server(fp + (64 << 20), max_chains=n_chains, max_batch=max_batch,
+                       batched=1 if max_batch > 1 else 0)
     ids = []
     for c, ((cfg, _, data, sigma, q0, minv, cvar), fld) in enumerate(zip(inputs, flds)):
         ids.append(srv.admit(fld, data, sigma, q0, minv, cvar, cfg.gain_scatter, EPS, n_leapfrog,

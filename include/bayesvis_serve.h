@@ -42,7 +42,8 @@ typedef struct hmc_server hmc_server;
 typedef struct {
   int32_t max_chains;          /* request-table capacity, >= 1 */
   int32_t max_batch;           /* requests per tick, >= 1 */
-  int32_t batched;             /* 1: batched launches across chains; 0: one chain per launch */
+  int32_t batched;             /* 1: a tick's evaluations overlap on several streams;
+                                  0: they run one after another on the server stream */
   int32_t reserved;
 } hmc_server_config;
 

@@ -4,6 +4,7 @@
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstdarg>
 #include <map>
@@ -334,6 +335,7 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
   auto& S = f->scr;
   const size_t kpad = f->basis->kpad;
   S.img = cv.take<float>(nfq * nvp);
+  S.apad = cv.take<float>(static_cast<size_t>(round_up(f->n_freq, 64)) * kpad);
   S.dimg = cv.take<float>(nfq * nvp);
   S.vu = cv.take<float2>(nt * nfq * f->n_ubl);
   S.gco = cv.take<float>(nt * nfq * static_cast<size_t>(f->gstride));
@@ -374,11 +376,15 @@ static void fill_shape(vis_field* f, const vis_basis* basis, const vis_field_des
   f->fwd_macs = g.vis_pix_time * f->n_ubl * d->n_freq;
   f->asplit = choose_asplit(d->n_freq, basis->kpad, g.nv_pad);
   {
-    // forward synthesis: enough (pixel tile x mode split) blocks for ~4 per CU
+    // forward synthesis: as many mode splits as fill one round of resident
+    // blocks (4 per CU on 256 CUs) without starting a partial second round
     const int tiles = ceil_div(d->n_freq, 64) * (g.nv_pad / 64);
     const int nm = (d->lmax + 1) * (d->lmax + 1);
-    f->fsplit = std::max(1, std::min(ceil_div(1024, tiles), std::max(1, nm / 512)));
+    f->fsplit = std::max(1, std::min(1024 / std::max(1, tiles), std::max(1, nm / 512)));
   }
+  // tuning overrides (split-K factors of the two synthesis GEMMs)
+  if (const char* e = getenv("BV_FSPLIT")) f->fsplit = std::max(1, std::min(64, atoi(e)));
+  if (const char* e = getenv("BV_ASPLIT")) f->asplit = std::max(1, std::min(64, atoi(e)));
 }
 
 template <class T>

@@ -77,9 +77,22 @@ __device__ __forceinline__ int xcd_logical(int bid, int nblocks) {
 template <int D>
 struct Tile {
   static constexpr int RT = (2 * D + 15) / 16;  // 16-wide MFMA tiles per side
-  static constexpr int W = 16 * RT;             // padded side
-  static constexpr int PITCH = W + 1;           // LDS row pitch (floats): conflict-free rows
+  static constexpr int W = 16 * RT;             // padded side = LDS row length (floats)
 };
+
+// LDS layout of the per-pixel operand rows: row px holds W floats as W/4
+// groups of 4; logical group g sits at physical group g ^ swz(px).  The
+// swizzle makes a wavefront's 128-bit row writes hit every bank group evenly
+// and keeps the MFMA operand reads (16 consecutive columns of one row per
+// 16 lanes, the next row in the next 16 lanes) free of bank conflicts.
+template <int W>
+__device__ __forceinline__ int swz(int px) {
+  return W == 16 ? ((px >> 1) & 3) : (((px & 1) << 2) | ((px >> 1) & 3));
+}
+template <int W>
+__device__ __forceinline__ int lds_at(int px, int col) {
+  return px * W + ((((col >> 2) ^ swz<W>(px))) << 2) + (col & 3);
+}
 
 // Geometry of one (time, visible pixel) entry.
 struct Geo {
@@ -88,32 +101,45 @@ struct Geo {
 };
 
 // Powers alpha^n (n = 1..D) and beta^m w (m = 1..D) of one pixel into its LDS
-// rows, zero padding up to W; visit(n, alpha^n, beta^n w) sees every power
-// while it is still in registers.
+// rows (row px of As / Bs, zero padding up to W); visit(n, alpha^n, beta^n w)
+// sees every power while it is still in registers.  With alpha = exp(-i t),
+// alpha^(n+1) = 2 cos(t) alpha^n - alpha^(n-1) (the three-term recurrence of
+// cos(n t) and sin(n t)), one FMA per component; the same holds for beta^m w.
 template <int D, int W, class Visit>
-__device__ __forceinline__ void write_powers(float* arow, float* brow, float c1, float s1, float c2,
-                                             float s2, float w, Visit visit) {
-  float ar = c1, ai = -s1;
-  float br = c2 * w, bi = -s2 * w;
+__device__ __forceinline__ void write_powers(float* As, float* Bs, int px, float c1, float s1,
+                                             float c2, float s2, float w, Visit visit) {
+  float av[W], bv[W];
+  float ar0 = 1.f, ai0 = 0.f, ar = c1, ai = -s1;
+  float br0 = w, bi0 = 0.f, br = c2 * w, bi = -s2 * w;
+  const float t1 = 2.f * c1, t2 = 2.f * c2;
 #pragma unroll
   for (int n = 0; n < D; ++n) {
-    arow[2 * n] = ar;
-    arow[2 * n + 1] = ai;
-    brow[2 * n] = br;
-    brow[2 * n + 1] = bi;
+    av[2 * n] = ar;
+    av[2 * n + 1] = ai;
+    bv[2 * n] = br;
+    bv[2 * n + 1] = bi;
     visit(n, ar, ai, br, bi);
-    const float nar = ar * c1 + ai * s1;  // (ar + i ai)(c1 - i s1)
-    const float nai = ai * c1 - ar * s1;
-    const float nbr = br * c2 + bi * s2;
-    const float nbi = bi * c2 - br * s2;
+    const float nar = t1 * ar - ar0, nai = t1 * ai - ai0;
+    const float nbr = t2 * br - br0, nbi = t2 * bi - bi0;
+    ar0 = ar; ai0 = ai; br0 = br; bi0 = bi;
     ar = nar; ai = nai; br = nbr; bi = nbi;
   }
 #pragma unroll
-  for (int r = 2 * D; r < W; ++r) { arow[r] = 0.f; brow[r] = 0.f; }
+  for (int r = 2 * D; r < W; ++r) av[r] = bv[r] = 0.f;
+#pragma unroll
+  for (int g = 0; g < W / 4; ++g) {
+    const int o = px * W + ((g ^ swz<W>(px)) << 2);
+    *reinterpret_cast<f4*>(As + o) = f4{av[4 * g], av[4 * g + 1], av[4 * g + 2], av[4 * g + 3]};
+    *reinterpret_cast<f4*>(Bs + o) = f4{bv[4 * g], bv[4 * g + 1], bv[4 * g + 2], bv[4 * g + 3]};
+  }
 }
 
 // ------------------------------------------------------------------ forward --
 // One wavefront per (t, nu); loops over the pixel chunks visible at t.
+// Software pipeline per chunk: the MFMA operands of chunk k are read from LDS
+// into registers, then the 16 MFMAs of chunk k are interleaved with the
+// vector-ALU generation of chunk k+1's powers (written to LDS), so the matrix
+// and vector pipes work at the same time; geometry is loaded two chunks ahead.
 template <int D>
 __global__ void __launch_bounds__(64)
 k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
@@ -123,9 +149,9 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
              const int2* __restrict__ ubl_nm, const float* __restrict__ img,
              const float* __restrict__ fwhm, float2* __restrict__ vu) {
   using T = Tile<D>;
-  constexpr int RT = T::RT, W = T::W, PITCH = T::PITCH;
-  __shared__ float As[64 * PITCH];
-  __shared__ float Bs[64 * PITCH];
+  constexpr int RT = T::RT, W = T::W;
+  __shared__ __attribute__((aligned(16))) float As[64 * W];
+  __shared__ __attribute__((aligned(16))) float Bs[64 * W];
   const int lane = threadIdx.x;
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nf * nt) return;
@@ -145,54 +171,71 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
   for (int n = 0; n < D; ++n) axr[n] = axi[n] = bxr[n] = bxi[n] = 0.f;
 
   const int cbeg = tchunk_off[t], cend = tchunk_off[t + 1];
-  float* arow = As + lane * PITCH;
-  float* brow = Bs + lane * PITCH;
   const double* p1t = P1 + static_cast<size_t>(t) * nvp;
   const double* p2t = P2 + static_cast<size_t>(t) * nvp;
   const float* tht = TH2 + static_cast<size_t>(t) * nvp;
   const float* imf = img + static_cast<size_t>(f) * nvp;
-  // software pipeline: the next chunk's inputs are in flight while this one computes
-  double np1 = 0.0, np2 = 0.0;
-  float nth = 0.f, nim = 0.f;
-  if (cbeg < cend) {
-    const int k = tchunk[cbeg] * kChunk + lane;
-    np1 = p1t[k]; np2 = p2t[k]; nth = tht[k]; nim = imf[k];
-  }
-  for (int ci = cbeg; ci < cend; ++ci) {
-    const double p1 = np1, p2 = np2;
-    const float th2 = nth, iv = nim;
-    if (ci + 1 < cend) {
-      const int k = tchunk[ci + 1] * kChunk + lane;
-      np1 = p1t[k]; np2 = p2t[k]; nth = tht[k]; nim = imf[k];
-    }
-    const float x1 = reduced_cycles(nu, p1);
-    const float x2 = reduced_cycles(nu, p2);
-    const float s = d_omega * exp2f(-th2 * kb) * iv;
+
+  struct G { double p1, p2; float th, iv; };
+  auto load = [&](int ci) {
+    const int k = tchunk[ci] * kChunk + lane;
+    return G{p1t[k], p2t[k], tht[k], imf[k]};
+  };
+  // powers of one chunk into LDS; `live` = 0 turns a padding pass into a no-op
+  auto generate = [&](const G& g, float live) {
+    const float x1 = reduced_cycles(nu, g.p1);
+    const float x2 = reduced_cycles(nu, g.p2);
+    const float s = live * d_omega * exp2f(-g.th * kb) * g.iv;
     float s1, c1, s2, c2;
     sincos_rev(x1, s1, c1);
     sincos_rev(x2, s2, c2);
-    write_powers<D, W>(arow, brow, c1, s1, c2, s2, s,
+    write_powers<D, W>(As, Bs, lane, c1, s1, c2, s2, s,
                        [&](int n, float ar, float ai, float br, float bi) {
                          axr[n] += ar * s;
                          axi[n] += ai * s;
                          bxr[n] += br;
                          bxi[n] += bi;
                        });
-    wave_sync();
-#pragma unroll 4
+  };
+  float a[16][RT], b[16][RT];
+  auto operands = [&]() {
+#pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int px = 4 * q + (lane >> 4);
-      float a[RT], b[RT];
 #pragma unroll
-      for (int i = 0; i < RT; ++i) a[i] = As[px * PITCH + 16 * i + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < RT; ++j) b[j] = Bs[px * PITCH + 16 * j + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < RT; ++i)
-#pragma unroll
-        for (int j = 0; j < RT; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
+      for (int i = 0; i < RT; ++i) {
+        a[q][i] = As[lds_at<W>(px, 16 * i + (lane & 15))];
+        b[q][i] = Bs[lds_at<W>(px, 16 * i + (lane & 15))];
+      }
     }
+  };
+  if (cend > cbeg) {
+    generate(load(cbeg), 1.0f);
+    G gn = load(min(cbeg + 1, cend - 1));
     wave_sync();
+    operands();
+    wave_sync();
+    for (int ci = cbeg; ci < cend; ++ci) {
+      const G gn2 = load(min(ci + 2, cend - 1));
+      // MFMAs of chunk ci (register operands) interleaved with chunk ci+1's generation
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int j = 0; j < RT; ++j) acc[i][j] = mfma4(a[q][i], b[q][j], acc[i][j]);
+      generate(gn, ci + 1 < cend ? 1.0f : 0.0f);
+#pragma unroll
+      for (int q = 0; q < 16 * RT * RT; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 8 / (RT * RT), 0);  // vector ALU
+        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // one LDS write (128-bit)
+      }
+      wave_sync();
+      operands();
+      wave_sync();
+      gn = gn2;
+    }
   }
 #pragma unroll
   for (int n = 0; n < D; ++n) {
@@ -255,10 +298,10 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
              const float* __restrict__ fwhm, const float* __restrict__ gco,
              float* __restrict__ dimg, float* __restrict__ f_part) {
   using T = Tile<D>;
-  constexpr int RT = T::RT, W = T::W, PITCH = T::PITCH;
+  constexpr int RT = T::RT, W = T::W;
   constexpr int NMAT = RT * RT * 256;
-  __shared__ float As[64 * PITCH];
-  __shared__ float Bs[64 * PITCH];
+  __shared__ __attribute__((aligned(16))) float As[64 * W];
+  __shared__ __attribute__((aligned(16))) float Bs[64 * W];
   const int lane = threadIdx.x;
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nf * nchunks) return;
@@ -272,8 +315,6 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
   const float ival = img[static_cast<size_t>(f) * nvp + k];
   const int2 tr = chunk_t[chunk];
   float acc_i = 0.f, acc_f = 0.f;
-  float* arow = As + lane * PITCH;
-  float* brow = Bs + lane * PITCH;
   const size_t gst = static_cast<size_t>(nf) * gstride;
   // software pipeline over t
   double np1 = P1[static_cast<size_t>(tr.x) * nvp + k];
@@ -301,7 +342,7 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
     sincos_rev(x2, s2, c2);
     // axis terms: sum_n Re[omega(n,0) alpha^n] + Re[omega(0,n) beta^n]
     float zax = 0.f;
-    write_powers<D, W>(arow, brow, c1, s1, c2, s2, 1.0f,
+    write_powers<D, W>(As, Bs, lane, c1, s1, c2, s2, 1.0f,
                        [&](int n, float ar, float ai, float br, float bi) {
                          const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 4 * n);
                          zax += ax[0] * ar - ax[1] * ai + ax[2] * br - ax[3] * bi;
@@ -319,9 +360,10 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
         for (int kt = 0; kt < RT; ++kt)
 #pragma unroll
           for (int s = 0; s < 4; ++s)
-            tacc = mfma4(gv[i][kt][s], Bs[px * PITCH + 16 * kt + 4 * s + (lane >> 4)], tacc);
+            tacc = mfma4(gv[i][kt][s], Bs[lds_at<W>(px, 16 * kt + 4 * s + (lane >> 4))], tacc);
+        const f4 av = *reinterpret_cast<const f4*>(As + lds_at<W>(px, 16 * i + 4 * (lane >> 4)));
 #pragma unroll
-        for (int r = 0; r < 4; ++r) zp += As[px * PITCH + 16 * i + 4 * (lane >> 4) + r] * tacc[r];
+        for (int r = 0; r < 4; ++r) zp += av[r] * tacc[r];
       }
       zp += __shfl_xor(zp, 16);
       zp += __shfl_xor(zp, 32);

@@ -58,6 +58,7 @@ namespace bv {
 // Per-evaluation scratch of one field (device).
 struct FieldScratch {
   float* img = nullptr;            // [n_freq][nv_pad] sky at visible pixels
+  float* apad = nullptr;           // [nf_pad][kpad] sky coefficients, zero-padded rows
   float* dimg = nullptr;           // [n_freq][nv_pad] dL/dI
   float2* vu = nullptr;            // [n_time][n_freq][n_ubl] gain-free unique visibilities
   float* gco = nullptr;            // [n_time][n_freq][gstride] adjoint coefficients, MFMA layout

@@ -167,6 +167,7 @@ struct Slot {
 };
 
 constexpr int kSlots = 3;
+constexpr int kSubStreams = 4;   // evaluation streams of a batched tick (hardware queues)
 
 }  // namespace bv
 
@@ -186,6 +187,9 @@ struct hmc_server {
   Slot slots[kSlots];
   int next_slot = 0;
   int rr = 0;                         // round-robin start
+  hipStream_t sub[kSubStreams] = {};
+  hipEvent_t ev_pre = nullptr;
+  hipEvent_t ev_sub[kSubStreams] = {};
   std::vector<uint64_t> req_latency_ns;
   uint64_t n_requests = 0;
   vis_status worker_status = VIS_OK;
@@ -315,14 +319,27 @@ void hmc_server::enqueue(Tick& t) {
   hip_or_throw(hipMemcpyAsync(S.dev_blk, S.host_blk, sizeof(int) * 3 * (nb + 1),
                               hipMemcpyHostToDevice, stream), "prefix upload");
   launch_hmc_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
-  for (const Chain* c : evs) {
+  // evaluations: in a batched tick the chains' evaluation sequences run on
+  // several streams so the kernels of different fields overlap on the device
+  const int nsub = (cfg.batched && evs.size() > 1) ? std::min<int>(kSubStreams, evs.size()) : 0;
+  if (nsub > 0) {
+    hip_or_throw(hipEventRecord(ev_pre, stream), "event record");
+    for (int i = 0; i < nsub; ++i) hip_or_throw(hipStreamWaitEvent(sub[i], ev_pre, 0), "stream wait");
+  }
+  for (size_t k = 0; k < evs.size(); ++k) {
+    const Chain* c = evs[k];
     const float* q = c->ptr(c->L.off_q);
     float* g = c->ptr(c->L.off_gchi);
+    hipStream_t es = nsub > 0 ? sub[k % nsub] : stream;
     const vis_status s = chi2_and_grad(
         c->field, reinterpret_cast<const vis_c64*>(c->data), c->sigma_n, q,
         reinterpret_cast<const vis_c64*>(q + c->L.goff), q + c->L.len - 1, &c->st()->chi2, g,
-        reinterpret_cast<vis_c64*>(g + c->L.goff), g + c->L.len - 1, stream);
+        reinterpret_cast<vis_c64*>(g + c->L.goff), g + c->L.len - 1, es);
     if (s != VIS_OK) throw Failure{s};
+  }
+  for (int i = 0; i < nsub; ++i) {
+    hip_or_throw(hipEventRecord(ev_sub[i], sub[i]), "event record");
+    hip_or_throw(hipStreamWaitEvent(stream, ev_sub[i], 0), "stream wait");
   }
   launch_hmc_elem(S.dev_tasks + nb, npost, S.dev_blk + (nb + 1), bpost, stream);
   launch_hmc_finalize(S.dev_tasks + 2 * nb, npost, stream);
@@ -458,6 +475,13 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
       std::memset(S.host_blk, 0, sizeof(int) * 3 * (nb + 1));
     }
     s->arena.init(base + reserve, arena_bytes - reserve);
+    if (cfg->batched) {
+      for (int i = 0; i < kSubStreams; ++i) {
+        BV_HIP(hipStreamCreateWithFlags(&s->sub[i], hipStreamNonBlocking));
+        BV_HIP(hipEventCreateWithFlags(&s->ev_sub[i], hipEventDisableTiming));
+      }
+      BV_HIP(hipEventCreateWithFlags(&s->ev_pre, hipEventDisableTiming));
+    }
     s->chains.reserve(cfg->max_chains);
     s->worker = std::thread([s] { s->run(); });
     *out = s;
@@ -652,6 +676,11 @@ vis_status hmc_server_destroy(hmc_server* s) {
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   for (Chain* c : s->chains) delete c;
+  for (int i = 0; i < kSubStreams; ++i) {
+    if (s->sub[i]) (void)hipStreamDestroy(s->sub[i]);
+    if (s->ev_sub[i]) (void)hipEventDestroy(s->ev_sub[i]);
+  }
+  if (s->ev_pre) (void)hipEventDestroy(s->ev_pre);
   for (auto& S : s->slots) {
     if (S.host_tasks) (void)hipHostFree(S.host_tasks);
     if (S.host_blk) (void)hipHostFree(S.host_blk);

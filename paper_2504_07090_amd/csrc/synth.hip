@@ -23,15 +23,39 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// apad[f][c] = alm[f][c] for f < nf, c < nm, else 0 (rows of kpad floats,
+// 64 rows per 64-row tile), so the GEMMs load aligned, unconditional vectors.
+__global__ void __launch_bounds__(256)
+k_pad_alm(int nf, int nm, int kpad, int nrows, const float* __restrict__ alm, float* __restrict__ apad) {
+  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<long>(nrows) * kpad) return;
+  const int f = static_cast<int>(idx / kpad), c = static_cast<int>(idx - static_cast<long>(f) * kpad);
+  apad[idx] = (f < nf && c < nm) ? alm[static_cast<size_t>(f) * nm + c] : 0.f;
+}
+
+void pad_alm(const vis_field* f, const float* alm, hipStream_t st) {
+  const int kpad = f->basis->kpad;
+  const int nrows = static_cast<int>(round_up(f->n_freq, 64));
+  const long n = static_cast<long>(nrows) * kpad;
+  ProfScope ps(&f->prof, "k_pad_alm", st);
+  k_pad_alm<<<ceil_div(n, 256), 256, 0, st>>>(f->n_freq, f->n_modes, kpad, nrows, alm, f->scr.apad);
+  check_launch("k_pad_alm");
+}
+
 // part[s][f][k] = sum_{c in split s, c < nm} alm[f][c] Y[vpix[k]][c]
 // Block tile 64 (f) x 64 (k), K step 32, 4 waves as 2 x 2 sub-tiles of 32 x 32;
-// the mode range is split over blockIdx.z so the grid fills the chip, and the
-// splits are summed in a fixed order afterwards.
+// the mode range is split over blockIdx.z and the splits are summed in a
+// fixed order afterwards.  Three-stage pipeline: step t is computed from LDS
+// buffer t % 3 while step t+1 is stored into the next buffer and step t+3 is
+// being fetched into registers, so two compute phases cover each load.
 __global__ void __launch_bounds__(256)
-k_synth_fwd_f32(int nf, int nm, int nvp, int kpad, int kps, const float* __restrict__ alm,
+k_synth_fwd_f32(int nf, int nm, int nvp, int kpad, int kps, const float* __restrict__ apad,
                 const float* __restrict__ Y, const int* __restrict__ vpix, float* __restrict__ part) {
-  __shared__ float As[2][64][33];
-  __shared__ float Bs[2][64][33];
+  // pitch 34: the operand reads (16 rows x 4 columns per instruction) land on
+  // 2 row + column, distinct over each half-wavefront
+  __shared__ __attribute__((aligned(16))) float As[3][64][34];
+  __shared__ __attribute__((aligned(16))) float Bs[3][64][34];
+  typedef float f2 __attribute__((ext_vector_type(2)));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64, split = blockIdx.z;
   const int kbeg = split * kps, kend = min(nm, kbeg + kps);
@@ -39,47 +63,69 @@ k_synth_fwd_f32(int nf, int nm, int nvp, int kpad, int kps, const float* __restr
   const int lr = tid >> 2, lk = (tid & 3) * 8;
   const int arow = m0 + lr;
   const float* yrow = Y + static_cast<size_t>(vpix[n0 + lr]) * kpad;
-  const float* arow_p = alm + static_cast<size_t>(arow) * nm;
+  const float* arow_p = apad + static_cast<size_t>(arow) * kpad;   // padded rows: always in range
   f4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  float ra[8];
-  f4 rb0, rb1;
+  f4 ra[3][2];
+  f4 rb[3][2];
   const int ksteps = (kend - kbeg + 31) / 32;
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int c = k0 + lk + q;
-      ra[q] = (arow < nf && c < kend) ? arow_p[c] : 0.f;
-    }
-    rb0 = *reinterpret_cast<const f4*>(yrow + k0 + lk);
-    rb1 = *reinterpret_cast<const f4*>(yrow + k0 + lk + 4);
-  };
-  if (ksteps > 0) gload(kbeg);
-  for (int s = 0; s < ksteps; ++s) {
-    const int buf = s & 1;
+  // modes in [kend, next split) belong to the next split: zero them in A
+  auto gload = [&](int t, f4 (&a)[2], f4 (&b)[2]) {
+    const int kk = kbeg + 32 * min(t, ksteps - 1) + lk;
+    a[0] = *reinterpret_cast<const f4*>(arow_p + kk);
+    a[1] = *reinterpret_cast<const f4*>(arow_p + kk + 4);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      As[buf][lr][lk + q] = ra[q];
-      As[buf][lr][lk + 4 + q] = ra[4 + q];
-      Bs[buf][lr][lk + q] = rb0[q];
-      Bs[buf][lr][lk + 4 + q] = rb1[q];
+      a[0][q] = kk + q < kend ? a[0][q] : 0.f;
+      a[1][q] = kk + 4 + q < kend ? a[1][q] : 0.f;
     }
-    __syncthreads();
-    if (s + 1 < ksteps) gload(kbeg + (s + 1) * 32);
+    b[0] = *reinterpret_cast<const f4*>(yrow + kk);
+    b[1] = *reinterpret_cast<const f4*>(yrow + kk + 4);
+  };
+  auto store = [&](int buf, const f4 (&a)[2], const f4 (&b)[2]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f4& u = a[q >> 1];
+      *reinterpret_cast<f2*>(&As[buf][lr][lk + 2 * q]) = f2{u[2 * (q & 1)], u[2 * (q & 1) + 1]};
+      const f4& v = b[q >> 1];
+      *reinterpret_cast<f2*>(&Bs[buf][lr][lk + 2 * q]) = f2{v[2 * (q & 1)], v[2 * (q & 1) + 1]};
+    }
+  };
+  auto compute = [&](int buf) {
+    float av[8][2], bv[8][2];
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[buf][wm + 16 * i + (lane & 15)][4 * kk + (lane >> 4)];
+      for (int i = 0; i < 2; ++i) av[kk][i] = As[buf][wm + 16 * i + (lane & 15)][4 * kk + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[buf][wn + 16 * j + (lane & 15)][4 * kk + (lane >> 4)];
+      for (int j = 0; j < 2; ++j) bv[kk][j] = Bs[buf][wn + 16 * j + (lane & 15)][4 * kk + (lane >> 4)];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma4(av[kk][i], bv[kk][j], acc[i][j]);
+  };
+  // stage t: store step t+1 (fetched at stage t-2), sync, fetch step t+3, compute step t
+  auto stage = [&](int t, int cur, int nxt) {
+    if (t + 1 < ksteps) store(nxt, ra[nxt], rb[nxt]);
+    __syncthreads();
+    if (t + 3 < ksteps) gload(t + 3, ra[cur], rb[cur]);
+    compute(cur);
+  };
+  if (ksteps > 0) {
+    gload(0, ra[0], rb[0]);
+    gload(1, ra[1], rb[1]);
+    gload(2, ra[2], rb[2]);
+    store(0, ra[0], rb[0]);
+    for (int t = 0; t < ksteps; t += 3) {
+      stage(t, 0, 1);
+      if (t + 1 < ksteps) stage(t + 1, 1, 2);
+      if (t + 2 < ksteps) stage(t + 2, 2, 0);
     }
   }
   float* out = part + static_cast<size_t>(split) * nf * nvp;
@@ -106,12 +152,14 @@ k_sum_fwd_splits(int nsplit, long n, const float* __restrict__ part, float* __re
 }
 
 // part[s][f][c] = sum_{k in split s} dimg[f][k] Y[vpix[k]][c]
-// Block tile 64 (f) x 64 (c), K step 16 pixels.
+// Block tile 64 (f) x 64 (c), K step 16 pixels, three-stage pipeline as in
+// the forward.
 __global__ void __launch_bounds__(256)
 k_synth_adj_f32(int nf, int nvp, int kpad, int kps, const float* __restrict__ dimg,
                 const float* __restrict__ Y, const int* __restrict__ vpix, float* __restrict__ part) {
-  __shared__ float As[2][64][17];
-  __shared__ float Bs[2][16][80];
+  __shared__ __attribute__((aligned(16))) float As[3][64][18];
+  __shared__ __attribute__((aligned(16))) float Bs[3][16][80];
+  typedef float f2 __attribute__((ext_vector_type(2)));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64, split = blockIdx.z;
   const int kbeg = split * kps, kend = min(nvp, kbeg + kps);
@@ -124,38 +172,53 @@ k_synth_adj_f32(int nf, int nvp, int kpad, int kps, const float* __restrict__ di
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  f4 ra, rb;
+  f4 ra[3], rb[3];
   const int ksteps = (kend - kbeg + 15) / 16;
-  auto gload = [&](int k0) {
+  auto gload = [&](int t, f4& a, f4& b) {
+    const int k0 = kbeg + 16 * t;
     const int ka = k0 + lk;
-    ra = (arow < nf) ? *reinterpret_cast<const f4*>(dimg + static_cast<size_t>(arow) * nvp + ka)
-                     : f4{0.f, 0.f, 0.f, 0.f};
-    const int kb = k0 + br;
-    rb = *reinterpret_cast<const f4*>(Y + static_cast<size_t>(vpix[kb]) * kpad + n0 + bc);
-    // pixels past this split's end belong to the next split: zero their A values
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (ka + q >= kend) ra[q] = 0.f;
+    a = (t < ksteps && arow < nf)
+            ? *reinterpret_cast<const f4*>(dimg + static_cast<size_t>(arow) * nvp + ka)
+            : f4{0.f, 0.f, 0.f, 0.f};
+    const int kb = t < ksteps ? k0 + br : kbeg + br;
+    b = *reinterpret_cast<const f4*>(Y + static_cast<size_t>(vpix[kb]) * kpad + n0 + bc);
   };
-  if (ksteps > 0) gload(kbeg);
-  for (int s = 0; s < ksteps; ++s) {
-    const int buf = s & 1;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) As[buf][lr][lk + q] = ra[q];
-    *reinterpret_cast<f4*>(&Bs[buf][br][bc]) = rb;
-    __syncthreads();
-    if (s + 1 < ksteps) gload(kbeg + (s + 1) * 16);
+  auto store = [&](int buf, const f4& a, const f4& b) {
+    *reinterpret_cast<f2*>(&As[buf][lr][lk]) = f2{a[0], a[1]};
+    *reinterpret_cast<f2*>(&As[buf][lr][lk + 2]) = f2{a[2], a[3]};
+    *reinterpret_cast<f4*>(&Bs[buf][br][bc]) = b;
+  };
+  auto compute = [&](int buf) {
+    float av[4][2], bv[4][2];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[buf][wm + 16 * i + (lane & 15)][4 * kk + (lane >> 4)];
+      for (int i = 0; i < 2; ++i) av[kk][i] = As[buf][wm + 16 * i + (lane & 15)][4 * kk + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[buf][4 * kk + (lane >> 4)][wn + 16 * j + (lane & 15)];
+      for (int j = 0; j < 2; ++j) bv[kk][j] = Bs[buf][4 * kk + (lane >> 4)][wn + 16 * j + (lane & 15)];
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j) acc[i][j] = mfma4(av[kk][i], bv[kk][j], acc[i][j]);
+  };
+  auto stage = [&](int t, int cur, int nxt) {
+    if (t + 1 < ksteps) store(nxt, ra[nxt], rb[nxt]);
+    __syncthreads();
+    if (t + 3 < ksteps) gload(t + 3, ra[cur], rb[cur]);
+    compute(cur);
+  };
+  if (ksteps > 0) {
+    gload(0, ra[0], rb[0]);
+    gload(1, ra[1], rb[1]);
+    gload(2, ra[2], rb[2]);
+    store(0, ra[0], rb[0]);
+    for (int t = 0; t < ksteps; t += 3) {
+      stage(t, 0, 1);
+      if (t + 1 < ksteps) stage(t + 1, 1, 2);
+      if (t + 2 < ksteps) stage(t + 2, 2, 0);
     }
   }
   float* out = part + static_cast<size_t>(split) * nf * kpad;
@@ -183,12 +246,13 @@ k_reduce_splits(int nsplit, int nf, int nm, int kpad, const float* __restrict__ 
   grad[idx] = s;
 }
 
-void launch_synth_fwd_bf16x3(const vis_field* f, const float* alm, float* img, hipStream_t st);
+void launch_synth_fwd_bf16x3(const vis_field* f, const float* apad, float* img, hipStream_t st);
 void launch_synth_adj_bf16x3(const vis_field* f, const float* dimg, int kps, hipStream_t st);
 
 void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStream_t st) {
   if (f->precision == VIS_BF16X3) {
-    launch_synth_fwd_bf16x3(f, alm, img, st);
+    pad_alm(f, alm, st);
+    launch_synth_fwd_bf16x3(f, f->scr.apad, img, st);
     return;
   }
   const vis_basis* b = f->basis;
@@ -196,10 +260,11 @@ void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStrea
   const int nsplit = f->fsplit;
   const int kps = static_cast<int>(round_up(ceil_div(f->n_modes, nsplit), 32));
   dim3 grid(f->nv_pad / 64, ceil_div(f->n_freq, 64), nsplit);
+  pad_alm(f, alm, st);
   {
     ProfScope ps(&f->prof, "k_synth_fwd_f32", st);
-    k_synth_fwd_f32<<<grid, 256, 0, st>>>(f->n_freq, f->n_modes, f->nv_pad, b->kpad, kps, alm,
-                                           b->y32, f->tab.vpix, f->scr.a_part);
+    k_synth_fwd_f32<<<grid, 256, 0, st>>>(f->n_freq, f->n_modes, f->nv_pad, b->kpad, kps,
+                                           f->scr.apad, b->y32, f->tab.vpix, f->scr.a_part);
     check_launch("k_synth_fwd_f32");
   }
   const long n = static_cast<long>(f->n_freq) * f->nv_pad;

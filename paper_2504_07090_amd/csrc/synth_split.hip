@@ -45,7 +45,7 @@ __device__ __forceinline__ bf8 ld8(const unsigned short* p) {
 
 // img[f][k] = sum_{c < nm} alm[f][c] Y[vpix[k]][c]; tile 64 (f) x 64 (k), K step 32.
 __global__ void __launch_bounds__(256)
-k_synth_fwd_bf16x3(int nf, int nm, int nvp, int kpad, const float* __restrict__ alm,
+k_synth_fwd_bf16x3(int nf, int nm, int nvp, int kpad, const float* __restrict__ apad,
                    const unsigned short* __restrict__ Yh, const unsigned short* __restrict__ Yl,
                    const int* __restrict__ vpix, float* __restrict__ img) {
   __shared__ __attribute__((aligned(16))) unsigned short Ah[2][64 * kBP], Al[2][64 * kBP];
@@ -55,7 +55,7 @@ k_synth_fwd_bf16x3(int nf, int nm, int nvp, int kpad, const float* __restrict__ 
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = tid >> 2, lk = (tid & 3) * 8;
   const int arow = m0 + lr;
-  const float* ap = alm + static_cast<size_t>(arow) * nm;
+  const float* ap = apad + static_cast<size_t>(arow) * kpad;   // zero-padded rows
   const size_t yoff = static_cast<size_t>(vpix[n0 + lr]) * kpad;
   f4 acc[2][2];
 #pragma unroll
@@ -66,10 +66,12 @@ k_synth_fwd_bf16x3(int nf, int nm, int nvp, int kpad, const float* __restrict__ 
   us8 rbh, rbl;
   const int ksteps = (nm + 31) / 32;
   auto gload = [&](int k0) {
+    const f4 u = *reinterpret_cast<const f4*>(ap + k0 + lk);
+    const f4 v = *reinterpret_cast<const f4*>(ap + k0 + lk + 4);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int c = k0 + lk + q;
-      ra[q] = (arow < nf && c < nm) ? ap[c] : 0.f;
+    for (int q = 0; q < 4; ++q) {
+      ra[q] = u[q];
+      ra[4 + q] = v[q];
     }
     rbh = *reinterpret_cast<const us8*>(Yh + yoff + k0 + lk);
     rbl = *reinterpret_cast<const us8*>(Yl + yoff + k0 + lk);
@@ -222,13 +224,13 @@ k_synth_adj_bf16x3(int nf, int nvp, int kpad, int kps, const float* __restrict__
       }
 }
 
-void launch_synth_fwd_bf16x3(const vis_field* f, const float* alm, float* img, hipStream_t st) {
+void launch_synth_fwd_bf16x3(const vis_field* f, const float* apad, float* img, hipStream_t st) {
   const vis_basis* b = f->basis;
   BV_REQUIRE(b->ybh != nullptr, VIS_EINVAL, "basis has no bf16 split storage");
   dim3 grid(f->nv_pad / 64, ceil_div(f->n_freq, 64));
   ProfScope ps(&f->prof, "k_synth_fwd_bf16x3", st);
   k_synth_fwd_bf16x3<<<grid, 256, 0, st>>>(
-      f->n_freq, f->n_modes, f->nv_pad, b->kpad, alm, reinterpret_cast<const unsigned short*>(b->ybh),
+      f->n_freq, f->n_modes, f->nv_pad, b->kpad, apad, reinterpret_cast<const unsigned short*>(b->ybh),
       reinterpret_cast<const unsigned short*>(b->ybl), f->tab.vpix, img);
   check_launch("k_synth_fwd_bf16x3");
 }

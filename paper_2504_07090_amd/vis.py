@@ -127,12 +127,15 @@ class Basis:
         _check(_lib.vis_basis_create(C.byref(self.desc), _ptr(self.workspace), nbytes.value,
                                      C.c_void_p(_stream()), C.byref(h)), "vis_basis_create")
         self.handle = h
+        self._lib = _lib
         self.grid_nz, self.grid_nphi, self.lmax, self.storage = grid_nz, grid_nphi, lmax, storage
 
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h:
-            _lib.vis_basis_destroy(h)
+        # the library is held by the instance: module globals may already be
+        # cleared when this runs at interpreter exit
+        h, lib = getattr(self, "handle", None), getattr(self, "_lib", None)
+        if h and lib is not None:
+            lib.vis_basis_destroy(h)
             self.handle = None
 
 
@@ -169,6 +172,7 @@ class Field:
         _check(_lib.vis_field_create(basis.handle, C.byref(d), _ptr(self.workspace), nbytes.value,
                                      C.c_void_p(_stream()), C.byref(h)), "vis_field_create")
         self.handle = h
+        self._lib = _lib
         info = FieldInfo()
         _check(_lib.vis_field_get_info(h, C.byref(info)), "vis_field_get_info")
         self.info = info
@@ -189,9 +193,9 @@ class Field:
         return float(self.info.fwd_macs)
 
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h:
-            _lib.vis_field_destroy(h)
+        h, lib = getattr(self, "handle", None), getattr(self, "_lib", None)
+        if h and lib is not None:
+            lib.vis_field_destroy(h)
             self.handle = None
 
     # -- argument checks -----------------------------------------------------
