@@ -376,11 +376,12 @@ static void fill_shape(vis_field* f, const vis_basis* basis, const vis_field_des
   f->fwd_macs = g.vis_pix_time * f->n_ubl * d->n_freq;
   f->asplit = choose_asplit(d->n_freq, basis->kpad, g.nv_pad);
   {
-    // forward synthesis: as many mode splits as fill one round of resident
-    // blocks (4 per CU on 256 CUs) without starting a partial second round
+    // forward synthesis: split the modes until the grid holds ~3072 blocks
+    // (about four rounds of the 3 resident 52-KB-LDS blocks per CU), so the
+    // last partial round is short, keeping at least 512 modes per split
     const int tiles = ceil_div(d->n_freq, 64) * (g.nv_pad / 64);
     const int nm = (d->lmax + 1) * (d->lmax + 1);
-    f->fsplit = std::max(1, std::min(1024 / std::max(1, tiles), std::max(1, nm / 512)));
+    f->fsplit = std::max(1, std::min(ceil_div(3072, std::max(1, tiles)), std::max(1, nm / 512)));
   }
   // tuning overrides (split-K factors of the two synthesis GEMMs)
   if (const char* e = getenv("BV_FSPLIT")) f->fsplit = std::max(1, std::min(64, atoi(e)));

@@ -140,8 +140,11 @@ __device__ __forceinline__ void write_powers(float* As, float* Bs, int px, float
 // into registers, then the 16 MFMAs of chunk k are interleaved with the
 // vector-ALU generation of chunk k+1's powers (written to LDS), so the matrix
 // and vector pipes work at the same time; geometry is loaded two chunks ahead.
+// Four resident waves per SIMD (<= 128 VGPRs) for extents up to 8, so a
+// 61-dish field's 64 x 60 (nu, t) waves are all resident at once instead of
+// leaving a second, mostly idle round of waves.
 template <int D>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(D <= 8 ? 4 : 2)))
 k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
              const double* __restrict__ freq, const double* __restrict__ P1,
              const double* __restrict__ P2, const float* __restrict__ TH2,

@@ -22,6 +22,10 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
+// Dynamic LDS up to which the per-baseline cotangents are kept on chip
+// (61 dishes: 1830 baselines, 15 KB; 127 dishes: 8001 baselines, 64 KB).
+constexpr size_t kGainsCacheLds = 64 * 1024;
+
 struct GainArgs {
   int mode, nt, nf, nbl, nubl, nant;
   float inv_sig2;
@@ -42,12 +46,37 @@ struct GainArgs {
   int dr, dtile, rt, gstride;
 };
 
+// Sum of v over groups of `width` consecutive lanes (width a power of two
+// dividing 64), in a fixed butterfly order; every lane of a group gets the sum.
+__device__ __forceinline__ float2 group_sum(float2 v, int width) {
+  for (int o = 1; o < width; o <<= 1) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  return v;
+}
+
+// Largest power of two <= 256 / n, at most 16: threads that share one list.
+__host__ __device__ inline int lanes_per_item(int n) {
+  int w = 1;
+  while (w < 16 && 2 * w * n <= 256) w <<= 1;
+  return w;
+}
+
+// One block per (nu, t).  Pass 1 walks the physical baselines in order (the
+// data reads are coalesced), forming the model, the chi^2 terms and the
+// cotangent of every baseline; with CACHE the cotangents stay in LDS for the
+// two gathers that follow (per unique baseline and per antenna), otherwise
+// those gathers recompute them.  The gathers give each list `w` lanes that
+// combine their partial sums with a fixed butterfly.
+template <bool CACHE>
 __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
   extern __shared__ float2 sm[];
   float2* g = sm;              // [nant]
   float2* v = sm + a.nant;     // [nubl]
   float2* om = v + a.nubl;     // [nubl] collapsed coefficients omega_u
-  __shared__ double red[256];
+  float2* cs = om + a.nubl;    // [nbl] cotangents (CACHE only)
+  __shared__ double red[4];
   const int f = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
   const size_t slice = static_cast<size_t>(t) * a.nf + f;
   for (int i = tid; i < a.nant; i += 256) g[i] = a.gains[static_cast<size_t>(f) * a.nant + i];
@@ -62,59 +91,75 @@ __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
     const int2 ij = a.bl_ant[k];
     return cmul(g[ij.x], conjf2(g[ij.y]));
   };
-  // cotangent of baseline k
-  auto cot = [&](int k) {
+  auto cot_of = [&](int k, float2 m) {
     if (a.mode == kGainAdj) return din[k];
-    const float2 m = cmul(gprod(k), vis_of(k));
-    const float2 r = make_float2(din[k].x - m.x, din[k].y - m.y);
-    return make_float2(-2.f * a.inv_sig2 * r.x, -2.f * a.inv_sig2 * r.y);
+    return make_float2(-2.f * a.inv_sig2 * (din[k].x - m.x), -2.f * a.inv_sig2 * (din[k].y - m.y));
   };
   if (a.mode == kGainFwd) {
     float2* out = a.vis_out + slice * a.nbl;
     for (int k = tid; k < a.nbl; k += 256) out[k] = cmul(gprod(k), vis_of(k));
     return;
   }
-  if (a.mode == kGainChi2) {
-    double acc = 0.0;
-    for (int k = tid; k < a.nbl; k += 256) {
-      const float2 m = cmul(gprod(k), vis_of(k));
+  double acc = 0.0;
+  for (int k = tid; k < a.nbl; k += 256) {
+    const float2 m = cmul(gprod(k), vis_of(k));
+    if (a.mode == kGainChi2) {
       const double rx = static_cast<double>(din[k].x) - m.x;
       const double ry = static_cast<double>(din[k].y) - m.y;
       acc += rx * rx + ry * ry;
     }
-    red[tid] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o) red[tid] += red[tid + o];
-      __syncthreads();
-    }
-    if (tid == 0) a.chi_part[slice] = red[0] * static_cast<double>(a.inv_sig2);
+    if (CACHE) cs[k] = cot_of(k, m);
   }
-  for (int u = tid; u < a.nubl; u += 256) {
-    float2 o = make_float2(0.f, 0.f);
-    for (int e = a.u_off[u]; e < a.u_off[u + 1]; ++e) {
-      const int code = a.u_list[e];
-      const int k = code >> 1;
-      const float2 c = cot(k), G = gprod(k);
-      const float2 term = (code & 1) ? cmul(c, conjf2(G)) : cmul(conjf2(c), G);
-      o.x += term.x;
-      o.y += term.y;
-    }
-    om[u] = o;
+  if (a.mode == kGainChi2) {
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
   }
-  for (int ant = tid; ant < a.nant; ant += 256) {
-    float2 s = make_float2(0.f, 0.f);
-    for (int e = a.a_off[ant]; e < a.a_off[ant + 1]; ++e) {
-      const int code = a.a_list[e];
-      const int k = code >> 1;
-      const int2 ij = a.bl_ant[k];
-      const float2 c = cot(k), vk = vis_of(k);
-      const float2 term = (code & 1) ? cmul(cmul(conjf2(c), g[ij.x]), vk)
-                                     : cmul(cmul(c, g[ij.y]), conjf2(vk));
-      s.x += term.x;
-      s.y += term.y;
+  __syncthreads();
+  if (a.mode == kGainChi2 && tid == 0)
+    a.chi_part[slice] = ((red[0] + red[1]) + (red[2] + red[3])) * static_cast<double>(a.inv_sig2);
+  auto cot = [&](int k) {
+    if (CACHE) return cs[k];
+    return cot_of(k, cmul(gprod(k), vis_of(k)));
+  };
+  {
+    const int w = lanes_per_item(a.nubl), sub = tid & (w - 1);
+    for (int base = 0; base < a.nubl; base += 256 / w) {
+      const int u = base + tid / w;
+      float2 o = make_float2(0.f, 0.f);
+      if (u < a.nubl) {
+        for (int e = a.u_off[u] + sub; e < a.u_off[u + 1]; e += w) {
+          const int code = a.u_list[e];
+          const int k = code >> 1;
+          const float2 c = cot(k), G = gprod(k);
+          const float2 term = (code & 1) ? cmul(c, conjf2(G)) : cmul(conjf2(c), G);
+          o.x += term.x;
+          o.y += term.y;
+        }
+      }
+      o = group_sum(o, w);
+      if (u < a.nubl && sub == 0) om[u] = o;
     }
-    a.g_part[slice * a.nant + ant] = s;
+  }
+  {
+    const int w = lanes_per_item(a.nant), sub = tid & (w - 1);
+    for (int base = 0; base < a.nant; base += 256 / w) {
+      const int ant = base + tid / w;
+      float2 s = make_float2(0.f, 0.f);
+      if (ant < a.nant) {
+        for (int e = a.a_off[ant] + sub; e < a.a_off[ant + 1]; e += w) {
+          const int code = a.a_list[e];
+          const int k = code >> 1;
+          const int2 ij = a.bl_ant[k];
+          const float2 c = cot(k), vk = vis_of(k);
+          const float2 term = (code & 1) ? cmul(cmul(conjf2(c), g[ij.x]), vk)
+                                         : cmul(cmul(c, g[ij.y]), conjf2(vk));
+          s.x += term.x;
+          s.y += term.y;
+        }
+      }
+      s = group_sum(s, w);
+      if (ant < a.nant && sub == 0) a.g_part[slice * a.nant + ant] = s;
+    }
   }
   __syncthreads();
   // Adjoint coefficients.  Entry ((i * rt + kt) * 64 + l) * 4 + s holds
@@ -155,15 +200,39 @@ __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
   }
 }
 
+// Sum of x[0..n) by one 1024-thread block in a fixed order: four independent
+// strided partial sums per thread, then a butterfly per wave and the 16 wave
+// totals in index order.  Valid in thread 0.
+template <class T>
+__device__ double block_sum(const T* __restrict__ x, int n, double* red) {
+  const int tid = threadIdx.x;
+  double p[4] = {0.0, 0.0, 0.0, 0.0};
+  int i = tid;
+  for (; i + 3 * 1024 < n; i += 4 * 1024) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] += static_cast<double>(x[i + q * 1024]);
+  }
+  for (int q = 0; i < n; i += 1024, ++q) p[q & 3] += static_cast<double>(x[i]);
+  double acc = (p[0] + p[1]) + (p[2] + p[3]);
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  double tot = 0.0;
+  if (tid == 0)
+    for (int w = 0; w < 16; ++w) tot += red[w];
+  return tot;
+}
+
 // grad_gains[f][a] = sum_t g_part[t][f][a]; block (nblk-1) also totals chi^2
 // and dL/dF in FP64.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_reduce_grads(int nt, int nf, int nant, int nfpart, int with_chi2, const double* __restrict__ chi_part,
                double* chi2, const float2* __restrict__ g_part, float2* grad_gains,
                const float* __restrict__ f_part, float* grad_fwhm) {
   const int tid = threadIdx.x;
   if (blockIdx.x + 1 < gridDim.x) {
-    const int idx = blockIdx.x * 256 + tid;
+    const int idx = blockIdx.x * 1024 + tid;
     if (idx >= nf * nant || grad_gains == nullptr) return;
     float2 s = make_float2(0.f, 0.f);
     for (int t = 0; t < nt; ++t) {
@@ -174,29 +243,14 @@ k_reduce_grads(int nt, int nf, int nant, int nfpart, int with_chi2, const double
     grad_gains[idx] = s;
     return;
   }
-  __shared__ double red[256];
+  __shared__ double red[16];
   if (with_chi2) {
-    double acc = 0.0;
-    for (int i = tid; i < nt * nf; i += 256) acc += chi_part[i];
-    red[tid] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o) red[tid] += red[tid + o];
-      __syncthreads();
-    }
-    if (tid == 0) *chi2 = red[0];
-    __syncthreads();
+    const double tot = block_sum(chi_part, nt * nf, red);
+    if (tid == 0) *chi2 = tot;
   }
   if (grad_fwhm != nullptr) {
-    double acc = 0.0;
-    for (int i = tid; i < nfpart; i += 256) acc += f_part[i];
-    red[tid] = acc;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o) red[tid] += red[tid + o];
-      __syncthreads();
-    }
-    if (tid == 0) *grad_fwhm = static_cast<float>(red[0]);
+    const double tot = block_sum(f_part, nfpart, red);
+    if (tid == 0) *grad_fwhm = static_cast<float>(tot);
   }
 }
 
@@ -231,18 +285,22 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
   a.gstride = f->gstride;
   const size_t lds = sizeof(float2) * (f->n_ant + 2 * f->n_ubl);
   BV_REQUIRE(lds <= 48 * 1024, VIS_EINVAL, "field too large for the gains pass LDS budget");
+  const size_t lds_cached = lds + sizeof(float2) * f->n_bl;
   dim3 grid(f->n_freq, f->n_time);
   ProfScope ps(&f->prof, "k_gains", st);
-  k_gains<<<grid, 256, lds, st>>>(a);
+  if (mode != kGainFwd && lds_cached <= kGainsCacheLds)
+    k_gains<true><<<grid, 256, lds_cached, st>>>(a);
+  else
+    k_gains<false><<<grid, 256, lds, st>>>(a);
   check_launch("k_gains");
 }
 
 void launch_reduce_grads(const vis_field* f, bool with_chi2, const double* chi_part, double* chi2,
                          const float2* g_part, float2* grad_gains, const float* f_part,
                          float* grad_fwhm, hipStream_t st) {
-  const int nblk = ceil_div(static_cast<long>(f->n_freq) * f->n_ant, 256) + 1;
+  const int nblk = (grad_gains != nullptr ? ceil_div(static_cast<long>(f->n_freq) * f->n_ant, 1024) : 0) + 1;
   ProfScope ps(&f->prof, "k_reduce_grads", st);
-  k_reduce_grads<<<nblk, 256, 0, st>>>(f->n_time, f->n_freq, f->n_ant, f->n_freq * f->n_chunks,
+  k_reduce_grads<<<nblk, 1024, 0, st>>>(f->n_time, f->n_freq, f->n_ant, f->n_freq * f->n_chunks,
                                        with_chi2 ? 1 : 0, chi_part, chi2, g_part, grad_gains,
                                        f_part, grad_fwhm);
   check_launch("k_reduce_grads");

@@ -173,15 +173,15 @@ def test_admission_by_footprint_and_release(mods):
     srv.release(ids[1])          # released while its work may be in flight
     lay, data, sig, q0, minv, cvar = ins[2]
     third = None
+    got = set()   # results that arrive while waiting for room count too
     for _ in range(200):
         third = srv.admit(flds[2], data, sig, q0, minv, cvar, 0.05, 0.1, 2, seed=1, stream_id=2)
         if third is not None:
             break
-        srv.poll(16, timeout_ms=20)
+        got |= {(r["chain"], r["trajectory"]) for r in srv.poll(16, timeout_ms=20)}
     assert third is not None
     srv.submit(third, 1)
     need = {(ids[0], 0), (ids[0], 1), (third, 0)}
-    got = set()
     for _ in range(600):
         got |= {(r["chain"], r["trajectory"]) for r in srv.poll(64, timeout_ms=100)}
         if need <= got:
