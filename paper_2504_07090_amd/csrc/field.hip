@@ -326,6 +326,7 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
   T.tchunk = cv.take<int>(std::max(1, n_tchunk));
   T.bl_ant = cv.take<int2>(f->n_bl);
   T.bl_u = cv.take<int>(f->n_bl);
+  T.bl_pos = cv.take<int4>(f->n_bl);
   T.u_off = cv.take<int>(f->n_ubl + 1);
   T.u_list = cv.take<int>(f->n_bl);
   T.a_off = cv.take<int>(f->n_ant + 1);
@@ -368,6 +369,12 @@ static void fill_shape(vis_field* f, const vis_basis* basis, const vis_field_des
   f->n_chunks = g.nv_pad / kChunk;
   f->n_tchunk = static_cast<int>(g.tchunk.size());
   f->extent = g.extent;
+  {
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+      f->n_cu = ncu;
+  }
   f->dtile = fringe_tile_extent(g.extent);
   f->gstride = adj_coef_stride(f->dtile);
   f->precision = d->precision;
@@ -492,12 +499,16 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
       bl_ant[k] = make_int2(g.bl_i[k], g.bl_j[k]);
       bl_u[k] = g.bl_sign[k] > 0 ? g.bl_u[k] : ~g.bl_u[k];
     }
+    std::vector<int4> bl_pos(f->n_bl, make_int4(0, 0, 0, 0));
     std::vector<int> u_off(f->n_ubl + 1, 0), u_list(f->n_bl);
     for (int k = 0; k < f->n_bl; ++k) u_off[g.bl_u[k] + 1]++;
     for (int u = 0; u < f->n_ubl; ++u) u_off[u + 1] += u_off[u];
     {
       std::vector<int> fill(u_off.begin(), u_off.end() - 1);
-      for (int k = 0; k < f->n_bl; ++k) u_list[fill[g.bl_u[k]]++] = (k << 1) | (g.bl_sign[k] < 0);
+      for (int k = 0; k < f->n_bl; ++k) {
+        bl_pos[k].x = fill[g.bl_u[k]];
+        u_list[fill[g.bl_u[k]]++] = (k << 1) | (g.bl_sign[k] < 0);
+      }
     }
     std::vector<int> a_off(f->n_ant + 1, 0), a_list(2 * static_cast<size_t>(f->n_bl));
     for (int k = 0; k < f->n_bl; ++k) { a_off[g.bl_i[k] + 1]++; a_off[g.bl_j[k] + 1]++; }
@@ -505,7 +516,9 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
     {
       std::vector<int> fill(a_off.begin(), a_off.end() - 1);
       for (int k = 0; k < f->n_bl; ++k) {
+        bl_pos[k].y = fill[g.bl_i[k]];
         a_list[fill[g.bl_i[k]]++] = (k << 1) | 0;
+        bl_pos[k].z = fill[g.bl_j[k]];
         a_list[fill[g.bl_j[k]]++] = (k << 1) | 1;
       }
     }
@@ -527,6 +540,7 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
     up(T.tchunk, g.tchunk, s);
     up(T.bl_ant, bl_ant, s);
     up(T.bl_u, bl_u, s);
+    up(T.bl_pos, bl_pos, s);
     up(T.u_off, u_off, s);
     up(T.u_list, u_list, s);
     up(T.a_off, a_off, s);

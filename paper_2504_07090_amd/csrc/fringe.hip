@@ -163,11 +163,16 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
   const float sig = static_cast<float>(fwhm[0] * (beam_ref / nu) * kFwhmToSigma);
   const float kb = 1.0f / (2.0f * sig * sig * static_cast<float>(kLn2));
 
-  f4 acc[RT][RT];
+  // NACC independent accumulator sets (consecutive MFMAs of a chunk go to
+  // different sets); one set measured fastest at 61 dishes
+  constexpr int NACC = 1;
+  f4 acc[NACC][RT][RT];
 #pragma unroll
-  for (int i = 0; i < RT; ++i)
+  for (int h = 0; h < NACC; ++h)
 #pragma unroll
-    for (int j = 0; j < RT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < RT; ++j) acc[h][i][j] = f4{0.f, 0.f, 0.f, 0.f};
   // per-lane partial sums of alpha^n S and beta^m S (the axis baselines)
   float axr[D], axi[D], bxr[D], bxi[D];
 #pragma unroll
@@ -226,7 +231,8 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
 #pragma unroll
         for (int i = 0; i < RT; ++i)
 #pragma unroll
-          for (int j = 0; j < RT; ++j) acc[i][j] = mfma4(a[q][i], b[q][j], acc[i][j]);
+          for (int j = 0; j < RT; ++j)
+            acc[q % NACC][i][j] = mfma4(a[q][i], b[q][j], acc[q % NACC][i][j]);
       generate(gn, ci + 1 < cend ? 1.0f : 0.0f);
 #pragma unroll
       for (int q = 0; q < 16 * RT * RT; ++q) {
@@ -257,7 +263,12 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
 #pragma unroll
     for (int j = 0; j < RT; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) P[(16 * i + 4 * (lane >> 4) + r) * W + 16 * j + (lane & 15)] = acc[i][j][r];
+      for (int r = 0; r < 4; ++r) {
+        float sum = acc[0][i][j][r];
+#pragma unroll
+        for (int h = 1; h < NACC; ++h) sum += acc[h][i][j][r];
+        P[(16 * i + 4 * (lane >> 4) + r) * W + 16 * j + (lane & 15)] = sum;
+      }
   float* AX = Bs;  // [D][4]: axr, axi, bxr, bxi
   if (lane == 0) {
 #pragma unroll
@@ -351,26 +362,33 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
                          zax += ax[0] * ar - ax[1] * ai + ax[2] * br - ax[3] * bi;
                        });
     wave_sync();
+    // T = G Bb for the four 16-pixel groups: the four MFMA chains are
+    // interleaved (pixel group innermost) so consecutive MFMAs are independent
     float zcore = 0.f;
 #pragma unroll
-    for (int pg = 0; pg < 4; ++pg) {
-      const int px = 16 * pg + (lane & 15);
-      float zp = 0.f;
+    for (int i = 0; i < RT; ++i) {
+      f4 tacc[4];
 #pragma unroll
-      for (int i = 0; i < RT; ++i) {
-        f4 tacc = f4{0.f, 0.f, 0.f, 0.f};
+      for (int pg = 0; pg < 4; ++pg) tacc[pg] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < RT; ++kt)
+      for (int kt = 0; kt < RT; ++kt)
 #pragma unroll
-          for (int s = 0; s < 4; ++s)
-            tacc = mfma4(gv[i][kt][s], Bs[lds_at<W>(px, 16 * kt + 4 * s + (lane >> 4))], tacc);
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int pg = 0; pg < 4; ++pg)
+            tacc[pg] = mfma4(gv[i][kt][s], Bs[lds_at<W>(16 * pg + (lane & 15), 16 * kt + 4 * s + (lane >> 4))],
+                             tacc[pg]);
+#pragma unroll
+      for (int pg = 0; pg < 4; ++pg) {
+        const int px = 16 * pg + (lane & 15);
         const f4 av = *reinterpret_cast<const f4*>(As + lds_at<W>(px, 16 * i + 4 * (lane >> 4)));
+        float zp = 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) zp += av[r] * tacc[r];
+        for (int r = 0; r < 4; ++r) zp += av[r] * tacc[pg][r];
+        zp += __shfl_xor(zp, 16);
+        zp += __shfl_xor(zp, 32);
+        if ((lane >> 4) == pg) zcore += zp;
       }
-      zp += __shfl_xor(zp, 16);
-      zp += __shfl_xor(zp, 32);
-      if ((lane >> 4) == pg) zcore = zp;
     }
     wave_sync();
     const float z = zcore + zax;

@@ -22,15 +22,16 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
-// Dynamic LDS up to which the per-baseline cotangents are kept on chip
-// (61 dishes: 1830 baselines, 15 KB; 127 dishes: 8001 baselines, 64 KB).
-constexpr size_t kGainsCacheLds = 64 * 1024;
+// Dynamic LDS up to which the per-baseline terms are staged on chip (three
+// complex values per baseline: 61 dishes, 1830 baselines, 46 KB).
+constexpr size_t kGainsSortedLds = 64 * 1024;
 
 struct GainArgs {
   int mode, nt, nf, nbl, nubl, nant;
   float inv_sig2;
   const int2* bl_ant;
   const int* bl_u;
+  const int4* bl_pos;
   const int* u_off;
   const int* u_list;
   const int* a_off;
@@ -44,6 +45,7 @@ struct GainArgs {
   float2* g_part;
   const int* ulut;
   int dr, dtile, rt, gstride;
+  int tslab;   // consecutive times per block
 };
 
 // Sum of v over groups of `width` consecutive lanes (width a power of two
@@ -63,120 +65,24 @@ __host__ __device__ inline int lanes_per_item(int n) {
   return w;
 }
 
-// One block per (nu, t).  Pass 1 walks the physical baselines in order (the
-// data reads are coalesced), forming the model, the chi^2 terms and the
-// cotangent of every baseline; with CACHE the cotangents stay in LDS for the
-// two gathers that follow (per unique baseline and per antenna), otherwise
-// those gathers recompute them.  The gathers give each list `w` lanes that
-// combine their partial sums with a fixed butterfly.
-template <bool CACHE>
-__global__ void __launch_bounds__(256) k_gains(GainArgs a) {
-  extern __shared__ float2 sm[];
-  float2* g = sm;              // [nant]
-  float2* v = sm + a.nant;     // [nubl]
-  float2* om = v + a.nubl;     // [nubl] collapsed coefficients omega_u
-  float2* cs = om + a.nubl;    // [nbl] cotangents (CACHE only)
-  __shared__ double red[4];
-  const int f = blockIdx.x, t = blockIdx.y, tid = threadIdx.x;
-  const size_t slice = static_cast<size_t>(t) * a.nf + f;
-  for (int i = tid; i < a.nant; i += 256) g[i] = a.gains[static_cast<size_t>(f) * a.nant + i];
-  for (int u = tid; u < a.nubl; u += 256) v[u] = a.vu[slice * a.nubl + u];
-  __syncthreads();
-  const float2* din = a.din + slice * a.nbl;
-  auto vis_of = [&](int k) {
-    const int u = a.bl_u[k];
-    return u >= 0 ? v[u] : conjf2(v[~u]);
-  };
-  auto gprod = [&](int k) {
-    const int2 ij = a.bl_ant[k];
-    return cmul(g[ij.x], conjf2(g[ij.y]));
-  };
-  auto cot_of = [&](int k, float2 m) {
-    if (a.mode == kGainAdj) return din[k];
-    return make_float2(-2.f * a.inv_sig2 * (din[k].x - m.x), -2.f * a.inv_sig2 * (din[k].y - m.y));
-  };
-  if (a.mode == kGainFwd) {
-    float2* out = a.vis_out + slice * a.nbl;
-    for (int k = tid; k < a.nbl; k += 256) out[k] = cmul(gprod(k), vis_of(k));
-    return;
-  }
-  double acc = 0.0;
-  for (int k = tid; k < a.nbl; k += 256) {
-    const float2 m = cmul(gprod(k), vis_of(k));
-    if (a.mode == kGainChi2) {
-      const double rx = static_cast<double>(din[k].x) - m.x;
-      const double ry = static_cast<double>(din[k].y) - m.y;
-      acc += rx * rx + ry * ry;
-    }
-    if (CACHE) cs[k] = cot_of(k, m);
-  }
-  if (a.mode == kGainChi2) {
-    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-    if ((tid & 63) == 0) red[tid >> 6] = acc;
-  }
-  __syncthreads();
-  if (a.mode == kGainChi2 && tid == 0)
-    a.chi_part[slice] = ((red[0] + red[1]) + (red[2] + red[3])) * static_cast<double>(a.inv_sig2);
-  auto cot = [&](int k) {
-    if (CACHE) return cs[k];
-    return cot_of(k, cmul(gprod(k), vis_of(k)));
-  };
-  {
-    const int w = lanes_per_item(a.nubl), sub = tid & (w - 1);
-    for (int base = 0; base < a.nubl; base += 256 / w) {
-      const int u = base + tid / w;
-      float2 o = make_float2(0.f, 0.f);
-      if (u < a.nubl) {
-        for (int e = a.u_off[u] + sub; e < a.u_off[u + 1]; e += w) {
-          const int code = a.u_list[e];
-          const int k = code >> 1;
-          const float2 c = cot(k), G = gprod(k);
-          const float2 term = (code & 1) ? cmul(c, conjf2(G)) : cmul(conjf2(c), G);
-          o.x += term.x;
-          o.y += term.y;
-        }
-      }
-      o = group_sum(o, w);
-      if (u < a.nubl && sub == 0) om[u] = o;
-    }
-  }
-  {
-    const int w = lanes_per_item(a.nant), sub = tid & (w - 1);
-    for (int base = 0; base < a.nant; base += 256 / w) {
-      const int ant = base + tid / w;
-      float2 s = make_float2(0.f, 0.f);
-      if (ant < a.nant) {
-        for (int e = a.a_off[ant] + sub; e < a.a_off[ant + 1]; e += w) {
-          const int code = a.a_list[e];
-          const int k = code >> 1;
-          const int2 ij = a.bl_ant[k];
-          const float2 c = cot(k), vk = vis_of(k);
-          const float2 term = (code & 1) ? cmul(cmul(conjf2(c), g[ij.x]), vk)
-                                         : cmul(cmul(c, g[ij.y]), conjf2(vk));
-          s.x += term.x;
-          s.y += term.y;
-        }
-      }
-      s = group_sum(s, w);
-      if (ant < a.nant && sub == 0) a.g_part[slice * a.nant + ant] = s;
-    }
-  }
-  __syncthreads();
-  // Adjoint coefficients.  Entry ((i * rt + kt) * 64 + l) * 4 + s holds
-  // G[r][c], r = 16 i + (l & 15), c = 16 kt + 4 s + (l >> 4), with
-  // r = 2 (n - 1) + (Re / Im of alpha^n), c = 2 (m - 1) + (Re / Im of beta^m):
-  //   G = w+r + w-r (Re Re), w-r - w+r (Im Im), w-i - w+i (Re Im), -w+i - w-i (Im Re),
-  // w+- = omega(n, +-m).  After rt*rt*256 entries follow, for n = 1..dtile,
-  // (omega(n, 0).re, omega(n, 0).im, omega(0, n).re, omega(0, n).im).
+// Adjoint coefficients of one (t, nu) slice from the collapsed omega in LDS.
+// Entry ((i * rt + kt) * 64 + l) * 4 + s holds G[r][c], r = 16 i + (l & 15),
+// c = 16 kt + 4 s + (l >> 4), with r = 2 (n - 1) + (Re / Im of alpha^n),
+// c = 2 (m - 1) + (Re / Im of beta^m):
+//   G = w+r + w-r (Re Re), w-r - w+r (Im Im), w-i - w+i (Re Im), -w+i - w-i (Im Re),
+// w+- = omega(n, +-m).  After rt*rt*256 entries follow, for n = 1..dtile,
+// (omega(n, 0).re, omega(n, 0).im, omega(0, n).re, omega(0, n).im).
+__device__ __forceinline__ void write_coefficients(const GainArgs& a, const float2* om,
+                                                   const int* ulut, size_t slice, int tid) {
   const int lw = 2 * a.dr + 1;
   auto omega = [&](int n1, int n2) {
     if (n1 > a.dr || n2 > a.dr || n2 < -a.dr) return make_float2(0.f, 0.f);
-    const int u = a.ulut[n1 * lw + n2 + a.dr];
+    const int u = ulut[n1 * lw + n2 + a.dr];
     return u >= 0 ? om[u] : make_float2(0.f, 0.f);
   };
   float* G = a.gco + slice * a.gstride;
   const int nmat = a.rt * a.rt * 256;
-  for (int e = tid; e < a.gstride; e += 256) {
+  for (int e = tid; e < a.gstride; e += blockDim.x) {
     float val = 0.f;
     if (e < nmat) {
       const int s4 = e & 3, l = (e >> 2) & 63, blk = e >> 8;
@@ -197,6 +103,198 @@ __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
       val = (comp & 1) ? w0.y : w0.x;
     }
     G[e] = val;
+  }
+}
+
+// Gains pass over (t, nu) slices.  Pass 1 walks the physical baselines in
+// order (the data reads are coalesced), forming the model, the chi^2 terms and
+// the cotangent of every baseline.
+//
+// SORTED (fields of up to kGainsMaxPerThread * 256 baselines whose staging
+// fits in LDS): a block handles `tslab` consecutive times of one channel and
+// keeps its baselines' table entries in registers across them.  Pass 1 also
+// forms each baseline's contribution to its unique baseline's omega and to its
+// two antennas' gradients and stores them in LDS at the baseline's positions
+// in the per-unique and per-antenna lists, so the sums that follow run over
+// contiguous LDS ranges.  Otherwise (one slice per block) the sums walk the
+// lists and recompute the terms.  Each list gets `w` lanes that combine their
+// partial sums with a fixed butterfly, so every result has a fixed order.
+constexpr int kGainsMaxPerThread = 8;
+
+template <bool SORTED>
+__global__ void __launch_bounds__(256) k_gains(GainArgs a) {
+  extern __shared__ float2 sm[];
+  float2* g = sm;              // [nant]
+  float2* v = sm + a.nant;     // [nubl]
+  float2* om = v + a.nubl;     // [nubl] collapsed coefficients omega_u
+  float2* tu = om + a.nubl;    // [nbl] omega terms in u_list order (SORTED)
+  float2* ta = tu + a.nbl;     // [2 nbl] antenna terms in a_list order (SORTED)
+  int* ulut = reinterpret_cast<int*>(ta + 2 * a.nbl);   // SORTED: LDS copy of the lookup
+  __shared__ double red[4];
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const int t0 = blockIdx.y * a.tslab, t1 = min(a.nt, t0 + a.tslab);
+  const int nlut = (a.dr + 1) * (2 * a.dr + 1);
+  for (int i = tid; i < a.nant; i += 256) g[i] = a.gains[static_cast<size_t>(f) * a.nant + i];
+  if (SORTED)
+    for (int i = tid; i < nlut; i += 256) ulut[i] = a.ulut[i];
+  int2 ij_r[SORTED ? kGainsMaxPerThread : 1];
+  int uc_r[SORTED ? kGainsMaxPerThread : 1];
+  int4 pos_r[SORTED ? kGainsMaxPerThread : 1];
+  if (SORTED) {
+#pragma unroll
+    for (int q = 0; q < kGainsMaxPerThread; ++q) {
+      const int k = tid + 256 * q;
+      if (k < a.nbl) {
+        ij_r[q] = a.bl_ant[k];
+        uc_r[q] = a.bl_u[k];
+        pos_r[q] = a.bl_pos[k];
+      }
+    }
+  }
+  auto omega_term = [&](bool neg, float2 c, float2 G) {
+    return neg ? cmul(c, conjf2(G)) : cmul(conjf2(c), G);
+  };
+  auto ant_term = [&](int role, int2 ij, float2 c, float2 vk) {
+    return role ? cmul(cmul(conjf2(c), g[ij.x]), vk) : cmul(cmul(c, g[ij.y]), conjf2(vk));
+  };
+  // SORTED: the next slice's data and unique visibilities are loaded into
+  // registers while the current one is processed
+  float2 d_r[SORTED ? kGainsMaxPerThread : 1], v_r = make_float2(0.f, 0.f);
+  auto fetch = [&](int t) {
+    const size_t sl = static_cast<size_t>(t) * a.nf + f;
+#pragma unroll
+    for (int q = 0; q < kGainsMaxPerThread; ++q) {
+      const int k = tid + 256 * q;
+      if (k < a.nbl) d_r[q] = a.din[sl * a.nbl + k];
+    }
+    if (tid < a.nubl) v_r = a.vu[sl * a.nubl + tid];
+  };
+  if (SORTED && t0 < t1) fetch(t0);
+  for (int t = t0; t < t1; ++t) {
+    const size_t slice = static_cast<size_t>(t) * a.nf + f;
+    __syncthreads();   // the previous slice is done with v, om, tu, ta
+    float2 dcur[SORTED ? kGainsMaxPerThread : 1];
+    if (SORTED) {
+      if (tid < a.nubl) v[tid] = v_r;
+#pragma unroll
+      for (int q = 0; q < kGainsMaxPerThread; ++q) dcur[q] = d_r[q];
+      __syncthreads();
+      if (t + 1 < t1) fetch(t + 1);
+    } else {
+      for (int u = tid; u < a.nubl; u += 256) v[u] = a.vu[slice * a.nubl + u];
+      __syncthreads();
+    }
+    const float2* din = a.din + slice * a.nbl;
+    auto vis_of = [&](int k) {
+      const int u = a.bl_u[k];
+      return u >= 0 ? v[u] : conjf2(v[~u]);
+    };
+    auto gprod = [&](int k) {
+      const int2 ij = a.bl_ant[k];
+      return cmul(g[ij.x], conjf2(g[ij.y]));
+    };
+    auto cot_of = [&](int k, float2 m) {
+      if (a.mode == kGainAdj) return din[k];
+      return make_float2(-2.f * a.inv_sig2 * (din[k].x - m.x), -2.f * a.inv_sig2 * (din[k].y - m.y));
+    };
+    if (a.mode == kGainFwd) {
+      float2* out = a.vis_out + slice * a.nbl;
+      for (int k = tid; k < a.nbl; k += 256) out[k] = cmul(gprod(k), vis_of(k));
+      continue;
+    }
+    double acc = 0.0;
+    auto chi_term = [&](int k, float2 m) {
+      if (a.mode == kGainChi2) {
+        const double rx = static_cast<double>(din[k].x) - m.x;
+        const double ry = static_cast<double>(din[k].y) - m.y;
+        acc += rx * rx + ry * ry;
+      }
+    };
+    if (SORTED) {
+#pragma unroll
+      for (int q = 0; q < kGainsMaxPerThread; ++q) {
+        const int k = tid + 256 * q;
+        if (k < a.nbl) {
+          const int2 ij = ij_r[q];
+          const int ucode = uc_r[q];
+          const float2 G = cmul(g[ij.x], conjf2(g[ij.y]));
+          const float2 vk = ucode >= 0 ? v[ucode] : conjf2(v[~ucode]);
+          const float2 m = cmul(G, vk);
+          const float2 dk = dcur[q];
+          if (a.mode == kGainChi2) {
+            const double rx = static_cast<double>(dk.x) - m.x;
+            const double ry = static_cast<double>(dk.y) - m.y;
+            acc += rx * rx + ry * ry;
+          }
+          const float2 c = a.mode == kGainAdj
+                               ? dk
+                               : make_float2(-2.f * a.inv_sig2 * (dk.x - m.x), -2.f * a.inv_sig2 * (dk.y - m.y));
+          tu[pos_r[q].x] = omega_term(ucode < 0, c, G);
+          ta[pos_r[q].y] = ant_term(0, ij, c, vk);
+          ta[pos_r[q].z] = ant_term(1, ij, c, vk);
+        }
+      }
+    } else if (a.mode == kGainChi2) {
+      for (int k = tid; k < a.nbl; k += 256) chi_term(k, cmul(gprod(k), vis_of(k)));
+    }
+    if (a.mode == kGainChi2) {
+      for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+      if ((tid & 63) == 0) red[tid >> 6] = acc;
+    }
+    __syncthreads();
+    if (a.mode == kGainChi2 && tid == 0)
+      a.chi_part[slice] = ((red[0] + red[1]) + (red[2] + red[3])) * static_cast<double>(a.inv_sig2);
+    {
+      const int w = lanes_per_item(a.nubl), sub = tid & (w - 1);
+      for (int base = 0; base < a.nubl; base += 256 / w) {
+        const int u = base + tid / w;
+        float2 o = make_float2(0.f, 0.f);
+        if (u < a.nubl) {
+          for (int e = a.u_off[u] + sub; e < a.u_off[u + 1]; e += w) {
+            float2 term;
+            if (SORTED) {
+              term = tu[e];
+            } else {
+              const int code = a.u_list[e];
+              const int k = code >> 1;
+              const float2 G = gprod(k);
+              term = omega_term(code & 1, cot_of(k, cmul(G, vis_of(k))), G);
+            }
+            o.x += term.x;
+            o.y += term.y;
+          }
+        }
+        o = group_sum(o, w);
+        if (u < a.nubl && sub == 0) om[u] = o;
+      }
+    }
+    {
+      const int w = lanes_per_item(a.nant), sub = tid & (w - 1);
+      for (int base = 0; base < a.nant; base += 256 / w) {
+        const int ant = base + tid / w;
+        float2 s = make_float2(0.f, 0.f);
+        if (ant < a.nant) {
+          for (int e = a.a_off[ant] + sub; e < a.a_off[ant + 1]; e += w) {
+            float2 term;
+            if (SORTED) {
+              term = ta[e];
+            } else {
+              const int code = a.a_list[e];
+              const int k = code >> 1;
+              const int2 ij = a.bl_ant[k];
+              const float2 vk = vis_of(k);
+              term = ant_term(code & 1, ij, cot_of(k, cmul(gprod(k), vk)), vk);
+            }
+            s.x += term.x;
+            s.y += term.y;
+          }
+        }
+        s = group_sum(s, w);
+        if (ant < a.nant && sub == 0) a.g_part[slice * a.nant + ant] = s;
+      }
+    }
+    __syncthreads();
+    write_coefficients(a, om, SORTED ? ulut : a.ulut, slice, tid);
   }
 }
 
@@ -267,6 +365,7 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
   a.inv_sig2 = sigma_n > 0.f ? 1.0f / (sigma_n * sigma_n) : 0.f;
   a.bl_ant = f->tab.bl_ant;
   a.bl_u = f->tab.bl_u;
+  a.bl_pos = f->tab.bl_pos;
   a.u_off = f->tab.u_off;
   a.u_list = f->tab.u_list;
   a.a_off = f->tab.a_off;
@@ -285,13 +384,21 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
   a.gstride = f->gstride;
   const size_t lds = sizeof(float2) * (f->n_ant + 2 * f->n_ubl);
   BV_REQUIRE(lds <= 48 * 1024, VIS_EINVAL, "field too large for the gains pass LDS budget");
-  const size_t lds_cached = lds + sizeof(float2) * f->n_bl;
-  dim3 grid(f->n_freq, f->n_time);
+  const size_t lds_sorted = lds + 3 * sizeof(float2) * f->n_bl +
+                            sizeof(int) * (f->extent + 1) * (2 * f->extent + 1);
   ProfScope ps(&f->prof, "k_gains", st);
-  if (mode != kGainFwd && lds_cached <= kGainsCacheLds)
-    k_gains<true><<<grid, 256, lds_cached, st>>>(a);
-  else
+  if (mode != kGainFwd && lds_sorted <= kGainsSortedLds && f->n_bl <= 256 * kGainsMaxPerThread &&
+      f->n_ubl <= 256) {
+    // enough times per block that the grid is about one round of resident blocks
+    const long slots = static_cast<long>(f->n_cu) * std::max<long>(1, (160 * 1024) / static_cast<long>(lds_sorted + 64));
+    a.tslab = std::max(1, std::min(f->n_time, ceil_div(static_cast<long>(f->n_time) * f->n_freq, slots)));
+    dim3 grid(f->n_freq, ceil_div(f->n_time, a.tslab));
+    k_gains<true><<<grid, 256, lds_sorted, st>>>(a);
+  } else {
+    a.tslab = 1;
+    dim3 grid(f->n_freq, f->n_time);
     k_gains<false><<<grid, 256, lds, st>>>(a);
+  }
   check_launch("k_gains");
 }
 

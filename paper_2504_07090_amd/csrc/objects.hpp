@@ -81,6 +81,8 @@ struct FieldTables {
   int* tchunk = nullptr;           // [sum] chunk indices
   int2* bl_ant = nullptr;          // [n_bl] (i, j)
   int* bl_u = nullptr;             // [n_bl] unique index, negative-encoded sign: u or ~u
+  int4* bl_pos = nullptr;          // [n_bl] position of baseline k in u_list, and of its
+                                   //   (k, role 0) and (k, role 1) entries in a_list
   int* u_off = nullptr;            // [n_ubl + 1] CSR unique -> physical
   int* u_list = nullptr;           // [n_bl] (bl << 1) | (sign < 0)
   int* a_off = nullptr;            // [n_ant + 1] CSR antenna -> baselines
@@ -97,6 +99,7 @@ struct vis_field {
   int n_modes = 0, lmax = 0;
   int nv = 0, nv_pad = 0, n_chunks = 0, n_tchunk = 0;
   int extent = 0;                  // D = max |n1|, |n2|
+  int n_cu = 256;                  // compute units of the field's device
   int dtile = 0;                   // compile-time extent of the fringe kernels (>= extent)
   int gstride = 0;                 // floats per (t, nu) of the adjoint coefficient table
   int precision = VIS_FP32;

@@ -151,6 +151,15 @@ def test_forward_hex_sides(vis, side):
     rga, rgg, rgf = model.adjoint(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), y)
     assert rel_norm(ga.cpu().numpy(), rga) <= 2e-5
     assert rel_norm(gg.cpu().numpy(), rgg) <= 2e-5
+    # chi^2 path (127 dishes take the gains pass that walks the baseline lists)
+    _, sig, data = model.make_data(of, d)
+    ddev = torch.tensor(np.ascontiguousarray(data), dtype=torch.complex64, device="cuda")
+    x2, ga, gg, gf = vis.chi2_and_grad(fld, ddev, sig, alm * 1.2, g, fw)
+    rx2, rga, rgg, rgf = model.chi2_and_grad(of, data, sig, d.alm * 1.2, d.gains, w.fwhm_ref_rad(cfg))
+    e = [rel_norm(ga.cpu().numpy(), rga), rel_norm(gg.cpu().numpy(), rgg),
+         abs(float(gf) - rgf) / abs(rgf), abs(float(x2) - rx2) / rx2]
+    say("hex side", side, "chi2 grad errs (a, g, F, chi2)", e)
+    assert max(e) <= 2e-4
 
 
 def test_lmax_prefix_of_larger_basis(vis):
