@@ -215,8 +215,8 @@ static void validate_field(const vis_basis* basis, const vis_field_desc* d) {
   BV_REQUIRE(std::isfinite(d->latitude_rad) && std::fabs(d->latitude_rad) <= kPi / 2, VIS_EINVAL,
              "latitude out of range");
   BV_REQUIRE(d->beam_ref_hz > 0.0, VIS_EINVAL, "beam_ref_hz must be positive");
-  BV_REQUIRE(d->precision == VIS_FP32 || d->precision == VIS_BF16X3, VIS_EINVAL,
-             "precision %d is not available (VIS_FP32 and VIS_BF16X3 are)", d->precision);
+  BV_REQUIRE(d->precision == VIS_FP32 || d->precision == VIS_BF16X3 || d->precision == VIS_FP16X3,
+             VIS_EINVAL, "precision %d is not one of VIS_FP32, VIS_BF16X3, VIS_FP16X3", d->precision);
   const uint32_t need = d->precision == VIS_FP32 ? 1u : d->precision == VIS_BF16X3 ? 2u : 4u;
   BV_REQUIRE((basis->storage & need) != 0, VIS_EINVAL,
              "the basis was created without the storage this precision needs");
@@ -338,6 +338,12 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
   S.img = cv.take<float>(nfq * nvp);
   S.apad = cv.take<float>(static_cast<size_t>(round_up(f->n_freq, 64)) * kpad);
   S.dimg = cv.take<float>(nfq * nvp);
+  if (f->precision != VIS_FP32) {
+    const size_t nfp = static_cast<size_t>(round_up(f->n_freq, 64));
+    S.dsplit = cv.take<float>(nfp * nvp);
+    S.rscale = cv.take<float>(nfp);
+    S.rmax = cv.take<float>(nfp * ceil_div(std::max<long>(kpad, nvp), 2048));
+  }
   S.vu = cv.take<float2>(nt * nfq * f->n_ubl);
   S.gco = cv.take<float>(nt * nfq * static_cast<size_t>(f->gstride));
   S.chi_part = cv.take<double>(nt * nfq);

@@ -60,6 +60,10 @@ struct FieldScratch {
   float* img = nullptr;            // [n_freq][nv_pad] sky at visible pixels
   float* apad = nullptr;           // [nf_pad][kpad] sky coefficients, zero-padded rows
   float* dimg = nullptr;           // [n_freq][nv_pad] dL/dI
+  float* dsplit = nullptr;         // split fields: [nf_pad][nv_pad] floats holding the
+                                   //   16-bit hi plane then the lo plane of dL/dI
+  float* rscale = nullptr;         // split fields: [nf_pad] inverse row scales
+  float* rmax = nullptr;           // split fields: [nf_pad][ceil(max(kpad, nv_pad) / 2048)]
   float2* vu = nullptr;            // [n_time][n_freq][n_ubl] gain-free unique visibilities
   float* gco = nullptr;            // [n_time][n_freq][gstride] adjoint coefficients, MFMA layout
   double* chi_part = nullptr;      // [n_time * n_freq]

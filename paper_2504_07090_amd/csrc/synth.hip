@@ -246,48 +246,49 @@ k_reduce_splits(int nsplit, int nf, int nm, int kpad, const float* __restrict__ 
   grad[idx] = s;
 }
 
-void launch_synth_fwd_bf16x3(const vis_field* f, const float* apad, float* img, hipStream_t st);
-void launch_synth_adj_bf16x3(const vis_field* f, const float* dimg, int kps, hipStream_t st);
+void launch_synth_fwd_split(const vis_field* f, const float* alm, float* dst, int nsplit, int kps,
+                            hipStream_t st);
+void launch_synth_adj_split(const vis_field* f, const float* dimg, int kps, hipStream_t st);
 
 void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStream_t st) {
-  if (f->precision == VIS_BF16X3) {
-    pad_alm(f, alm, st);
-    launch_synth_fwd_bf16x3(f, f->scr.apad, img, st);
-    return;
-  }
   const vis_basis* b = f->basis;
-  BV_REQUIRE(b->y32 != nullptr, VIS_EINVAL, "basis has no FP32 storage");
   const int nsplit = f->fsplit;
   const int kps = static_cast<int>(round_up(ceil_div(f->n_modes, nsplit), 32));
-  dim3 grid(f->nv_pad / 64, ceil_div(f->n_freq, 64), nsplit);
-  pad_alm(f, alm, st);
-  {
+  float* dst = nsplit > 1 ? f->scr.a_part : img;
+  if (f->precision == VIS_FP32) {
+    BV_REQUIRE(b->y32 != nullptr, VIS_EINVAL, "basis has no FP32 storage");
+    pad_alm(f, alm, st);
+    dim3 grid(f->nv_pad / 64, ceil_div(f->n_freq, 64), nsplit);
     ProfScope ps(&f->prof, "k_synth_fwd_f32", st);
     k_synth_fwd_f32<<<grid, 256, 0, st>>>(f->n_freq, f->n_modes, f->nv_pad, b->kpad, kps,
-                                           f->scr.apad, b->y32, f->tab.vpix, f->scr.a_part);
+                                           f->scr.apad, b->y32, f->tab.vpix, dst);
     check_launch("k_synth_fwd_f32");
+  } else {
+    launch_synth_fwd_split(f, alm, dst, nsplit, kps, st);
   }
-  const long n = static_cast<long>(f->n_freq) * f->nv_pad;
-  ProfScope ps(&f->prof, "k_sum_fwd_splits", st);
-  k_sum_fwd_splits<<<ceil_div(n, 256), 256, 0, st>>>(nsplit, n, f->scr.a_part, img);
-  check_launch("k_sum_fwd_splits");
+  if (nsplit > 1) {
+    const long n = static_cast<long>(f->n_freq) * f->nv_pad;
+    ProfScope ps(&f->prof, "k_sum_fwd_splits", st);
+    k_sum_fwd_splits<<<ceil_div(n, 256), 256, 0, st>>>(nsplit, n, f->scr.a_part, img);
+    check_launch("k_sum_fwd_splits");
+  }
 }
 
 void launch_synth_adj(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st) {
   const vis_basis* b = f->basis;
   const int nsplit = f->asplit;
-  if (f->precision == VIS_BF16X3) {
+  if (f->precision != VIS_FP32) {
     const int kps = static_cast<int>(round_up(ceil_div(f->nv_pad, nsplit), 32));
-    launch_synth_adj_bf16x3(f, dimg, kps, st);
+    launch_synth_adj_split(f, dimg, kps, st);
   } else {
-  BV_REQUIRE(b->y32 != nullptr, VIS_EINVAL, "basis has no FP32 storage");
-  const int kps = static_cast<int>(round_up(ceil_div(f->nv_pad, nsplit), 16));
-  const int ncol = static_cast<int>(round_up(f->n_modes, 64));
-  dim3 grid(ncol / 64, ceil_div(f->n_freq, 64), nsplit);
-  ProfScope ps(&f->prof, "k_synth_adj_f32", st);
-  k_synth_adj_f32<<<grid, 256, 0, st>>>(f->n_freq, f->nv_pad, b->kpad, kps, dimg, b->y32,
-                                         f->tab.vpix, f->scr.a_part);
-  check_launch("k_synth_adj_f32");
+    BV_REQUIRE(b->y32 != nullptr, VIS_EINVAL, "basis has no FP32 storage");
+    const int kps = static_cast<int>(round_up(ceil_div(f->nv_pad, nsplit), 16));
+    const int ncol = static_cast<int>(round_up(f->n_modes, 64));
+    dim3 grid(ncol / 64, ceil_div(f->n_freq, 64), nsplit);
+    ProfScope ps(&f->prof, "k_synth_adj_f32", st);
+    k_synth_adj_f32<<<grid, 256, 0, st>>>(f->n_freq, f->nv_pad, b->kpad, kps, dimg, b->y32,
+                                           f->tab.vpix, f->scr.a_part);
+    check_launch("k_synth_adj_f32");
   }
   const long n = static_cast<long>(f->n_freq) * f->n_modes;
   ProfScope ps(&f->prof, "k_reduce_splits", st);

@@ -208,6 +208,9 @@ def test_invalid_inputs_raise(vis, c0):
     with pytest.raises(vis.VisError):
         e = w.lattice_basis(cfg)
         vis.Field(basis, [[0, 0], [1, 0]], e[0], e[1], [150e6], [0.0], -0.5, 30)  # lmax > basis
+    with pytest.raises(vis.VisError):
+        e = w.lattice_basis(cfg)
+        vis.Field(basis, [[0, 0], [1, 0]], e[0], e[1], [150e6], [0.0], -0.5, 5, precision=4)
 
 
 @pytest.fixture(scope="module")
@@ -218,80 +221,109 @@ def c1(vis):
 
 
 C1_CHANS = [0, 37]
+C1_GRAD_CHAN = 37
 
 
-def test_forward_c1_sampled_channels(vis, c1):
-    """Full C1 size (61 dishes, 49152 px, lmax 100, 64 ch, 60 t) in the benchmarked
-    launch configuration; the oracle computes channels 0 and 37 over all times."""
+@pytest.fixture(scope="module")
+def c1_ref(c1):
+    """Oracle visibilities of the sampled C1 channels over all times."""
     cfg, basis, fld, d = c1
-    alm, g, fw = _dev_params(d, cfg)
-    say("vis_forward c1")
-    m = vis.forward(fld, alm, g, fw).cpu().numpy()
     of = model.Field(cfg)
-    ref = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), chans=C1_CHANS)
-    err = chan_rel_err(m[:, C1_CHANS], ref)
-    say("c1 per-channel rel err", err)
-    assert np.all(err <= 1e-5)
+    return model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), chans=C1_CHANS)
 
 
-def test_grad_c1_sampled_channel(vis, c1):
-    """chi^2 gradient of one C1 channel: every term of channel f's gradient
-    depends only on channel f's data, so the oracle evaluates that channel alone."""
+@pytest.fixture(scope="module")
+def c1_grad_ref(c1):
+    """Data holding one channel (others zero) and the oracle chi^2 gradient of that
+    channel at a * 1.2: every term of channel f's gradient depends only on
+    channel f's data, so the oracle evaluates that channel alone."""
     cfg, basis, fld, d = c1
-    f = 37
+    f = C1_GRAD_CHAN
     of = model.Field(cfg)
     ref_m = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), chans=[f])
     sig = model.noise_sigma(cfg, ref_m)
     data_f = ref_m + sig * math.sqrt(2) * d.noise_unit[:, [f], :]
     data = np.zeros((cfg.n_time, cfg.n_freq, fld.n_bl), dtype=np.complex64)
     data[:, f] = data_f[:, 0]
+    rx2, rga, rgg, rgf = model.chi2_and_grad(of, data_f, sig, d.alm * 1.2, d.gains,
+                                             w.fwhm_ref_rad(cfg), chans=[f])
+    return data, sig, rga[0], rgg[0]
+
+
+def test_forward_c1_sampled_channels(vis, c1, c1_ref):
+    """Full C1 size (61 dishes, 49152 px, lmax 100, 64 ch, 60 t) in the benchmarked
+    launch configuration; the oracle computes channels 0 and 37 over all times."""
+    cfg, basis, fld, d = c1
+    alm, g, fw = _dev_params(d, cfg)
+    say("vis_forward c1")
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    err = chan_rel_err(m[:, C1_CHANS], c1_ref)
+    say("c1 per-channel rel err", err)
+    assert np.all(err <= 1e-5)
+
+
+def test_grad_c1_sampled_channel(vis, c1, c1_grad_ref):
+    cfg, basis, fld, d = c1
+    data, sig, rga, rgg = c1_grad_ref
     alm, g, fw = _dev_params(d, cfg, alm_scale=1.2)
     say("chi2_and_grad c1")
     x2, ga, gg, gf = vis.chi2_and_grad(fld, torch.tensor(data, device="cuda"), sig, alm, g, fw)
-    rx2, rga, rgg, rgf = model.chi2_and_grad(of, data_f, sig, d.alm * 1.2, d.gains,
-                                             w.fwhm_ref_rad(cfg), chans=[f])
-    e_a = rel_norm(ga[f].cpu().numpy(), rga[0])
-    e_g = rel_norm(gg[f].cpu().numpy(), rgg[0])
+    e_a = rel_norm(ga[C1_GRAD_CHAN].cpu().numpy(), rga)
+    e_g = rel_norm(gg[C1_GRAD_CHAN].cpu().numpy(), rgg)
     say("c1 grad errs", e_a, e_g)
     assert e_a <= 2e-4 and e_g <= 2e-4
 
 
 # ---------------------------------------------------------------- split precision --
-# bf16 hi/lo split synthesis: each operand carries ~16 significant bits and the
-# dropped lo*lo term is ~2^-16 relative per product; summed over ~10^4 modes
-# with random signs the visibility error stays well inside the 1e-4 bar.
+# Split synthesis: bf16 hi/lo operands carry ~16 significant bits and the
+# dropped lo*lo term is ~2^-16 relative per product; fp16 hi/lo with a power-of-
+# two row scale carries ~22 bits.  Summed over ~10^4 modes with random signs
+# the visibility error stays well inside the 1e-4 bar in both cases.
 
-def test_forward_c0_bf16x3(vis, c0):
+SPLIT = pytest.mark.parametrize("prec", [2, 3], ids=["bf16x3", "fp16x3"])
+
+
+@SPLIT
+def test_forward_c0_split(vis, c0, prec):
     cfg, _, _, d, of, m_true, sig, data = c0
-    basis, fld, _ = _setup(vis, cfg, precision=vis.VIS_BF16X3)
+    basis, fld, _ = _setup(vis, cfg, precision=prec)
     alm, g, fw = _dev_params(d, cfg)
     m = vis.forward(fld, alm, g, fw).cpu().numpy()
     err = chan_rel_err(m, m_true)
-    say("c0 bf16x3 per-channel rel err", err)
+    say("c0 split", prec, "per-channel rel err", err)
     assert np.all(err <= 1e-4)
 
 
-def test_grad_c0_bf16x3(vis, c0):
+@SPLIT
+def test_grad_c0_split(vis, c0, prec):
     cfg, _, _, d, of, m_true, sig, data = c0
-    basis, fld, _ = _setup(vis, cfg, precision=vis.VIS_BF16X3)
+    basis, fld, _ = _setup(vis, cfg, precision=prec)
     alm, g, fw = _dev_params(d, cfg, alm_scale=1.2)
     x2, ga, gg, gf = vis.chi2_and_grad(fld, torch.tensor(data, dtype=torch.complex64, device="cuda"),
                                        sig, alm, g, fw)
     rx2, rga, rgg, rgf = model.chi2_and_grad(of, data, sig, d.alm * 1.2, d.gains, w.fwhm_ref_rad(cfg))
     e = [rel_norm(ga.cpu().numpy(), rga), rel_norm(gg.cpu().numpy(), rgg),
          abs(float(gf) - rgf) / abs(rgf), abs(float(x2) - rx2) / rx2]
-    say("c0 bf16x3 grad errs (a, g, F, chi2)", e)
+    say("c0 split", prec, "grad errs (a, g, F, chi2)", e)
     assert max(e) <= 2e-3
 
 
-def test_forward_c1_bf16x3_sampled(vis, c1):
+@SPLIT
+def test_c1_split_sampled(vis, c1, c1_ref, c1_grad_ref, prec):
+    """Full C1 size with split synthesis: per-channel visibility error on the
+    sampled channels and the gradient error of one channel."""
     cfg, _, _, d = c1
-    basis = vis.basis_for(cfg, storage=vis.STORAGE_FOR[vis.VIS_BF16X3])
-    fld = vis.Field.from_config(basis, cfg, vis.VIS_BF16X3)
+    basis = vis.basis_for(cfg, storage=vis.STORAGE_FOR[prec])
+    fld = vis.Field.from_config(basis, cfg, prec)
     alm, g, fw = _dev_params(d, cfg)
     m = vis.forward(fld, alm, g, fw).cpu().numpy()
-    of = model.Field(cfg)
-    ref = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), chans=C1_CHANS)
-    err = chan_rel_err(m[:, C1_CHANS], ref)
-    say("c1 bf16x3 per-channel rel err", err)
+    err = chan_rel_err(m[:, C1_CHANS], c1_ref)
+    say("c1 split", prec, "per-channel rel err", err)
     assert np.all(err <= 1e-4)
+    data, sig, rga, rgg = c1_grad_ref
+    alm, g, fw = _dev_params(d, cfg, alm_scale=1.2)
+    x2, ga, gg, gf = vis.chi2_and_grad(fld, torch.tensor(data, device="cuda"), sig, alm, g, fw)
+    e_a = rel_norm(ga[C1_GRAD_CHAN].cpu().numpy(), rga)
+    e_g = rel_norm(gg[C1_GRAD_CHAN].cpu().numpy(), rgg)
+    say("c1 split", prec, "grad errs", e_a, e_g)
+    assert e_a <= 2e-3 and e_g <= 2e-3
