@@ -197,33 +197,42 @@ k_synth_adj_split(int nf, int nvp, int kpad, int kps, const unsigned short* __re
   const int kbeg = split * kps, kend = min(nvp, kbeg + kps);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = tid >> 2, lk = (tid & 3) * 8;      // A: row f, 8 pixels
-  const int kr = tid >> 3, cg = (tid & 7) * 8;      // B: pixel row, 8 modes
+  const int pq = (tid >> 5) * 4, cp = (tid & 31) * 2;   // B: 4 pixel rows, 2 modes
   const size_t aoff = static_cast<size_t>(m0 + lr) * nvp;   // padded rows: in range
   f4 c1[2][2], c2[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) c1[i][j] = c2[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  us8 rah, ral, rbh, rbl;
+  us8 rah, ral;
+  unsigned rbh[4], rbl[4];   // modes (cp, cp + 1) of pixel rows pq .. pq + 3
   // kbeg and kps are multiples of 32 and nvp of 64: steps stay inside the split
   const int ksteps = (kend - kbeg + 31) / 32;
   auto gload = [&](int k0) {
     rah = *reinterpret_cast<const us8*>(Dh + aoff + k0 + lk);
     ral = *reinterpret_cast<const us8*>(Dl + aoff + k0 + lk);
-    const size_t yo = static_cast<size_t>(vpix[k0 + kr]) * kpad + n0 + cg;
-    rbh = *reinterpret_cast<const us8*>(Yh + yo);
-    rbl = *reinterpret_cast<const us8*>(Yl + yo);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const size_t yo = static_cast<size_t>(vpix[k0 + pq + r]) * kpad + n0 + cp;
+      rbh[r] = *reinterpret_cast<const unsigned*>(Yh + yo);
+      rbl[r] = *reinterpret_cast<const unsigned*>(Yl + yo);
+    }
+  };
+  // B tile transposed into [mode][pixel]: four pixels of one mode per 64-bit store
+  auto bstore = [&](unsigned short* B, const unsigned (&v)[4]) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    const u2 even = u2{(v[0] & 0xFFFFu) | (v[1] << 16), (v[2] & 0xFFFFu) | (v[3] << 16)};
+    const u2 odd = u2{(v[0] >> 16) | (v[1] & 0xFFFF0000u), (v[2] >> 16) | (v[3] & 0xFFFF0000u)};
+    *reinterpret_cast<u2*>(&B[cp * kHP + pq]) = even;
+    *reinterpret_cast<u2*>(&B[(cp + 1) * kHP + pq]) = odd;
   };
   if (ksteps > 0) gload(kbeg);
   for (int s = 0; s < ksteps; ++s) {
     const int buf = s & 1;
     *reinterpret_cast<us8*>(&Ah[buf][lr * kHP + lk]) = rah;
     *reinterpret_cast<us8*>(&Al[buf][lr * kHP + lk]) = ral;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      Bh[buf][(cg + q) * kHP + kr] = rbh[q];
-      Bl[buf][(cg + q) * kHP + kr] = rbl[q];
-    }
+    bstore(Bh[buf], rbh);
+    bstore(Bl[buf], rbl);
     __syncthreads();
     if (s + 1 < ksteps) gload(kbeg + (s + 1) * 32);
     us8 ah[2], al[2], bh[2], bl[2];
