@@ -35,8 +35,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"hbm_gbs": 8000.0, "fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0}
+PEAK = {"hbm_gbs": 8000.0, "fp32_mfma_tflops": 157.3, "bf16_mfma_tflops": 2500.0,
+        "fp16_mfma_tflops": 2500.0}
 EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
+
+# HBM bytes per launch of the fringe kernels on this workload, from two
+# rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) of
+#     python3 bench.py --steps 3 --warmup 1 --no-serve --no-cpu-baseline --calibrate-copy
+# each scaled by the ratio of a 256 MiB device copy's known bytes to what the
+# same counter reads for it (profiles/fringe_c1_hbm_traffic.md).  The figure is
+# reported only while the kernel sources hash to the value it was taken with.
+TRAFFIC = {
+    "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/objects.hpp",
+                "paper_2504_07090_amd/csrc/common.hpp"],
+    "sha256": "5ed057803f9546a64a86fea143c69a89b7e84ed9f7d7f81df97913fddcc9651c",
+    "bytes_per_launch": {"k_fringe_adj": 502130793, "k_fringe_fwd": 204288313},
+}
+
+
+def sources_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    b = TRAFFIC["bytes_per_launch"].get(kernel)
+    if b is None or TRAFFIC["sha256"] != sources_sha256(TRAFFIC["sources"]):
+        return None
+    return b
 
 
 def log(*a):
@@ -156,10 +186,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
+    ap.add_argument("--serve-precision", default="bf16x3", choices=["bf16x3", "fp16x3"])
     ap.add_argument("--serve-chains", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with a 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -171,9 +204,12 @@ def main():
 
     torch.cuda.set_device(0)
     cfg = w.C1
-    prec = vis.VIS_FP32 if args.precision == "fp32" else vis.VIS_BF16X3
+    precs = {"fp32": vis.VIS_FP32, "bf16x3": vis.VIS_BF16X3, "fp16x3": vis.VIS_FP16X3}
+    prec = precs[args.precision]
+    sprec = precs[args.serve_precision]
     log("basis + fields", cfg.name)
-    basis = vis.basis_for(cfg, storage=1 | 2)
+    storage = vis.STORAGE_FOR[prec] | (0 if args.no_serve else 1 | vis.STORAGE_FOR[sprec])
+    basis = vis.basis_for(cfg, storage=storage)
     warm = make_chain(vis, serve, torch, basis, cfg, prec)
     timed = make_chain(vis, serve, torch, basis, cfg, prec)
     fld = timed[0]
@@ -221,7 +257,7 @@ def main():
                 else PEAK["bf16_mfma_tflops"]}
     roof.update({"achieved": work / (dom_ms * 1e-3) / 1e12, "unit": "TFLOP/s"})
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom) if prec == vis.VIS_FP32 else None
     roof["kernel"] = dom
     roof["kernel_ms"] = dom_ms
 
@@ -229,14 +265,13 @@ def main():
     if not args.no_serve:
         log("serving: building", args.serve_chains, "uneven chains")
         ins = serving_inputs(vis, serve, torch, basis, args.serve_chains)
-        log("serving: batched, bf16x3 synthesis")
-        fast = serving_bench(vis, serve, torch, basis, ins, vis.VIS_BF16X3,
-                             max_batch=args.serve_chains)
+        log("serving: batched,", args.serve_precision, "synthesis")
+        fast = serving_bench(vis, serve, torch, basis, ins, sprec, max_batch=args.serve_chains)
         log("serving: per-chain FP32 baseline, one request per tick")
         base = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32, max_batch=1)
         del ins
         serving = {"chains": args.serve_chains, "leapfrog_steps": 20,
-                   "batched_bf16x3": fast, "per_chain_fp32": base,
+                   "batched_" + args.serve_precision: fast, "per_chain_fp32": base,
                    "speedup": fast["grad_evals_per_s"] / base["grad_evals_per_s"]}
 
     cpu = None
@@ -248,7 +283,7 @@ def main():
         "metric": "fwd+adjoint complex MAC/s; batched-HMC grad evals/s + p50/p99 latency",
         "value": value, "unit": "complex MAC/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if prec == vis.VIS_FP32 else "bf16x3",
+        "vs_baseline": None, "dtype": "f32" if prec == vis.VIS_FP32 else args.precision,
         "data": "synthetic",
         "config": {"workload": cfg.name, "n_ant": fld.n_ant, "n_bl": fld.n_bl, "n_ubl": fld.n_ubl,
                    "n_pix": fld.info.n_pix, "n_pix_visible": nv, "lmax": cfg.lmax,
@@ -261,6 +296,13 @@ def main():
         "serving": serving,
         "cpu_baseline": cpu,
     }
+    if args.calibrate_copy:
+        # reference for the HBM byte counters: 256 MiB read + 256 MiB written
+        x = torch.empty(64 << 20, dtype=torch.float32, device="cuda").uniform_()
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     print(json.dumps(line))
 
 
