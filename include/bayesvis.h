@@ -79,6 +79,19 @@ typedef enum {
   VIS_FP16X3 = 3       /* synthesis as fp16 hi/lo split products (scaled lo), FP32 accumulate */
 } vis_precision;
 
+/* How a field evaluates the sky synthesis I = Y a (Sec. 3.2).
+ * DENSE: against the stored basis matrix Y restricted to the pixels above the
+ *   horizon (FP32, bf16x3 or fp16x3 per the field precision).
+ * SEPARABLE: on the RA x sin(dec) grid every column factorises,
+ *   Y(ring j, column k; l, m) = lambda_lm(z_j) T_m(alpha_k) (Sec. 3.2,
+ *   eq. fg_separable), so I is a Legendre sum per (m, ring) followed by an
+ *   azimuthal sum per ring; both run as FP32 MFMA GEMMs from small tables and
+ *   Y itself is never read (needs basis storage bit 3; FP32 fields only).   */
+typedef enum {
+  VIS_SYNTH_DENSE = 0,
+  VIS_SYNTH_SEPARABLE = 1
+} vis_synthesis;
+
 typedef struct { float re, im; } vis_c64;
 
 typedef struct vis_basis vis_basis;
@@ -90,7 +103,9 @@ typedef struct vis_field vis_field;
  * carried through the recurrence so high orders do not overflow).
  * Any field with a smaller lmax uses the leading (lmax'+1)^2 columns.
  * storage: bit 0 = FP32 copy (needed by VIS_FP32 fields), bit 1 = bf16
- * hi/lo copy (VIS_BF16X3), bit 2 = fp16 hi/lo copy (VIS_FP16X3).            */
+ * hi/lo copy (VIS_BF16X3), bit 2 = fp16 hi/lo copy (VIS_FP16X3), bit 3 =
+ * the factor tables of separable synthesis only (lambda_lm per ring and
+ * T_m per column, FP32; a few MB instead of n_pix x n_modes values).     */
 typedef struct {
   int32_t grid_nz, grid_nphi;
   int32_t lmax;
@@ -126,6 +141,7 @@ typedef struct {
   int32_t lmax;
   double beam_ref_hz;                /* nu_ref of the beam-width law */
   int32_t precision;                 /* vis_precision */
+  int32_t synthesis;                 /* vis_synthesis (0 = dense) */
 } vis_field_desc;
 
 typedef struct {
@@ -133,6 +149,7 @@ typedef struct {
   int32_t n_pix_visible;             /* pixels above the horizon at some time */
   int32_t lattice_extent;            /* max |dn| over baselines */
   int32_t precision;
+  int32_t synthesis;
   double d_omega;
   double fwd_macs;                   /* complex x real MACs of one fringe pass:
                                         sum over (u, t) of visible pixels x n_freq */

@@ -99,6 +99,7 @@ constexpr double kLn2 = 0.69314718055994531;
 
 constexpr int kChunk = 64;        // pixels per fringe chunk (one wavefront)
 constexpr int kMaxExtent = 16;    // max |lattice difference| supported
+constexpr int kSepPad = 4;        // zero azimuthal columns on each side of the separable T table
 constexpr float kBelowHorizon = 1e30f;  // theta^2 marker: beam exactly 0
 
 }  // namespace bv

@@ -160,8 +160,14 @@ static void carve_basis(vis_basis* b, Carver& cv) {
   b->yhh = (b->storage & 4u) ? cv.take<_Float16>(n) : nullptr;
   b->yhl = (b->storage & 4u) ? cv.take<_Float16>(n) : nullptr;
   // staging tables for the generator (Legendre values per ring, cos/sin per column)
-  b->lam = cv.take<double>(static_cast<size_t>(b->nz) * (b->lmax + 1) * (b->lmax + 2) / 2);
+  const size_t ntri = static_cast<size_t>(b->lmax + 1) * (b->lmax + 2) / 2;
+  b->lam = cv.take<double>(static_cast<size_t>(b->nz) * ntri);
   b->trig = cv.take<double>(static_cast<size_t>(b->nphi) * 2 * (b->lmax + 1));
+  if (b->storage & 8u) {
+    b->sep_lam = cv.take<float>(static_cast<size_t>(b->nz) * ntri);
+    b->sep_t = cv.take<float>(static_cast<size_t>(b->nphi) * b->kaz_t);
+    b->sep_tt = cv.take<float>(static_cast<size_t>(b->nphi) * b->kaz_t);
+  }
 }
 
 static void basis_shape(const vis_basis_desc* d, vis_basis* b) {
@@ -169,7 +175,7 @@ static void basis_shape(const vis_basis_desc* d, vis_basis* b) {
   BV_REQUIRE(d->grid_nz >= 2 && d->grid_nz <= 8192 && d->grid_nphi >= 4 && d->grid_nphi <= 16384,
              VIS_EINVAL, "grid %d x %d out of range", d->grid_nz, d->grid_nphi);
   BV_REQUIRE(d->lmax >= 0 && d->lmax <= 512, VIS_EINVAL, "lmax %d out of range [0, 512]", d->lmax);
-  BV_REQUIRE(d->storage != 0 && (d->storage & ~7u) == 0, VIS_EINVAL, "bad storage flags 0x%x",
+  BV_REQUIRE(d->storage != 0 && (d->storage & ~15u) == 0, VIS_EINVAL, "bad storage flags 0x%x",
              d->storage);
   b->nz = d->grid_nz;
   b->nphi = d->grid_nphi;
@@ -178,6 +184,7 @@ static void basis_shape(const vis_basis_desc* d, vis_basis* b) {
   b->n_modes = (d->lmax + 1) * (d->lmax + 1);
   b->kpad = static_cast<int>(round_up(b->n_modes, 64));
   b->storage = d->storage;
+  b->kaz_t = static_cast<int>(round_up(2 * d->lmax + 1 + 2 * kSepPad, 4));
 }
 
 // ---------------------------------------------------------------- field --
@@ -217,9 +224,17 @@ static void validate_field(const vis_basis* basis, const vis_field_desc* d) {
   BV_REQUIRE(d->beam_ref_hz > 0.0, VIS_EINVAL, "beam_ref_hz must be positive");
   BV_REQUIRE(d->precision == VIS_FP32 || d->precision == VIS_BF16X3 || d->precision == VIS_FP16X3,
              VIS_EINVAL, "precision %d is not one of VIS_FP32, VIS_BF16X3, VIS_FP16X3", d->precision);
-  const uint32_t need = d->precision == VIS_FP32 ? 1u : d->precision == VIS_BF16X3 ? 2u : 4u;
-  BV_REQUIRE((basis->storage & need) != 0, VIS_EINVAL,
-             "the basis was created without the storage this precision needs");
+  BV_REQUIRE(d->synthesis == VIS_SYNTH_DENSE || d->synthesis == VIS_SYNTH_SEPARABLE, VIS_EINVAL,
+             "synthesis %d is not one of VIS_SYNTH_DENSE, VIS_SYNTH_SEPARABLE", d->synthesis);
+  if (d->synthesis == VIS_SYNTH_SEPARABLE) {
+    BV_REQUIRE(d->precision == VIS_FP32, VIS_EINVAL, "separable synthesis runs in FP32 only");
+    BV_REQUIRE((basis->storage & 8u) != 0, VIS_EINVAL,
+               "the basis was created without the separable factor tables (storage bit 3)");
+  } else {
+    const uint32_t need = d->precision == VIS_FP32 ? 1u : d->precision == VIS_BF16X3 ? 2u : 4u;
+    BV_REQUIRE((basis->storage & need) != 0, VIS_EINVAL,
+               "the basis was created without the storage this precision needs");
+  }
 }
 
 static HostGeometry build_geometry(const vis_basis* basis, const vis_field_desc* d) {
@@ -335,9 +350,16 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
   T.ulut = cv.take<int>(static_cast<size_t>(f->extent + 1) * (2 * f->extent + 1));
   auto& S = f->scr;
   const size_t kpad = f->basis->kpad;
+  const bool dense = f->synthesis == VIS_SYNTH_DENSE;
   S.img = cv.take<float>(nfq * nvp);
-  S.apad = cv.take<float>(static_cast<size_t>(round_up(f->n_freq, 64)) * kpad);
+  if (dense) S.apad = cv.take<float>(static_cast<size_t>(round_up(f->n_freq, 64)) * kpad);
   S.dimg = cv.take<float>(nfq * nvp);
+  if (!dense) {
+    const size_t npix = f->basis->n_pix;
+    T.vidx = cv.take<int>(npix);
+    S.sep_g = cv.take<float>(static_cast<size_t>(f->basis->nz) * f->kaz * nfq);
+    S.sep_dfull = cv.take<float>(npix * nfq);
+  }
   if (f->precision != VIS_FP32) {
     const size_t nfp = static_cast<size_t>(round_up(f->n_freq, 64));
     S.dsplit = cv.take<float>(nfp * nvp);
@@ -349,8 +371,9 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
   S.chi_part = cv.take<double>(nt * nfq);
   S.g_part = cv.take<float2>(nt * nfq * f->n_ant);
   S.f_part = cv.take<float>(nfq * f->n_chunks);
-  S.a_part = cv.take<float>(std::max(static_cast<size_t>(f->asplit) * nfq * kpad,
-                                     static_cast<size_t>(f->fsplit) * nfq * nvp));
+  if (dense)
+    S.a_part = cv.take<float>(std::max(static_cast<size_t>(f->asplit) * nfq * kpad,
+                                       static_cast<size_t>(f->fsplit) * nfq * nvp));
 }
 
 static int choose_asplit(int n_freq, int kpad, int nv_pad) {
@@ -384,6 +407,8 @@ static void fill_shape(vis_field* f, const vis_basis* basis, const vis_field_des
   f->dtile = fringe_tile_extent(g.extent);
   f->gstride = adj_coef_stride(f->dtile);
   f->precision = d->precision;
+  f->synthesis = d->synthesis;
+  f->kaz = static_cast<int>(round_up(2 * d->lmax + 1, 4));
   f->d_omega = 4.0 * kPi / basis->n_pix;
   f->beam_ref_hz = d->beam_ref_hz;
   f->fwd_macs = g.vis_pix_time * f->n_ubl * d->n_freq;
@@ -451,10 +476,32 @@ vis_status vis_basis_create(const vis_basis_desc* desc, void* ws, size_t bytes, 
     double* dtrig = b->trig;
     BV_HIP(hipMemcpyAsync(dlam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, s));
     BV_HIP(hipMemcpyAsync(dtrig, trig.data(), trig.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    dim3 grid(ceil_div(b->kpad, 256), b->n_pix);
-    k_make_basis<<<grid, 256, 0, s>>>(b->nphi, b->n_modes, b->kpad, ntri, dlam, dtrig, b->lmax,
-                                      b->y32, b->ybh, b->ybl, b->yhh, b->yhl);
-    check_launch("k_make_basis");
+    if (b->storage & 7u) {
+      dim3 grid(ceil_div(b->kpad, 256), b->n_pix);
+      k_make_basis<<<grid, 256, 0, s>>>(b->nphi, b->n_modes, b->kpad, ntri, dlam, dtrig, b->lmax,
+                                        b->y32, b->ybh, b->ybl, b->yhh, b->yhl);
+      check_launch("k_make_basis");
+    }
+    std::vector<float> sl, st_, stt;
+    if (b->storage & 8u) {
+      // separable factors: Y(j, k; l, m) = lambda_l|m|(z_j) T_m(alpha_k)
+      sl.assign(lam.begin(), lam.end());
+      st_.assign(static_cast<size_t>(b->nphi) * b->kaz_t, 0.f);
+      stt.assign(static_cast<size_t>(b->nphi) * b->kaz_t, 0.f);
+      for (int k = 0; k < b->nphi; ++k) {
+        const double* tr = &trig[static_cast<size_t>(k) * 2 * (b->lmax + 1)];
+        for (int m = -b->lmax; m <= b->lmax; ++m) {
+          const int am = m < 0 ? -m : m;
+          const double v = m == 0 ? 1.0 : m > 0 ? std::sqrt(2.0) * tr[2 * am] : std::sqrt(2.0) * tr[2 * am + 1];
+          const int c = m + b->lmax + kSepPad;
+          st_[static_cast<size_t>(k) * b->kaz_t + c] = static_cast<float>(v);
+          stt[static_cast<size_t>(c) * b->nphi + k] = static_cast<float>(v);
+        }
+      }
+      BV_HIP(hipMemcpyAsync(b->sep_lam, sl.data(), sl.size() * sizeof(float), hipMemcpyHostToDevice, s));
+      BV_HIP(hipMemcpyAsync(b->sep_t, st_.data(), st_.size() * sizeof(float), hipMemcpyHostToDevice, s));
+      BV_HIP(hipMemcpyAsync(b->sep_tt, stt.data(), stt.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    }
     BV_HIP(hipStreamSynchronize(s));
     *out = b;
   });
@@ -555,6 +602,14 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
     up(T.ulut, ulut, s);
     // the padded tail of the sky scratch must stay finite (it is multiplied by a zero beam)
     BV_HIP(hipMemsetAsync(f->scr.img, 0, sizeof(float) * f->n_freq * f->nv_pad, s));
+    if (f->synthesis == VIS_SYNTH_SEPARABLE) {
+      std::vector<int> vidx(basis->n_pix, -1);
+      for (int k = 0; k < f->nv; ++k) vidx[g.vpix[k]] = k;
+      up(T.vidx, vidx, s);
+      // rows of the Legendre stage beyond 2 lmax + 1 are never written: keep them zero
+      BV_HIP(hipMemsetAsync(f->scr.sep_g, 0,
+                            sizeof(float) * basis->nz * f->kaz * f->n_freq, s));
+    }
     BV_HIP(hipStreamSynchronize(s));
     *out = f;
   });
@@ -574,6 +629,7 @@ vis_status vis_field_get_info(const vis_field* f, vis_field_info* info) {
     info->n_modes = f->n_modes;
     info->n_pix_visible = f->nv;
     info->lattice_extent = f->extent;
+    info->synthesis = f->synthesis;
     info->precision = f->precision;
     info->d_omega = f->d_omega;
     info->fwd_macs = f->fwd_macs;

@@ -51,6 +51,13 @@ struct vis_basis {
   _Float16* yhl = nullptr;         // [n_pix][kpad] fp16 lo part, scaled by 2^11
   double* lam = nullptr;           // generator staging: normalised Legendre per ring
   double* trig = nullptr;          // generator staging: cos / sin (m alpha) per column
+  // separable-synthesis factor tables (storage bit 3), FP32:
+  //   sep_lam[j][l (l + 1) / 2 + m] = lambda_lm(z_j), m >= 0
+  //   sep_t[k][c], sep_tt[c][k] = T_m(alpha_k) with c = m + lmax + kSepPad, zero for |m| > lmax
+  int kaz_t = 0;                   // columns of sep_t: round_up(2 lmax + 1 + 2 kSepPad, 4)
+  float* sep_lam = nullptr;
+  float* sep_t = nullptr;
+  float* sep_tt = nullptr;
 };
 
 namespace bv {
@@ -64,6 +71,9 @@ struct FieldScratch {
                                    //   16-bit hi plane then the lo plane of dL/dI
   float* rscale = nullptr;         // split fields: [nf_pad] inverse row scales
   float* rmax = nullptr;           // split fields: [nf_pad][ceil(max(kpad, nv_pad) / 2048)]
+  float* sep_g = nullptr;          // separable fields: [nz][kaz][n_freq] Legendre stage output
+                                   //   (forward) or azimuthal stage output (adjoint)
+  float* sep_dfull = nullptr;      // separable fields: [n_pix][n_freq] dL/dI on the full grid
   float2* vu = nullptr;            // [n_time][n_freq][n_ubl] gain-free unique visibilities
   float* gco = nullptr;            // [n_time][n_freq][gstride] adjoint coefficients, MFMA layout
   double* chi_part = nullptr;      // [n_time * n_freq]
@@ -77,6 +87,7 @@ struct FieldScratch {
 struct FieldTables {
   double* freq = nullptr;          // [n_freq] Hz
   int* vpix = nullptr;             // [nv_pad] pixel index of each visible slot
+  int* vidx = nullptr;             // separable fields: [n_pix] visible slot of each pixel or -1
   double* p1 = nullptr;            // [n_time][nv_pad] (e1 . s) / c, seconds
   double* p2 = nullptr;            // [n_time][nv_pad] (e2 . s) / c
   float* th2 = nullptr;            // [n_time][nv_pad] zenith angle^2, kBelowHorizon if U <= 0
@@ -107,6 +118,8 @@ struct vis_field {
   int dtile = 0;                   // compile-time extent of the fringe kernels (>= extent)
   int gstride = 0;                 // floats per (t, nu) of the adjoint coefficient table
   int precision = VIS_FP32;
+  int synthesis = VIS_SYNTH_DENSE;
+  int kaz = 0;                     // separable: rows per ring of sep_g, round_up(2 lmax + 1, 4)
   int asplit = 1;                  // split-K factor of the adjoint synthesis
   int fsplit = 1;                  // split-K factor of the FP32 forward synthesis
   double d_omega = 0.0;

@@ -249,8 +249,14 @@ k_reduce_splits(int nsplit, int nf, int nm, int kpad, const float* __restrict__ 
 void launch_synth_fwd_split(const vis_field* f, const float* alm, float* dst, int nsplit, int kps,
                             hipStream_t st);
 void launch_synth_adj_split(const vis_field* f, const float* dimg, int kps, hipStream_t st);
+void launch_synth_fwd_sep(const vis_field* f, const float* alm, float* img, hipStream_t st);
+void launch_synth_adj_sep(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st);
 
 void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStream_t st) {
+  if (f->synthesis == VIS_SYNTH_SEPARABLE) {
+    launch_synth_fwd_sep(f, alm, img, st);
+    return;
+  }
   const vis_basis* b = f->basis;
   const int nsplit = f->fsplit;
   const int kps = static_cast<int>(round_up(ceil_div(f->n_modes, nsplit), 32));
@@ -275,6 +281,10 @@ void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStrea
 }
 
 void launch_synth_adj(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st) {
+  if (f->synthesis == VIS_SYNTH_SEPARABLE) {
+    launch_synth_adj_sep(f, dimg, grad_alm, st);
+    return;
+  }
   const vis_basis* b = f->basis;
   const int nsplit = f->asplit;
   if (f->precision != VIS_FP32) {

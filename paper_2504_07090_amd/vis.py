@@ -22,7 +22,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbayesvis.so")
 
 VIS_FP32, VIS_BF16X3, VIS_FP16X3 = 1, 2, 3
+VIS_SYNTH_DENSE, VIS_SYNTH_SEPARABLE = 0, 1
 STORAGE_FOR = {VIS_FP32: 1, VIS_BF16X3: 2, VIS_FP16X3: 4}
+STORAGE_SEPARABLE = 8   # factor tables of separable synthesis only
 
 
 class VisError(RuntimeError):
@@ -49,7 +51,7 @@ class FieldDesc(C.Structure):
                 ("n_freq", C.c_int32), ("freq_hz", C.POINTER(C.c_double)),
                 ("n_time", C.c_int32), ("lst_rad", C.POINTER(C.c_double)),
                 ("latitude_rad", C.c_double), ("lmax", C.c_int32), ("beam_ref_hz", C.c_double),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("synthesis", C.c_int32)]
 
 
 class FieldInfo(C.Structure):
@@ -57,7 +59,7 @@ class FieldInfo(C.Structure):
                 ("n_freq", C.c_int32), ("n_time", C.c_int32), ("n_pix", C.c_int32),
                 ("n_modes", C.c_int32), ("n_pix_visible", C.c_int32),
                 ("lattice_extent", C.c_int32), ("precision", C.c_int32),
-                ("d_omega", C.c_double), ("fwd_macs", C.c_double)]
+                ("synthesis", C.c_int32), ("d_omega", C.c_double), ("fwd_macs", C.c_double)]
 
 
 _vp = C.c_void_p
@@ -143,7 +145,8 @@ class Field:
     """One observation (array, band, times) bound to a basis."""
 
     def __init__(self, basis: Basis, ant_lattice, e1, e2, freqs, lsts, latitude_rad: float,
-                 lmax: int, beam_ref_hz: float = 150e6, precision: int = VIS_FP32):
+                 lmax: int, beam_ref_hz: float = 150e6, precision: int = VIS_FP32,
+                 synthesis: int = VIS_SYNTH_DENSE):
         self.basis = basis
         self.device = basis.device
         ant = np.ascontiguousarray(np.asarray(ant_lattice, dtype=np.int32).reshape(-1, 2))
@@ -163,6 +166,7 @@ class Field:
         d.lmax = int(lmax)
         d.beam_ref_hz = float(beam_ref_hz)
         d.precision = int(precision)
+        d.synthesis = int(synthesis)
         self.desc = d
         nbytes = C.c_size_t()
         _check(_lib.vis_field_workspace_bytes(basis.handle, C.byref(d), C.byref(nbytes)),
@@ -179,13 +183,15 @@ class Field:
         self.n_ant, self.n_bl, self.n_ubl = info.n_ant, info.n_bl, info.n_ubl
         self.n_freq, self.n_time, self.n_modes = info.n_freq, info.n_time, info.n_modes
         self.precision = precision
+        self.synthesis = synthesis
 
     @classmethod
-    def from_config(cls, basis: Basis, cfg: workload.FieldConfig, precision: int = VIS_FP32):
+    def from_config(cls, basis: Basis, cfg: workload.FieldConfig, precision: int = VIS_FP32,
+                    synthesis: int = VIS_SYNTH_DENSE):
         e = workload.lattice_basis(cfg)
         return cls(basis, workload.antenna_lattice(cfg), e[0], e[1], workload.frequencies(cfg),
                    workload.lsts(cfg), workload.latitude_rad(cfg), cfg.lmax, cfg.beam_ref_hz,
-                   precision)
+                   precision, synthesis)
 
     @property
     def fwd_macs(self) -> float:

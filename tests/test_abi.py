@@ -63,3 +63,48 @@ def test_binding_fails_loudly_without_library(tmp_path):
         (pkg / f).write_text(open(os.path.join(ROOT, "paper_2504_07090_amd", f)).read())
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert r.returncode != 0 and "not built" in r.stderr
+
+
+STRUCTS = {
+    # C struct name -> (python module, ctypes class name)
+    "vis_basis_desc": ("vis", "BasisDesc"),
+    "vis_field_desc": ("vis", "FieldDesc"),
+    "vis_field_info": ("vis", "FieldInfo"),
+    "vis_kernel_time": ("vis", "KernelTime"),
+    "hmc_server_config": ("serve", "ServerConfig"),
+    "hmc_chain_init": ("serve", "ChainInit"),
+    "hmc_result": ("serve", "Result"),
+    "hmc_stats": ("serve", "Stats"),
+}
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the ABI structs have the size and field offsets the
+    C compiler gives the header's declarations."""
+    import importlib
+    mods = {m: importlib.import_module("paper_2504_07090_amd." + m) for m in ("vis", "serve")}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bayesvis.h"',
+             '#include "bayesvis_serve.h"', "int main(void) {"]
+    for cname, (mod, pyname) in STRUCTS.items():
+        cls = getattr(mods[mod], pyname)
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, *_ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            parts = line.split()
+            got[(parts[0], parts[1])] = int(parts[2])
+    for cname, (mod, pyname) in STRUCTS.items():
+        cls = getattr(mods[mod], pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, *_ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

@@ -327,3 +327,98 @@ def test_c1_split_sampled(vis, c1, c1_ref, c1_grad_ref, prec):
     e_g = rel_norm(gg[C1_GRAD_CHAN].cpu().numpy(), rgg)
     say("c1 split", prec, "grad errs", e_a, e_g)
     assert e_a <= 2e-3 and e_g <= 2e-3
+
+
+# ------------------------------------------------------------ separable synthesis --
+# The basis holds only the factor tables (storage bit 3): no Y matrix exists, so
+# these fields cannot silently fall back to the dense product.
+
+def _sep_field(vis, cfg, basis_lmax=None):
+    basis = vis.Basis(cfg.grid_nz, cfg.grid_nphi, basis_lmax or cfg.lmax, vis.STORAGE_SEPARABLE)
+    return basis, vis.Field.from_config(basis, cfg, vis.VIS_FP32, vis.VIS_SYNTH_SEPARABLE)
+
+
+def test_separable_c0_forward_and_gradient(vis, c0):
+    cfg, _, _, d, of, m_true, sig, data = c0
+    basis, fld = _sep_field(vis, cfg)
+    assert fld.info.synthesis == vis.VIS_SYNTH_SEPARABLE
+    alm, g, fw = _dev_params(d, cfg)
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    err = chan_rel_err(m, m_true)
+    say("c0 separable per-channel rel err", err)
+    assert np.all(err <= 1e-5)
+    alm, g, fw = _dev_params(d, cfg, alm_scale=1.2)
+    x2, ga, gg, gf = vis.chi2_and_grad(fld, torch.tensor(data, dtype=torch.complex64, device="cuda"),
+                                       sig, alm, g, fw)
+    rx2, rga, rgg, rgf = model.chi2_and_grad(of, data, sig, d.alm * 1.2, d.gains, w.fwhm_ref_rad(cfg))
+    e = [rel_norm(ga.cpu().numpy(), rga), rel_norm(gg.cpu().numpy(), rgg),
+         abs(float(gf) - rgf) / abs(rgf), abs(float(x2) - rx2) / rx2]
+    say("c0 separable grad errs (a, g, F, chi2)", e)
+    assert max(e) <= 2e-4
+
+
+def test_separable_adjoint_matches_oracle_and_dot(vis, c0):
+    cfg, _, _, d, of, *_ = c0
+    basis, fld = _sep_field(vis, cfg)
+    alm, g, fw = _dev_params(d, cfg)
+    rng = np.random.default_rng(11)
+    y = rng.normal(size=(cfg.n_time, cfg.n_freq, fld.n_bl)) + 1j * rng.normal(size=(cfg.n_time, cfg.n_freq, fld.n_bl))
+    ydev = torch.tensor(y, dtype=torch.complex64, device="cuda")
+    ga, gg, gf = vis.adjoint(fld, alm, g, fw, ydev)
+    rga, rgg, rgf = model.adjoint(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), y)
+    e = [rel_norm(ga.cpu().numpy(), rga), rel_norm(gg.cpu().numpy(), rgg)]
+    say("c0 separable adjoint errs (a, g)", e)
+    assert max(e) <= 2e-5
+    # <y, A x> = <A^T y, x> for the sky part (the model is linear in a)
+    x = torch.tensor(rng.normal(size=d.alm.shape), dtype=torch.float32, device="cuda")
+    ax = vis.forward(fld, x, g, fw).cpu().numpy().astype(np.complex128)
+    gx, _, _ = vis.adjoint(fld, x, g, fw, ydev)
+    lhs = float(np.sum(np.real(np.conj(y) * ax)))
+    rhs = float(np.sum(gx.cpu().numpy().astype(np.float64) * x.cpu().numpy()))
+    say("separable dot test", lhs, rhs)
+    assert abs(lhs - rhs) <= 1e-5 * np.linalg.norm(ax) * np.linalg.norm(y)
+
+
+def test_separable_lmax_prefix_and_hex7(vis):
+    """A field lmax below the basis lmax, and a 127-dish field (two MFMA tiles per side)."""
+    for cfg, blmax in [(w.scaled(w.C0, lmax=9, n_freq=2, n_time=2), 20),
+                       (w.scaled(w.C0, array="hex", array_size=7, n_freq=3, n_time=3,
+                                 freq_lo_hz=120e6, freq_hi_hz=130e6, lmax=12), 12)]:
+        basis, fld = _sep_field(vis, cfg, blmax)
+        d = w.draw(cfg)
+        of = model.Field(cfg)
+        alm, g, fw = _dev_params(d, cfg)
+        m = vis.forward(fld, alm, g, fw).cpu().numpy()
+        ref = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg))
+        err = chan_rel_err(m, ref)
+        say("separable", cfg.name, "basis lmax", blmax, "rel err", err)
+        assert np.all(err <= 1e-5)
+
+
+def test_separable_rejected_without_tables_or_in_split_precision(vis, c0):
+    cfg, basis, *_ = c0     # FP32 Y only, no factor tables
+    with pytest.raises(vis.VisError):
+        vis.Field.from_config(basis, cfg, vis.VIS_FP32, vis.VIS_SYNTH_SEPARABLE)
+    sb = vis.Basis(cfg.grid_nz, cfg.grid_nphi, cfg.lmax, vis.STORAGE_SEPARABLE)
+    with pytest.raises(vis.VisError):
+        vis.Field.from_config(sb, cfg, vis.VIS_BF16X3, vis.VIS_SYNTH_SEPARABLE)
+    with pytest.raises(vis.VisError):
+        vis.Field.from_config(sb, cfg, vis.VIS_FP32, vis.VIS_SYNTH_DENSE)   # no Y stored
+
+
+def test_c1_separable_sampled(vis, c1, c1_ref, c1_grad_ref):
+    """Full C1 size with separable synthesis against the oracle."""
+    cfg, _, _, d = c1
+    basis, fld = _sep_field(vis, cfg)
+    alm, g, fw = _dev_params(d, cfg)
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    err = chan_rel_err(m[:, C1_CHANS], c1_ref)
+    say("c1 separable per-channel rel err", err)
+    assert np.all(err <= 1e-5)
+    data, sig, rga, rgg = c1_grad_ref
+    alm, g, fw = _dev_params(d, cfg, alm_scale=1.2)
+    x2, ga, gg, gf = vis.chi2_and_grad(fld, torch.tensor(data, device="cuda"), sig, alm, g, fw)
+    e_a = rel_norm(ga[C1_GRAD_CHAN].cpu().numpy(), rga)
+    e_g = rel_norm(gg[C1_GRAD_CHAN].cpu().numpy(), rgg)
+    say("c1 separable grad errs", e_a, e_g)
+    assert e_a <= 2e-4 and e_g <= 2e-4
