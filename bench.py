@@ -2,7 +2,8 @@
 
 Step: one leapfrog step of an HMC chain on the 61-dish hex / 49152-pixel /
 lmax 100 / 64-channel / 60-time workload, run through the serving runtime:
-kick + drift, sky synthesis I = Y a, forward fringe contraction, gains +
+kick + drift, sky synthesis I = Y a (separable Legendre + azimuthal stages by
+default, `--synthesis dense` for the product with the stored Y), forward fringe contraction, gains +
 residual + FP64 chi^2, residual collapse and gain gradient, adjoint fringe
 contraction, adjoint synthesis, prior terms + kick, FP64 energy partials
 (and the Metropolis test at the end of the trajectory).  The timed chain has
@@ -16,9 +17,9 @@ counted once for the forward and once for the adjoint contraction.
 Serving (`serving` key): 64 concurrent chains on uneven hex fields
 (19-127 dishes, 16-128 channels, 10-120 times, lmax 30-100), one trajectory
 of 20 leapfrog steps each, through the batched server with split-precision
-(bf16 hi/lo) synthesis, against the same request stream through the plain
-FP32 path one request per tick: gradient evaluations per second and request
-latency p50/p99.
+(bf16 hi/lo) dense synthesis and with FP32 separable synthesis, against the
+same request stream through the plain FP32 dense path one request per tick:
+gradient evaluations per second and request latency p50/p99.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -101,10 +102,10 @@ def cpu_baseline(cfg, chan: int = 37):
                        f"elementwise NumPy single-threaded, BLAS {blas_threads} threads")}
 
 
-def make_chain(vis, serve, torch, basis, cfg, prec, start_scale=1.0):
+def make_chain(vis, serve, torch, basis, cfg, prec, synthesis=0):
     """Field, synthetic data, inverse mass and prior for one chain of config cfg."""
     from paper_2504_07090_amd import workload as w
-    fld = vis.Field.from_config(basis, cfg, prec)
+    fld = vis.Field.from_config(basis, cfg, prec, synthesis)
     d = w.draw(cfg)
     alm = torch.tensor(d.alm, dtype=torch.float32, device="cuda")
     g = torch.tensor(d.gains, dtype=torch.complex64, device="cuda")
@@ -150,10 +151,11 @@ def serving_inputs(vis, serve, torch, basis, n_chains):
     return out
 
 
-def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=20):
+def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=20, synthesis=0):
     """One trajectory of n_leapfrog steps per chain; all chains submitted at once."""
     n_chains = len(inputs)
-    flds = [f if prec == vis.VIS_FP32 else vis.Field.from_config(basis, cfg, prec)
+    flds = [f if (prec == vis.VIS_FP32 and synthesis == 0)
+            else vis.Field.from_config(basis, cfg, prec, synthesis)
             for (cfg, f, *_rest) in inputs]
     fp = sum(serve.Server.footprint(f) for f in flds)
     srv = serve.Server(fp + (64 << 20), max_chains=n_chains, max_batch=max_batch,
@@ -188,6 +190,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--serve-precision", default="bf16x3", choices=["bf16x3", "fp16x3"])
+    ap.add_argument("--synthesis", default="separable", choices=["separable", "dense"],
+                    help="sky synthesis of the timed chain (separable: FP32 only)")
     ap.add_argument("--serve-chains", type=int, default=64)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -207,11 +211,15 @@ def main():
     precs = {"fp32": vis.VIS_FP32, "bf16x3": vis.VIS_BF16X3, "fp16x3": vis.VIS_FP16X3}
     prec = precs[args.precision]
     sprec = precs[args.serve_precision]
-    log("basis + fields", cfg.name)
-    storage = vis.STORAGE_FOR[prec] | (0 if args.no_serve else 1 | vis.STORAGE_FOR[sprec])
+    synth = vis.VIS_SYNTH_SEPARABLE if args.synthesis == "separable" else vis.VIS_SYNTH_DENSE
+    if synth == vis.VIS_SYNTH_SEPARABLE and prec != vis.VIS_FP32:
+        raise SystemExit("separable synthesis runs in FP32 only")
+    log("basis + fields", cfg.name, args.synthesis, "synthesis")
+    storage = (vis.STORAGE_SEPARABLE if synth == vis.VIS_SYNTH_SEPARABLE else vis.STORAGE_FOR[prec]) | \
+        (0 if args.no_serve else 1 | vis.STORAGE_FOR[sprec] | vis.STORAGE_SEPARABLE)
     basis = vis.basis_for(cfg, storage=storage)
-    warm = make_chain(vis, serve, torch, basis, cfg, prec)
-    timed = make_chain(vis, serve, torch, basis, cfg, prec)
+    warm = make_chain(vis, serve, torch, basis, cfg, prec, synth)
+    timed = make_chain(vis, serve, torch, basis, cfg, prec, synth)
     fld = timed[0]
     srv = serve.Server(serve.Server.footprint(fld) * 2 + (64 << 20), max_chains=2, max_batch=2)
     fldw, dataw, sigw, q0w, minvw, cvarw, _ = warm
@@ -265,14 +273,19 @@ def main():
     if not args.no_serve:
         log("serving: building", args.serve_chains, "uneven chains")
         ins = serving_inputs(vis, serve, torch, basis, args.serve_chains)
-        log("serving: batched,", args.serve_precision, "synthesis")
+        log("serving: batched,", args.serve_precision, "dense synthesis")
         fast = serving_bench(vis, serve, torch, basis, ins, sprec, max_batch=args.serve_chains)
-        log("serving: per-chain FP32 baseline, one request per tick")
+        log("serving: batched, FP32 separable synthesis")
+        sep = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32, max_batch=args.serve_chains,
+                            synthesis=vis.VIS_SYNTH_SEPARABLE)
+        log("serving: per-chain FP32 baseline (dense synthesis), one request per tick")
         base = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32, max_batch=1)
         del ins
         serving = {"chains": args.serve_chains, "leapfrog_steps": 20,
-                   "batched_" + args.serve_precision: fast, "per_chain_fp32": base,
-                   "speedup": fast["grad_evals_per_s"] / base["grad_evals_per_s"]}
+                   "batched_" + args.serve_precision: fast, "batched_fp32_separable": sep,
+                   "per_chain_fp32": base,
+                   "speedup": fast["grad_evals_per_s"] / base["grad_evals_per_s"],
+                   "speedup_separable": sep["grad_evals_per_s"] / base["grad_evals_per_s"]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -285,7 +298,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if prec == vis.VIS_FP32 else args.precision,
         "data": "synthetic",
-        "config": {"workload": cfg.name, "n_ant": fld.n_ant, "n_bl": fld.n_bl, "n_ubl": fld.n_ubl,
+        "config": {"workload": cfg.name, "synthesis": args.synthesis,
+                   "n_ant": fld.n_ant, "n_bl": fld.n_bl, "n_ubl": fld.n_ubl,
                    "n_pix": fld.info.n_pix, "n_pix_visible": nv, "lmax": cfg.lmax,
                    "n_freq": cfg.n_freq, "n_time": cfg.n_time, "fwd_macs": fld.fwd_macs,
                    "leapfrog_steps": args.steps},
