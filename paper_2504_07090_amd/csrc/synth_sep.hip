@@ -32,6 +32,9 @@ __device__ __forceinline__ f4 sep_mfma(float a, float b, f4 c) {
 
 __device__ __forceinline__ int tri(int l, int am) { return l * (l + 1) / 2 + am; }
 
+constexpr int kSepBatch = 8;              // MFMAs whose operand loads are issued together
+constexpr int kSepStep = 4 * kSepBatch;   // K covered per batch
+
 // G[j][c][nu] = sum_{l=|m|}^{lmax} lam[j][tri(l, |m|)] a[nu][l^2 + l + m],  c = m + lmax.
 // grid (2 lmax + 1, ceil(nz / 16), ceil(nf / 16)); D rows = rings, columns = channels.
 __global__ void __launch_bounds__(64)
@@ -44,17 +47,17 @@ k_sep_leg_fwd(int nz, int nf, int nm, int lmax, int ntri, int kaz, const float* 
   const float* lrow = lam + static_cast<size_t>(j) * ntri;
   const float* arow = alm + static_cast<size_t>(f) * nm;
   f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-  for (int l0 = am; l0 <= lmax; l0 += 16) {
-    float a[4], b[4];
+  for (int l0 = am; l0 <= lmax; l0 += kSepStep) {
+    float a[kSepBatch], b[kSepBatch];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kSepBatch; ++q) {
       const int l = l0 + 4 * q + kk;
       const bool ok = l <= lmax;
       a[q] = ok ? lrow[tri(l, am)] : 0.f;
       b[q] = ok ? arow[l * l + l + m] : 0.f;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc = sep_mfma(a[q], b[q], acc);
+    for (int q = 0; q < kSepBatch; ++q) acc = sep_mfma(a[q], b[q], acc);
   }
   const int c = m + lmax, fo = f0 + (lane & 15);
 #pragma unroll
@@ -76,17 +79,17 @@ k_sep_az_fwd(int nphi, int nf, int kaz, int nc, int toff, const float* __restric
   const float* grow = G + static_cast<size_t>(j) * kaz * nf + f;
   const float* tcol = Tt + static_cast<size_t>(toff) * nphi + k;
   f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-  for (int c0 = 0; c0 < nc; c0 += 16) {
-    float a[4], b[4];
+  for (int c0 = 0; c0 < nc; c0 += kSepStep) {
+    float a[kSepBatch], b[kSepBatch];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kSepBatch; ++q) {
       const int c = c0 + 4 * q + kk;
       const bool ok = c < nc;
       a[q] = ok ? grow[static_cast<size_t>(c) * nf] : 0.f;
       b[q] = ok ? tcol[static_cast<size_t>(c) * nphi] : 0.f;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc = sep_mfma(a[q], b[q], acc);
+    for (int q = 0; q < kSepBatch; ++q) acc = sep_mfma(a[q], b[q], acc);
   }
   const int ko = k0 + (lane & 15);
   if (ko < nphi) {
@@ -133,17 +136,17 @@ k_sep_az_adj(int nphi, int nf, int kaz, int nc, int kaz_t, int toff, const float
   const float* trow = T + toff + c;
   const float* drow = dfull + static_cast<size_t>(j) * nphi * nf + f;
   f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < nphi; k0 += 16) {
-    float a[4], b[4];
+  for (int k0 = 0; k0 < nphi; k0 += kSepStep) {
+    float a[kSepBatch], b[kSepBatch];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kSepBatch; ++q) {
       const int k = k0 + 4 * q + kk;
       const bool ok = k < nphi;
       a[q] = ok ? trow[static_cast<size_t>(k) * kaz_t] : 0.f;
       b[q] = ok ? drow[static_cast<size_t>(k) * nf] : 0.f;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc = sep_mfma(a[q], b[q], acc);
+    for (int q = 0; q < kSepBatch; ++q) acc = sep_mfma(a[q], b[q], acc);
   }
   const int fo = f0 + (lane & 15);
 #pragma unroll
@@ -166,17 +169,17 @@ k_sep_leg_adj(int nz, int nf, int nm, int lmax, int ntri, int kaz, const float* 
   const int c = m + lmax;
   const float* hcol = H + static_cast<size_t>(c) * nf + f;
   f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-  for (int jb = 0; jb < nz; jb += 16) {
-    float a[4], b[4];
+  for (int jb = 0; jb < nz; jb += kSepStep) {
+    float a[kSepBatch], b[kSepBatch];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kSepBatch; ++q) {
       const int j = jb + 4 * q + kk;
       const bool ok = j < nz;
       a[q] = ok ? lam[static_cast<size_t>(j) * ntri + tri(l, am)] : 0.f;
       b[q] = ok ? hcol[static_cast<size_t>(j) * kaz * nf] : 0.f;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc = sep_mfma(a[q], b[q], acc);
+    for (int q = 0; q < kSepBatch; ++q) acc = sep_mfma(a[q], b[q], acc);
   }
   const int fo = f0 + (lane & 15);
 #pragma unroll

@@ -110,18 +110,28 @@ def test_trajectory_matches_oracle(mods):
         np.testing.assert_allclose(qg, q_or, rtol=1e-6)
 
 
+# (hex side, channels, times, lmax, precision, synthesis): every evaluation path
+# of the library appears in the mix
+MIXED = [(3, 4, 3, 10, 1, 0), (4, 3, 5, 14, 1, 1), (3, 6, 2, 20, 2, 0), (5, 2, 4, 8, 3, 0),
+         (4, 5, 3, 16, 1, 1)]
+
+
 def _mixed_fields(vis, basis):
     cfgs = [w.scaled(w.C0, array="hex", array_size=s, n_freq=nf, n_time=nt, lmax=lm,
                      freq_lo_hz=120e6, freq_hi_hz=130e6, seed=3000 + i)
-            for i, (s, nf, nt, lm) in enumerate([(3, 4, 3, 10), (4, 3, 5, 14), (3, 6, 2, 20),
-                                                 (5, 2, 4, 8), (4, 5, 3, 16)])]
-    return cfgs, [vis.Field.from_config(basis, c) for c in cfgs]
+            for i, (s, nf, nt, lm, _, _) in enumerate(MIXED)]
+    return cfgs, [vis.Field.from_config(basis, c, prec, syn)
+                  for c, (*_, prec, syn) in zip(cfgs, MIXED)]
+
+
+def _mixed_basis(vis):
+    return vis.Basis(32, 96, 20, 1 | 2 | 4 | vis.STORAGE_SEPARABLE)
 
 
 def test_alone_equals_mix(mods):
     """A chain's trajectories are bitwise identical alone and batched with others."""
     vis, serve = mods
-    basis = vis.Basis(32, 96, 20, 1)
+    basis = _mixed_basis(vis)
     cfgs, flds = _mixed_fields(vis, basis)
     inputs = []
     for c, f in zip(cfgs, flds):
@@ -153,7 +163,7 @@ def test_alone_equals_mix(mods):
 
 def test_admission_by_footprint_and_release(mods):
     vis, serve = mods
-    basis = vis.Basis(32, 96, 20, 1)
+    basis = _mixed_basis(vis)
     cfgs, flds = _mixed_fields(vis, basis)
     fps = [serve.Server.footprint(f) for f in flds[:3]]
     # room for the tick tables, chains 0 and 1, and 256 bytes less than chain 2 needs:
@@ -192,7 +202,7 @@ def test_admission_by_footprint_and_release(mods):
 
 def test_nonfinite_chain_is_isolated(mods):
     vis, serve = mods
-    basis = vis.Basis(32, 96, 20, 1)
+    basis = _mixed_basis(vis)
     cfgs, flds = _mixed_fields(vis, basis)
     srv = serve.Server(128 << 20, max_chains=4, max_batch=4)
     good = _chain_inputs(vis, serve, flds[0], cfgs[0], w.draw(cfgs[0]))
@@ -215,7 +225,7 @@ def test_nonfinite_chain_is_isolated(mods):
 
 def test_latency_stats_recorded(mods):
     vis, serve = mods
-    basis = vis.Basis(32, 96, 20, 1)
+    basis = _mixed_basis(vis)
     cfgs, flds = _mixed_fields(vis, basis)
     srv = serve.Server(128 << 20, max_chains=4, max_batch=4)
     ins = _chain_inputs(vis, serve, flds[0], cfgs[0], w.draw(cfgs[0]))
