@@ -60,6 +60,19 @@ __device__ __forceinline__ void sincos_rev(float x, float& s, float& c) {
 #endif
 }
 
+// x[l] + x[l ^ 16] and x[l] + x[l ^ 32] with the gfx950 lane-swap instructions
+// (vector ALU; a generic shuffle would go through the LDS crossbar).
+__device__ __forceinline__ float sum_xor16(float x) {
+  const unsigned u = __float_as_uint(x);
+  const auto p = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+__device__ __forceinline__ float sum_xor32(float x) {
+  const unsigned u = __float_as_uint(x);
+  const auto p = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  return __uint_as_float(p[0]) + __uint_as_float(p[1]);
+}
+
 // Reduced phase of nu * p in cycles, in [-1/2, 1/2], formed in FP64.
 __device__ __forceinline__ float reduced_cycles(double nu, double p) {
   const double x = nu * p;
@@ -385,8 +398,7 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
         float zp = 0.f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) zp += av[r] * tacc[pg][r];
-        zp += __shfl_xor(zp, 16);
-        zp += __shfl_xor(zp, 32);
+        zp = sum_xor32(sum_xor16(zp));
         if ((lane >> 4) == pg) zcore += zp;
       }
     }
