@@ -192,6 +192,48 @@ vis_status chi2_and_grad(const vis_field* field, const vis_c64* data, float sigm
                          double* chi2, float* grad_alm, vis_c64* grad_gains,
                          float* grad_fwhm, void* stream);
 
+/* --------------------------------------------------------- delay filter --
+ * Sec. 2.1 (eq. rime_filter, eq. gpr) and Sec. 3.5 (eq. filtered_noise):
+ * model and data are multiplied along frequency by the real high-pass filter
+ *     F = I - C_fg (C_fg + noise_ratio I)^-1,
+ *     C_fg(nu, nu') = sinc(2 tau_max (nu - nu')),  sinc(x) = sin(pi x) / (pi x),
+ * (a tophat of half-width tau_max in delay; the paper uses 250 ns and 1e-8)
+ * and the likelihood keeps the diagonal of the filtered noise covariance:
+ *     chi^2_F = sum |(F (d - m))_nu|^2 / (sigma_n^2 (F F^T)_nu,nu).
+ *
+ * vis_filter_build: host only (no device call).  F_out [n_freq][n_freq]
+ *   row-major and fft_diag [n_freq] = (F F^T)_nu,nu, both FP64, computed with
+ *   a Cholesky solve of (C_fg + noise_ratio I).  VIS_EINVAL: n_freq out of
+ *   [1, 4096], non-finite or non-positive frequencies, tau_max < 0,
+ *   noise_ratio <= 0, or a matrix that is not positive definite.
+ * vis_filter_create: builds F and uploads it (FP32) into the caller's
+ *   workspace (vis_filter_workspace_bytes); the filter belongs to any field
+ *   with the same channels.                                                 */
+typedef struct vis_filter vis_filter;
+
+vis_status vis_filter_build(int32_t n_freq, const double* freq_hz, double tau_max_s,
+                            double noise_ratio, double* F_out, double* fft_diag);
+vis_status vis_filter_workspace_bytes(int32_t n_freq, size_t* bytes);
+vis_status vis_filter_create(int32_t n_freq, const double* freq_hz, double tau_max_s,
+                             double noise_ratio, void* workspace_dev, size_t bytes, void* stream,
+                             vis_filter** out);
+vis_status vis_filter_destroy(vis_filter* filter);
+
+/* chi2_filtered_and_grad: chi^2_F and its gradient (same outputs and NULL
+ * rules as chi2_and_grad).  The filter couples channels, so the whole field
+ * is evaluated: model visibilities, then F (d - m) and the cotangent
+ * -2 F^T ((F (d - m)) / N~) as two real GEMMs over frequency per time on
+ * MFMA, then the adjoint pass.  work: device scratch of at least
+ * vis_filtered_work_bytes(field) bytes, owned by the caller, not kept
+ * between calls.  VIS_EINVAL: the filter's n_freq differs from the field's;
+ * VIS_ENOMEM: work too small.                                              */
+vis_status vis_filtered_work_bytes(const vis_field* field, size_t* bytes);
+vis_status chi2_filtered_and_grad(const vis_field* field, const vis_filter* filter,
+                                  const vis_c64* data, float sigma_n, const float* alm,
+                                  const vis_c64* gains, const float* fwhm, double* chi2,
+                                  float* grad_alm, vis_c64* grad_gains, float* grad_fwhm,
+                                  void* work, size_t work_bytes, void* stream);
+
 /* ------------------------------------------------------------ profiling --
  * Optional per-field kernel timing: when enabled, every kernel the field
  * launches is bracketed by a pair of hipEvents on the launch stream and its

@@ -16,6 +16,7 @@ follows.  Modules:
 ``sky``        equal-area grid, real spherical harmonics, I = Y a     Sec. 2.1, 3.2, App. A
 ``rime``       directions, Gaussian power beam, direct-sum RIME       Sec. 2.1 (eq. rime_discrete)
 ``model``      gains, residual, chi^2 and its analytic gradient       Sec. 2.3 (eq. likelihood)
+``filter``     delay filter and the filtered chi^2                   Sec. 2.1 (eq. rime_filter, gpr), 3.5
 ``hmc``        leapfrog / Hamiltonian with a diagonal mass matrix    Sec. 4.2, App. B
 ``philox``     Philox-4x32-10 counter-based generator (Salmon et al. 2011)
 

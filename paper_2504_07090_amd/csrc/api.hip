@@ -80,4 +80,27 @@ vis_status chi2_and_grad(const vis_field* f, const vis_c64* data, float sigma_n,
   });
 }
 
+vis_status chi2_filtered_and_grad(const vis_field* f, const vis_filter* flt, const vis_c64* data,
+                                  float sigma_n, const float* alm, const vis_c64* gains,
+                                  const float* fwhm, double* chi2, float* grad_alm,
+                                  vis_c64* grad_gains, float* grad_fwhm, void* work,
+                                  size_t work_bytes, void* stream) {
+  return guarded([&] {
+    check_field(f);
+    BV_REQUIRE(data && alm && gains && fwhm && chi2 && work, VIS_EINVAL, "null device pointer");
+    BV_REQUIRE(sigma_n > 0.f && sigma_n < 3.0e38f, VIS_EINVAL, "sigma_n must be positive and finite");
+    const FilteredWork w = carve_filtered_work(f, work, work_bytes);
+    hipStream_t s = as_stream(stream);
+    forward_core(f, alm, fwhm, s);
+    launch_gains(f, kGainFwd, f->scr.vu, reinterpret_cast<const float2*>(gains), nullptr, 0.f, w.m,
+                 nullptr, nullptr, nullptr, s);
+    launch_filter_chi2(f, flt, reinterpret_cast<const float2*>(data), sigma_n, w, chi2, s);
+    if (!(grad_alm || grad_gains || grad_fwhm)) return;
+    launch_filter_cot(f, flt, w, s);
+    launch_gains(f, kGainAdj, f->scr.vu, reinterpret_cast<const float2*>(gains), w.m, 0.f, nullptr,
+                 nullptr, f->scr.gco, f->scr.g_part, s);
+    adjoint_tail(f, fwhm, grad_alm, reinterpret_cast<float2*>(grad_gains), grad_fwhm, false, nullptr, s);
+  });
+}
+
 }  // extern "C"

@@ -149,6 +149,21 @@ inline int adj_coef_stride(int dtile) {
   return static_cast<int>(round_up(rt * rt * 256 + 4 * dtile, 64));
 }
 
+// Delay-filtered likelihood: scratch carved from the caller's work buffer
+// (model / cotangent visibilities, the weighted filtered residual, chi^2
+// partials per wavefront), and the two GEMM passes over frequency.
+struct FilteredWork {
+  float2* m = nullptr;      // [n_time][n_freq][n_bl] model, then the cotangent
+  float2* w = nullptr;      // [n_time][n_freq][n_bl] F (d - m) / N~
+  double* part = nullptr;
+  long nparts = 0;
+  size_t bytes = 0;
+};
+FilteredWork carve_filtered_work(const vis_field* f, void* work, size_t bytes);
+void launch_filter_chi2(const vis_field* f, const vis_filter* flt, const float2* data, float sigma_n,
+                        const FilteredWork& w, double* chi2, hipStream_t st);
+void launch_filter_cot(const vis_field* f, const vis_filter* flt, const FilteredWork& w, hipStream_t st);
+
 enum GainMode { kGainFwd = 0, kGainChi2 = 1, kGainAdj = 2 };
 void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const float2* gains,
                   const float2* data_or_dvis, float sigma_n, float2* vis_out, double* chi_part,

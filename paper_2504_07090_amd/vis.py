@@ -281,6 +281,78 @@ class VisChi2Function(torch.autograd.Function):
         return ga * s, gg * s, gf * s, None, None, None
 
 
+# ------------------------------------------------------------------ delay filter --
+_dp = C.POINTER(C.c_double)
+_lib.vis_filter_build.argtypes = [C.c_int32, _dp, C.c_double, C.c_double, _dp, _dp]
+_lib.vis_filter_workspace_bytes.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+_lib.vis_filter_create.argtypes = [C.c_int32, _dp, C.c_double, C.c_double, _vp, C.c_size_t, _vp,
+                                   C.POINTER(_vp)]
+_lib.vis_filter_destroy.argtypes = [_vp]
+_lib.vis_filtered_work_bytes.argtypes = [_vp, C.POINTER(C.c_size_t)]
+_lib.chi2_filtered_and_grad.argtypes = [_vp, _vp, _vp, C.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                        _vp, C.c_size_t, _vp]
+
+
+def filter_build(freqs, tau_max: float = 250e-9, noise_ratio: float = 1e-8):
+    """The library's delay filter F and diag(F F^T), computed on the host (FP64)."""
+    fr = np.ascontiguousarray(np.asarray(freqs, dtype=np.float64))
+    n = len(fr)
+    f = np.empty((n, n), dtype=np.float64)
+    d = np.empty(n, dtype=np.float64)
+    _check(_lib.vis_filter_build(n, fr.ctypes.data_as(_dp), float(tau_max), float(noise_ratio),
+                                 f.ctypes.data_as(_dp), d.ctypes.data_as(_dp)), "vis_filter_build")
+    return f, d
+
+
+class Filter:
+    """Delay filter of one channel list, resident on the device."""
+
+    def __init__(self, freqs, tau_max: float = 250e-9, noise_ratio: float = 1e-8,
+                 device: str = "cuda"):
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
+        fr = np.ascontiguousarray(np.asarray(freqs, dtype=np.float64))
+        nbytes = C.c_size_t()
+        _check(_lib.vis_filter_workspace_bytes(len(fr), C.byref(nbytes)), "filter size")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        _check(_lib.vis_filter_create(len(fr), fr.ctypes.data_as(_dp), float(tau_max),
+                                      float(noise_ratio), _ptr(self.workspace), nbytes.value,
+                                      C.c_void_p(_stream()), C.byref(h)), "vis_filter_create")
+        self.handle = h
+        self._lib = _lib
+        self.n_freq = len(fr)
+
+    def __del__(self):
+        h, lib = getattr(self, "handle", None), getattr(self, "_lib", None)
+        if h and lib is not None:
+            lib.vis_filter_destroy(h)
+            self.handle = None
+
+
+def chi2_filtered_and_grad(field: Field, filt: Filter, data, sigma_n: float, alm, gains, fwhm,
+                           grads: bool = True):
+    """(chi^2_F as a 0-d float64 tensor, gradients) of the delay-filtered likelihood."""
+    field._params(alm, gains, fwhm)
+    _need(data, "data", torch.complex64, field._vis_shape(), field.device)
+    if not (sigma_n > 0 and math.isfinite(sigma_n)):
+        raise ValueError("sigma_n must be positive and finite")
+    nbytes = C.c_size_t()
+    _check(_lib.vis_filtered_work_bytes(field.handle, C.byref(nbytes)), "filtered work size")
+    work = torch.empty(nbytes.value, dtype=torch.uint8, device=field.device)
+    x2 = torch.empty((), dtype=torch.float64, device=field.device)
+    if grads:
+        ga, gg, gf = torch.empty_like(alm), torch.empty_like(gains), torch.empty_like(fwhm)
+    else:
+        ga = gg = gf = None
+    _check(_lib.chi2_filtered_and_grad(field.handle, filt.handle, _ptr(data), C.c_float(sigma_n),
+                                       _ptr(alm), _ptr(gains), _ptr(fwhm), _ptr(x2), _ptr(ga),
+                                       _ptr(gg), _ptr(gf), _ptr(work), nbytes.value,
+                                       C.c_void_p(_stream())), "chi2_filtered_and_grad")
+    return x2, ga, gg, gf
+
+
 class KernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
