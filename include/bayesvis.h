@@ -192,6 +192,23 @@ vis_status chi2_and_grad(const vis_field* field, const vis_c64* data, float sigm
                          double* chi2, float* grad_alm, vis_c64* grad_gains,
                          float* grad_fwhm, void* stream);
 
+/* ------------------------------------------------------------ map-making --
+ * vis_make_map: the diagonally normalised map estimate of Sec. 6
+ * (eq. vis_to_map, eq. map_psf) per channel,
+ *     map_p = Re(A^H y)_p / (A^H A)_pp,
+ * with A the beam-and-fringe response including the gains (eq. rime_matrix)
+ * stacked over times and baselines; this is x_hat = D A^H N^-1 y for
+ * N proportional to the identity and D = diag(A^H N^-1 A)^-1, so the
+ * point-spread function has a unit diagonal.  data device [n_time][n_freq]
+ * [n_bl] vis_c64; gains, fwhm as for vis_forward; map device [n_freq][n_pix]
+ * (grid order, ring-major) float, 0 for pixels never above the horizon and
+ * where (A^H A)_pp < 1e-6 max_p (A^H A)_pp of the channel (there the ratio
+ * only amplifies noise);
+ * weight (may be NULL) device [n_freq][n_pix] float, (A^H A)_pp.  Runs the
+ * adjoint fringe pass unchanged; the field's scratch is reused.            */
+vis_status vis_make_map(const vis_field* field, const vis_c64* data, const vis_c64* gains,
+                        const float* fwhm, float* map, float* weight, void* stream);
+
 /* --------------------------------------------------------- delay filter --
  * Sec. 2.1 (eq. rime_filter, eq. gpr) and Sec. 3.5 (eq. filtered_noise):
  * model and data are multiplied along frequency by the real high-pass filter

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbayesvis.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["field.hip", "synth.hip", "synth_split.hip", "synth_sep.hip", "fringe.hip", "gains.hip", "filter.hip", "api.hip",
+SOURCES = ["field.hip", "synth.hip", "synth_split.hip", "synth_sep.hip", "fringe.hip", "gains.hip", "filter.hip", "mapmaking.hip", "api.hip",
            "hmc.hip", "serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

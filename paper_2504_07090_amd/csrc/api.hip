@@ -80,6 +80,19 @@ vis_status chi2_and_grad(const vis_field* f, const vis_c64* data, float sigma_n,
   });
 }
 
+vis_status vis_make_map(const vis_field* f, const vis_c64* data, const vis_c64* gains,
+                        const float* fwhm, float* map, float* weight, void* stream) {
+  return guarded([&] {
+    check_field(f);
+    BV_REQUIRE(data && gains && fwhm && map, VIS_EINVAL, "null device pointer");
+    hipStream_t s = as_stream(stream);
+    launch_gains(f, kGainMap, f->scr.vu, reinterpret_cast<const float2*>(gains),
+                 reinterpret_cast<const float2*>(data), 0.f, nullptr, nullptr, f->scr.gco, nullptr, s);
+    launch_fringe_adj(f, f->scr.img, fwhm, f->scr.gco, f->scr.dimg, f->scr.f_part, s);
+    launch_map_finish(f, gains, fwhm, map, weight, s);
+  });
+}
+
 vis_status chi2_filtered_and_grad(const vis_field* f, const vis_filter* flt, const vis_c64* data,
                                   float sigma_n, const float* alm, const vis_c64* gains,
                                   const float* fwhm, double* chi2, float* grad_alm,

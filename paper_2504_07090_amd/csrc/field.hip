@@ -354,9 +354,9 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
   S.img = cv.take<float>(nfq * nvp);
   if (dense) S.apad = cv.take<float>(static_cast<size_t>(round_up(f->n_freq, 64)) * kpad);
   S.dimg = cv.take<float>(nfq * nvp);
+  T.vidx = cv.take<int>(f->basis->n_pix);
   if (!dense) {
     const size_t npix = f->basis->n_pix;
-    T.vidx = cv.take<int>(npix);
     S.sep_g = cv.take<float>(static_cast<size_t>(f->basis->nz) * f->kaz * nfq);
     S.sep_dfull = cv.take<float>(npix * nfq);
   }
@@ -602,10 +602,12 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
     up(T.ulut, ulut, s);
     // the padded tail of the sky scratch must stay finite (it is multiplied by a zero beam)
     BV_HIP(hipMemsetAsync(f->scr.img, 0, sizeof(float) * f->n_freq * f->nv_pad, s));
-    if (f->synthesis == VIS_SYNTH_SEPARABLE) {
+    {
       std::vector<int> vidx(basis->n_pix, -1);
       for (int k = 0; k < f->nv; ++k) vidx[g.vpix[k]] = k;
       up(T.vidx, vidx, s);
+    }
+    if (f->synthesis == VIS_SYNTH_SEPARABLE) {
       // rows of the Legendre stage beyond 2 lmax + 1 are never written: keep them zero
       BV_HIP(hipMemsetAsync(f->scr.sep_g, 0,
                             sizeof(float) * basis->nz * f->kaz * f->n_freq, s));

@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
       return cmul(g[ij.x], conjf2(g[ij.y]));
     };
     auto cot_of = [&](int k, float2 m) {
-      if (a.mode == kGainAdj) return din[k];
+      if (a.mode == kGainAdj || a.mode == kGainMap) return din[k];
       return make_float2(-2.f * a.inv_sig2 * (din[k].x - m.x), -2.f * a.inv_sig2 * (din[k].y - m.y));
     };
     if (a.mode == kGainFwd) {
@@ -226,12 +226,14 @@ __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
             const double ry = static_cast<double>(dk.y) - m.y;
             acc += rx * rx + ry * ry;
           }
-          const float2 c = a.mode == kGainAdj
+          const float2 c = (a.mode == kGainAdj || a.mode == kGainMap)
                                ? dk
                                : make_float2(-2.f * a.inv_sig2 * (dk.x - m.x), -2.f * a.inv_sig2 * (dk.y - m.y));
           tu[pos_r[q].x] = omega_term(ucode < 0, c, G);
-          ta[pos_r[q].y] = ant_term(0, ij, c, vk);
-          ta[pos_r[q].z] = ant_term(1, ij, c, vk);
+          if (a.mode != kGainMap) {
+            ta[pos_r[q].y] = ant_term(0, ij, c, vk);
+            ta[pos_r[q].z] = ant_term(1, ij, c, vk);
+          }
         }
       }
     } else if (a.mode == kGainChi2) {
@@ -268,7 +270,7 @@ __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
         if (u < a.nubl && sub == 0) om[u] = o;
       }
     }
-    {
+    if (a.mode != kGainMap) {
       const int w = lanes_per_item(a.nant), sub = tid & (w - 1);
       for (int base = 0; base < a.nant; base += 256 / w) {
         const int ant = base + tid / w;

@@ -87,7 +87,7 @@ struct FieldScratch {
 struct FieldTables {
   double* freq = nullptr;          // [n_freq] Hz
   int* vpix = nullptr;             // [nv_pad] pixel index of each visible slot
-  int* vidx = nullptr;             // separable fields: [n_pix] visible slot of each pixel or -1
+  int* vidx = nullptr;             // [n_pix] visible slot of each pixel or -1
   double* p1 = nullptr;            // [n_time][nv_pad] (e1 . s) / c, seconds
   double* p2 = nullptr;            // [n_time][nv_pad] (e2 . s) / c
   float* th2 = nullptr;            // [n_time][nv_pad] zenith angle^2, kBelowHorizon if U <= 0
@@ -164,7 +164,11 @@ void launch_filter_chi2(const vis_field* f, const vis_filter* flt, const float2*
                         const FilteredWork& w, double* chi2, hipStream_t st);
 void launch_filter_cot(const vis_field* f, const vis_filter* flt, const FilteredWork& w, hipStream_t st);
 
-enum GainMode { kGainFwd = 0, kGainChi2 = 1, kGainAdj = 2 };
+// kGainMap: the adjoint pass's collapse of a given cotangent onto the unique
+// baselines only (no gain gradient; the unique visibilities are not read).
+enum GainMode { kGainFwd = 0, kGainChi2 = 1, kGainAdj = 2, kGainMap = 3 };
+void launch_map_finish(const vis_field* f, const vis_c64* gains, const float* fwhm, float* map,
+                       float* weight, hipStream_t st);
 void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const float2* gains,
                   const float2* data_or_dvis, float sigma_n, float2* vis_out, double* chi_part,
                   float* gco, float2* g_part, hipStream_t st);

@@ -281,6 +281,24 @@ class VisChi2Function(torch.autograd.Function):
         return ga * s, gg * s, gf * s, None, None, None
 
 
+# -------------------------------------------------------------------- map-making --
+_lib.vis_make_map.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+
+
+def make_map(field: Field, data, gains, fwhm, with_weight: bool = True):
+    """(map [n_freq][n_pix], weight [n_freq][n_pix] or None): Re(A^H y) / diag(A^H A)."""
+    dev = field.device
+    _need(gains, "gains", torch.complex64, (field.n_freq, field.n_ant), dev)
+    _need(fwhm, "fwhm", torch.float32, (1,), dev)
+    _need(data, "data", torch.complex64, field._vis_shape(), dev)
+    npix = field.info.n_pix
+    out = torch.empty((field.n_freq, npix), dtype=torch.float32, device=dev)
+    wgt = torch.empty_like(out) if with_weight else None
+    _check(_lib.vis_make_map(field.handle, _ptr(data), _ptr(gains), _ptr(fwhm), _ptr(out), _ptr(wgt),
+                             C.c_void_p(_stream())), "vis_make_map")
+    return out, wgt
+
+
 # ------------------------------------------------------------------ delay filter --
 _dp = C.POINTER(C.c_double)
 _lib.vis_filter_build.argtypes = [C.c_int32, _dp, C.c_double, C.c_double, _dp, _dp]
