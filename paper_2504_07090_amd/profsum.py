@@ -3,6 +3,9 @@
     python -m paper_2504_07090_amd.profsum stats <kernel_stats.csv> "<command>"
     python -m paper_2504_07090_amd.profsum counters <counter_collection.csv> "<command>"
 
+`traffic_report` turns one FETCH_SIZE and one WRITE_SIZE run into HBM bytes
+per launch, scaled by a device copy of known size at the end of each run.
+
 `stats` lists the kernels by total GPU time; `counters` gives, per kernel,
 the number of dispatches and the mean value of every collected counter per
 dispatch (FETCH_SIZE and WRITE_SIZE are in KiB).
@@ -54,6 +57,40 @@ def summarise_counters(path: str, command: str, top: int = 20) -> str:
     for k in ks:
         out.append(f"| `{k}` | {calls[k]} | " + " | ".join(f"{means[k].get(c, 0.0):.1f}" for c in names) + " |")
     return "\n".join(out) + "\n"
+
+
+def traffic_report(fetch_csv: str, write_csv: str, command: str, kernels, sha: str,
+                   copy_kib: float = 262144.0):
+    """Markdown report of HBM bytes per launch from one FETCH_SIZE and one
+    WRITE_SIZE run, each scaled by what the counter reads for the run's last
+    dispatch, a device copy of copy_kib KiB read and written."""
+    def last_copy(path):
+        rows = [r for r in csv.DictReader(open(path)) if r["Kernel_Name"] == "__amd_rocclr_copyBuffer"]
+        return float(rows[-1]["Counter_Value"])
+    cf, cw = last_copy(fetch_csv), last_copy(write_csv)
+    ff, fw = copy_kib / cf, copy_kib / cw
+    fm, fn = counter_means(fetch_csv)
+    wm, _ = counter_means(write_csv)
+    out = ["# HBM traffic of the evaluation kernels (61-dish workload)", "",
+           "Counters from two rocprofv3 runs, one per counter:", "", "```",
+           command.format(C="FETCH_SIZE"), command.format(C="WRITE_SIZE"), "```", "",
+           f"The last dispatch of each run is a {copy_kib / 1024:.0f} MiB device-to-device copy "
+           "(`--calibrate-copy`), read and written once:", "",
+           "| counter | copy reads as (KiB) | scale factor |", "|---|---:|---:|",
+           f"| FETCH_SIZE | {cf:.1f} | {ff:.3f} |", f"| WRITE_SIZE | {cw:.1f} | {fw:.3f} |", "",
+           "Per dispatch (means over the run; KiB as read, bytes after scaling):", "",
+           "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch (scaled) |",
+           "|---|---:|---:|---:|---:|"]
+    per = {}
+    for k in kernels:
+        if k not in fm:
+            continue
+        f, wv = fm[k]["FETCH_SIZE"], wm.get(k, {}).get("WRITE_SIZE", 0.0)
+        b = (f * ff + wv * fw) * 1024
+        per[k] = b
+        out.append(f"| `{k}` | {fn[k]} | {f:.1f} | {wv:.1f} | {b:.4g} |")
+    out += ["", f"Fringe kernel sources (fringe.hip, common.hpp) sha256 at the time of the runs: `{sha}`.", ""]
+    return "\n".join(out) + "\n", per
 
 
 if __name__ == "__main__":
