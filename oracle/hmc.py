@@ -1,4 +1,4 @@
-"""Hamiltonian Monte Carlo with a diagonal mass matrix (oracle).
+"""Hamiltonian Monte Carlo with a diagonal or block-dense mass matrix (oracle).
 
 Sec. 4.2 and App. B: HMC simulates Hamiltonian dynamics of position q
 (the parameters) and momentum p in the potential U = -log posterior, with
@@ -6,6 +6,10 @@ mass matrix M; the kinetic energy is K = p^T M^-1 p / 2, the position moves
 as dq/dt = M^-1 p, and momenta are drawn as p = L_M p0 with p0 ~ N(0, 1).
 For a diagonal M these reduce to element-wise operations:
     K = sum p^2 minv / 2,   dq/dt = minv p,   p = p0 / sqrt(minv).
+App. B (dense mass matrices): with a Cholesky factor M = L L^T the three
+quantities become triangular solves, K = z^T z / 2 with L z = p, the velocity
+M^-1 p = L^-T z, and momenta p = L z0 (``BlockMass``: dense blocks on chosen
+index ranges, diagonal elsewhere).
 One trajectory is L leapfrog steps of size eps,
     p <- p - eps/2 grad U(q);  q <- q + eps minv p;  p <- p - eps/2 grad U(q),
 followed by a Metropolis test accepting with probability min(1, exp(H0 - H1)),
@@ -26,8 +30,65 @@ import math
 from typing import Callable, Tuple
 
 import numpy as np
+import scipy.linalg
 
 from . import model, philox
+
+
+class DiagonalMass:
+    """M = diag(1 / minv): velocity minv p, K = sum minv p^2 / 2, p = z / sqrt(minv)."""
+
+    def __init__(self, minv: np.ndarray):
+        self.minv = np.asarray(minv, dtype=np.float64)
+
+    def velocity(self, p):
+        return self.minv * p
+
+    def kinetic(self, p) -> float:
+        return 0.5 * float(np.sum(self.minv * p * p))
+
+    def draw(self, z):
+        return z / np.sqrt(self.minv)
+
+
+class BlockMass(DiagonalMass):
+    """Diagonal mass matrix except for dense blocks M_b = L_b L_b^T on index
+    ranges [off_b, off_b + n_b) (App. B): with L z = p (forward substitution)
+    the kinetic energy is z^T z / 2 and the velocity M^-1 p = L^-T z (backward
+    substitution); momenta are drawn as p = L z0, z0 ~ N(0, 1)."""
+
+    def __init__(self, minv: np.ndarray, blocks):
+        super().__init__(minv)
+        self.blocks = [(int(o), np.asarray(l, dtype=np.float64)) for o, l in blocks]
+
+    def velocity(self, p):
+        v = super().velocity(p)
+        for o, l in self.blocks:
+            n = len(l)
+            z = scipy.linalg.solve_triangular(l, p[o:o + n], lower=True)
+            v[o:o + n] = scipy.linalg.solve_triangular(l.T, z, lower=False)
+        return v
+
+    def kinetic(self, p) -> float:
+        mask = np.ones(len(p), dtype=bool)
+        k = 0.0
+        for o, l in self.blocks:
+            n = len(l)
+            mask[o:o + n] = False
+            z = scipy.linalg.solve_triangular(l, p[o:o + n], lower=True)
+            k += 0.5 * float(z @ z)
+        return k + 0.5 * float(np.sum(self.minv[mask] * p[mask] * p[mask]))
+
+    def draw(self, z):
+        p = super().draw(z)
+        for o, l in self.blocks:
+            n = len(l)
+            p[o:o + n] = l @ z[o:o + n]
+        return p
+
+
+def _as_mass(m):
+    return m if isinstance(m, DiagonalMass) else DiagonalMass(m)
 
 
 def pack(alm: np.ndarray, gains: np.ndarray, fwhm: float) -> np.ndarray:
@@ -66,45 +127,81 @@ class Posterior:
         return u, grad
 
 
-def kinetic(p: np.ndarray, minv: np.ndarray) -> float:
-    return 0.5 * float(np.sum(minv * p * p))
+def kinetic(p: np.ndarray, minv) -> float:
+    return _as_mass(minv).kinetic(p)
 
 
 def leapfrog(q: np.ndarray, p: np.ndarray, grad: np.ndarray, eps: float, n_steps: int,
-             minv: np.ndarray, potential_and_grad: Callable):
-    """n_steps leapfrog steps from (q, p) with grad = grad U(q); returns (q, p, U, grad)."""
+             minv, potential_and_grad: Callable):
+    """n_steps leapfrog steps from (q, p) with grad = grad U(q); returns (q, p, U, grad).
+    ``minv`` is the inverse-mass diagonal or a mass object (DiagonalMass, BlockMass)."""
+    mass = _as_mass(minv)
     q = q.copy()
     p = p.copy()
     u = None
     for _ in range(n_steps):
         p = p - 0.5 * eps * grad
-        q = q + eps * minv * p
+        q = q + eps * mass.velocity(p)
         u, grad = potential_and_grad(q)
         p = p - 0.5 * eps * grad
     return q, p, u, grad
 
 
-def draw_momentum(minv: np.ndarray, seed: int, stream: int, traj: int,
+def draw_momentum(minv, seed: int, stream: int, traj: int,
                   normal_index: np.ndarray = None) -> np.ndarray:
-    """p = z / sqrt(minv); element j takes normal number normal_index[j] (default j)
-    of the (seed, stream, traj) Philox sequence."""
+    """p = M^(1/2)-factor times z; element j takes normal number normal_index[j]
+    (default j) of the (seed, stream, traj) Philox sequence."""
+    mass = _as_mass(minv)
+    n = len(mass.minv)
     if normal_index is None:
-        z = philox.normals(minv.size, seed, stream, traj)
+        z = philox.normals(n, seed, stream, traj)
     else:
         z = philox.normals(int(np.max(normal_index)) + 1, seed, stream, traj)[normal_index]
-    return z / np.sqrt(minv)
+    return mass.draw(z)
 
 
 def trajectory(q0: np.ndarray, u0: float, grad0: np.ndarray, eps: float, n_steps: int,
-               minv: np.ndarray, potential_and_grad: Callable, seed: int, stream: int,
+               minv, potential_and_grad: Callable, seed: int, stream: int,
                traj: int, normal_index: np.ndarray = None):
     """One HMC transition.  Returns (q, U, grad, accepted, H0, H1)."""
-    p0 = draw_momentum(minv, seed, stream, traj, normal_index)
-    h0 = u0 + kinetic(p0, minv)
-    q1, p1, u1, g1 = leapfrog(q0, p0, grad0, eps, n_steps, minv, potential_and_grad)
-    h1 = u1 + kinetic(p1, minv)
+    mass = _as_mass(minv)
+    p0 = draw_momentum(mass, seed, stream, traj, normal_index)
+    h0 = u0 + mass.kinetic(p0)
+    q1, p1, u1, g1 = leapfrog(q0, p0, grad0, eps, n_steps, mass, potential_and_grad)
+    h1 = u1 + mass.kinetic(p1)
     u = philox.accept_uniform(seed, stream, traj)
     accepted = math.isfinite(h1) and u < math.exp(min(0.0, h0 - h1))
     if accepted:
         return q1, u1, g1, True, h0, h1
     return q0, u0, grad0, False, h0, h1
+
+
+def gain_gauss_newton_blocks(field: model.Field, alm: np.ndarray, gains: np.ndarray,
+                             fwhm: float, sigma_n: float) -> np.ndarray:
+    """Per-channel Gauss-Newton Hessian of chi^2 / 2 in the real gain components,
+    H_f = Re(J_f^H J_f) / sigma_n^2 with J_f the Jacobian of channel f's model
+    visibilities with respect to (Re g_k, Im g_k) (App. B: the mass matrix
+    approximates the Hessian).  Each visibility is linear in every single real
+    gain component, so central differences give J_f exactly up to rounding.
+    Returns [n_freq][2 n_ant][2 n_ant] in the (Re, Im)-interleaved order."""
+    nf, na = gains.shape
+    out = np.empty((nf, 2 * na, 2 * na))
+    for f in range(nf):
+        cols = []
+        for k in range(na):
+            for d in (1.0, 1j):
+                gp, gm = gains.copy(), gains.copy()
+                gp[f, k] += d
+                gm[f, k] -= d
+                jc = (model.forward(field, alm, gp, fwhm, [f]) - model.forward(field, alm, gm, fwhm, [f])) / 2
+                cols.append(jc.reshape(-1))
+        j = np.stack(cols, axis=1)
+        out[f] = (j.conj().T @ j).real / sigma_n ** 2
+    return out
+
+
+def gain_block_mass(minv: np.ndarray, chol: np.ndarray, goff: int) -> BlockMass:
+    """BlockMass with dense per-channel gain blocks M_f = chol[f] chol[f]^T placed
+    at goff + f * n (n = chol.shape[1]); every other parameter keeps minv."""
+    n = chol.shape[1]
+    return BlockMass(minv, [(goff + f * n, np.tril(chol[f])) for f in range(chol.shape[0])])

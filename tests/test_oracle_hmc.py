@@ -101,3 +101,158 @@ def test_hmc_samples_gaussian():
     xs = np.array(xs)
     assert np.all(np.abs(xs.mean(0) - mu) < 6 * np.sqrt(var / 300))
     assert np.all(np.abs(xs.var(0) / var - 1) < 0.25)
+
+
+# ---- dense mass matrices via Cholesky factors (App. B) ----
+
+def _spd(n, rng, cond=30.0):
+    q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    return (q * np.geomspace(1.0, cond, n)) @ q.T
+
+
+def _block_mass(rng, n=12, nb=2, off=3):
+    total = off + nb * n + 2
+    minv = rng.uniform(0.5, 2.0, total)
+    ms = [_spd(n, rng) for _ in range(nb)]
+    mass = hmc.BlockMass(minv, [(off + b * n, np.linalg.cholesky(m)) for b, m in enumerate(ms)])
+    full = np.diag(1.0 / minv)
+    for b, m in enumerate(ms):
+        s = slice(off + b * n, off + (b + 1) * n)
+        full[s, s] = m
+    return mass, full
+
+
+def test_block_mass_kinetic_and_velocity_match_full_solve():
+    """K = p^T M^-1 p / 2 and dq/dt = M^-1 p through the triangular solves equal a
+    general (LU) solve with the assembled mass matrix."""
+    rng = np.random.default_rng(21)
+    mass, full = _block_mass(rng)
+    for _ in range(3):
+        p = rng.normal(size=len(full))
+        v = np.linalg.solve(full, p)
+        assert np.max(np.abs(mass.velocity(p) - v)) <= 1e-12 * np.max(np.abs(v))
+        assert abs(mass.kinetic(p) - 0.5 * p @ v) <= 1e-12 * abs(p @ v)
+
+
+def test_block_mass_momentum_covariance():
+    """Momenta p = L z0 have covariance M (Monte Carlo over trajectories)."""
+    rng = np.random.default_rng(22)
+    mass, full = _block_mass(rng, n=4, nb=1, off=1)
+    ps = np.array([hmc.draw_momentum(mass, seed=3, stream=1, traj=t) for t in range(6000)])
+    cov = ps.T @ ps / len(ps)
+    scale = np.sqrt(np.outer(np.diag(full), np.diag(full)))
+    assert np.max(np.abs(cov - full) / scale) < 0.08
+
+
+def test_block_mass_with_diagonal_factor_is_diagonal_mass():
+    """A diagonal Cholesky factor reproduces the diagonal-mass trajectory."""
+    rng = np.random.default_rng(23)
+    n = 6
+    minv = rng.uniform(0.5, 2.0, n)
+    lvals = rng.uniform(0.7, 1.5, 4)
+    bm = hmc.BlockMass(minv, [(1, np.diag(lvals))])
+    dm = minv.copy()
+    dm[1:5] = 1.0 / lvals ** 2
+    mu = rng.normal(size=n)
+    pg = lambda q: (0.5 * float(np.sum((q - mu) ** 2)), q - mu)
+    q0 = np.zeros(n)
+    u0, g0 = pg(q0)
+    a = hmc.trajectory(q0, u0, g0, 0.3, 6, bm, pg, 5, 2, 1)
+    b = hmc.trajectory(q0, u0, g0, 0.3, 6, dm, pg, 5, 2, 1)
+    assert a[3] == b[3]
+    assert np.max(np.abs(a[0] - b[0])) <= 1e-12
+    assert abs(a[4] - b[4]) <= 1e-12 * abs(b[4]) and abs(a[5] - b[5]) <= 1e-12 * abs(b[5])
+
+
+def _gain_mass(post, q0, minv):
+    nf, nm, na = post.shape
+    alm, gains, fw = hmc.unpack(q0, nf, nm, na)
+    h = hmc.gain_gauss_newton_blocks(post.field, alm, gains, fw, post.sigma_n)
+    h += np.eye(2 * na)[None] / post.gvar
+    return hmc.gain_block_mass(minv, np.linalg.cholesky(h), nf * nm), h
+
+
+def test_gain_gauss_newton_blocks_match_gradient_differences(tiny_posterior):
+    """The Gauss-Newton gain block equals the gain-gain Hessian of chi^2 / 2 at a
+    noise-free point (residual zero), where the two coincide; the Hessian is taken
+    by central differences of the oracle gradient."""
+    post, q0, _ = tiny_posterior
+    nf, nm, na = post.shape
+    alm, gains, fw = hmc.unpack(q0, nf, nm, na)
+    exact = hmc.Posterior(post.field, model.forward(post.field, alm, gains, fw), post.sigma_n,
+                          post.alm_var, 1e6)
+    h = hmc.gain_gauss_newton_blocks(post.field, alm, gains, fw, post.sigma_n)
+    f = 1
+    off = nf * nm + f * 2 * na
+    for k in (0, 3, 2 * na - 1):
+        hh = 1e-4
+        qp, qm = q0.copy(), q0.copy()
+        qp[off + k] += hh
+        qm[off + k] -= hh
+        col = (exact.potential_and_grad(qp)[1] - exact.potential_and_grad(qm)[1]) / (2 * hh)
+        ref = col[off:off + 2 * na] - np.eye(2 * na)[k] / exact.gvar
+        assert np.max(np.abs(h[f, :, k] - ref)) <= 1e-6 * np.max(np.abs(h[f]))
+        # no coupling into the other channel's gains
+        other = nf * nm
+        assert np.max(np.abs(col[other:other + 2 * na])) <= 1e-6 * np.max(np.abs(h[f]))
+
+
+def test_dense_mass_leapfrog_reversible_and_second_order(tiny_posterior):
+    post, q0, minv = tiny_posterior
+    mass, _ = _gain_mass(post, q0, minv)
+    u0, g0 = post.potential_and_grad(q0)
+    p0 = hmc.draw_momentum(mass, seed=5, stream=0, traj=0)
+    q1, p1, u1, g1 = hmc.leapfrog(q0, p0, g0, 0.1, 10, mass, post.potential_and_grad)
+    q2, p2, _, _ = hmc.leapfrog(q1, -p1, g1, 0.1, 10, mass, post.potential_and_grad)
+    assert np.max(np.abs(q2 - q0)) < 1e-10 * np.max(np.abs(q0))
+    assert np.max(np.abs(-p2 - p0)) < 1e-8 * np.max(np.abs(p0))
+    errs = []
+    for eps, n in ((0.05, 10), (0.025, 20)):
+        qe, pe, ue, _ = hmc.leapfrog(q0, p0, g0, eps, n, mass, post.potential_and_grad)
+        errs.append(abs((ue + mass.kinetic(pe)) - (u0 + mass.kinetic(p0))))
+    assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def test_dense_mass_samples_correlated_gaussian():
+    """With M equal to the precision of a strongly correlated 2-D Gaussian, HMC
+    reproduces its mean and covariance (statistical)."""
+    mu = np.array([0.5, -1.0])
+    cov = np.array([[1.0, 0.95], [0.95, 1.0]])
+    prec = np.linalg.inv(cov)
+    pg = lambda q: (0.5 * float((q - mu) @ prec @ (q - mu)), prec @ (q - mu))
+    mass = hmc.BlockMass(np.ones(2), [(0, np.linalg.cholesky(prec))])
+    q = np.zeros(2)
+    u, g = pg(q)
+    xs = []
+    for t in range(3000):
+        q, u, g, acc, h0, h1 = hmc.trajectory(q, u, g, 0.5, 4, mass, pg, 13, 0, t)
+        if t >= 100:
+            xs.append(q.copy())
+    xs = np.array(xs)
+    c = np.cov(xs.T)
+    assert np.all(np.abs(xs.mean(0) - mu) < 0.1)
+    assert np.max(np.abs(c - cov)) < 0.12
+
+
+def test_planted_forward_only_velocity_is_caught(monkeypatch):
+    """Dropping the backward substitution (velocity L^-1 p) breaks the solve pin."""
+    def vel(self, p):
+        v = hmc.DiagonalMass.velocity(self, p)
+        for o, l in self.blocks:
+            v[o:o + len(l)] = np.linalg.solve(l, p[o:o + len(l)])
+        return v
+    monkeypatch.setattr(hmc.BlockMass, "velocity", vel)
+    with pytest.raises(AssertionError):
+        test_block_mass_kinetic_and_velocity_match_full_solve()
+
+
+def test_planted_transposed_draw_is_caught(monkeypatch):
+    """Drawing p = L^T z0 instead of L z0 breaks the covariance pin."""
+    def draw(self, z):
+        p = hmc.DiagonalMass.draw(self, z)
+        for o, l in self.blocks:
+            p[o:o + len(l)] = l.T @ z[o:o + len(l)]
+        return p
+    monkeypatch.setattr(hmc.BlockMass, "draw", draw)
+    with pytest.raises(AssertionError):
+        test_block_mass_momentum_covariance()
