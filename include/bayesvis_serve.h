@@ -13,7 +13,7 @@ extern "C" {
 
 /* ------------------------------------------------------------- serving --
  * Continuous-batching HMC server (Sec. 4.2, App. B with a diagonal mass
- * matrix).  Each chain owns a field, data, a parameter vector q =
+ * matrix, optionally with dense per-channel gain blocks).  Each chain owns a field, data, a parameter vector q =
  * [a (n_freq*n_modes), gains as (Re, Im) pairs (n_freq*n_ant*2), F] and an
  * inverse mass diagonal of the same length, all resident in the server's
  * arena.  The potential is U = chi^2/2 + sum a^2 / (2 C) + sum |g - 1|^2 /
@@ -60,6 +60,19 @@ typedef struct {
   int32_t adapt_step;
   uint64_t seed;               /* Philox key */
   uint32_t stream_id;          /* Philox counter word 2 (distinct per chain) */
+  /* Dense gain mass (App. B), or NULL for the diagonal minv everywhere.
+   * Device [n_freq][2 n_ant][2 n_ant] float, row-major: for each channel f
+   * the lower-triangular Cholesky factor L_f of the mass block M_f = L_f L_f^T
+   * over that channel's gain components in layout order (Re g_0, Im g_0,
+   * Re g_1, ...).  Only the lower triangle is read (copied into the arena at
+   * admission); the diagonal must be positive and every entry finite, else
+   * admission fails with VIS_EINVAL.  minv is then ignored on the gains; the
+   * sky coefficients and F keep their diagonal masses.  With M_f dense the
+   * server computes K = z^T z / 2 with L z = p (forward substitution), the
+   * drift eps L^-T z (backward substitution) and momenta p = L z0, where z0
+   * takes the normals a diagonal mass would use for the same elements; the
+   * inverse of M_f is never formed.  2 n_ant <= 256.                       */
+  const float* gain_chol;
 } hmc_chain_init;
 
 typedef struct {
@@ -85,6 +98,9 @@ typedef struct {
  * variances, reduction partials); admission succeeds when a free block of
  * this size exists.  The field workspace and the data are the caller's.    */
 size_t hmc_chain_footprint_bytes(const vis_field* field);
+/* The same for a chain admitted with gain_chol (adds two padded copies of the
+ * factors: about 8 n_freq (2 n_ant)^2 bytes).                              */
+size_t hmc_chain_footprint_dense_gain_bytes(const vis_field* field);
 vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size_t arena_bytes,
                              void* stream, hmc_server** out);
 /* VIS_EAGAIN: the arena has no room for this chain now (retry after a release). */

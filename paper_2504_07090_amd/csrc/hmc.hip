@@ -1,4 +1,5 @@
-// Leapfrog / Hamiltonian kernels for HMC with a diagonal mass matrix.
+// Leapfrog / Hamiltonian kernels for HMC with a diagonal mass matrix and,
+// optionally, dense per-channel gain blocks (further below).
 //
 // Sec. 4.2 and App. B: with M = diag(1 / minv) the kinetic energy is
 // K = sum minv p^2 / 2, the drift is dq = eps minv p, and momenta are drawn as
@@ -104,14 +105,19 @@ k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__
         continue;
       }
       const float mi = T.minv[i];
+      // gains under a dense block mass: momentum draw, drift and kinetic
+      // energy belong to k_hmc_gainblk, which runs after this kernel
+      const bool dense = T.lrow != nullptr && i >= T.goff && i < T.goff + T.ngain;
       float p = T.p[i];
       if (T.op & kOpBegin) {
-        p = z[e] * rsqrtf(mi);
-        acc_k0 += 0.5 * static_cast<double>(mi) * p * p;
+        if (!dense) {
+          p = z[e] * rsqrtf(mi);
+          acc_k0 += 0.5 * static_cast<double>(mi) * p * p;
+        }
         T.q0[i] = T.q[i];
         T.grad0[i] = T.grad[i];
       }
-      if (T.op & kOpKickDrift) {
+      if ((T.op & kOpKickDrift) && !dense) {
         p -= 0.5f * eps * T.grad[i];
         T.q[i] += eps * mi * p;
       }
@@ -130,7 +136,7 @@ k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__
         T.grad[i] = g;
         if (T.op & kOpPost) {
           p -= 0.5f * eps * g;
-          acc_k += 0.5 * static_cast<double>(mi) * p * p;
+          if (!dense) acc_k += 0.5 * static_cast<double>(mi) * p * p;
         }
       }
       T.p[i] = p;
@@ -153,6 +159,193 @@ k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__
   }
 }
 
+// ------------------------------------------------ dense gain mass blocks --
+// App. B: with M_f = L L^T the kinetic energy is K = z^T z / 2 where L z = p
+// (forward substitution), the velocity is M^-1 p = L^-T z (backward
+// substitution after the forward one) and momenta are drawn as p = L z0; the
+// inverse of M is never formed.  One wave owns one channel's block and lane l
+// holds rows 4l .. 4l+3.  A sweep walks the columns in order (column-oriented
+// substitution): the pivot of column j is broadcast from the lane that holds
+// row j, and every lane updates its four rows from one 16-byte load of that
+// column, issued kGainPrefetch columns ahead.  Blocks are padded to a
+// multiple of kGainPrefetch rows with identity rows, which leave the solves
+// unchanged, so the unrolled sweep needs no bounds test.
+constexpr int kGainPrefetch = kGainBlockPad;
+
+enum Sweep : int { kSweepForward, kSweepBackward, kSweepProduct };
+
+__device__ __forceinline__ float lane_bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// At m + j * nb4 sit the nb4 entries that column step j multiplies: column j
+// of L (forward solve L y = x, product y = L x; from the transposed copy) or
+// row j of L (backward solve L^T y = x; from the row-major copy).  rd holds
+// 1 / L_ii of the lane's rows; nb4 is a multiple of kGainPrefetch.  x is consumed.  The loads are unconditional
+// (the zero triangle is read too) so that the prefetch ring never waits on a
+// branch; lanes past the block read its last four rows and their results
+// are discarded by the caller.
+template <int MODE>
+__device__ void sweep(const float* __restrict__ m, int nb4, float x[4], const float rd[4],
+                      float y[4]) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  typedef const __attribute__((address_space(1))) v4f gv4f;   // global, not flat
+  const int lane = threadIdx.x & 63;
+  const int i0 = min(4 * lane, nb4 - 4);
+  y[0] = y[1] = y[2] = y[3] = 0.f;
+  auto fetch = [&](int s) {
+    s = min(s, nb4 - 1);
+    const int j = MODE == kSweepBackward ? nb4 - 1 - s : s;
+    return *(gv4f*)(m + static_cast<size_t>(j) * nb4 + i0);
+  };
+  // the prologue loads stay in ring order, so that at the loop head the wait
+  // for slot u is the same whether the loop was entered or repeated
+  v4f c[kGainPrefetch];
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < kGainPrefetch; ++u) {
+    c[u] = fetch(u);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  for (int s0 = 0; s0 < nb4; s0 += kGainPrefetch) {
+#pragma unroll
+    for (int u = 0; u < kGainPrefetch; ++u) {
+      {
+        const int j = MODE == kSweepBackward ? nb4 - 1 - (s0 + u) : s0 + u;
+        const int comp = MODE == kSweepBackward ? 3 - (u & 3) : (u & 3);   // j & 3
+        const int jl = j >> 2;
+        const float cc[4] = {c[u].x, c[u].y, c[u].z, c[u].w};
+        if (MODE == kSweepProduct) {
+          const float zj = lane_bcast(x[comp], jl);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) y[r] = fmaf(cc[r], zj, y[r]);
+        } else {
+          const float piv = x[comp] * rd[comp];
+          const float zj = lane_bcast(piv, jl);
+          if (lane == jl) y[comp] = piv;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) x[r] = fmaf(-cc[r], zj, x[r]);
+        }
+        // refill the slot just consumed, kGainPrefetch columns ahead.  The
+        // scheduling barrier keeps the load after the slot's last use (so it
+        // reuses the slot's registers and the ring needs no copies that would
+        // wait on the load); the empty asm keeps the optimizer from turning
+        // the ring into loads at the loop head.
+        __builtin_amdgcn_sched_barrier(0);
+        c[u] = fetch(s0 + u + kGainPrefetch);
+        asm volatile("" ::: "memory");
+      }
+    }
+  }
+}
+
+__device__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ float pick4(const float z[4], int k) {
+  return k == 0 ? z[0] : k == 1 ? z[1] : k == 2 ? z[2] : z[3];
+}
+
+__global__ void __launch_bounds__(64)
+k_hmc_gainblk(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__ chan0) {
+  int lo = 0, hi = ntask - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (chan0[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const HmcTask T = tasks[lo];
+  const int f = b - chan0[lo];
+  if (T.lrow == nullptr || f >= T.nchan) return;   // uniform over the wave
+  const int lane = threadIdx.x;
+  const int nb = T.nb, nb4 = T.nb4;
+  const size_t mo = static_cast<size_t>(f) * nb4 * nb4;
+  const float* lr = T.lrow + mo;
+  const float* lc = T.lcol + mo;
+  const int e0 = T.goff + f * nb;     // layout index of the block's first element
+  const float eps = T.st->eps;
+  float rd[4], p[4], x[4], y[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = 4 * lane + r;
+    rd[r] = i < nb4 ? 1.0f / lr[static_cast<size_t>(i) * nb4 + i] : 1.0f;
+    p[r] = i < nb ? T.p[e0 + i] : 0.f;
+  }
+  if (T.op & kOpBegin) {
+    // z0 takes the same normals a diagonal mass would use for these elements
+    double k0 = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * lane + r;
+      x[r] = 0.f;
+      if (i < nb) {
+        const int e = e0 + i;
+        float z4[4];
+        normals4(T.seed, T.stream, T.traj, static_cast<uint32_t>(e >> 2), z4);
+        x[r] = pick4(z4, e & 3);
+        k0 += 0.5 * static_cast<double>(x[r]) * x[r];
+      }
+    }
+    sweep<kSweepProduct>(lc, nb4, x, rd, p);   // p = L z0, K0 = |z0|^2 / 2
+    k0 = wave_sum_f64(k0);
+    if (lane == 0) T.part_k0g[f] = k0;
+  }
+  if (T.op & kOpKickDrift) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * lane + r;
+      if (i < nb) p[r] -= 0.5f * eps * T.grad[e0 + i];
+      x[r] = p[r];
+    }
+    sweep<kSweepForward>(lc, nb4, x, rd, y);    // L z = p
+    sweep<kSweepBackward>(lr, nb4, y, rd, x);   // L^T v = z
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * lane + r;
+      if (i < nb) T.q[e0 + i] += eps * x[r];
+    }
+  }
+  if (T.op & kOpEnd) {
+    // kinetic energy of the final momentum (after the closing half kick)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[r] = p[r];
+    sweep<kSweepForward>(lc, nb4, x, rd, y);
+    double k = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) k += 0.5 * static_cast<double>(y[r]) * y[r];
+    k = wave_sum_f64(k);
+    if (lane == 0) T.part_kg[f] = k;
+  }
+  if (T.op & (kOpBegin | kOpKickDrift)) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * lane + r;
+      if (i < nb) T.p[e0 + i] = p[r];
+    }
+  }
+}
+
+// Row-major padded copy and transposed copy of the caller's factors; only
+// the lower triangle is read.
+__global__ void __launch_bounds__(256)
+k_gain_mass_setup(const float* __restrict__ chol, int nb, int nb4, float* __restrict__ lrow,
+                  float* __restrict__ lcol, int* __restrict__ bad) {
+  const int i = blockIdx.x;
+  const size_t f = blockIdx.y;
+  for (int j = threadIdx.x; j < nb4; j += blockDim.x) {
+    float v = i == j ? 1.0f : 0.0f;
+    if (i < nb && j <= i) {
+      v = chol[(f * nb + i) * nb + j];
+      if (!isfinite(v) || (i == j && !(v > 0.0f))) *bad = 1;
+    }
+    lrow[(f * nb4 + i) * nb4 + j] = v;
+    lcol[(f * nb4 + j) * nb4 + i] = v;
+  }
+}
+
 // One block per task: totals in FP64, Hamiltonian and Metropolis test at the
 // end of a trajectory, step-size adaptation.
 __global__ void __launch_bounds__(kHmcThreads)
@@ -166,6 +359,12 @@ k_hmc_finalize(const HmcTask* __restrict__ tasks) {
     if (T.op & kOpEnd) {
       sk += T.part_k[i];
       sk0 += T.part_k0[i];
+    }
+  }
+  if ((T.op & kOpEnd) && T.lrow != nullptr) {
+    for (int f = threadIdx.x; f < T.nchan; f += kHmcThreads) {
+      sk += T.part_kg[f];
+      sk0 += T.part_k0g[f];
     }
   }
   su = block_sum(su, red);
@@ -212,6 +411,20 @@ void launch_hmc_elem(const HmcTask* tasks_dev, int ntask, const int* blk0_dev, i
   if (ntask == 0 || nblocks == 0) return;
   k_hmc_elem<<<nblocks, kHmcThreads, 0, st>>>(tasks_dev, ntask, blk0_dev);
   check_launch("k_hmc_elem");
+}
+
+void launch_hmc_gainblk(const HmcTask* tasks_dev, int ntask, const int* chan0_dev, int nchan,
+                        hipStream_t st) {
+  if (ntask == 0 || nchan == 0) return;
+  k_hmc_gainblk<<<nchan, 64, 0, st>>>(tasks_dev, ntask, chan0_dev);
+  check_launch("k_hmc_gainblk");
+}
+
+void launch_gain_mass_setup(const float* chol, int nchan, int nb, int nb4, float* lrow,
+                            float* lcol, int* bad, hipStream_t st) {
+  if (nchan == 0) return;
+  k_gain_mass_setup<<<dim3(nb4, nchan), 256, 0, st>>>(chol, nb, nb4, lrow, lcol, bad);
+  check_launch("k_gain_mass_setup");
 }
 
 void launch_hmc_finalize(const HmcTask* tasks_dev, int ntask, hipStream_t st) {

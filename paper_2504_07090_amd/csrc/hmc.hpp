@@ -7,6 +7,8 @@ namespace bv {
 
 constexpr int kHmcThreads = 256;
 constexpr int kHmcPerBlock = 4096;   // parameters per elementwise block
+constexpr int kGainBlockMax = 256;   // largest dense gain block (2 n_ant)
+constexpr int kGainBlockPad = 16;    // dense gain blocks are padded to a multiple of this
 
 enum HmcOp : int {
   kOpBegin = 1,        // draw p, save q0 / grad0, K0 partials
@@ -44,6 +46,12 @@ struct HmcTask {
   double* part_k0;
   HmcState* st;
   HmcState* st_out;  // finalize copies the state here for the host read-back
+  // dense per-channel gain mass blocks M_f = L_f L_f^T (null: diagonal minv)
+  const float* lrow;  // [n_freq][nb4][nb4] L row-major, padded with identity rows
+  const float* lcol;  // the same blocks transposed (L column-major)
+  double* part_kg;    // [n_freq] kinetic-energy partials of the gain blocks
+  double* part_k0g;
+  int nchan, nb, nb4; // channels, block size 2 n_ant, padded size (multiple of kGainBlockPad)
   uint64_t seed;
   int len, nalm, goff, ngain;
   float gvar_inv;
@@ -53,6 +61,15 @@ struct HmcTask {
 
 void launch_hmc_elem(const HmcTask* tasks_dev, int ntask, const int* blk0_dev, int nblocks,
                      hipStream_t st);
+// One wave per (task, channel) of the tasks with dense gain blocks; chan0 is
+// an exclusive prefix over tasks of their channel counts (0 for tasks
+// without dense blocks).
+void launch_hmc_gainblk(const HmcTask* tasks_dev, int ntask, const int* chan0_dev, int nchan,
+                        hipStream_t st);
+// Admission: pads / transposes the caller's factors and flags a non-positive
+// or non-finite diagonal or a non-finite entry in *bad.
+void launch_gain_mass_setup(const float* chol, int nchan, int nb, int nb4, float* lrow,
+                            float* lcol, int* bad, hipStream_t st);
 void launch_hmc_finalize(const HmcTask* tasks_dev, int ntask, hipStream_t st);
 
 }  // namespace bv

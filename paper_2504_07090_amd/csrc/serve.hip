@@ -37,11 +37,14 @@ static uint64_t now_ns() {
 
 struct ChainLayout {
   int nalm, goff, ngain, len, nblk;
+  int nchan = 0, nb = 0, nb4 = 0;   // dense gain blocks (nchan = 0: none)
   size_t off_q, off_p, off_grad, off_gchi, off_minv, off_q0, off_grad0, off_cvar;
-  size_t off_pu, off_pk, off_pk0, off_state, bytes;
+  size_t off_pu, off_pk, off_pk0, off_state;
+  size_t off_lrow = 0, off_lcol = 0, off_pkg = 0, off_pk0g = 0, off_flag = 0;
+  size_t bytes;
 };
 
-static ChainLayout chain_layout(const vis_field* f) {
+static ChainLayout chain_layout(const vis_field* f, bool dense_gains) {
   ChainLayout L;
   L.nalm = f->n_freq * f->n_modes;
   L.goff = static_cast<int>(round_up(L.nalm, 64));
@@ -67,6 +70,17 @@ static ChainLayout chain_layout(const vis_field* f) {
   L.off_pk = at(sizeof(double) * L.nblk);
   L.off_pk0 = at(sizeof(double) * L.nblk);
   L.off_state = at(sizeof(HmcState));
+  if (dense_gains) {
+    L.nchan = f->n_freq;
+    L.nb = 2 * f->n_ant;
+    L.nb4 = static_cast<int>(round_up(L.nb, kGainBlockPad));
+    const size_t mb = sizeof(float) * static_cast<size_t>(L.nchan) * L.nb4 * L.nb4;
+    L.off_lrow = at(mb);
+    L.off_lcol = at(mb);
+    L.off_pkg = at(sizeof(double) * L.nchan);
+    L.off_pk0g = at(sizeof(double) * L.nchan);
+    L.off_flag = at(sizeof(int));
+  }
   L.bytes = round_up(cv.used, 256);
   return L;
 }
@@ -159,7 +173,7 @@ struct Tick {
 // Pinned host staging + device table slots, one per in-flight tick.
 struct Slot {
   HmcTask* host_tasks = nullptr;     // pinned: [4][max_batch] task tables
-  int* host_blk = nullptr;           // pinned: [3][max_batch + 1] block prefixes
+  int* host_blk = nullptr;           // pinned: [kPrefixes][max_batch + 1] block prefixes
   HmcState* host_states = nullptr;   // pinned: [max_batch] read-back
   HmcTask* dev_tasks = nullptr;      // in the arena
   int* dev_blk = nullptr;
@@ -167,6 +181,9 @@ struct Slot {
 };
 
 constexpr int kSlots = 3;
+// block prefixes of a tick: pre, post and restore elementwise launches, then
+// the channel prefixes of the pre and post gain-block launches
+constexpr int kPrefixes = 5;
 constexpr int kSubStreams = 4;   // evaluation streams of a batched tick (hardware queues)
 
 }  // namespace bv
@@ -256,7 +273,9 @@ void hmc_server::enqueue(Tick& t) {
   HmcTask* rst = S.host_tasks + 3 * nb;
   int* pre_blk = S.host_blk;
   int* post_blk = S.host_blk + (nb + 1);
-  int npre = 0, npost = 0, nrst = 0, bpre = 0, bpost = 0;
+  int* pre_chan = S.host_blk + 3 * (nb + 1);
+  int* post_chan = S.host_blk + 4 * (nb + 1);
+  int npre = 0, npost = 0, nrst = 0, bpre = 0, bpost = 0, cpre = 0, cpost = 0;
   std::vector<const Chain*> evs;
   for (const TickEntry& e : t.entries) {
     Chain* c = e.c;
@@ -281,6 +300,15 @@ void hmc_server::enqueue(Tick& t) {
     T.ngain = c->L.ngain;
     T.gvar_inv = c->gvar_inv;
     T.nblk = c->L.nblk;
+    if (c->L.nchan > 0) {
+      T.lrow = c->ptr(c->L.off_lrow);
+      T.lcol = c->ptr(c->L.off_lcol);
+      T.part_kg = reinterpret_cast<double*>(c->base + c->L.off_pkg);
+      T.part_k0g = reinterpret_cast<double*>(c->base + c->L.off_pk0g);
+      T.nchan = c->L.nchan;
+      T.nb = c->L.nb;
+      T.nb4 = c->L.nb4;
+    }
     T.stream = c->stream;
     T.traj = static_cast<uint32_t>(e.traj < 0 ? 0 : e.traj);
     const bool is_init = e.init;
@@ -289,16 +317,20 @@ void hmc_server::enqueue(Tick& t) {
       HmcTask P = T;
       P.op = kOpKickDrift | (e.first ? kOpBegin : 0);
       pre_blk[npre] = bpre;
+      pre_chan[npre] = cpre;
       pre[npre++] = P;
       bpre += P.nblk;
+      cpre += c->L.nchan;
     }
     HmcTask Q = T;
     Q.op = is_init ? kOpInit : (kOpPost | (e.ends ? kOpEnd : 0));
     post_blk[npost] = bpost;
+    post_chan[npost] = cpost;
     post[npost] = Q;
     fin[npost] = Q;
     npost++;
     bpost += Q.nblk;
+    if (e.ends) cpost += c->L.nchan;   // the gain blocks' final kinetic energy
     if (e.ends) {
       HmcTask R = T;
       R.op = kOpRestore;
@@ -308,6 +340,8 @@ void hmc_server::enqueue(Tick& t) {
   }
   pre_blk[npre] = bpre;
   post_blk[npost] = bpost;
+  pre_chan[npre] = cpre;
+  post_chan[npost] = cpost;
   // restore tasks reuse the post block prefix layout of their own list
   std::vector<int> rst_blk(nrst + 1, 0);
   for (int i = 0; i < nrst; ++i) rst_blk[i + 1] = rst_blk[i] + rst[i].nblk;
@@ -316,9 +350,10 @@ void hmc_server::enqueue(Tick& t) {
 
   hip_or_throw(hipMemcpyAsync(S.dev_tasks, S.host_tasks, sizeof(HmcTask) * 4 * nb,
                               hipMemcpyHostToDevice, stream), "task upload");
-  hip_or_throw(hipMemcpyAsync(S.dev_blk, S.host_blk, sizeof(int) * 3 * (nb + 1),
+  hip_or_throw(hipMemcpyAsync(S.dev_blk, S.host_blk, sizeof(int) * kPrefixes * (nb + 1),
                               hipMemcpyHostToDevice, stream), "prefix upload");
   launch_hmc_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
+  launch_hmc_gainblk(S.dev_tasks, npre, S.dev_blk + 3 * (nb + 1), cpre, stream);
   // evaluations: in a batched tick the chains' evaluation sequences run on
   // several streams so the kernels of different fields overlap on the device
   const int nsub = (cfg.batched && evs.size() > 1) ? std::min<int>(kSubStreams, evs.size()) : 0;
@@ -342,6 +377,7 @@ void hmc_server::enqueue(Tick& t) {
     hip_or_throw(hipStreamWaitEvent(stream, ev_sub[i], 0), "stream wait");
   }
   launch_hmc_elem(S.dev_tasks + nb, npost, S.dev_blk + (nb + 1), bpost, stream);
+  launch_hmc_gainblk(S.dev_tasks + nb, npost, S.dev_blk + 4 * (nb + 1), cpost, stream);
   launch_hmc_finalize(S.dev_tasks + 2 * nb, npost, stream);
   launch_hmc_elem(S.dev_tasks + 3 * nb, nrst, S.dev_blk + 2 * (nb + 1), rst_blk[nrst], stream);
   // read back the state of every chain in the tick (gathered by the finalize kernel)
@@ -441,7 +477,12 @@ extern "C" {
 
 size_t hmc_chain_footprint_bytes(const vis_field* field) {
   if (field == nullptr) return 0;
-  return chain_layout(field).bytes;
+  return chain_layout(field, false).bytes;
+}
+
+size_t hmc_chain_footprint_dense_gain_bytes(const vis_field* field) {
+  if (field == nullptr) return 0;
+  return chain_layout(field, true).bytes;
 }
 
 vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size_t arena_bytes,
@@ -456,7 +497,7 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
     s->stream = as_stream(stream);
     const int nb = cfg->max_batch;
     const size_t task_bytes = round_up(sizeof(HmcTask) * 4 * nb, 256);
-    const size_t blk_bytes = round_up(sizeof(int) * 3 * (nb + 1), 256);
+    const size_t blk_bytes = round_up(sizeof(int) * kPrefixes * (nb + 1), 256);
     const size_t st_bytes = round_up(sizeof(HmcState) * nb, 256);
     const size_t per = task_bytes + blk_bytes + st_bytes;
     const size_t reserve = kSlots * per;
@@ -469,10 +510,10 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
       S.dev_blk = reinterpret_cast<int*>(base + i * per + task_bytes);
       S.dev_states = reinterpret_cast<HmcState*>(base + i * per + task_bytes + blk_bytes);
       BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_tasks), sizeof(HmcTask) * 4 * nb));
-      BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_blk), sizeof(int) * 3 * (nb + 1)));
+      BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_blk), sizeof(int) * kPrefixes * (nb + 1)));
       BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_states), sizeof(HmcState) * nb));
       std::memset(S.host_tasks, 0, sizeof(HmcTask) * 4 * nb);
-      std::memset(S.host_blk, 0, sizeof(int) * 3 * (nb + 1));
+      std::memset(S.host_blk, 0, sizeof(int) * kPrefixes * (nb + 1));
     }
     s->arena.init(base + reserve, arena_bytes - reserve);
     if (cfg->batched) {
@@ -505,7 +546,11 @@ vis_status hmc_chain_admit(hmc_server* s, const hmc_chain_init* in, int32_t* cha
     BV_REQUIRE(in->n_leapfrog >= 1 && in->n_leapfrog <= 100000, VIS_EINVAL, "n_leapfrog out of range");
     BV_REQUIRE(in->eps > 0.f && in->sigma_n > 0.f && in->gain_prior_sigma > 0.f, VIS_EINVAL,
                "eps, sigma_n and gain_prior_sigma must be positive");
-    const ChainLayout L = chain_layout(in->field);
+    const bool dense = in->gain_chol != nullptr;
+    BV_REQUIRE(!dense || 2 * in->field->n_ant <= kGainBlockMax, VIS_EINVAL,
+               "dense gain mass blocks hold at most %d antennas (field has %d)",
+               kGainBlockMax / 2, in->field->n_ant);
+    const ChainLayout L = chain_layout(in->field, dense);
     Chain* c = nullptr;
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -551,12 +596,27 @@ vis_status hmc_chain_admit(hmc_server* s, const hmc_chain_init* in, int32_t* cha
     BV_HIP(hipMemcpyAsync(c->ptr(L.off_minv), in->minv, vf, hipMemcpyDeviceToDevice, cs));
     BV_HIP(hipMemcpyAsync(c->ptr(L.off_cvar), in->alm_prior_var, sizeof(float) * L.nalm,
                           hipMemcpyDeviceToDevice, cs));
+    int bad = 0;
+    if (dense) {
+      int* flag = reinterpret_cast<int*>(c->base + L.off_flag);
+      launch_gain_mass_setup(in->gain_chol, L.nchan, L.nb, L.nb4, c->ptr(L.off_lrow),
+                             c->ptr(L.off_lcol), flag, cs);
+      BV_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, cs));
+    }
     HmcState hs{};
     hs.eps = hs.eps0 = hs.eps_used = in->eps;
     hs.adapt = in->adapt_step ? 1 : 0;
     BV_HIP(hipMemcpyAsync(c->st(), &hs, sizeof(HmcState), hipMemcpyHostToDevice, cs));
     BV_HIP(hipStreamSynchronize(cs));
     (void)hipStreamDestroy(cs);
+    if (bad) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->arena.release(static_cast<size_t>(c->off), c->L.bytes);
+      s->chains[c->id] = nullptr;
+      delete c;
+      BV_REQUIRE(false, VIS_EINVAL,
+                 "gain_chol: non-finite entry or non-positive diagonal in the lower triangle");
+    }
     {
       std::lock_guard<std::mutex> lk(s->mu);
       c->releasing = false;

@@ -29,7 +29,7 @@ class ChainInit(C.Structure):
     _fields_ = [("field", _vp), ("data", _vp), ("sigma_n", C.c_float), ("q0", _vp),
                 ("minv", _vp), ("alm_prior_var", _vp), ("gain_prior_sigma", C.c_float),
                 ("eps", C.c_float), ("n_leapfrog", C.c_int32), ("adapt_step", C.c_int32),
-                ("seed", C.c_uint64), ("stream_id", C.c_uint32)]
+                ("seed", C.c_uint64), ("stream_id", C.c_uint32), ("gain_chol", _vp)]
 
 
 class Result(C.Structure):
@@ -44,8 +44,9 @@ class Stats(C.Structure):
                 ("max_ms", C.c_double), ("arena_free_bytes", C.c_int64), ("live_chains", C.c_int32)]
 
 
-_lib.hmc_chain_footprint_bytes.argtypes = [_vp]
-_lib.hmc_chain_footprint_bytes.restype = C.c_size_t
+for _n in ("hmc_chain_footprint_bytes", "hmc_chain_footprint_dense_gain_bytes"):
+    getattr(_lib, _n).argtypes = [_vp]
+    getattr(_lib, _n).restype = C.c_size_t
 _lib.hmc_server_create.argtypes = [C.POINTER(ServerConfig), _vp, C.c_size_t, _vp, C.POINTER(_vp)]
 _lib.hmc_chain_admit.argtypes = [_vp, C.POINTER(ChainInit), C.POINTER(C.c_int32)]
 _lib.hmc_submit.argtypes = [_vp, C.c_int32, C.c_int32]
@@ -123,24 +124,32 @@ class Server:
         self._keep = {}
 
     @staticmethod
-    def footprint(field: V.Field) -> int:
+    def footprint(field: V.Field, dense_gains: bool = False) -> int:
+        if dense_gains:
+            return int(_lib.hmc_chain_footprint_dense_gain_bytes(field.handle))
         return int(_lib.hmc_chain_footprint_bytes(field.handle))
 
     def admit(self, field: V.Field, data: torch.Tensor, sigma_n: float, q0: torch.Tensor,
               minv: torch.Tensor, alm_prior_var: torch.Tensor, gain_prior_sigma: float,
               eps: float, n_leapfrog: int, seed: int, stream_id: int,
-              adapt_step: bool = False) -> Optional[int]:
-        """Chain id, or None if the arena has no room now (VIS_EAGAIN)."""
+              adapt_step: bool = False, gain_chol: Optional[torch.Tensor] = None) -> Optional[int]:
+        """Chain id, or None if the arena has no room now (VIS_EAGAIN).
+        gain_chol: optional [n_freq][2 n_ant][2 n_ant] lower Cholesky factors of
+        dense per-channel gain mass blocks."""
         lay = Layout(field)
         V._need(data, "data", torch.complex64, (field.n_time, field.n_freq, field.n_bl), field.device)
         V._need(q0, "q0", torch.float32, (lay.length,), field.device)
         V._need(minv, "minv", torch.float32, (lay.length,), field.device)
         V._need(alm_prior_var, "alm_prior_var", torch.float32, (field.n_freq, field.n_modes),
                 field.device)
+        if gain_chol is not None:
+            V._need(gain_chol, "gain_chol", torch.float32,
+                    (field.n_freq, 2 * field.n_ant, 2 * field.n_ant), field.device)
         torch.cuda.current_stream().synchronize()
         init = ChainInit(field.handle, data.data_ptr(), sigma_n, q0.data_ptr(), minv.data_ptr(),
                          alm_prior_var.data_ptr(), gain_prior_sigma, eps, n_leapfrog,
-                         1 if adapt_step else 0, seed, stream_id)
+                         1 if adapt_step else 0, seed, stream_id,
+                         None if gain_chol is None else gain_chol.data_ptr())
         cid = C.c_int32()
         st = _lib.hmc_chain_admit(self.handle, C.byref(init), C.byref(cid))
         if st == VIS_EAGAIN:

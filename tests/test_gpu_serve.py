@@ -42,12 +42,20 @@ def _chain_inputs(vis, serve, fld, cfg, d, sigma=None, data=None, scale=1.0):
     return lay, data, sigma, q0, minv, cvar
 
 
-def test_trajectory_matches_oracle(mods):
+@pytest.mark.parametrize("case", ["diagonal", "dense_rhombus16", "dense_hex19"])
+def test_trajectory_matches_oracle(mods, case):
     """One 5-step trajectory from the same q0, momentum stream and mass matrix:
     the GPU move agrees with the FP64 oracle's to 1e-3 of its length, and the
-    accept decision and energies agree."""
+    accept decision and energies agree.  The dense cases give every channel's
+    gains a dense mass block (App. B): the Gauss-Newton gain Hessian plus the
+    prior, through its Cholesky factor; 19 antennas make a 38-row block that
+    the server pads."""
     vis, serve = mods
-    cfg = w.scaled(w.C0, lmax=4, n_freq=2, n_time=2)
+    if case == "dense_hex19":
+        cfg = w.scaled(w.C0, array="hex", array_size=3, lmax=4, n_freq=2, n_time=2,
+                       freq_lo_hz=120e6, freq_hi_hz=130e6)
+    else:
+        cfg = w.scaled(w.C0, lmax=4, n_freq=2, n_time=2)
     basis = vis.basis_for(cfg)
     fld = vis.Field.from_config(basis, cfg)
     d = w.draw(cfg)
@@ -64,13 +72,20 @@ def test_trajectory_matches_oracle(mods):
         qp[i] += h
         hd[i] = (post.potential_and_grad(qp)[1][i] - g0[i]) / h
     minv_or = 1.0 / hd
+    mass_or, chol32 = minv_or, None
+    if case != "diagonal":
+        hg = ohmc.gain_gauss_newton_blocks(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), sig)
+        hg += np.eye(hg.shape[1])[None] / post.gvar
+        # both sides use the same float32 factor
+        chol32 = np.linalg.cholesky(hg).astype(np.float32)
+        mass_or = ohmc.gain_block_mass(minv_or, chol32.astype(np.float64), cfg.n_freq * cfg.n_modes)
     eps, nl, seed, stream = 0.15, 5, 11, 3
     lay = serve.Layout(fld)
     nalm, ng = lay.nalm, lay.ngain
     # the server draws normal i for element i of its padded layout
     idx = np.concatenate([np.arange(nalm), lay.goff + np.arange(ng), [lay.length - 1]])
     u0, gr0 = post.potential_and_grad(q_or)
-    q1, u1, g1, acc, h0, h1 = ohmc.trajectory(q_or, u0, gr0, eps, nl, minv_or,
+    q1, u1, g1, acc, h0, h1 = ohmc.trajectory(q_or, u0, gr0, eps, nl, mass_or,
                                               post.potential_and_grad, seed, stream, 0,
                                               normal_index=idx)
 
@@ -87,11 +102,13 @@ def test_trajectory_matches_oracle(mods):
     minv_l = to_lay(minv_or)
     minv_l[nalm:lay.goff] = 1.0
     srv = serve.Server(64 << 20, max_chains=4, max_batch=4)
+    say("case", case, "n_ant", fld.n_ant)
     cid = srv.admit(fld, torch.tensor(data, dtype=torch.complex64, device="cuda"), sig,
                     torch.tensor(to_lay(q_or), dtype=torch.float32, device="cuda"),
                     torch.tensor(minv_l, dtype=torch.float32, device="cuda"),
                     torch.tensor(d.alm_var, dtype=torch.float32, device="cuda"),
-                    cfg.gain_scatter, eps, nl, seed, stream)
+                    cfg.gain_scatter, eps, nl, seed, stream,
+                    gain_chol=None if chol32 is None else torch.tensor(chol32, device="cuda"))
     srv.submit(cid, 1)
     res = srv.wait(1)
     qg = from_lay(srv.position(cid, lay.length, "cuda").double().cpu().numpy())
@@ -128,22 +145,45 @@ def _mixed_basis(vis):
     return vis.Basis(32, 96, 20, 1 | 2 | 4 | vis.STORAGE_SEPARABLE)
 
 
+def _dense_gain_chol(lay, minv, n_freq, n_ant, seed):
+    """Factors of a dense gain mass with the diagonal of 1 / minv: M_f = D^1/2 C D^1/2,
+    D = 1 / minv on channel f's gains, C the unit-diagonal normalisation of
+    I + 0.2 S S^T / n with S random (off-diagonal correlations of a few tenths)."""
+    rng = np.random.default_rng(seed)
+    n = 2 * n_ant
+    dg = (1.0 / minv[lay.goff:lay.goff + lay.ngain].double().cpu().numpy()).reshape(n_freq, n)
+    out = np.empty((n_freq, n, n), dtype=np.float32)
+    for f in range(n_freq):
+        s = rng.normal(size=(n, n))
+        c = np.eye(n) + 0.2 * s @ s.T / n
+        c /= np.sqrt(np.outer(np.diag(c), np.diag(c)))
+        m = np.sqrt(dg[f])[:, None] * c * np.sqrt(dg[f])[None, :]
+        out[f] = np.linalg.cholesky(m)
+    return torch.tensor(out, device="cuda")
+
+
 def test_alone_equals_mix(mods):
-    """A chain's trajectories are bitwise identical alone and batched with others."""
+    """A chain's trajectories are bitwise identical alone and batched with others,
+    for a diagonal-mass chain and for a chain with dense gain mass blocks."""
     vis, serve = mods
     basis = _mixed_basis(vis)
     cfgs, flds = _mixed_fields(vis, basis)
     inputs = []
     for c, f in zip(cfgs, flds):
         inputs.append(_chain_inputs(vis, serve, f, c, w.draw(c)))
+    # chain 1 (37 antennas: 74-row blocks, padded to 80) has dense gain blocks
+    chols = {1: _dense_gain_chol(inputs[1][0], inputs[1][4], flds[1].n_freq, flds[1].n_ant, 17)}
 
     def run(which):
         srv = serve.Server(256 << 20, max_chains=8, max_batch=8)
         ids = {}
         for k in which:
             lay, data, sig, q0, minv, cvar = inputs[k]
-            ids[k] = srv.admit(flds[k], data, sig, q0, minv, cvar, cfgs[k].gain_scatter, 0.2, 4,
-                               seed=99, stream_id=k, adapt_step=True)
+            # eps 0.2 is too long a step for these fields (rejections, adaptation);
+            # the dense chain takes 0.05, which these fields accept
+            eps = 0.05 if k in chols else 0.2
+            ids[k] = srv.admit(flds[k], data, sig, q0, minv, cvar, cfgs[k].gain_scatter, eps, 4,
+                               seed=99, stream_id=k, adapt_step=True, gain_chol=chols.get(k))
             srv.submit(ids[k], 3)
         res = srv.wait(3 * len(which))
         pos = {k: srv.position(ids[k], inputs[k][0].length, "cuda") for k in which}
@@ -153,12 +193,51 @@ def test_alone_equals_mix(mods):
         return per, pos
 
     alone, pos_a = run([0])
+    alone1, pos_a1 = run([1])
     mix, pos_m = run([0, 1, 2, 3, 4])
     assert all(r["status"] == 0 for rs in mix.values() for r in rs)
-    for ra, rm in zip(alone[0], mix[0]):
-        for key in ("trajectory", "accepted", "h0", "h1", "chi2", "eps"):
-            assert ra[key] == rm[key], key
-    assert torch.equal(pos_a[0], pos_m[0])
+    for k, al, pa in ((0, alone, pos_a), (1, alone1, pos_a1)):
+        assert len(al[k]) == len(mix[k]) == 3
+        for ra, rm in zip(al[k], mix[k]):
+            for key in ("trajectory", "accepted", "h0", "h1", "chi2", "eps"):
+                assert ra[key] == rm[key], (k, key)
+        assert torch.equal(pa[k], pos_m[k]), k
+    # the dense chain moved (at least one accepted trajectory) and its energies are finite
+    assert any(r["accepted"] for r in mix[1]) and all(math.isfinite(r["h1"]) for r in mix[1])
+
+
+def test_dense_gain_mass_admission_checks(mods):
+    """A factor with a non-positive diagonal is refused with VIS_EINVAL and leaves
+    the arena as it was; the footprint of a dense chain covers its factors."""
+    vis, serve = mods
+    basis = _mixed_basis(vis)
+    cfgs, flds = _mixed_fields(vis, basis)
+    ins = _chain_inputs(vis, serve, flds[0], cfgs[0], w.draw(cfgs[0]))
+    lay = ins[0]
+    nb = 2 * flds[0].n_ant
+    nb16 = (nb + 15) // 16 * 16
+    assert serve.Server.footprint(flds[0], True) >= serve.Server.footprint(flds[0]) \
+        + 2 * 4 * flds[0].n_freq * nb16 * nb16
+    srv = serve.Server(128 << 20, max_chains=4, max_batch=4)
+    free0 = srv.stats()["arena_free_bytes"]
+    bad = _dense_gain_chol(lay, ins[4], flds[0].n_freq, flds[0].n_ant, 3)
+    bad[1, 5, 5] = -1.0
+    with pytest.raises(vis.VisError):
+        srv.admit(flds[0], *ins[1:], 0.05, 0.1, 2, 5, 0, gain_chol=bad)
+    assert srv.stats()["arena_free_bytes"] == free0
+    bad[1, 5, 5] = 1.0
+    bad[0, 7, 2] = float("nan")
+    with pytest.raises(vis.VisError):
+        srv.admit(flds[0], *ins[1:], 0.05, 0.1, 2, 5, 0, gain_chol=bad)
+    # the upper triangle is never read
+    good = _dense_gain_chol(lay, ins[4], flds[0].n_freq, flds[0].n_ant, 3)
+    good[:, 0, 1:] = float("nan")
+    c = srv.admit(flds[0], *ins[1:], 0.05, 0.1, 2, 5, 0, gain_chol=good)
+    assert c is not None
+    srv.submit(c, 1)
+    r = srv.wait(1)[0]
+    assert r["status"] == 0 and math.isfinite(r["h1"])
+    srv.close()
 
 
 def test_admission_by_footprint_and_release(mods):
