@@ -17,7 +17,8 @@ counted once for the forward and once for the adjoint contraction.
 Serving (`serving` key): 64 concurrent chains on uneven hex fields
 (19-127 dishes, 16-128 channels, 10-120 times, lmax 30-100), one trajectory
 of 20 leapfrog steps each, through the batched server with split-precision
-(bf16 hi/lo) dense synthesis and with FP32 separable synthesis, against the
+(bf16 hi/lo) dense synthesis and with FP32 separable synthesis (also with
+dense per-channel gain mass blocks, App. B), against the
 same request stream through the plain FP32 dense path one request per tick:
 gradient evaluations per second and request latency p50/p99.
 
@@ -150,19 +151,28 @@ def serving_inputs(vis, serve, torch, basis, n_chains):
     return out
 
 
-def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=20, synthesis=0):
-    """One trajectory of n_leapfrog steps per chain; all chains submitted at once."""
+def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=20, synthesis=0,
+                  dense_gains=False):
+    """One trajectory of n_leapfrog steps per chain; all chains submitted at once.
+    dense_gains: every chain gets dense per-channel gain mass blocks (the
+    Gauss-Newton gain Hessian plus the prior, built before timing)."""
     n_chains = len(inputs)
     flds = [f if (prec == vis.VIS_FP32 and synthesis == 0)
             else vis.Field.from_config(basis, cfg, prec, synthesis)
             for (cfg, f, *_rest) in inputs]
-    fp = sum(serve.Server.footprint(f) for f in flds)
+    chols = [None] * n_chains
+    if dense_gains:
+        for c, ((cfg, _, data, sigma, q0, minv, cvar), fld) in enumerate(zip(inputs, flds)):
+            alm, g, fw = serve.Layout(fld).unpack(q0)
+            chols[c] = serve.gain_mass_chol(fld, alm.contiguous(), g.contiguous(), fw.contiguous(),
+                                            sigma, cfg.gain_scatter)
+    fp = sum(serve.Server.footprint(f, dense_gains) for f in flds)
     srv = serve.Server(fp + (64 << 20), max_chains=n_chains, max_batch=max_batch,
                        batched=1 if max_batch > 1 else 0)
     ids = []
     for c, ((cfg, _, data, sigma, q0, minv, cvar), fld) in enumerate(zip(inputs, flds)):
         ids.append(srv.admit(fld, data, sigma, q0, minv, cvar, cfg.gain_scatter, EPS, n_leapfrog,
-                             seed=7, stream_id=c, adapt_step=True))
+                             seed=7, stream_id=c, adapt_step=True, gain_chol=chols[c]))
     wait_requests(srv, n_chains)
     srv.stats(reset=True)
     torch.cuda.synchronize()
@@ -277,11 +287,16 @@ def main():
         log("serving: batched, FP32 separable synthesis")
         sep = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32, max_batch=args.serve_chains,
                             synthesis=vis.VIS_SYNTH_SEPARABLE)
+        log("serving: batched, FP32 separable synthesis, dense gain mass blocks")
+        sep_dg = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32,
+                               max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
+                               dense_gains=True)
         log("serving: per-chain FP32 baseline (dense synthesis), one request per tick")
         base = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32, max_batch=1)
         del ins
         serving = {"chains": args.serve_chains, "leapfrog_steps": 20,
                    "batched_" + args.serve_precision: fast, "batched_fp32_separable": sep,
+                   "batched_fp32_separable_dense_gain_mass": sep_dg,
                    "per_chain_fp32": base,
                    "speedup": fast["grad_evals_per_s"] / base["grad_evals_per_s"],
                    "speedup_separable": sep["grad_evals_per_s"] / base["grad_evals_per_s"]}

@@ -110,6 +110,45 @@ def diag_hessian(field: V.Field, alm, gains, fwhm, sigma_n: float, n_probes: int
     return h
 
 
+def gain_mass_chol(field: V.Field, alm, gains, fwhm, sigma_n: float,
+                   gain_prior_sigma: float) -> torch.Tensor:
+    """Cholesky factors [n_freq][2 n_ant][2 n_ant] (float32, device) of dense
+    per-channel gain mass blocks M_f = H_f + (2 / s_g^2) I, with H_f the
+    Gauss-Newton Hessian of chi^2 / 2 in the real gain components (App. B: the
+    mass matrix approximates the Hessian; every antenna pair couples through its
+    baseline).  With V_ij = g_i conj(g_j) M_ij and M the model without gains
+    (from vis_forward with unit gains), summed over times:
+        H[x_i, x_i] = H[y_i, y_i] = sum over i's baselines of |g_other|^2 |M|^2,
+        H[x_i, x_j] = -H[y_i, y_j] = Re w,  H[x_i, y_j] = H[y_i, x_j] = Im w,
+        w = g_i g_j |M_ij|^2,
+    all over sigma_n^2.  Set-up code for the chain's mass matrix, not part of a
+    leapfrog step."""
+    na, nf = field.n_ant, field.n_freq
+    m = V.forward(field, alm, torch.ones_like(gains), fwhm)
+    m2 = (m.abs().double() ** 2).sum(0)                       # [f][bl], sum over times
+    del m
+    iu = torch.triu_indices(na, na, 1, device=gains.device)   # baselines (i, j), i < j, in order
+    i, j = iu[0], iu[1]
+    g = gains.to(torch.complex128)
+    gi, gj = g[:, i], g[:, j]
+    d = torch.zeros(nf, na, dtype=torch.float64, device=gains.device)
+    d.index_add_(1, i, (gj.abs() ** 2) * m2)
+    d.index_add_(1, j, (gi.abs() ** 2) * m2)
+    wv = gi * gj * m2
+    h = torch.zeros(nf, 2 * na, 2 * na, dtype=torch.float64, device=gains.device)
+    k = torch.arange(na, device=gains.device)
+    h[:, 2 * k, 2 * k] = d
+    h[:, 2 * k + 1, 2 * k + 1] = d
+    for a, b in ((i, j), (j, i)):
+        h[:, 2 * a, 2 * b] = wv.real
+        h[:, 2 * a + 1, 2 * b + 1] = -wv.real
+        h[:, 2 * a, 2 * b + 1] = wv.imag
+        h[:, 2 * a + 1, 2 * b] = wv.imag
+    h /= sigma_n ** 2
+    h += (2.0 / gain_prior_sigma ** 2) * torch.eye(2 * na, dtype=torch.float64, device=gains.device)
+    return torch.linalg.cholesky(h.cpu()).float().to(gains.device).contiguous()
+
+
 class Server:
     def __init__(self, arena_bytes: int, max_chains: int = 64, max_batch: int = 64,
                  batched: int = 1, device: str = "cuda"):

@@ -314,3 +314,29 @@ def test_latency_stats_recorded(mods):
     st = srv.stats()
     assert st["requests"] == 1 + 2 * 3 and 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
     srv.close()
+
+
+def test_gain_mass_chol_matches_oracle_gauss_newton(mods):
+    """The set-up helper's dense gain mass equals the oracle's Gauss-Newton gain
+    blocks (Jacobian by central differences of the FP64 forward model) plus the
+    prior precision."""
+    vis, serve = mods
+    cfg = w.scaled(w.C0, array="hex", array_size=3, lmax=6, n_freq=3, n_time=2,
+                   freq_lo_hz=120e6, freq_hi_hz=130e6)
+    basis = vis.basis_for(cfg)
+    fld = vis.Field.from_config(basis, cfg)
+    d = w.draw(cfg)
+    of = model.Field(cfg)
+    sig = 0.37
+    fw = w.fwhm_ref_rad(cfg)
+    ref = ohmc.gain_gauss_newton_blocks(of, d.alm, d.gains, fw, sig)
+    ref += np.eye(ref.shape[1])[None] * 2.0 / cfg.gain_scatter ** 2
+    l = serve.gain_mass_chol(fld, torch.tensor(d.alm, dtype=torch.float32, device="cuda"),
+                             torch.tensor(d.gains, dtype=torch.complex64, device="cuda"),
+                             torch.tensor([fw], dtype=torch.float32, device="cuda"), sig,
+                             cfg.gain_scatter).double().cpu().numpy()
+    got = l @ np.transpose(l, (0, 2, 1))
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    say("gain mass rel err", err)
+    assert err <= 1e-5
+    assert np.allclose(l, np.tril(l))
