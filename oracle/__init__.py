@@ -17,7 +17,10 @@ follows.  Modules:
 ``rime``       directions, Gaussian power beam, direct-sum RIME       Sec. 2.1 (eq. rime_discrete)
 ``model``      gains, residual, chi^2 and its analytic gradient       Sec. 2.3 (eq. likelihood)
 ``filter``     delay filter and the filtered chi^2                   Sec. 2.1 (eq. rime_filter, gpr), 3.5
-``hmc``        leapfrog / Hamiltonian with a diagonal mass matrix    Sec. 4.2, App. B
+``hmc``        leapfrog / Hamiltonian, diagonal or block-dense mass  Sec. 4.2, App. B
+``nuts``       No-U-Turn sampler, biased progressive sampling        Sec. 4.2 (Hoffman & Gelman 2014,
+               Betancourt 2017)
+``mapmaking``  diagonally normalised dirty map                        Sec. 6
 ``philox``     Philox-4x32-10 counter-based generator (Salmon et al. 2011)
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
