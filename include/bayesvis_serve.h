@@ -13,7 +13,8 @@ extern "C" {
 
 /* ------------------------------------------------------------- serving --
  * Continuous-batching HMC server (Sec. 4.2, App. B with a diagonal mass
- * matrix, optionally with dense per-channel gain blocks).  Each chain owns a field, data, a parameter vector q =
+ * matrix, optionally with dense per-channel gain blocks; fixed-length
+ * trajectories or the No-U-Turn sampler).  Each chain owns a field, data, a parameter vector q =
  * [a (n_freq*n_modes), gains as (Re, Im) pairs (n_freq*n_ant*2), F] and an
  * inverse mass diagonal of the same length, all resident in the server's
  * arena.  The potential is U = chi^2/2 + sum a^2 / (2 C) + sum |g - 1|^2 /
@@ -73,18 +74,40 @@ typedef struct {
    * takes the normals a diagonal mass would use for the same elements; the
    * inverse of M_f is never formed.  2 n_ant <= 256.                       */
   const float* gain_chol;
+  /* 0: fixed-length trajectories of n_leapfrog steps with a Metropolis test.
+   * 1..10: the No-U-Turn sampler (Sec. 4.2; Hoffman & Gelman 2014) with at
+   * most this many trajectory doublings (2^d - 1 leapfrog steps; n_leapfrog
+   * is then ignored).  Doubling j grows 2^j steps in the direction given by
+   * bit 0 of Philox counter (j, trajectory, stream, 2) (+1 if set); inside a
+   * subtree the candidate is drawn multinomially (leaf replaces it with
+   * probability w / sum w, w = exp(H0 - H), uniform from counter (s,
+   * trajectory, stream, 3), s = the step index); a completed subtree's
+   * candidate becomes the proposal with probability min(1, W_sub / W)
+   * (biased progressive sampling, Betancourt 2017; counter (j, trajectory,
+   * stream, 4)).  A span with end momenta p_a, p_b and momentum sum r turns
+   * when (M^-1 p_a).(r - (p_a+p_b)/2) <= 0 or (M^-1 p_b).(...) <= 0; every
+   * aligned power-of-two span inside a subtree and the whole trajectory after
+   * each doubling are checked; a turn inside a subtree, or a leaf with
+   * H - H0 > 1000 or non-finite, discards that subtree and ends the
+   * trajectory.  The chain moves to the proposal (hmc_result.accepted = 1 if
+   * it differs from the start).  Step-size adaptation uses the mean over the
+   * leaves of min(1, exp(H0 - H)).  Requires gain_chol == NULL.            */
+  int32_t nuts_max_depth;
 } hmc_chain_init;
 
 typedef struct {
   int32_t chain;
   int32_t trajectory;          /* 0-based trajectory index of this chain */
   int32_t accepted;
-  int32_t status;              /* VIS_OK or VIS_ENUMERIC (non-finite H) */
+  int32_t status;              /* VIS_OK, VIS_ENUMERIC (non-finite H) or VIS_EDEVICE (a NUTS
+                                  trajectory overran its step bound: an internal error) */
   double h0, h1;               /* Hamiltonian before / after (FP64) */
   double chi2;                 /* chi^2 at the chain's position after the transition */
   float eps;                   /* step size used */
   int32_t n_grad;              /* gradient evaluations in this trajectory */
   uint64_t t_submit_ns, t_done_ns;   /* host steady-clock timestamps */
+  int32_t tree_depth;          /* NUTS: doublings begun (0 for fixed-length HMC) */
+  float accept_stat;           /* Metropolis probability, or the NUTS mean of min(1, exp(H0 - H)) */
 } hmc_result;
 
 typedef struct {
@@ -101,6 +124,9 @@ size_t hmc_chain_footprint_bytes(const vis_field* field);
 /* The same for a chain admitted with gain_chol (adds two padded copies of the
  * factors: about 8 n_freq (2 n_ant)^2 bytes).                              */
 size_t hmc_chain_footprint_dense_gain_bytes(const vis_field* field);
+/* The same for a NUTS chain (adds the trajectory ends, candidate, proposal,
+ * momentum sums and 20 checkpoint vectors: 32 vectors of the parameter length). */
+size_t hmc_chain_footprint_nuts_bytes(const vis_field* field);
 vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size_t arena_bytes,
                              void* stream, hmc_server** out);
 /* VIS_EAGAIN: the arena has no room for this chain now (retry after a release). */

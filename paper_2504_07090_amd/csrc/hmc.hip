@@ -72,20 +72,254 @@ __device__ double block_sum(double v, double* red) {
   return r;
 }
 
-// One block handles kHmcPerBlock consecutive parameters of one chain.
-__global__ void __launch_bounds__(kHmcThreads)
-k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__ blk0) {
-  __shared__ double red[kHmcThreads];
-  // locate the task: blk0 is an exclusive prefix over tasks of their block counts
+// grad U at element i from the chi^2 gradient and the priors; adds the prior
+// part of U to acc_u.
+__device__ __forceinline__ float grad_potential(const HmcTask& T, int i, float q, double& acc_u) {
+  float g = 0.5f * T.gchi[i];
+  if (i < T.nalm) {
+    g += q / T.cvar[i];
+    acc_u += 0.5 * static_cast<double>(q) * q / T.cvar[i];
+  } else if (i >= T.goff && i < T.goff + T.ngain) {
+    const float dg = q - ((i - T.goff) % 2 == 0 ? 1.0f : 0.0f);
+    g += dg * T.gvar_inv;
+    acc_u += 0.5 * static_cast<double>(dg) * dg * T.gvar_inv;
+  }
+  return g;
+}
+
+// Sums N values over the block in a fixed order (wave butterflies, then the
+// four wave totals in order); every thread receives the totals.
+template <int N>
+__device__ void block_sum_n(double v[N], double* lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) lds[w * N + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = ((lds[k] + lds[N + k]) + lds[2 * N + k]) + lds[3 * N + k];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- NUTS --
+// Sec. 4.2: the No-U-Turn sampler (Hoffman & Gelman 2014) with multinomial
+// sampling inside each subtree and biased progressive sampling across
+// doublings (Betancourt 2017).  A trajectory grows by doublings; doubling j
+// adds 2^j leapfrog steps in a direction drawn from Philox counter
+// (j, trajectory, stream, 2), starting from the trajectory's end on that
+// side.  Every step is one tick: the element kernel moves the state, the
+// evaluation gives the gradient, the element kernel kicks and forms the
+// partial dot products of the U-turn checks, the finalize kernel takes the
+// decisions in FP64 and the apply pass acts on them.  The U-turn checks of
+// the subtree being built use the checkpoint scheme of iterative NUTS
+// (Phan, Pradhan & Jankowiak 2019): at an even leaf n its momentum and the
+// running momentum sum are stored in checkpoint popcount(n >> 1); at an odd
+// leaf the spans that end at n (one per trailing one bit of n) are checked
+// against checkpoints popcount(n >> 1) - ones + 1 .. popcount(n >> 1).  A span
+// with end momenta p_a, p_b and momentum sum r turns when
+// (M^-1 p_a).(r - (p_a + p_b)/2) <= 0 or (M^-1 p_b).(r - (p_a + p_b)/2) <= 0.
+// Only diagonal masses are supported here.
+
+__device__ __forceinline__ int nuts_direction(const HmcTask& T, int j) {
+  const uint4 x = philox10(make_uint4(static_cast<uint32_t>(j), T.traj, T.stream, 2u),
+                           make_uint2(static_cast<uint32_t>(T.seed), static_cast<uint32_t>(T.seed >> 32)));
+  return (x.x & 1u) ? 1 : -1;
+}
+
+__device__ __forceinline__ double philox_unit(const HmcTask& T, uint32_t c0, uint32_t c3) {
+  return unit_open(philox10(make_uint4(c0, T.traj, T.stream, c3),
+                            make_uint2(static_cast<uint32_t>(T.seed), static_cast<uint32_t>(T.seed >> 32))).x);
+}
+
+// checkpoints checked at leaf n (empty for even n)
+__device__ __forceinline__ void nuts_ckpt_range(int leaf, int& lo, int& hi) {
+  lo = 0;
+  hi = -1;
+  if (leaf & 1) {
+    hi = __popc(static_cast<unsigned>(leaf) >> 1);
+    lo = hi - __builtin_ctz(~static_cast<unsigned>(leaf)) + 1;
+  }
+}
+
+__device__ void nuts_elem(const HmcTask& T, int lb, double* lds) {
+  HmcState* st = T.st;
+  const bool begin = (T.op & kOpBegin) != 0;
+  if (T.op & kOpNutsApply) {
+    if (!st->act) return;                            // nothing decided this tick
+  } else if (!begin && st->done) {
+    return;                                          // finished: a no-op step
+  }
+  const float eps = st->eps;
+  float* V = T.nuts;
+  const size_t vs = static_cast<size_t>(T.vstride);
+  auto vec = [&](int k) { return V + static_cast<size_t>(k) * vs; };
+  const int dir = begin ? nuts_direction(T, 0) : st->dir;
+  const int leaf = begin ? 0 : st->leaf;
+  const int depth = begin ? 0 : st->depth;
+  const float e = dir > 0 ? eps : -eps;
+  int ck_lo, ck_hi;
+  nuts_ckpt_range(leaf, ck_lo, ck_hi);
+  const bool last = leaf == (1 << depth) - 1;
+  const int beg = lb * kHmcPerBlock;
+  double acc[kNutsDots + 3];   // dots, then U, K, K0
+#pragma unroll
+  for (int k = 0; k < kNutsDots + 3; ++k) acc[k] = 0.0;
+  // decisions of the finalize kernel (apply pass)
+  const int a_cand = st->act_cand, a_ckpt = st->act_ckpt, a_merge = st->act_merge,
+            a_prop = st->act_prop, a_finish = st->act_finish, a_dir = st->act_dir;
+  for (int i0 = beg + threadIdx.x * 4; i0 < beg + kHmcPerBlock; i0 += kHmcThreads * 4) {
+    float z[4];
+    if ((T.op & kOpNutsPre) && begin)
+      normals4(T.seed, T.stream, T.traj, static_cast<uint32_t>(i0 >> 2), z);
+#pragma unroll
+    for (int el = 0; el < 4; ++el) {
+      const int i = i0 + el;
+      if (i >= T.len) break;
+      if (i >= T.nalm && i < T.goff) continue;  // alignment padding: never touched
+      const float mi = T.minv[i];
+      if (T.op & kOpNutsPre) {
+        float q = T.q[i], p = T.p[i], g = T.grad[i];
+        if (begin) {
+          p = z[el] * rsqrtf(mi);
+          acc[kNutsDots + 2] += 0.5 * static_cast<double>(mi) * p * p;
+          T.q0[i] = q;
+          T.grad0[i] = g;
+          vec(kNqL)[i] = q; vec(kNqR)[i] = q; vec(kNqP)[i] = q;
+          vec(kNpL)[i] = p; vec(kNpR)[i] = p;
+          vec(kNgL)[i] = g; vec(kNgR)[i] = g; vec(kNgP)[i] = g;
+          vec(kNrho)[i] = p;
+          vec(kNrhos)[i] = 0.f;
+        } else if (leaf == 0) {   // a new subtree starts at the end on its side
+          q = vec(dir > 0 ? kNqR : kNqL)[i];
+          p = vec(dir > 0 ? kNpR : kNpL)[i];
+          g = vec(dir > 0 ? kNgR : kNgL)[i];
+          T.grad[i] = g;
+        }
+        p -= 0.5f * e * g;
+        q += e * mi * p;
+        T.q[i] = q;
+        T.p[i] = p;
+      }
+      if (T.op & kOpNutsPost) {
+        const float q = T.q[i];
+        const float g = grad_potential(T, i, q, acc[kNutsDots]);
+        const float p = T.p[i] - 0.5f * e * g;
+        acc[kNutsDots + 1] += 0.5 * static_cast<double>(mi) * p * p;
+        T.grad[i] = g;
+        T.p[i] = p;
+        const float rs = vec(kNrhos)[i] + p;   // subtree momentum sum with this leaf
+#pragma unroll
+        for (int c = 0; c < kNutsMaxDepth; ++c) {
+          if (c >= ck_lo && c <= ck_hi) {
+            const float cp = vec(kNckp + c)[i];
+            const float adj = rs - vec(kNckr + c)[i] + 0.5f * (cp - p);
+            acc[2 * c] += static_cast<double>(mi * cp) * adj;
+            acc[2 * c + 1] += static_cast<double>(mi * p) * adj;
+          }
+        }
+        if (last) {   // whole-trajectory check, used if this leaf completes the subtree
+          const float po = vec(dir > 0 ? kNpL : kNpR)[i];
+          const float adj = vec(kNrho)[i] + rs - 0.5f * (po + p);
+          acc[2 * kNutsMaxDepth] += static_cast<double>(mi * po) * adj;
+          acc[2 * kNutsMaxDepth + 1] += static_cast<double>(mi * p) * adj;
+        }
+      }
+      if (T.op & kOpNutsApply) {
+        const float q = T.q[i], p = T.p[i], g = T.grad[i];
+        const float rs = vec(kNrhos)[i] + p;
+        if (a_cand) {
+          vec(kNqC)[i] = q;
+          vec(kNgC)[i] = g;
+        }
+        if (a_ckpt >= 0) {
+          vec(kNckp + a_ckpt)[i] = p;
+          vec(kNckr + a_ckpt)[i] = rs;
+        }
+        if (a_merge) {
+          if (a_prop) {
+            vec(kNqP)[i] = vec(kNqC)[i];
+            vec(kNgP)[i] = vec(kNgC)[i];
+          }
+          vec(kNrho)[i] += rs;
+          vec(kNrhos)[i] = 0.f;
+          vec(a_dir > 0 ? kNqR : kNqL)[i] = q;
+          vec(a_dir > 0 ? kNpR : kNpL)[i] = p;
+          vec(a_dir > 0 ? kNgR : kNgL)[i] = g;
+        } else {
+          vec(kNrhos)[i] = rs;
+        }
+        if (a_finish) {
+          T.q[i] = vec(kNqP)[i];
+          T.grad[i] = vec(kNgP)[i];
+        }
+      }
+    }
+  }
+  if (T.op & kOpNutsApply) return;
+  block_sum_n<kNutsDots + 3>(acc, lds);
+  if (threadIdx.x != 0) return;
+  if ((T.op & kOpNutsPre) && begin) {
+    T.part_k0[lb] = acc[kNutsDots + 2];
+    if (lb == 0) {
+      st->u0 = st->u;
+      st->chi2_0 = st->chi2;
+      st->u_prop = st->u;
+      st->chi2_prop = st->chi2;
+      st->logw = 0.0;
+      st->logw_sub = -INFINITY;
+      st->acc_sum = 0.0;
+      st->depth = 0;
+      st->leaf = 0;
+      st->dir = dir;
+      st->nsteps = 0;
+      st->done = 0;
+      st->moved = 0;
+      st->act = 0;
+    }
+  }
+  if (T.op & kOpNutsPost) {
+    T.part_u[lb] = acc[kNutsDots];
+    T.part_k[lb] = acc[kNutsDots + 1];
+#pragma unroll
+    for (int k = 0; k < kNutsDots; ++k) T.part_nuts[static_cast<size_t>(lb) * kNutsDots + k] = acc[k];
+  }
+}
+
+__device__ __forceinline__ int find_task(const int* __restrict__ blk0, int ntask, int b) {
+  // blk0 is an exclusive prefix over tasks of their block counts
   int lo = 0, hi = ntask - 1;
-  const int b = blockIdx.x;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (blk0[mid] <= b) lo = mid; else hi = mid - 1;
   }
-  const HmcTask T = tasks[lo];
-  const int lb = b - blk0[lo];
-  if (lb >= T.nblk) return;
+  return lo;
+}
+
+constexpr int kNutsOps = kOpNutsPre | kOpNutsPost | kOpNutsApply;
+
+// The NUTS element work; the same task tables as k_hmc_elem, whose tasks it skips.
+__global__ void __launch_bounds__(kHmcThreads)
+k_nuts_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__ blk0) {
+  __shared__ double red_n[4 * (kNutsDots + 3)];
+  const int k = find_task(blk0, ntask, blockIdx.x);
+  const HmcTask T = tasks[k];
+  const int lb = blockIdx.x - blk0[k];
+  if (lb >= T.nblk || !(T.op & kNutsOps)) return;
+  nuts_elem(T, lb, red_n);
+}
+
+// One block handles kHmcPerBlock consecutive parameters of one chain.
+__global__ void __launch_bounds__(kHmcThreads)
+k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__ blk0) {
+  __shared__ double red[kHmcThreads];
+  const int k = find_task(blk0, ntask, blockIdx.x);
+  const HmcTask T = tasks[k];
+  const int lb = blockIdx.x - blk0[k];
+  if (lb >= T.nblk || (T.op & kNutsOps)) return;
   HmcState* st = T.st;
   const float eps = st->eps;
   const int beg = lb * kHmcPerBlock;
@@ -123,16 +357,7 @@ k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__
       }
       if (T.op & (kOpPost | kOpInit)) {
         // assemble grad U from the chi^2 gradient and the priors
-        const float q = T.q[i];
-        float g = 0.5f * T.gchi[i];
-        if (i < T.nalm) {
-          g += q / T.cvar[i];
-          acc_u += 0.5 * static_cast<double>(q) * q / T.cvar[i];
-        } else if (i >= T.goff && i < T.goff + T.ngain) {
-          const float dg = q - ((i - T.goff) % 2 == 0 ? 1.0f : 0.0f);
-          g += dg * T.gvar_inv;
-          acc_u += 0.5 * static_cast<double>(dg) * dg * T.gvar_inv;
-        }
+        const float g = grad_potential(T, i, T.q[i], acc_u);
         T.grad[i] = g;
         if (T.op & kOpPost) {
           p -= 0.5f * eps * g;
@@ -346,13 +571,133 @@ k_gain_mass_setup(const float* __restrict__ chol, int nb, int nb4, float* __rest
   }
 }
 
+__device__ __forceinline__ double log_add_exp(double a, double b) {
+  const double m = fmax(a, b);
+  if (m == -INFINITY) return m;
+  return m + log1p(exp(-fabs(a - b)));
+}
+
+// Decisions of one NUTS step, in FP64 on one thread (see the NUTS notes above).
+__device__ void nuts_finalize(const HmcTask& T, double* lds) {
+  HmcState* st = T.st;
+  if (st->done) {   // a step scheduled after the trajectory finished
+    if (threadIdx.x == 0) {
+      st->act = 0;
+      st->finished_now = 0;
+      *T.st_out = *st;
+    }
+    return;
+  }
+  double v[kNutsDots + 3];   // dots, U, K, K0
+#pragma unroll
+  for (int k = 0; k < kNutsDots + 3; ++k) v[k] = 0.0;
+  for (int b = threadIdx.x; b < T.nblk; b += kHmcThreads) {
+#pragma unroll
+    for (int k = 0; k < kNutsDots; ++k) v[k] += T.part_nuts[static_cast<size_t>(b) * kNutsDots + k];
+    v[kNutsDots] += T.part_u[b];
+    v[kNutsDots + 1] += T.part_k[b];
+    v[kNutsDots + 2] += T.part_k0[b];
+  }
+  block_sum_n<kNutsDots + 3>(v, lds);
+  if (threadIdx.x != 0) return;
+  const double u = 0.5 * st->chi2 + v[kNutsDots];
+  const double h0 = st->u0 + v[kNutsDots + 2];
+  const double h = u + v[kNutsDots + 1];
+  const int s = st->nsteps;
+  if (s == 0) st->h_prop = h0;       // the proposal starts as the initial state
+  st->nsteps = s + 1;
+  st->acc_sum += isfinite(h) && isfinite(h0) ? exp(fmin(0.0, h0 - h)) : 0.0;
+  st->act = 1;
+  st->act_dir = st->dir;
+  st->act_cand = 0;
+  st->act_ckpt = -1;
+  st->act_merge = 0;
+  st->act_prop = 0;
+  st->act_finish = 0;
+  st->finished_now = 0;
+  bool finish = false;
+  if (!isfinite(h0) || !isfinite(h) || h - h0 > 1000.0) {
+    finish = true;   // divergent leaf: its subtree is discarded
+  } else {
+    const double lw = h0 - h;
+    const double lws = log_add_exp(st->logw_sub, lw);
+    // multinomial candidate of the subtree, in progressive form
+    if (philox_unit(T, static_cast<uint32_t>(s), 3u) < exp(lw - lws)) {
+      st->act_cand = 1;
+      st->u_cand = u;
+      st->chi2_cand = st->chi2;
+      st->h_cand = h;
+    }
+    st->logw_sub = lws;
+    const int leaf = st->leaf;
+    if ((leaf & 1) == 0) {
+      st->act_ckpt = __popc(static_cast<unsigned>(leaf) >> 1);
+    } else {
+      int lo, hi;
+      nuts_ckpt_range(leaf, lo, hi);
+#pragma unroll
+      for (int c = 0; c < kNutsMaxDepth; ++c)
+        if (c >= lo && c <= hi && (v[2 * c] <= 0.0 || v[2 * c + 1] <= 0.0)) finish = true;   // a span turned
+    }
+    if (!finish && leaf == (1 << st->depth) - 1) {
+      // subtree complete: biased progressive sampling, then the whole-trajectory check
+      st->act_merge = 1;
+      if (philox_unit(T, static_cast<uint32_t>(st->depth), 4u) < exp(fmin(0.0, lws - st->logw))) {
+        st->act_prop = 1;
+        st->u_prop = st->u_cand;
+        st->chi2_prop = st->chi2_cand;
+        st->h_prop = st->h_cand;
+        st->moved = 1;
+      }
+      st->logw = log_add_exp(st->logw, lws);
+      if (v[2 * kNutsMaxDepth] <= 0.0 || v[2 * kNutsMaxDepth + 1] <= 0.0 ||
+          st->depth + 1 >= T.nuts_depth) {
+        finish = true;
+      } else {
+        st->depth += 1;
+        st->leaf = 0;
+        st->dir = nuts_direction(T, st->depth);
+        st->logw_sub = -INFINITY;
+      }
+    } else if (!finish) {
+      st->leaf = leaf + 1;
+    }
+  }
+  if (finish) {
+    st->act_finish = 1;
+    st->done = 1;
+    st->finished_now = 1;
+    st->u = st->u_prop;
+    st->chi2 = st->chi2_prop;
+    st->h0 = h0;
+    st->h1 = st->h_prop;
+    st->accepted = st->moved;
+    st->status = isfinite(h0) ? 0 : -6;
+    st->eps_used = st->eps;
+    const double stat = st->acc_sum / st->nsteps;
+    st->accept_stat = static_cast<float>(stat);
+    if (st->adapt) {
+      const float e = st->eps;
+      st->eps = stat < 0.2 ? e / 1.2f : fminf(st->eps0, 1.2f * e);
+    }
+  } else {
+    st->u = u;
+  }
+  *T.st_out = *st;
+}
+
 // One block per task: totals in FP64, Hamiltonian and Metropolis test at the
 // end of a trajectory, step-size adaptation.
 __global__ void __launch_bounds__(kHmcThreads)
 k_hmc_finalize(const HmcTask* __restrict__ tasks) {
   __shared__ double red[kHmcThreads];
+  __shared__ double red_n[4 * (kNutsDots + 3)];
   const HmcTask T = tasks[blockIdx.x];
   HmcState* st = T.st;
+  if (T.op & kOpNutsPost) {
+    nuts_finalize(T, red_n);
+    return;
+  }
   double su = 0.0, sk = 0.0, sk0 = 0.0;
   for (int i = threadIdx.x; i < T.nblk; i += kHmcThreads) {
     su += T.part_u[i];
@@ -392,6 +737,7 @@ k_hmc_finalize(const HmcTask* __restrict__ tasks) {
   const double acc_prob = finite ? exp(fmin(0.0, h0 - h1)) : 0.0;
   const int accepted = finite && un < acc_prob;
   st->accepted = accepted;
+  st->accept_stat = static_cast<float>(acc_prob);
   st->status = isfinite(h0) ? 0 : -6;
   st->eps_used = st->eps;
   if (!accepted) {
@@ -425,6 +771,13 @@ void launch_gain_mass_setup(const float* chol, int nchan, int nb, int nb4, float
   if (nchan == 0) return;
   k_gain_mass_setup<<<dim3(nb4, nchan), 256, 0, st>>>(chol, nb, nb4, lrow, lcol, bad);
   check_launch("k_gain_mass_setup");
+}
+
+void launch_nuts_elem(const HmcTask* tasks_dev, int ntask, const int* blk0_dev, int nblocks,
+                      hipStream_t st) {
+  if (ntask == 0 || nblocks == 0) return;
+  k_nuts_elem<<<nblocks, kHmcThreads, 0, st>>>(tasks_dev, ntask, blk0_dev);
+  check_launch("k_nuts_elem");
 }
 
 void launch_hmc_finalize(const HmcTask* tasks_dev, int ntask, hipStream_t st) {

@@ -9,6 +9,18 @@ constexpr int kHmcThreads = 256;
 constexpr int kHmcPerBlock = 4096;   // parameters per elementwise block
 constexpr int kGainBlockMax = 256;   // largest dense gain block (2 n_ant)
 constexpr int kGainBlockPad = 16;    // dense gain blocks are padded to a multiple of this
+constexpr int kNutsMaxDepth = 10;    // NUTS doublings (at most 2^10 - 1 leapfrog steps)
+// per-block NUTS partials: U-turn dots of every checkpoint (two each), then
+// the two dots of the whole-trajectory check
+constexpr int kNutsDots = 2 * kNutsMaxDepth + 2;
+// NUTS vectors of a chain, each of the chain's padded length: the trajectory
+// ends (q, p, grad on the left and right), the subtree candidate and the
+// proposal (q, grad), the momentum sums of the trajectory and of the subtree
+// being built, then kNutsMaxDepth checkpoint momenta and momentum sums.
+enum NutsVec : int {
+  kNqL, kNpL, kNgL, kNqR, kNpR, kNgR, kNqC, kNgC, kNqP, kNgP, kNrho, kNrhos, kNckp,
+  kNckr = kNckp + kNutsMaxDepth, kNutsVecs = kNckr + kNutsMaxDepth
+};
 
 enum HmcOp : int {
   kOpBegin = 1,        // draw p, save q0 / grad0, K0 partials
@@ -16,7 +28,11 @@ enum HmcOp : int {
   kOpPost = 4,         // grad = grad chi^2 / 2 + prior; p -= eps/2 grad; U, K partials
   kOpInit = 8,         // grad and U partials at the initial position, no kick
   kOpEnd = 16,         // finalize: this evaluation ends a trajectory
-  kOpRestore = 32      // q = q0, grad = grad0 if the trajectory was rejected
+  kOpRestore = 32,     // q = q0, grad = grad0 if the trajectory was rejected
+  // NUTS chains (the same launches, other element work)
+  kOpNutsPre = 64,     // new subtree: start from the end on its side; kick + drift by dir * eps
+  kOpNutsPost = 128,   // grad, kick, U / K partials and the U-turn dots
+  kOpNutsApply = 256   // act on the finalize decisions (candidate, checkpoint, merge, finish)
 };
 
 // Device-resident scalars of one chain.
@@ -29,6 +45,18 @@ struct HmcState {
   int adapt;
   int accepted, restore, status;
   int pad;
+  // NUTS (zero for fixed-length HMC)
+  double logw, logw_sub;      // log total weight of the trajectory / of the subtree being built
+  double acc_sum;             // sum over leaves of min(1, exp(H0 - H))
+  double u_cand, chi2_cand, h_cand, u_prop, chi2_prop, h_prop;
+  int depth, dir, leaf, nsteps;
+  int done;                   // trajectory finished; steps until the next start are no-ops
+  int finished_now;           // this step finished it (the host reports the result)
+  int act;                    // this step's decisions are to be applied
+  int act_cand, act_ckpt, act_merge, act_prop, act_finish;
+  int act_dir;                // direction of the step being applied (the merge updates that end)
+  int moved;
+  float accept_stat;
 };
 
 // One chain's work in one kernel launch.
@@ -52,6 +80,9 @@ struct HmcTask {
   double* part_kg;    // [n_freq] kinetic-energy partials of the gain blocks
   double* part_k0g;
   int nchan, nb, nb4; // channels, block size 2 n_ant, padded size (multiple of kGainBlockPad)
+  float* nuts;        // NUTS vectors (null for fixed-length HMC), kNutsVecs x vstride floats
+  double* part_nuts;  // [nblk][kNutsDots]
+  int nuts_depth, vstride;
   uint64_t seed;
   int len, nalm, goff, ngain;
   float gvar_inv;
@@ -70,6 +101,10 @@ void launch_hmc_gainblk(const HmcTask* tasks_dev, int ntask, const int* chan0_de
 // or non-finite diagonal or a non-finite entry in *bad.
 void launch_gain_mass_setup(const float* chol, int nchan, int nb, int nb4, float* lrow,
                             float* lcol, int* bad, hipStream_t st);
+// NUTS element work over the same task tables (skips fixed-length HMC tasks,
+// which k_hmc_elem handles and this kernel's tasks skip in turn).
+void launch_nuts_elem(const HmcTask* tasks_dev, int ntask, const int* blk0_dev, int nblocks,
+                      hipStream_t st);
 void launch_hmc_finalize(const HmcTask* tasks_dev, int ntask, hipStream_t st);
 
 }  // namespace bv

@@ -41,10 +41,12 @@ struct ChainLayout {
   size_t off_q, off_p, off_grad, off_gchi, off_minv, off_q0, off_grad0, off_cvar;
   size_t off_pu, off_pk, off_pk0, off_state;
   size_t off_lrow = 0, off_lcol = 0, off_pkg = 0, off_pk0g = 0, off_flag = 0;
+  int vstride = 0;                  // NUTS vectors (vstride = 0: fixed-length HMC)
+  size_t off_nuts = 0, off_pnuts = 0;
   size_t bytes;
 };
 
-static ChainLayout chain_layout(const vis_field* f, bool dense_gains) {
+static ChainLayout chain_layout(const vis_field* f, bool dense_gains, bool nuts) {
   ChainLayout L;
   L.nalm = f->n_freq * f->n_modes;
   L.goff = static_cast<int>(round_up(L.nalm, 64));
@@ -80,6 +82,11 @@ static ChainLayout chain_layout(const vis_field* f, bool dense_gains) {
     L.off_pkg = at(sizeof(double) * L.nchan);
     L.off_pk0g = at(sizeof(double) * L.nchan);
     L.off_flag = at(sizeof(int));
+  }
+  if (nuts) {
+    L.vstride = static_cast<int>(round_up(L.len, 64));
+    L.off_nuts = at(sizeof(float) * static_cast<size_t>(kNutsVecs) * L.vstride);
+    L.off_pnuts = at(sizeof(double) * static_cast<size_t>(L.nblk) * kNutsDots);
   }
   L.bytes = round_up(cv.used, 256);
   return L;
@@ -136,6 +143,7 @@ struct Chain {
   float sigma_n = 1.f;
   float gvar_inv = 0.f;
   int n_leapfrog = 1;
+  int nuts_depth = 0;         // > 0: NUTS with at most this many doublings
   uint64_t seed = 0;
   uint32_t stream = 0;
   ChainLayout L{};
@@ -160,6 +168,7 @@ struct TickEntry {
   bool init;        // gradient at the admitted position (no leapfrog step)
   bool first;       // first step of a trajectory: draw the momentum
   bool ends;        // last step of a trajectory: energies and Metropolis test
+  bool nuts;        // a NUTS step (the device decides where the trajectory ends)
   int traj;
   uint64_t t_enqueue;
 };
@@ -181,8 +190,8 @@ struct Slot {
 };
 
 constexpr int kSlots = 3;
-// block prefixes of a tick: pre, post and restore elementwise launches, then
-// the channel prefixes of the pre and post gain-block launches
+// block prefixes of a tick: pre, post and restore/apply elementwise launches,
+// then the channel prefixes of the pre and post gain-block launches
 constexpr int kPrefixes = 5;
 constexpr int kSubStreams = 4;   // evaluation streams of a batched tick (hardware queues)
 
@@ -234,7 +243,7 @@ bool hmc_server::build_tick(Tick& t) {
   for (int k = 0; k < n && static_cast<int>(t.entries.size()) < cfg.max_batch; ++k) {
     Chain* c = chains[(rr + k) % n];
     if (c == nullptr || c->releasing || c->failed) continue;
-    TickEntry e{c, false, false, false, 0, now_ns()};
+    TickEntry e{c, false, false, false, c->nuts_depth > 0, 0, now_ns()};
     if (!c->initialised) {
       c->initialised = true;
       e.init = true;
@@ -252,7 +261,10 @@ bool hmc_server::build_tick(Tick& t) {
     } else {
       continue;
     }
-    if (!e.init && c->step == c->n_leapfrog) {
+    if (e.init) e.nuts = false;
+    // fixed-length HMC knows its last step; a NUTS chain runs until the host
+    // reads back that the device finished the trajectory
+    if (!e.init && !e.nuts && c->step == c->n_leapfrog) {
       e.ends = true;
       c->running = false;
       c->step = 0;
@@ -276,6 +288,7 @@ void hmc_server::enqueue(Tick& t) {
   int* pre_chan = S.host_blk + 3 * (nb + 1);
   int* post_chan = S.host_blk + 4 * (nb + 1);
   int npre = 0, npost = 0, nrst = 0, bpre = 0, bpost = 0, cpre = 0, cpost = 0;
+  int nuts_tasks = 0, hmc_tasks = 0;
   std::vector<const Chain*> evs;
   for (const TickEntry& e : t.entries) {
     Chain* c = e.c;
@@ -309,13 +322,20 @@ void hmc_server::enqueue(Tick& t) {
       T.nb = c->L.nb;
       T.nb4 = c->L.nb4;
     }
+    if (c->L.vstride > 0) {
+      T.nuts = c->ptr(c->L.off_nuts);
+      T.part_nuts = reinterpret_cast<double*>(c->base + c->L.off_pnuts);
+      T.nuts_depth = c->nuts_depth;
+      T.vstride = c->L.vstride;
+    }
     T.stream = c->stream;
     T.traj = static_cast<uint32_t>(e.traj < 0 ? 0 : e.traj);
+    if (e.nuts) ++nuts_tasks; else ++hmc_tasks;
     const bool is_init = e.init;
     // pre-evaluation: momentum draw at a trajectory start, then kick + drift
     if (!is_init) {
       HmcTask P = T;
-      P.op = kOpKickDrift | (e.first ? kOpBegin : 0);
+      P.op = (e.nuts ? kOpNutsPre : kOpKickDrift) | (e.first ? kOpBegin : 0);
       pre_blk[npre] = bpre;
       pre_chan[npre] = cpre;
       pre[npre++] = P;
@@ -323,7 +343,7 @@ void hmc_server::enqueue(Tick& t) {
       cpre += c->L.nchan;
     }
     HmcTask Q = T;
-    Q.op = is_init ? kOpInit : (kOpPost | (e.ends ? kOpEnd : 0));
+    Q.op = is_init ? kOpInit : e.nuts ? kOpNutsPost : (kOpPost | (e.ends ? kOpEnd : 0));
     post_blk[npost] = bpost;
     post_chan[npost] = cpost;
     post[npost] = Q;
@@ -331,9 +351,9 @@ void hmc_server::enqueue(Tick& t) {
     npost++;
     bpost += Q.nblk;
     if (e.ends) cpost += c->L.nchan;   // the gain blocks' final kinetic energy
-    if (e.ends) {
+    if (e.ends || (e.nuts && !is_init)) {
       HmcTask R = T;
-      R.op = kOpRestore;
+      R.op = e.nuts ? kOpNutsApply : kOpRestore;
       rst[nrst++] = R;
     }
     evs.push_back(c);
@@ -352,7 +372,8 @@ void hmc_server::enqueue(Tick& t) {
                               hipMemcpyHostToDevice, stream), "task upload");
   hip_or_throw(hipMemcpyAsync(S.dev_blk, S.host_blk, sizeof(int) * kPrefixes * (nb + 1),
                               hipMemcpyHostToDevice, stream), "prefix upload");
-  launch_hmc_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
+  if (hmc_tasks) launch_hmc_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
+  if (nuts_tasks) launch_nuts_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
   launch_hmc_gainblk(S.dev_tasks, npre, S.dev_blk + 3 * (nb + 1), cpre, stream);
   // evaluations: in a batched tick the chains' evaluation sequences run on
   // several streams so the kernels of different fields overlap on the device
@@ -377,9 +398,13 @@ void hmc_server::enqueue(Tick& t) {
     hip_or_throw(hipStreamWaitEvent(stream, ev_sub[i], 0), "stream wait");
   }
   launch_hmc_elem(S.dev_tasks + nb, npost, S.dev_blk + (nb + 1), bpost, stream);
+  if (nuts_tasks) launch_nuts_elem(S.dev_tasks + nb, npost, S.dev_blk + (nb + 1), bpost, stream);
   launch_hmc_gainblk(S.dev_tasks + nb, npost, S.dev_blk + 4 * (nb + 1), cpost, stream);
   launch_hmc_finalize(S.dev_tasks + 2 * nb, npost, stream);
-  launch_hmc_elem(S.dev_tasks + 3 * nb, nrst, S.dev_blk + 2 * (nb + 1), rst_blk[nrst], stream);
+  if (hmc_tasks)
+    launch_hmc_elem(S.dev_tasks + 3 * nb, nrst, S.dev_blk + 2 * (nb + 1), rst_blk[nrst], stream);
+  if (nuts_tasks)
+    launch_nuts_elem(S.dev_tasks + 3 * nb, nrst, S.dev_blk + 2 * (nb + 1), rst_blk[nrst], stream);
   // read back the state of every chain in the tick (gathered by the finalize kernel)
   hip_or_throw(hipMemcpyAsync(S.host_states, S.dev_states, sizeof(HmcState) * npost,
                               hipMemcpyDeviceToHost, stream), "state read-back");
@@ -399,24 +424,34 @@ void hmc_server::complete(Tick& t) {
     n_requests += 1;
     const HmcState& hs = S.host_states[i];
     const bool bad = hs.status != 0;
-    if ((e.ends || bad) && !c->failed) {
+    const bool nuts_end = e.nuts && hs.finished_now;
+    // a NUTS trajectory ends within 2^depth - 1 steps; the bound guards the schedule
+    const bool overrun = e.nuts && !hs.finished_now && c->running &&
+                         c->step > (1 << c->nuts_depth) + 2 * kSlots;
+    if (nuts_end) {
+      c->running = false;
+      c->step = 0;
+    }
+    if ((e.ends || nuts_end || bad || overrun) && !c->failed) {
       hmc_result r{};
       r.chain = c->id;
       r.trajectory = e.traj;
-      r.accepted = bad ? 0 : hs.accepted;
-      r.status = bad ? VIS_ENUMERIC : VIS_OK;
+      r.accepted = bad || overrun ? 0 : hs.accepted;
+      r.status = overrun ? VIS_EDEVICE : bad ? VIS_ENUMERIC : VIS_OK;
       r.h0 = hs.h0;
       r.h1 = hs.h1;
       r.chi2 = hs.chi2;
       r.eps = hs.eps_used;
-      r.n_grad = e.init ? 1 : c->n_leapfrog;
+      r.n_grad = e.init ? 1 : e.nuts ? hs.nsteps : c->n_leapfrog;
+      r.tree_depth = e.nuts ? hs.depth + 1 : 0;
+      r.accept_stat = hs.accept_stat;
       if (!e.init && !c->traj_submit_ns.empty()) {
         r.t_submit_ns = c->traj_submit_ns.front();
         c->traj_submit_ns.pop_front();
       }
       r.t_done_ns = tnow;
       results.push_back(r);
-      if (bad) {
+      if (bad || overrun) {
         // a non-finite energy stops this chain only; its queued work is dropped
         c->failed = true;
         c->pending = 0;
@@ -477,12 +512,17 @@ extern "C" {
 
 size_t hmc_chain_footprint_bytes(const vis_field* field) {
   if (field == nullptr) return 0;
-  return chain_layout(field, false).bytes;
+  return chain_layout(field, false, false).bytes;
 }
 
 size_t hmc_chain_footprint_dense_gain_bytes(const vis_field* field) {
   if (field == nullptr) return 0;
-  return chain_layout(field, true).bytes;
+  return chain_layout(field, true, false).bytes;
+}
+
+size_t hmc_chain_footprint_nuts_bytes(const vis_field* field) {
+  if (field == nullptr) return 0;
+  return chain_layout(field, false, true).bytes;
 }
 
 vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size_t arena_bytes,
@@ -547,10 +587,14 @@ vis_status hmc_chain_admit(hmc_server* s, const hmc_chain_init* in, int32_t* cha
     BV_REQUIRE(in->eps > 0.f && in->sigma_n > 0.f && in->gain_prior_sigma > 0.f, VIS_EINVAL,
                "eps, sigma_n and gain_prior_sigma must be positive");
     const bool dense = in->gain_chol != nullptr;
+    BV_REQUIRE(in->nuts_max_depth >= 0 && in->nuts_max_depth <= kNutsMaxDepth, VIS_EINVAL,
+               "nuts_max_depth must be in [0, %d]", kNutsMaxDepth);
+    BV_REQUIRE(!(dense && in->nuts_max_depth > 0), VIS_EINVAL,
+               "NUTS chains take a diagonal mass (gain_chol must be NULL)");
     BV_REQUIRE(!dense || 2 * in->field->n_ant <= kGainBlockMax, VIS_EINVAL,
                "dense gain mass blocks hold at most %d antennas (field has %d)",
                kGainBlockMax / 2, in->field->n_ant);
-    const ChainLayout L = chain_layout(in->field, dense);
+    const ChainLayout L = chain_layout(in->field, dense, in->nuts_max_depth > 0);
     Chain* c = nullptr;
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -581,6 +625,7 @@ vis_status hmc_chain_admit(hmc_server* s, const hmc_chain_init* in, int32_t* cha
       c->sigma_n = in->sigma_n;
       c->gvar_inv = 2.0f / (in->gain_prior_sigma * in->gain_prior_sigma);
       c->n_leapfrog = in->n_leapfrog;
+      c->nuts_depth = in->nuts_max_depth;
       c->seed = in->seed;
       c->stream = in->stream_id;
       c->releasing = true;  // not schedulable until its buffers are initialised

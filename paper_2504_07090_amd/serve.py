@@ -29,14 +29,16 @@ class ChainInit(C.Structure):
     _fields_ = [("field", _vp), ("data", _vp), ("sigma_n", C.c_float), ("q0", _vp),
                 ("minv", _vp), ("alm_prior_var", _vp), ("gain_prior_sigma", C.c_float),
                 ("eps", C.c_float), ("n_leapfrog", C.c_int32), ("adapt_step", C.c_int32),
-                ("seed", C.c_uint64), ("stream_id", C.c_uint32), ("gain_chol", _vp)]
+                ("seed", C.c_uint64), ("stream_id", C.c_uint32), ("gain_chol", _vp),
+                ("nuts_max_depth", C.c_int32)]
 
 
 class Result(C.Structure):
     _fields_ = [("chain", C.c_int32), ("trajectory", C.c_int32), ("accepted", C.c_int32),
                 ("status", C.c_int32), ("h0", C.c_double), ("h1", C.c_double),
                 ("chi2", C.c_double), ("eps", C.c_float), ("n_grad", C.c_int32),
-                ("t_submit_ns", C.c_uint64), ("t_done_ns", C.c_uint64)]
+                ("t_submit_ns", C.c_uint64), ("t_done_ns", C.c_uint64), ("tree_depth", C.c_int32),
+                ("accept_stat", C.c_float)]
 
 
 class Stats(C.Structure):
@@ -44,7 +46,8 @@ class Stats(C.Structure):
                 ("max_ms", C.c_double), ("arena_free_bytes", C.c_int64), ("live_chains", C.c_int32)]
 
 
-for _n in ("hmc_chain_footprint_bytes", "hmc_chain_footprint_dense_gain_bytes"):
+for _n in ("hmc_chain_footprint_bytes", "hmc_chain_footprint_dense_gain_bytes",
+           "hmc_chain_footprint_nuts_bytes"):
     getattr(_lib, _n).argtypes = [_vp]
     getattr(_lib, _n).restype = C.c_size_t
 _lib.hmc_server_create.argtypes = [C.POINTER(ServerConfig), _vp, C.c_size_t, _vp, C.POINTER(_vp)]
@@ -163,7 +166,9 @@ class Server:
         self._keep = {}
 
     @staticmethod
-    def footprint(field: V.Field, dense_gains: bool = False) -> int:
+    def footprint(field: V.Field, dense_gains: bool = False, nuts: bool = False) -> int:
+        if nuts:
+            return int(_lib.hmc_chain_footprint_nuts_bytes(field.handle))
         if dense_gains:
             return int(_lib.hmc_chain_footprint_dense_gain_bytes(field.handle))
         return int(_lib.hmc_chain_footprint_bytes(field.handle))
@@ -171,10 +176,12 @@ class Server:
     def admit(self, field: V.Field, data: torch.Tensor, sigma_n: float, q0: torch.Tensor,
               minv: torch.Tensor, alm_prior_var: torch.Tensor, gain_prior_sigma: float,
               eps: float, n_leapfrog: int, seed: int, stream_id: int,
-              adapt_step: bool = False, gain_chol: Optional[torch.Tensor] = None) -> Optional[int]:
+              adapt_step: bool = False, gain_chol: Optional[torch.Tensor] = None,
+              nuts_max_depth: int = 0) -> Optional[int]:
         """Chain id, or None if the arena has no room now (VIS_EAGAIN).
         gain_chol: optional [n_freq][2 n_ant][2 n_ant] lower Cholesky factors of
-        dense per-channel gain mass blocks."""
+        dense per-channel gain mass blocks.  nuts_max_depth > 0: No-U-Turn
+        trajectories of at most that many doublings (n_leapfrog ignored)."""
         lay = Layout(field)
         V._need(data, "data", torch.complex64, (field.n_time, field.n_freq, field.n_bl), field.device)
         V._need(q0, "q0", torch.float32, (lay.length,), field.device)
@@ -188,7 +195,7 @@ class Server:
         init = ChainInit(field.handle, data.data_ptr(), sigma_n, q0.data_ptr(), minv.data_ptr(),
                          alm_prior_var.data_ptr(), gain_prior_sigma, eps, n_leapfrog,
                          1 if adapt_step else 0, seed, stream_id,
-                         None if gain_chol is None else gain_chol.data_ptr())
+                         None if gain_chol is None else gain_chol.data_ptr(), nuts_max_depth)
         cid = C.c_int32()
         st = _lib.hmc_chain_admit(self.handle, C.byref(init), C.byref(cid))
         if st == VIS_EAGAIN:

@@ -127,6 +127,86 @@ def test_trajectory_matches_oracle(mods, case):
         np.testing.assert_allclose(qg, q_or, rtol=1e-6)
 
 
+@pytest.mark.parametrize("case", ["depth_limit", "u_turn"])
+def test_nuts_trajectories_match_oracle(mods, case):
+    """Three consecutive NUTS trajectories from the same start, momentum stream
+    and diagonal mass: tree depth, leapfrog steps, whether the chain moved, H0
+    and H of the proposal agree with the FP64 oracle's NUTS, and so does the
+    position after each trajectory (to 1e-3 of the move).  "depth_limit": the
+    data posterior at eps 0.12, whose stiff directions keep trajectories going
+    to the 6-doubling limit; "u_turn": noise 300x larger (the prior dominates)
+    at eps 0.4 with 8 doublings allowed, where trajectories end by the
+    no-U-turn criterion after 63-127 steps."""
+    from oracle import nuts as onuts
+    vis, serve = mods
+    cfg = w.scaled(w.C0, lmax=4, n_freq=2, n_time=2)
+    basis = vis.basis_for(cfg)
+    fld = vis.Field.from_config(basis, cfg)
+    d = w.draw(cfg)
+    of = model.Field(cfg)
+    _, sig, data = model.make_data(of, d)
+    if case == "u_turn":
+        sig *= 300.0
+        eps, depth = 0.4, 8
+    else:
+        eps, depth = 0.12, 6
+    post = ohmc.Posterior(of, data, sig, d.alm_var, cfg.gain_scatter)
+    q_or = ohmc.pack(d.alm, d.gains, w.fwhm_ref_rad(cfg))
+    _, g0 = post.potential_and_grad(q_or)
+    hd = np.empty(q_or.size)
+    for i in range(q_or.size):
+        h = 1e-6 * max(1.0, abs(q_or[i]))
+        qp = q_or.copy()
+        qp[i] += h
+        hd[i] = (post.potential_and_grad(qp)[1][i] - g0[i]) / h
+    minv_or = (1.0 / hd).astype(np.float32).astype(np.float64)
+    seed, stream = 5, 2
+    lay = serve.Layout(fld)
+    nalm, ng = lay.nalm, lay.ngain
+    idx = np.concatenate([np.arange(nalm), lay.goff + np.arange(ng), [lay.length - 1]])
+
+    def to_lay(v):
+        out = np.zeros(lay.length)
+        out[:nalm] = v[:nalm]
+        out[lay.goff:lay.goff + ng] = v[nalm:nalm + ng]
+        out[-1] = v[-1]
+        return out
+
+    def from_lay(v):
+        return np.concatenate([v[:nalm], v[lay.goff:lay.goff + ng], v[-1:]])
+
+    minv_l = to_lay(minv_or)
+    minv_l[nalm:lay.goff] = 1.0
+    srv = serve.Server(64 << 20, max_chains=2, max_batch=2)
+    cid = srv.admit(fld, torch.tensor(data, dtype=torch.complex64, device="cuda"), sig,
+                    torch.tensor(to_lay(q_or), dtype=torch.float32, device="cuda"),
+                    torch.tensor(minv_l, dtype=torch.float32, device="cuda"),
+                    torch.tensor(d.alm_var, dtype=torch.float32, device="cuda"),
+                    cfg.gain_scatter, eps, 1, seed, stream, nuts_max_depth=depth)
+    q, (u, g) = q_or, post.potential_and_grad(q_or)
+    reasons = []
+    for t in range(3):
+        srv.submit(cid, 1)
+        r = srv.wait(1)[0]
+        qg = from_lay(srv.position(cid, lay.length, "cuda").double().cpu().numpy())
+        o = onuts.trajectory(q, u, g, eps, depth, minv_or, post.potential_and_grad, seed, stream, t,
+                             normal_index=idx)
+        say("nuts traj", t, "oracle", o.depth, o.n_steps, o.moved, o.reason, o.h0, o.h_prop,
+            "gpu", r["tree_depth"], r["n_grad"], r["accepted"], r["h0"], r["h1"], r["accept_stat"])
+        assert r["status"] == 0 and r["trajectory"] == t
+        assert (r["tree_depth"], r["n_grad"], bool(r["accepted"])) == (o.depth, o.n_steps, o.moved)
+        assert abs(r["h0"] - o.h0) <= 1e-4 * abs(o.h0) and abs(r["h1"] - o.h_prop) <= 1e-4 * abs(o.h_prop)
+        # the statistic averages min(1, exp(H0 - H)) over the leaves; FP32 energies
+        # carry ~1e-3 absolute error at this U ~ 550, so it agrees to a few 1e-3
+        assert abs(r["accept_stat"] - o.accept_stat) <= 5e-3
+        move = np.linalg.norm(o.q - q)
+        assert np.linalg.norm(qg - o.q) <= 1e-3 * max(move, 1e-12 * np.linalg.norm(q))
+        q, u, g = o.q, o.u, o.g
+        reasons.append(o.reason)
+    srv.close()
+    assert ("turn" in reasons) == (case == "u_turn")
+
+
 # (hex side, channels, times, lmax, precision, synthesis): every evaluation path
 # of the library appears in the mix
 MIXED = [(3, 4, 3, 10, 1, 0), (4, 3, 5, 14, 1, 1), (3, 6, 2, 20, 2, 0), (5, 2, 4, 8, 3, 0),
@@ -171,8 +251,10 @@ def test_alone_equals_mix(mods):
     inputs = []
     for c, f in zip(cfgs, flds):
         inputs.append(_chain_inputs(vis, serve, f, c, w.draw(c)))
-    # chain 1 (37 antennas: 74-row blocks, padded to 80) has dense gain blocks
+    # chain 1 (37 antennas: 74-row blocks, padded to 80) has dense gain blocks;
+    # chain 3 runs NUTS
     chols = {1: _dense_gain_chol(inputs[1][0], inputs[1][4], flds[1].n_freq, flds[1].n_ant, 17)}
+    nuts_depth = {3: 5}
 
     def run(which):
         srv = serve.Server(256 << 20, max_chains=8, max_batch=8)
@@ -181,9 +263,10 @@ def test_alone_equals_mix(mods):
             lay, data, sig, q0, minv, cvar = inputs[k]
             # eps 0.2 is too long a step for these fields (rejections, adaptation);
             # the dense chain takes 0.05, which these fields accept
-            eps = 0.05 if k in chols else 0.2
+            eps = 0.05 if k in chols or k in nuts_depth else 0.2
             ids[k] = srv.admit(flds[k], data, sig, q0, minv, cvar, cfgs[k].gain_scatter, eps, 4,
-                               seed=99, stream_id=k, adapt_step=True, gain_chol=chols.get(k))
+                               seed=99, stream_id=k, adapt_step=True, gain_chol=chols.get(k),
+                               nuts_max_depth=nuts_depth.get(k, 0))
             srv.submit(ids[k], 3)
         res = srv.wait(3 * len(which))
         pos = {k: srv.position(ids[k], inputs[k][0].length, "cuda") for k in which}
@@ -194,12 +277,14 @@ def test_alone_equals_mix(mods):
 
     alone, pos_a = run([0])
     alone1, pos_a1 = run([1])
+    alone3, pos_a3 = run([3])
     mix, pos_m = run([0, 1, 2, 3, 4])
     assert all(r["status"] == 0 for rs in mix.values() for r in rs)
-    for k, al, pa in ((0, alone, pos_a), (1, alone1, pos_a1)):
+    assert all(r["tree_depth"] >= 1 for r in mix[3])
+    for k, al, pa in ((0, alone, pos_a), (1, alone1, pos_a1), (3, alone3, pos_a3)):
         assert len(al[k]) == len(mix[k]) == 3
         for ra, rm in zip(al[k], mix[k]):
-            for key in ("trajectory", "accepted", "h0", "h1", "chi2", "eps"):
+            for key in ("trajectory", "accepted", "h0", "h1", "chi2", "eps", "n_grad", "tree_depth"):
                 assert ra[key] == rm[key], (k, key)
         assert torch.equal(pa[k], pos_m[k]), k
     # the dense chain moved (at least one accepted trajectory) and its energies are finite
@@ -229,6 +314,12 @@ def test_dense_gain_mass_admission_checks(mods):
     bad[0, 7, 2] = float("nan")
     with pytest.raises(vis.VisError):
         srv.admit(flds[0], *ins[1:], 0.05, 0.1, 2, 5, 0, gain_chol=bad)
+    # NUTS takes a diagonal mass only, and at most 10 doublings
+    good = _dense_gain_chol(lay, ins[4], flds[0].n_freq, flds[0].n_ant, 3)
+    with pytest.raises(vis.VisError):
+        srv.admit(flds[0], *ins[1:], 0.05, 0.1, 2, 5, 0, gain_chol=good, nuts_max_depth=3)
+    with pytest.raises(vis.VisError):
+        srv.admit(flds[0], *ins[1:], 0.05, 0.1, 2, 5, 0, nuts_max_depth=11)
     # the upper triangle is never read
     good = _dense_gain_chol(lay, ins[4], flds[0].n_freq, flds[0].n_ant, 3)
     good[:, 0, 1:] = float("nan")
