@@ -18,7 +18,8 @@ Serving (`serving` key): 64 concurrent chains on uneven hex fields
 (19-127 dishes, 16-128 channels, 10-120 times, lmax 30-100), one trajectory
 of 20 leapfrog steps each, through the batched server with split-precision
 (bf16 hi/lo) dense synthesis and with FP32 separable synthesis (also with
-dense per-channel gain mass blocks, App. B), against the
+dense per-channel gain mass blocks, App. B, and as No-U-Turn trajectories of
+at most 31 steps), against the
 same request stream through the plain FP32 dense path one request per tick:
 gradient evaluations per second and request latency p50/p99.
 
@@ -152,10 +153,12 @@ def serving_inputs(vis, serve, torch, basis, n_chains):
 
 
 def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=20, synthesis=0,
-                  dense_gains=False):
+                  dense_gains=False, nuts_depth=0):
     """One trajectory of n_leapfrog steps per chain; all chains submitted at once.
     dense_gains: every chain gets dense per-channel gain mass blocks (the
-    Gauss-Newton gain Hessian plus the prior, built before timing)."""
+    Gauss-Newton gain Hessian plus the prior, built before timing).
+    nuts_depth > 0: one No-U-Turn trajectory per chain instead (at most
+    2^nuts_depth - 1 steps, ended by the device)."""
     n_chains = len(inputs)
     flds = [f if (prec == vis.VIS_FP32 and synthesis == 0)
             else vis.Field.from_config(basis, cfg, prec, synthesis)
@@ -166,13 +169,14 @@ def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=
             alm, g, fw = serve.Layout(fld).unpack(q0)
             chols[c] = serve.gain_mass_chol(fld, alm.contiguous(), g.contiguous(), fw.contiguous(),
                                             sigma, cfg.gain_scatter)
-    fp = sum(serve.Server.footprint(f, dense_gains) for f in flds)
+    fp = sum(serve.Server.footprint(f, dense_gains, nuts_depth > 0) for f in flds)
     srv = serve.Server(fp + (64 << 20), max_chains=n_chains, max_batch=max_batch,
                        batched=1 if max_batch > 1 else 0)
     ids = []
     for c, ((cfg, _, data, sigma, q0, minv, cvar), fld) in enumerate(zip(inputs, flds)):
         ids.append(srv.admit(fld, data, sigma, q0, minv, cvar, cfg.gain_scatter, EPS, n_leapfrog,
-                             seed=7, stream_id=c, adapt_step=True, gain_chol=chols[c]))
+                             seed=7, stream_id=c, adapt_step=True, gain_chol=chols[c],
+                             nuts_max_depth=nuts_depth))
     wait_requests(srv, n_chains)
     srv.stats(reset=True)
     torch.cuda.synchronize()
@@ -185,11 +189,21 @@ def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=
         raise RuntimeError("a serving chain failed: " + str([r for r in res if r["status"]][:2]))
     st = srv.stats()
     srv.close()
-    macs = sum(2.0 * f.fwd_macs for f in flds) * n_leapfrog
+    by_chain = {i: c for c, i in enumerate(ids)}
+    # leapfrog steps that belong to trajectories (a NUTS chain also runs up to
+    # two no-op steps between the device's end of a trajectory and the host's
+    # next start; those count in "requests" but not here)
+    steps = [r["n_grad"] for r in res]
+    macs = sum(2.0 * flds[by_chain[r["chain"]]].fwd_macs * r["n_grad"] for r in res)
     acc = sum(r["accepted"] for r in res) / len(res)
-    return {"grad_evals_per_s": st["requests"] / (t1 - t0), "p50_ms": st["p50_ms"],
-            "p99_ms": st["p99_ms"], "requests": st["requests"], "wall_s": t1 - t0,
-            "complex_macs_per_s": macs / (t1 - t0), "acceptance": acc, "max_batch": max_batch}
+    out = {"grad_evals_per_s": st["requests"] / (t1 - t0), "p50_ms": st["p50_ms"],
+           "p99_ms": st["p99_ms"], "requests": st["requests"], "wall_s": t1 - t0,
+           "complex_macs_per_s": macs / (t1 - t0), "acceptance": acc, "max_batch": max_batch}
+    if nuts_depth:
+        out.update({"trajectory_grad_evals_per_s": sum(steps) / (t1 - t0),
+                    "mean_steps": sum(steps) / len(steps), "max_depth": nuts_depth,
+                    "depths": sorted(r["tree_depth"] for r in res)[::max(1, len(res) // 8)]})
+    return out
 
 
 def main():
@@ -291,12 +305,17 @@ def main():
         sep_dg = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32,
                                max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
                                dense_gains=True)
+        log("serving: batched, FP32 separable synthesis, NUTS (at most 5 doublings)")
+        sep_nuts = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32,
+                                 max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
+                                 nuts_depth=5)
         log("serving: per-chain FP32 baseline (dense synthesis), one request per tick")
         base = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32, max_batch=1)
         del ins
         serving = {"chains": args.serve_chains, "leapfrog_steps": 20,
                    "batched_" + args.serve_precision: fast, "batched_fp32_separable": sep,
                    "batched_fp32_separable_dense_gain_mass": sep_dg,
+                   "batched_fp32_separable_nuts": sep_nuts,
                    "per_chain_fp32": base,
                    "speedup": fast["grad_evals_per_s"] / base["grad_evals_per_s"],
                    "speedup_separable": sep["grad_evals_per_s"] / base["grad_evals_per_s"]}

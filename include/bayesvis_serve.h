@@ -45,7 +45,13 @@ typedef struct {
   int32_t max_batch;           /* requests per tick, >= 1 */
   int32_t batched;             /* 1: a tick's evaluations overlap on several streams;
                                   0: they run one after another on the server stream */
-  int32_t reserved;
+  int32_t inflight_ticks;       /* ticks queued on the device at once: 0 or 1 = one (the host
+                                  builds the next tick after the current one completes),
+                                  2 = two (the next tick is built and queued while the
+                                  current one runs).  Two hide the host's tick work but
+                                  double each request's latency and make NUTS chains run a
+                                  no-op step after each trajectory; at ticks of milliseconds
+                                  and more one is as fast. */
 } hmc_server_config;
 
 typedef struct {
@@ -135,7 +141,10 @@ vis_status hmc_submit(hmc_server* s, int32_t chain_id, int32_t n_trajectories);
 /* Copies up to max finished trajectories; waits up to timeout_ms (0 = no wait). */
 vis_status hmc_poll(hmc_server* s, hmc_result* out, int32_t max, int32_t* n_out,
                     int32_t timeout_ms);
-/* Copies the chain's current position (device pointer q_out, length of q). */
+/* Copies the chain's current position (device pointer q_out, length of q).
+ * VIS_EAGAIN while trajectories are queued or running; a tick that is still
+ * in flight for the chain after its last result (a NUTS step scheduled before
+ * the host saw the end of the trajectory) is waited for, up to 30 s.      */
 vis_status hmc_chain_position(hmc_server* s, int32_t chain_id, float* q_out, void* stream);
 vis_status hmc_chain_release(hmc_server* s, int32_t chain_id);
 /* Request-latency percentiles since creation or the last reset.            */

@@ -8,10 +8,13 @@
 // batched elementwise launch (kick / drift / momentum draw), the evaluations,
 // one batched post-kick launch, one FP64 finalize launch (energies,
 // Metropolis test, step-size adaptation) and a batched restore launch.
-// Because a trajectory always has n_leapfrog steps, the host knows the step
-// schedule in advance and enqueues the next tick before the previous one
-// finishes; results are read back asynchronously through pinned staging.
-// Chains admitted or submitted while ticks are in flight join the next tick.
+// A fixed-length trajectory has n_leapfrog steps, so the host knows its step
+// schedule in advance; a NUTS trajectory ends when the device decides, and a
+// step the host scheduled after that runs as a no-op.  By default the next
+// tick is built once the current one completes (one tick in flight); with
+// inflight_ticks = 2 it is built and queued while the current one runs.
+// Results are read back through pinned staging.  Chains admitted or
+// submitted while a tick is in flight join the next tick.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -213,6 +216,7 @@ struct hmc_server {
   Slot slots[kSlots];
   int next_slot = 0;
   int rr = 0;                         // round-robin start
+  int depth = 1;                      // ticks queued on the device at once
   hipStream_t sub[kSubStreams] = {};
   hipEvent_t ev_pre = nullptr;
   hipEvent_t ev_sub[kSubStreams] = {};
@@ -477,22 +481,22 @@ void hmc_server::run() {
         std::unique_lock<std::mutex> lk(mu);
         while (true) {
           if (stop && inflight.empty()) return;
-          if (!stop && static_cast<int>(inflight.size()) < kSlots - 1 && build_tick(t)) break;
+          if (!stop && static_cast<int>(inflight.size()) < depth && build_tick(t)) break;
           if (!inflight.empty()) break;
           cv_work.wait_for(lk, std::chrono::milliseconds(5));
         }
       }
-      if (!t.entries.empty()) {
+      const bool built = !t.entries.empty();
+      if (built) {
         t.slot = next_slot;
         next_slot = (next_slot + 1) % kSlots;
         hip_or_throw(hipEventCreateWithFlags(&t.done, hipEventDisableTiming), "event create");
         enqueue(t);
         inflight.push_back(std::move(t));
       }
-      // keep at most kSlots - 1 ticks in flight; complete the oldest when full
-      // or when nothing new could be scheduled
-      if (!inflight.empty() &&
-          (static_cast<int>(inflight.size()) >= kSlots - 1 || t.entries.empty())) {
+      // keep at most `depth` ticks in flight; complete the oldest when full or
+      // when nothing new could be scheduled
+      if (!inflight.empty() && (static_cast<int>(inflight.size()) >= depth || !built)) {
         Tick& old = inflight.front();
         complete(old);
         (void)hipEventDestroy(old.done);
@@ -532,8 +536,11 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
     BV_REQUIRE(cfg && out && arena_dev, VIS_EINVAL, "null argument");
     BV_REQUIRE(cfg->max_chains >= 1 && cfg->max_chains <= 4096, VIS_EINVAL, "max_chains out of range");
     BV_REQUIRE(cfg->max_batch >= 1 && cfg->max_batch <= 1024, VIS_EINVAL, "max_batch out of range");
+    BV_REQUIRE(cfg->inflight_ticks >= 0 && cfg->inflight_ticks <= kSlots - 1, VIS_EINVAL,
+               "inflight_ticks must be 0, 1 or 2");
     s = new hmc_server();
     s->cfg = *cfg;
+    s->depth = cfg->inflight_ticks == 2 ? 2 : 1;
     s->stream = as_stream(stream);
     const int nb = cfg->max_batch;
     const size_t task_bytes = round_up(sizeof(HmcTask) * 4 * nb, 256);
@@ -710,12 +717,18 @@ vis_status hmc_chain_position(hmc_server* s, int32_t id, float* q_out, void* str
     BV_REQUIRE(s && q_out, VIS_EINVAL, "null argument");
     Chain* c = nullptr;
     {
-      std::lock_guard<std::mutex> lk(s->mu);
+      std::unique_lock<std::mutex> lk(s->mu);
       BV_REQUIRE(id >= 0 && id < static_cast<int>(s->chains.size()) && s->chains[id] != nullptr,
                  VIS_ENOTFOUND, "unknown chain %d", id);
       c = s->chains[id];
-      BV_REQUIRE(c->inflight == 0 && !c->running && c->pending == 0, VIS_EAGAIN,
-                 "chain %d still has work in flight", id);
+      BV_REQUIRE(!c->running && c->pending == 0, VIS_EAGAIN, "chain %d still has work queued", id);
+      // a tick built before the host saw the chain's last result (a NUTS step
+      // that the device turns into a no-op) may still be in flight: wait for it
+      s->cv_done.wait_for(lk, std::chrono::seconds(30), [&] {
+        return s->chains[id] != c || c->inflight == 0 || s->worker_status != VIS_OK;
+      });
+      BV_REQUIRE(s->chains[id] == c, VIS_ENOTFOUND, "chain %d was released", id);
+      BV_REQUIRE(c->inflight == 0, VIS_EAGAIN, "chain %d still has work in flight", id);
     }
     // the server stream orders this copy after the chain's last tick
     BV_HIP(hipMemcpyAsync(q_out, c->ptr(c->L.off_q), sizeof(float) * c->L.len,

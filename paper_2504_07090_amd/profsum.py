@@ -19,13 +19,16 @@ def _short(name: str) -> str:
     return name.split("(")[0].replace("void ", "")[:70]
 
 
-def summarise(path: str, command: str, top: int = 16) -> str:
+def summarise(path: str, command: str, top: int = 16, also=()) -> str:
+    """The top kernels by total time, plus every kernel whose name contains one
+    of the strings in ``also``."""
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    rows = rows[:top] + [r for r in rows[top:] if any(a in r["Name"] for a in also)]
     out = ["# rocprofv3 kernel statistics", "", "Command:", "", "```", command, "```", "",
            "| kernel | calls | avg us | min us | max us | % of GPU time |",
            "|---|---:|---:|---:|---:|---:|"]
-    for r in rows[:top]:
+    for r in rows:
         out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                    f"{float(r['Percentage']):.1f} |")
@@ -94,5 +97,10 @@ def traffic_report(fetch_csv: str, write_csv: str, command: str, kernels, sha: s
 
 
 if __name__ == "__main__":
+    # stats <csv> <command> [top] [name substrings always listed ...]
     mode, path, cmd = sys.argv[1], sys.argv[2], sys.argv[3]
-    print(summarise(path, cmd) if mode == "stats" else summarise_counters(path, cmd))
+    if mode == "stats":
+        top = int(sys.argv[4]) if len(sys.argv) > 4 else 16
+        print(summarise(path, cmd, top, tuple(sys.argv[5:])))
+    else:
+        print(summarise_counters(path, cmd))

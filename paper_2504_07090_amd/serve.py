@@ -22,7 +22,7 @@ _vp = C.c_void_p
 
 class ServerConfig(C.Structure):
     _fields_ = [("max_chains", C.c_int32), ("max_batch", C.c_int32), ("batched", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("inflight_ticks", C.c_int32)]
 
 
 class ChainInit(C.Structure):
@@ -154,10 +154,10 @@ def gain_mass_chol(field: V.Field, alm, gains, fwhm, sigma_n: float,
 
 class Server:
     def __init__(self, arena_bytes: int, max_chains: int = 64, max_batch: int = 64,
-                 batched: int = 1, device: str = "cuda"):
+                 batched: int = 1, device: str = "cuda", inflight_ticks: int = 1):
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
         self.stream = torch.cuda.Stream(device=self.arena.device)
-        cfg = ServerConfig(max_chains, max_batch, batched, 0)
+        cfg = ServerConfig(max_chains, max_batch, batched, inflight_ticks)
         h = C.c_void_p()
         V._check(_lib.hmc_server_create(C.byref(cfg), C.c_void_p(self.arena.data_ptr()),
                                         self.arena.numel(), C.c_void_p(self.stream.cuda_stream),

@@ -244,7 +244,8 @@ def _dense_gain_chol(lay, minv, n_freq, n_ant, seed):
 
 def test_alone_equals_mix(mods):
     """A chain's trajectories are bitwise identical alone and batched with others,
-    for a diagonal-mass chain and for a chain with dense gain mass blocks."""
+    for a diagonal-mass chain, a chain with dense gain mass blocks and a NUTS
+    chain, and with one or two ticks in flight."""
     vis, serve = mods
     basis = _mixed_basis(vis)
     cfgs, flds = _mixed_fields(vis, basis)
@@ -256,8 +257,8 @@ def test_alone_equals_mix(mods):
     chols = {1: _dense_gain_chol(inputs[1][0], inputs[1][4], flds[1].n_freq, flds[1].n_ant, 17)}
     nuts_depth = {3: 5}
 
-    def run(which):
-        srv = serve.Server(256 << 20, max_chains=8, max_batch=8)
+    def run(which, inflight=1):
+        srv = serve.Server(256 << 20, max_chains=8, max_batch=8, inflight_ticks=inflight)
         ids = {}
         for k in which:
             lay, data, sig, q0, minv, cvar = inputs[k]
@@ -279,7 +280,14 @@ def test_alone_equals_mix(mods):
     alone1, pos_a1 = run([1])
     alone3, pos_a3 = run([3])
     mix, pos_m = run([0, 1, 2, 3, 4])
+    # two ticks in flight (the next built while the current runs): same results
+    mix2, pos_m2 = run([0, 1, 2, 3, 4], inflight=2)
     assert all(r["status"] == 0 for rs in mix.values() for r in rs)
+    for k in range(5):
+        for ra, rm in zip(mix[k], mix2[k]):
+            for key in ("trajectory", "accepted", "h0", "h1", "chi2", "eps", "n_grad", "tree_depth"):
+                assert ra[key] == rm[key], (k, key, "inflight 2")
+        assert torch.equal(pos_m[k], pos_m2[k]), (k, "inflight 2")
     assert all(r["tree_depth"] >= 1 for r in mix[3])
     for k, al, pa in ((0, alone, pos_a), (1, alone1, pos_a1), (3, alone3, pos_a3)):
         assert len(al[k]) == len(mix[k]) == 3
