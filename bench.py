@@ -47,11 +47,13 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 #     python3 bench.py --steps 3 --warmup 1 --no-serve --no-cpu-baseline --calibrate-copy
 # each scaled by the ratio of a 256 MiB device copy's known bytes to what the
 # same counter reads for it (profiles/fringe_c1_hbm_traffic.md).  The figure is
-# reported only while the kernel sources hash to the value it was taken with.
+# reported only while the kernel sources and build flags hash to the value it
+# was taken with.
 TRAFFIC = {
-    "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp"],
-    "sha256": "055d7320f647299c9e81d930ffe9e6c841c7aca3624b362c219496de460b6a62",
-    "bytes_per_launch": {"k_fringe_adj": 539024338, "k_fringe_fwd": 202402447},
+    "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
+                "paper_2504_07090_amd/build.py"],
+    "sha256": "dff3c7ef6bcb8c9af5c46af1c27adc87bcfdb1e09792a0b4e233e4badcc4c05f",
+    "bytes_per_launch": {"k_fringe_adj": 540569599, "k_fringe_fwd": 201897791},
 }
 
 

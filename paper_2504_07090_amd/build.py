@@ -21,8 +21,12 @@ SOURCES = ["field.hip", "synth.hip", "synth_split.hip", "synth_sep.hip", "fringe
            "hmc.hip", "serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# MFMA operands and results in ordinary VGPRs (on gfx950 they share one
+# register file with the accumulator registers): no accumulator-register reads after every MFMA chain, and no
+# kernel needs more registers for it (checked per kernel, no scratch).
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-I" + os.path.join(HERE, "..", "include")]
 
 

@@ -96,6 +96,32 @@ def traffic_report(fetch_csv: str, write_csv: str, command: str, kernels, sha: s
     return "\n".join(out) + "\n", per
 
 
+def mfma_report(path: str, command: str, kernels, n_xcd: int = 8, n_simd: int = 1024) -> str:
+    """Markdown table of MFMA and VALU activity per dispatch from one counter run
+    (SQ_VALU_MFMA_BUSY_CYCLES, SQ_VALU_MFMA_COEXEC_CYCLES, SQ_INSTS_VALU,
+    SQ_INSTS_MFMA, GRBM_GUI_ACTIVE).  The CSV sums GRBM_GUI_ACTIVE over the
+    XCDs; divided by n_xcd it is the dispatch's active cycles, and
+    MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x n_simd)."""
+    m, n = counter_means(path)
+    out = ["# MFMA and VALU activity of the fringe kernels (61-dish workload)", "",
+           "Counters from one rocprofv3 run:", "", "```", command, "```", "",
+           f"Active cycles = GRBM_GUI_ACTIVE / {n_xcd} (the CSV sums it over the XCDs); "
+           f"MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x {n_simd} SIMDs).", "",
+           "| kernel | dispatches | MFMA instr | VALU instr | VALU per MFMA | active cycles | "
+           "MFMA busy | MFMA+VALU co-issue cycles |", "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for k in kernels:
+        if k not in m:
+            continue
+        v = m[k]
+        act = v["GRBM_GUI_ACTIVE"] / n_xcd
+        busy = v["SQ_VALU_MFMA_BUSY_CYCLES"] / (act * n_simd)
+        mf = v["SQ_INSTS_MFMA"]
+        out.append(f"| `{k}` | {n[k]} | {mf:.4g} | {v['SQ_INSTS_VALU']:.4g} | "
+                   f"{v['SQ_INSTS_VALU'] / mf if mf else float('nan'):.2f} | {act:.4g} | {100 * busy:.1f}% | "
+                   f"{v['SQ_VALU_MFMA_COEXEC_CYCLES']:.0f} |")
+    return "\n".join(out) + "\n"
+
+
 if __name__ == "__main__":
     # stats <csv> <command> [top] [name substrings always listed ...]
     mode, path, cmd = sys.argv[1], sys.argv[2], sys.argv[3]
