@@ -342,6 +342,11 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
   const float ival = img[static_cast<size_t>(f) * nvp + k];
   const int2 tr = chunk_t[chunk];
   float acc_i = 0.f, acc_f = 0.f;
+  // Partial sums, over this lane's four rows of every row tile, of the core and
+  // alpha-axis terms of the pixels of the four 16-pixel groups, weighted by B
+  // and by B theta^2; reduced across the row groups once, after the time loop.
+  float pz_i[4] = {0.f, 0.f, 0.f, 0.f}, pz_f[4] = {0.f, 0.f, 0.f, 0.f};
+  __shared__ float2 BW[64];   // (B, B theta^2) of every pixel of the chunk at this t
   const size_t gst = static_cast<size_t>(nf) * gstride;
   // software pipeline over t
   double np1 = P1[static_cast<size_t>(tr.x) * nvp + k];
@@ -361,28 +366,43 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
 #pragma unroll
       for (int kt = 0; kt < RT; ++kt)
         gv[i][kt] = *reinterpret_cast<const f4*>(G + ((i * RT + kt) * 64 + lane) * 4);
+    // alpha-axis coefficients of this lane's rows 16 i + 4 (lane >> 4) + 0..3,
+    // i.e. powers 8 i + 2 (lane >> 4) and the next: (Re, -Im) of omega(n, 0).
+    // Adding them to T = G Bb (through the first MFMA's accumulator input)
+    // puts sum_n Re[omega(n, 0) alpha^n] into the per-pixel dot with A.
+    f4 g1[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      const int pn = 8 * i + 2 * (lane >> 4);
+      const f4 x0 = *reinterpret_cast<const f4*>(G + NMAT + 4 * min(pn, D - 1));
+      const f4 x1 = *reinterpret_cast<const f4*>(G + NMAT + 4 * min(pn + 1, D - 1));
+      g1[i] = f4{pn < D ? x0[0] : 0.f, pn < D ? -x0[1] : 0.f,
+                 pn + 1 < D ? x1[0] : 0.f, pn + 1 < D ? -x1[1] : 0.f};
+    }
     const float bm = exp2f(-th2 * kb);
     const float x1 = reduced_cycles(nu, p1);
     const float x2 = reduced_cycles(nu, p2);
     float s1, c1, s2, c2;
     sincos_rev(x1, s1, c1);
     sincos_rev(x2, s2, c2);
-    // axis terms: sum_n Re[omega(n,0) alpha^n] + Re[omega(0,n) beta^n]
+    // beta-axis terms of this lane's pixel: sum_n Re[omega(0, n) beta^n]
     float zax = 0.f;
     write_powers<D, W>(As, Bs, lane, c1, s1, c2, s2, 1.0f,
                        [&](int n, float ar, float ai, float br, float bi) {
                          const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 4 * n);
-                         zax += ax[0] * ar - ax[1] * ai + ax[2] * br - ax[3] * bi;
+                         zax += ax[2] * br - ax[3] * bi;
                        });
+    BW[lane] = make_float2(bm, bm * th2);
     wave_sync();
-    // T = G Bb for the four 16-pixel groups: the four MFMA chains are
-    // interleaved (pixel group innermost) so consecutive MFMAs are independent
-    float zcore = 0.f;
+    float2 bw[4];
+#pragma unroll
+    for (int pg = 0; pg < 4; ++pg) bw[pg] = BW[16 * pg + (lane & 15)];
+    // T = G Bb + alpha-axis rows for the four 16-pixel groups: the four MFMA
+    // chains are interleaved (pixel group innermost) so consecutive MFMAs are
+    // independent
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       f4 tacc[4];
-#pragma unroll
-      for (int pg = 0; pg < 4; ++pg) tacc[pg] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kt = 0; kt < RT; ++kt)
 #pragma unroll
@@ -390,7 +410,7 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
 #pragma unroll
           for (int pg = 0; pg < 4; ++pg)
             tacc[pg] = mfma4(gv[i][kt][s], Bs[lds_at<W>(16 * pg + (lane & 15), 16 * kt + 4 * s + (lane >> 4))],
-                             tacc[pg]);
+                             (kt == 0 && s == 0) ? g1[i] : tacc[pg]);
 #pragma unroll
       for (int pg = 0; pg < 4; ++pg) {
         const int px = 16 * pg + (lane & 15);
@@ -398,15 +418,23 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
         float zp = 0.f;
 #pragma unroll
         for (int r = 0; r < 4; ++r) zp += av[r] * tacc[pg][r];
-        zp = sum_xor32(sum_xor16(zp));
-        if ((lane >> 4) == pg) zcore += zp;
+        pz_i[pg] += bw[pg].x * zp;
+        pz_f[pg] += bw[pg].y * zp;
       }
     }
     wave_sync();
-    const float z = zcore + zax;
-    acc_i += bm * z;
-    acc_f += bm * th2 * z;
+    acc_i += bm * zax;
+    acc_f += bm * th2 * zax;
   }
+  // the four row groups of each pixel sit in lanes l, l ^ 16, l ^ 32, l ^ 48
+#pragma unroll
+  for (int pg = 0; pg < 4; ++pg) {
+    pz_i[pg] = sum_xor32(sum_xor16(pz_i[pg]));
+    pz_f[pg] = sum_xor32(sum_xor16(pz_f[pg]));
+  }
+  const int own = lane >> 4;   // this lane's pixel is column lane & 15 of group lane >> 4
+  acc_i += own == 0 ? pz_i[0] : own == 1 ? pz_i[1] : own == 2 ? pz_i[2] : pz_i[3];
+  acc_f += own == 0 ? pz_f[0] : own == 1 ? pz_f[1] : own == 2 ? pz_f[2] : pz_f[3];
   dimg[static_cast<size_t>(f) * nvp + k] = d_omega * acc_i;
   float pf = acc_f * ival;
 #pragma unroll
