@@ -52,8 +52,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "dff3c7ef6bcb8c9af5c46af1c27adc87bcfdb1e09792a0b4e233e4badcc4c05f",
-    "bytes_per_launch": {"k_fringe_adj": 540569599, "k_fringe_fwd": 201897791},
+    "sha256": "4b48f6f901dc583727a3bb4cd7c9d26d1dcc799cd9843a8074bd902716f9c51e",
+    "bytes_per_launch": {"k_fringe_adj": 412771924, "k_fringe_fwd": 202159976},
 }
 
 
