@@ -400,6 +400,17 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
     // T = G Bb + alpha-axis rows for the four 16-pixel groups: the four MFMA
     // chains are interleaved (pixel group innermost) so consecutive MFMAs are
     // independent
+    // B operand: lane l supplies column 4 (l >> 4) + s of the 16-column block kt
+    // in MFMA step s (the coefficient layout uses the same order), so its four
+    // steps' values are one 16-byte read of group l >> 4 of its pixel's row
+    // (conflict-free; four scalar reads of rows 16 apart would share banks)
+    f4 bq[RT][4];
+#pragma unroll
+    for (int kt = 0; kt < RT; ++kt)
+#pragma unroll
+      for (int pg = 0; pg < 4; ++pg)
+        bq[kt][pg] = *reinterpret_cast<const f4*>(
+            Bs + lds_at<W>(16 * pg + (lane & 15), 16 * kt + 4 * (lane >> 4)));
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       f4 tacc[4];
@@ -409,8 +420,7 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int pg = 0; pg < 4; ++pg)
-            tacc[pg] = mfma4(gv[i][kt][s], Bs[lds_at<W>(16 * pg + (lane & 15), 16 * kt + 4 * s + (lane >> 4))],
-                             (kt == 0 && s == 0) ? g1[i] : tacc[pg]);
+            tacc[pg] = mfma4(gv[i][kt][s], bq[kt][pg][s], (kt == 0 && s == 0) ? g1[i] : tacc[pg]);
 #pragma unroll
       for (int pg = 0; pg < 4; ++pg) {
         const int px = 16 * pg + (lane & 15);

@@ -87,7 +87,10 @@ __device__ __forceinline__ void write_coefficients(const GainArgs& a, const floa
     if (e < nmat) {
       const int s4 = e & 3, l = (e >> 2) & 63, blk = e >> 8;
       const int i = blk / a.rt, kt = blk - i * a.rt;
-      const int r = 16 * i + (l & 15), c = 16 * kt + 4 * s4 + (l >> 4);
+      // lane l feeds row l & 15 and, in MFMA step s4, column 4 (l >> 4) + s4 of
+      // the 16-column block kt (the adjoint reads its B operand for the four
+      // steps as one 16-byte LDS load)
+      const int r = 16 * i + (l & 15), c = 16 * kt + 4 * (l >> 4) + s4;
       const int n = (r >> 1) + 1, m = (c >> 1) + 1;
       if (n <= a.dtile && m <= a.dtile) {
         const float2 wp = omega(n, m), wm = omega(n, -m);
