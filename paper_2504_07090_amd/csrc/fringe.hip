@@ -348,24 +348,31 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
   float pz_i[4] = {0.f, 0.f, 0.f, 0.f}, pz_f[4] = {0.f, 0.f, 0.f, 0.f};
   __shared__ float2 BW[64];   // (B, B theta^2) of every pixel of the chunk at this t
   const size_t gst = static_cast<size_t>(nf) * gstride;
-  // software pipeline over t
+  // software pipeline over t: the geometry and this lane's coefficients of
+  // time t + 1 load while time t is processed
+  auto gco_at = [&](int t) { return gco + t * gst + static_cast<size_t>(f) * gstride; };
   double np1 = P1[static_cast<size_t>(tr.x) * nvp + k];
   double np2 = P2[static_cast<size_t>(tr.x) * nvp + k];
   float nth = TH2[static_cast<size_t>(tr.x) * nvp + k];
+  f4 ngv[RT][RT], nx0[RT], nx1[RT];
+  auto load_coefficients = [&](int t) {
+    const float* G = gco_at(t);
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+#pragma unroll
+      for (int kt = 0; kt < RT; ++kt)
+        ngv[i][kt] = *reinterpret_cast<const f4*>(G + ((i * RT + kt) * 64 + lane) * 4);
+      const int pn = 8 * i + 2 * (lane >> 4);
+      nx0[i] = *reinterpret_cast<const f4*>(G + NMAT + 4 * min(pn, D - 1));
+      nx1[i] = *reinterpret_cast<const f4*>(G + NMAT + 4 * min(pn + 1, D - 1));
+    }
+  };
+  load_coefficients(tr.x);
   for (int t = tr.x; t <= tr.y; ++t) {
     const double p1 = np1, p2 = np2;
     const float th2 = nth;
-    if (t < tr.y) {
-      const size_t g = static_cast<size_t>(t + 1) * nvp + k;
-      np1 = P1[g]; np2 = P2[g]; nth = TH2[g];
-    }
-    const float* G = gco + t * gst + static_cast<size_t>(f) * gstride;
+    const float* G = gco_at(t);
     f4 gv[RT][RT];
-#pragma unroll
-    for (int i = 0; i < RT; ++i)
-#pragma unroll
-      for (int kt = 0; kt < RT; ++kt)
-        gv[i][kt] = *reinterpret_cast<const f4*>(G + ((i * RT + kt) * 64 + lane) * 4);
     // alpha-axis coefficients of this lane's rows 16 i + 4 (lane >> 4) + 0..3,
     // i.e. powers 8 i + 2 (lane >> 4) and the next: (Re, -Im) of omega(n, 0).
     // Adding them to T = G Bb (through the first MFMA's accumulator input)
@@ -373,11 +380,16 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
     f4 g1[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
+#pragma unroll
+      for (int kt = 0; kt < RT; ++kt) gv[i][kt] = ngv[i][kt];
       const int pn = 8 * i + 2 * (lane >> 4);
-      const f4 x0 = *reinterpret_cast<const f4*>(G + NMAT + 4 * min(pn, D - 1));
-      const f4 x1 = *reinterpret_cast<const f4*>(G + NMAT + 4 * min(pn + 1, D - 1));
-      g1[i] = f4{pn < D ? x0[0] : 0.f, pn < D ? -x0[1] : 0.f,
-                 pn + 1 < D ? x1[0] : 0.f, pn + 1 < D ? -x1[1] : 0.f};
+      g1[i] = f4{pn < D ? nx0[i][0] : 0.f, pn < D ? -nx0[i][1] : 0.f,
+                 pn + 1 < D ? nx1[i][0] : 0.f, pn + 1 < D ? -nx1[i][1] : 0.f};
+    }
+    if (t < tr.y) {
+      const size_t g = static_cast<size_t>(t + 1) * nvp + k;
+      np1 = P1[g]; np2 = P2[g]; nth = TH2[g];
+      load_coefficients(t + 1);
     }
     const float bm = exp2f(-th2 * kb);
     const float x1 = reduced_cycles(nu, p1);
