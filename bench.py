@@ -52,8 +52,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "4b48f6f901dc583727a3bb4cd7c9d26d1dcc799cd9843a8074bd902716f9c51e",
-    "bytes_per_launch": {"k_fringe_adj": 412771924, "k_fringe_fwd": 202159976},
+    "sha256": "f7564905f7f28ff5fb149b218bfc4dac806e1d405ec7e68befd39e2a398021d6",
+    "bytes_per_launch": {"k_fringe_adj": 586724206, "k_fringe_fwd": 202363640},
 }
 
 
