@@ -164,7 +164,10 @@ static void carve_basis(vis_basis* b, Carver& cv) {
   b->lam = cv.take<double>(static_cast<size_t>(b->nz) * ntri);
   b->trig = cv.take<double>(static_cast<size_t>(b->nphi) * 2 * (b->lmax + 1));
   if (b->storage & 8u) {
-    b->sep_lam = cv.take<float>(static_cast<size_t>(b->nz) * ntri);
+    size_t nl = 0;
+    for (int m = 0; m <= b->lmax; ++m) nl += static_cast<size_t>(b->nz) * sep_lpad(b->lmax, m);
+    b->sep_lam = cv.take<float>(nl);
+    b->sep_loff = cv.take<int>(static_cast<size_t>(b->lmax) + 2);
     b->sep_t = cv.take<float>(static_cast<size_t>(b->nphi) * b->kaz_t);
     b->sep_tt = cv.take<float>(static_cast<size_t>(b->nphi) * b->kaz_t);
   }
@@ -359,6 +362,7 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
     const size_t npix = f->basis->n_pix;
     S.sep_g = cv.take<float>(static_cast<size_t>(f->basis->nz) * f->kaz * nfq);
     S.sep_dfull = cv.take<float>(npix * nfq);
+    S.sep_at = cv.take<float>(static_cast<size_t>(f->n_modes) * nfq);
   }
   if (f->precision != VIS_FP32) {
     const size_t nfp = static_cast<size_t>(round_up(f->n_freq, 64));
@@ -482,10 +486,20 @@ vis_status vis_basis_create(const vis_basis_desc* desc, void* ws, size_t bytes, 
                                         b->y32, b->ybh, b->ybl, b->yhh, b->yhl);
       check_launch("k_make_basis");
     }
-    std::vector<float> sl, st_, stt;
+    std::vector<float> sl, st_, stt;   // host staging, alive until the stream synchronises
+    std::vector<int> loff;
     if (b->storage & 8u) {
       // separable factors: Y(j, k; l, m) = lambda_l|m|(z_j) T_m(alpha_k)
-      sl.assign(lam.begin(), lam.end());
+      // Legendre factors in m-major blocks: block m holds nz rows of l = m .. lmax
+      loff.assign(static_cast<size_t>(b->lmax) + 2, 0);
+      for (int m = 0; m <= b->lmax; ++m) loff[m + 1] = loff[m] + b->nz * sep_lpad(b->lmax, m);
+      sl.assign(static_cast<size_t>(loff[b->lmax + 1]), 0.f);
+      for (int m = 0; m <= b->lmax; ++m)
+        for (int j = 0; j < b->nz; ++j)
+          for (int l = m; l <= b->lmax; ++l)
+            sl[static_cast<size_t>(loff[m]) + static_cast<size_t>(j) * sep_lpad(b->lmax, m) + (l - m)] =
+                static_cast<float>(lam[static_cast<size_t>(j) * ntri + static_cast<size_t>(l) * (l + 1) / 2 + m]);
+      BV_HIP(hipMemcpyAsync(b->sep_loff, loff.data(), loff.size() * sizeof(int), hipMemcpyHostToDevice, s));
       st_.assign(static_cast<size_t>(b->nphi) * b->kaz_t, 0.f);
       stt.assign(static_cast<size_t>(b->nphi) * b->kaz_t, 0.f);
       for (int k = 0; k < b->nphi; ++k) {

@@ -52,10 +52,13 @@ struct vis_basis {
   double* lam = nullptr;           // generator staging: normalised Legendre per ring
   double* trig = nullptr;          // generator staging: cos / sin (m alpha) per column
   // separable-synthesis factor tables (storage bit 3), FP32:
-  //   sep_lam[j][l (l + 1) / 2 + m] = lambda_lm(z_j), m >= 0
+  //   sep_lam: per m >= 0 a block of nz rows of sep_lpad(m) = round_up(lmax - m + 1, 8)
+  //   floats, row j holding lambda_lm(z_j) for l = m .. lmax then zeros; block m
+  //   starts at sep_loff[m] (so both Legendre stages read consecutive l)
   //   sep_t[k][c], sep_tt[c][k] = T_m(alpha_k) with c = m + lmax + kSepPad, zero for |m| > lmax
   int kaz_t = 0;                   // columns of sep_t: round_up(2 lmax + 1 + 2 kSepPad, 4)
   float* sep_lam = nullptr;
+  int* sep_loff = nullptr;         // [lmax + 2] block offsets of sep_lam (floats)
   float* sep_t = nullptr;
   float* sep_tt = nullptr;
 };
@@ -74,6 +77,7 @@ struct FieldScratch {
   float* sep_g = nullptr;          // separable fields: [nz][kaz][n_freq] Legendre stage output
                                    //   (forward) or azimuthal stage output (adjoint)
   float* sep_dfull = nullptr;      // separable fields: [n_pix][n_freq] dL/dI on the full grid
+  float* sep_at = nullptr;         // separable fields: [n_modes][n_freq] sky coefficients transposed
   float2* vu = nullptr;            // [n_time][n_freq][n_ubl] gain-free unique visibilities
   float* gco = nullptr;            // [n_time][n_freq][gstride] adjoint coefficients, MFMA layout
   double* chi_part = nullptr;      // [n_time * n_freq]

@@ -30,34 +30,58 @@ __device__ __forceinline__ f4 sep_mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ int tri(int l, int am) { return l * (l + 1) / 2 + am; }
-
 constexpr int kSepBatch = 8;              // MFMAs whose operand loads are issued together
 constexpr int kSepStep = 4 * kSepBatch;   // K covered per batch
 
-// G[j][c][nu] = sum_{l=|m|}^{lmax} lam[j][tri(l, |m|)] a[nu][l^2 + l + m],  c = m + lmax.
+// at[mode][nu] = a[nu][mode]: the sky coefficients transposed through a
+// 64 x 64 LDS tile, so the Legendre stage reads 16 channels of one mode as one
+// 64-byte segment.
+__global__ void __launch_bounds__(256)
+k_alm_transpose(int nf, int nm, const float* __restrict__ a, float* __restrict__ at) {
+  __shared__ float tile[64][65];
+  const int m0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int f = f0 + r, m = m0 + tx;
+    tile[r][tx] = (f < nf && m < nm) ? a[static_cast<size_t>(f) * nm + m] : 0.f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int m = m0 + r, f = f0 + tx;
+    if (m < nm && f < nf) at[static_cast<size_t>(m) * nf + f] = tile[tx][r];
+  }
+}
+
+// G[j][c][nu] = sum_{l=|m|}^{lmax} lambda_l|m|(z_j) a[nu][l^2 + l + m],  c = m + lmax.
 // grid (2 lmax + 1, ceil(nz / 16), ceil(nf / 16)); D rows = rings, columns = channels.
+// In MFMA step q the lanes of group kk = lane / 16 take l = l0 + 8 kk + q, so
+// every lane reads eight consecutive l of its ring's Legendre row (two
+// 16-byte loads) and each group of 16 lanes one 64-byte segment of `at`.
 __global__ void __launch_bounds__(64)
-k_sep_leg_fwd(int nz, int nf, int nm, int lmax, int ntri, int kaz, const float* __restrict__ lam,
-              const float* __restrict__ alm, float* __restrict__ G) {
+k_sep_leg_fwd(int nz, int nf, int lmax, int blmax, int kaz, const float* __restrict__ lam,
+              const int* __restrict__ loff, const float* __restrict__ at, float* __restrict__ G) {
   const int m = static_cast<int>(blockIdx.x) - lmax, am = m < 0 ? -m : m;
   const int j0 = blockIdx.y * 16, f0 = blockIdx.z * 16;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const int j = min(j0 + i, nz - 1), f = min(f0 + i, nf - 1);
-  const float* lrow = lam + static_cast<size_t>(j) * ntri;
-  const float* arow = alm + static_cast<size_t>(f) * nm;
+  const int lp = sep_lpad(blmax, am);
+  const float* lrow = lam + loff[am] + static_cast<size_t>(j) * lp;
   f4 acc = f4{0.f, 0.f, 0.f, 0.f};
   for (int l0 = am; l0 <= lmax; l0 += kSepStep) {
-    float a[kSepBatch], b[kSepBatch];
+    const int lb = l0 + 8 * kk;          // this lane's l = lb .. lb + 7
+    f4 a0 = f4{0.f, 0.f, 0.f, 0.f}, a1 = a0;
+    if (lb - am < lp) {                  // lp is a multiple of 8: all eight in the row or none
+      a0 = *reinterpret_cast<const f4*>(lrow + (lb - am));
+      a1 = *reinterpret_cast<const f4*>(lrow + (lb - am) + 4);
+    }
+    float b[kSepBatch];
 #pragma unroll
     for (int q = 0; q < kSepBatch; ++q) {
-      const int l = l0 + 4 * q + kk;
-      const bool ok = l <= lmax;
-      a[q] = ok ? lrow[tri(l, am)] : 0.f;
-      b[q] = ok ? arow[l * l + l + m] : 0.f;
+      const int l = lb + q;
+      b[q] = l <= lmax ? at[static_cast<size_t>(l * l + l + m) * nf + f] : 0.f;
     }
 #pragma unroll
-    for (int q = 0; q < kSepBatch; ++q) acc = sep_mfma(a[q], b[q], acc);
+    for (int q = 0; q < kSepBatch; ++q) acc = sep_mfma(q < 4 ? a0[q] : a1[q - 4], b[q], acc);
   }
   const int c = m + lmax, fo = f0 + (lane & 15);
 #pragma unroll
@@ -156,17 +180,20 @@ k_sep_az_adj(int nphi, int nf, int kaz, int nc, int kaz_t, int toff, const float
   }
 }
 
-// grad[nu][l^2 + l + m] = sum_j lam[j][tri(l, |m|)] H[j][m + lmax][nu], l = |m| .. lmax.
+// grad[nu][l^2 + l + m] = sum_j lambda_l|m|(z_j) H[j][m + lmax][nu], l = |m| .. lmax;
+// 16 lanes read 16 consecutive l of one ring row of the m-major Legendre table.
 // grid (2 lmax + 1, ceil((lmax + 1) / 16), ceil(nf / 16)); D rows = l, columns = channels.
 __global__ void __launch_bounds__(64)
-k_sep_leg_adj(int nz, int nf, int nm, int lmax, int ntri, int kaz, const float* __restrict__ lam,
-              const float* __restrict__ H, float* __restrict__ grad) {
+k_sep_leg_adj(int nz, int nf, int nm, int lmax, int blmax, int kaz, const float* __restrict__ lam,
+              const int* __restrict__ loff, const float* __restrict__ H, float* __restrict__ grad) {
   const int m = static_cast<int>(blockIdx.x) - lmax, am = m < 0 ? -m : m;
   const int l0 = am + 16 * static_cast<int>(blockIdx.y), f0 = blockIdx.z * 16;
   if (l0 > lmax) return;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const int l = min(l0 + i, lmax), f = min(f0 + i, nf - 1);
   const int c = m + lmax;
+  const int lp = sep_lpad(blmax, am);
+  const float* lcol = lam + loff[am] + (l - am);   // 16 lanes: 16 consecutive l of one ring
   const float* hcol = H + static_cast<size_t>(c) * nf + f;
   f4 acc = f4{0.f, 0.f, 0.f, 0.f};
   for (int jb = 0; jb < nz; jb += kSepStep) {
@@ -175,7 +202,7 @@ k_sep_leg_adj(int nz, int nf, int nm, int lmax, int ntri, int kaz, const float* 
     for (int q = 0; q < kSepBatch; ++q) {
       const int j = jb + 4 * q + kk;
       const bool ok = j < nz;
-      a[q] = ok ? lam[static_cast<size_t>(j) * ntri + tri(l, am)] : 0.f;
+      a[q] = ok ? lcol[static_cast<size_t>(j) * lp] : 0.f;
       b[q] = ok ? hcol[static_cast<size_t>(j) * kaz * nf] : 0.f;
     }
 #pragma unroll
@@ -192,13 +219,19 @@ k_sep_leg_adj(int nz, int nf, int nm, int lmax, int ntri, int kaz, const float* 
 void launch_synth_fwd_sep(const vis_field* f, const float* alm, float* img, hipStream_t st) {
   const vis_basis* b = f->basis;
   BV_REQUIRE(b->sep_lam != nullptr, VIS_EINVAL, "basis has no separable factor tables");
-  const int L = f->lmax, ntri = (b->lmax + 1) * (b->lmax + 2) / 2;
+  const int L = f->lmax;
   const int toff = b->lmax + kSepPad - L;   // T column of c = 0 (m = -L)
+  {
+    ProfScope ps(&f->prof, "k_alm_transpose", st);
+    dim3 grid(ceil_div(f->n_modes, 64), ceil_div(f->n_freq, 64));
+    k_alm_transpose<<<grid, 256, 0, st>>>(f->n_freq, f->n_modes, alm, f->scr.sep_at);
+    check_launch("k_alm_transpose");
+  }
   {
     ProfScope ps(&f->prof, "k_sep_leg_fwd", st);
     dim3 grid(2 * L + 1, ceil_div(b->nz, 16), ceil_div(f->n_freq, 16));
-    k_sep_leg_fwd<<<grid, 64, 0, st>>>(b->nz, f->n_freq, f->n_modes, L, ntri, f->kaz, b->sep_lam, alm,
-                                       f->scr.sep_g);
+    k_sep_leg_fwd<<<grid, 64, 0, st>>>(b->nz, f->n_freq, L, b->lmax, f->kaz, b->sep_lam, b->sep_loff,
+                                       f->scr.sep_at, f->scr.sep_g);
     check_launch("k_sep_leg_fwd");
   }
   ProfScope ps(&f->prof, "k_sep_az_fwd", st);
@@ -211,7 +244,7 @@ void launch_synth_fwd_sep(const vis_field* f, const float* alm, float* img, hipS
 void launch_synth_adj_sep(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st) {
   const vis_basis* b = f->basis;
   BV_REQUIRE(b->sep_lam != nullptr, VIS_EINVAL, "basis has no separable factor tables");
-  const int L = f->lmax, ntri = (b->lmax + 1) * (b->lmax + 2) / 2;
+  const int L = f->lmax;
   const int toff = b->lmax + kSepPad - L;
   {
     ProfScope ps(&f->prof, "k_sep_scatter", st);
@@ -229,8 +262,8 @@ void launch_synth_adj_sep(const vis_field* f, const float* dimg, float* grad_alm
   }
   ProfScope ps(&f->prof, "k_sep_leg_adj", st);
   dim3 grid(2 * L + 1, ceil_div(L + 1, 16), ceil_div(f->n_freq, 16));
-  k_sep_leg_adj<<<grid, 64, 0, st>>>(b->nz, f->n_freq, f->n_modes, L, ntri, f->kaz, b->sep_lam,
-                                     f->scr.sep_g, grad_alm);
+  k_sep_leg_adj<<<grid, 64, 0, st>>>(b->nz, f->n_freq, f->n_modes, L, b->lmax, f->kaz, b->sep_lam,
+                                     b->sep_loff, f->scr.sep_g, grad_alm);
   check_launch("k_sep_leg_adj");
 }
 
