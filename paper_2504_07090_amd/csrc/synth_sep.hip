@@ -34,21 +34,30 @@ constexpr int kSepBatch = 8;              // MFMAs whose operand loads are issue
 constexpr int kSepStep = 4 * kSepBatch;   // K covered per batch
 
 // at[mode][nu] = a[nu][mode]: the sky coefficients transposed through a
-// 64 x 64 LDS tile, so the Legendre stage reads 16 channels of one mode as one
-// 64-byte segment.
+// 16-mode x 64-channel LDS tile (one block per 16 modes, so the grid fills the
+// chip), so the Legendre stage reads 16 channels of one mode as one 64-byte
+// segment.
+constexpr int kTrModes = 16, kTrChans = 64;
 __global__ void __launch_bounds__(256)
 k_alm_transpose(int nf, int nm, const float* __restrict__ a, float* __restrict__ at) {
-  __shared__ float tile[64][65];
-  const int m0 = blockIdx.x * 64, f0 = blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int r = ty; r < 64; r += 4) {
-    const int f = f0 + r, m = m0 + tx;
-    tile[r][tx] = (f < nf && m < nm) ? a[static_cast<size_t>(f) * nm + m] : 0.f;
-  }
-  __syncthreads();
-  for (int r = ty; r < 64; r += 4) {
-    const int m = m0 + r, f = f0 + tx;
-    if (m < nm && f < nf) at[static_cast<size_t>(m) * nf + f] = tile[tx][r];
+  __shared__ float tile[kTrChans][kTrModes + 1];
+  const int m0 = blockIdx.x * kTrModes;
+  const int t = threadIdx.x;
+  for (int f0 = 0; f0 < nf; f0 += kTrChans) {
+    // read: 16 consecutive modes of 16 channel rows per pass
+    for (int e = t; e < kTrChans * kTrModes; e += 256) {
+      const int r = e / kTrModes, c = e % kTrModes;
+      const int f = f0 + r, m = m0 + c;
+      tile[r][c] = (f < nf && m < nm) ? a[static_cast<size_t>(f) * nm + m] : 0.f;
+    }
+    __syncthreads();
+    // write: 64 consecutive channels of 4 mode rows per pass
+    for (int e = t; e < kTrChans * kTrModes; e += 256) {
+      const int r = e / kTrChans, c = e % kTrChans;
+      const int m = m0 + r, f = f0 + c;
+      if (m < nm && f < nf) at[static_cast<size_t>(m) * nf + f] = tile[c][r];
+    }
+    __syncthreads();
   }
 }
 
@@ -93,38 +102,58 @@ k_sep_leg_fwd(int nz, int nf, int lmax, int blmax, int kaz, const float* __restr
 
 // img[nu][slot(j, k)] = sum_{c < nc} G[j][c][nu] Tt[c + toff][k] for visible pixels
 // (nc = 2 lmax + 1 rows of G per ring are used).
-// grid (ceil(nphi / 16), nz, ceil(nf / 16)); D rows = channels, columns = pixels.
+// grid (ceil(nphi / 32), nz, ceil(nf / 32)); each wave computes a 2 x 2 block of
+// 16 x 16 tiles (rows = channels, columns = pixels), so every operand load
+// feeds two MFMAs.
 __global__ void __launch_bounds__(64)
 k_sep_az_fwd(int nphi, int nf, int kaz, int nc, int toff, const float* __restrict__ Tt,
              const float* __restrict__ G, const int* __restrict__ vidx, int nvp, float* __restrict__ img) {
-  const int k0 = blockIdx.x * 16, j = blockIdx.y, f0 = blockIdx.z * 16;
+  const int k0 = blockIdx.x * 32, j = blockIdx.y, f0 = blockIdx.z * 32;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
-  const int f = min(f0 + i, nf - 1), k = min(k0 + i, nphi - 1);
-  const float* grow = G + static_cast<size_t>(j) * kaz * nf + f;
-  const float* tcol = Tt + static_cast<size_t>(toff) * nphi + k;
-  f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+  const float* grow[2];
+  const float* tcol[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    grow[h] = G + static_cast<size_t>(j) * kaz * nf + min(f0 + 16 * h + i, nf - 1);
+    tcol[h] = Tt + static_cast<size_t>(toff) * nphi + min(k0 + 16 * h + i, nphi - 1);
+  }
+  f4 acc[2][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) acc[h][g] = f4{0.f, 0.f, 0.f, 0.f};
   for (int c0 = 0; c0 < nc; c0 += kSepStep) {
-    float a[kSepBatch], b[kSepBatch];
+    float a[kSepBatch][2], b[kSepBatch][2];
 #pragma unroll
     for (int q = 0; q < kSepBatch; ++q) {
       const int c = c0 + 4 * q + kk;
       const bool ok = c < nc;
-      a[q] = ok ? grow[static_cast<size_t>(c) * nf] : 0.f;
-      b[q] = ok ? tcol[static_cast<size_t>(c) * nphi] : 0.f;
-    }
 #pragma unroll
-    for (int q = 0; q < kSepBatch; ++q) acc = sep_mfma(a[q], b[q], acc);
-  }
-  const int ko = k0 + (lane & 15);
-  if (ko < nphi) {
-    const int slot = vidx[j * nphi + ko];
-    if (slot >= 0) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int fo = f0 + 4 * kk + r;
-        if (fo < nf) img[static_cast<size_t>(fo) * nvp + slot] = acc[r];
+      for (int h = 0; h < 2; ++h) {
+        a[q][h] = ok ? grow[h][static_cast<size_t>(c) * nf] : 0.f;
+        b[q][h] = ok ? tcol[h][static_cast<size_t>(c) * nphi] : 0.f;
       }
     }
+#pragma unroll
+    for (int q = 0; q < kSepBatch; ++q)
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) acc[h][g] = sep_mfma(a[q][h], b[q][g], acc[h][g]);
+  }
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int ko = k0 + 16 * g + (lane & 15);
+    if (ko >= nphi) continue;
+    const int slot = vidx[j * nphi + ko];
+    if (slot < 0) continue;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int fo = f0 + 16 * h + 4 * kk + r;
+        if (fo < nf) img[static_cast<size_t>(fo) * nvp + slot] = acc[h][g][r];
+      }
   }
 }
 
@@ -150,33 +179,55 @@ k_sep_scatter(int npix, int nf, int nvp, const int* __restrict__ vidx, const flo
 }
 
 // H[j][c][nu] = sum_k T[k][c + toff] dfull[j nphi + k][nu] for c < nc = 2 lmax + 1.
-// grid (ceil(nc / 16), nz, ceil(nf / 16)); D rows = c, columns = channels.
+// grid (ceil(nc / 32), nz, ceil(nf / 32)); each wave computes a 2 x 2 block of
+// 16 x 16 tiles (rows = c, columns = channels).
 __global__ void __launch_bounds__(64)
 k_sep_az_adj(int nphi, int nf, int kaz, int nc, int kaz_t, int toff, const float* __restrict__ T,
              const float* __restrict__ dfull, float* __restrict__ H) {
-  const int c0 = blockIdx.x * 16, j = blockIdx.y, f0 = blockIdx.z * 16;
+  const int c0 = blockIdx.x * 32, j = blockIdx.y, f0 = blockIdx.z * 32;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
-  const int c = min(c0 + i, nc - 1), f = min(f0 + i, nf - 1);
-  const float* trow = T + toff + c;
-  const float* drow = dfull + static_cast<size_t>(j) * nphi * nf + f;
-  f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+  const float* trow[2];
+  const float* drow[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    trow[h] = T + toff + min(c0 + 16 * h + i, nc - 1);
+    drow[h] = dfull + static_cast<size_t>(j) * nphi * nf + min(f0 + 16 * h + i, nf - 1);
+  }
+  f4 acc[2][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int g = 0; g < 2; ++g) acc[h][g] = f4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < nphi; k0 += kSepStep) {
-    float a[kSepBatch], b[kSepBatch];
+    float a[kSepBatch][2], b[kSepBatch][2];
 #pragma unroll
     for (int q = 0; q < kSepBatch; ++q) {
       const int k = k0 + 4 * q + kk;
       const bool ok = k < nphi;
-      a[q] = ok ? trow[static_cast<size_t>(k) * kaz_t] : 0.f;
-      b[q] = ok ? drow[static_cast<size_t>(k) * nf] : 0.f;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        a[q][h] = ok ? trow[h][static_cast<size_t>(k) * kaz_t] : 0.f;
+        b[q][h] = ok ? drow[h][static_cast<size_t>(k) * nf] : 0.f;
+      }
     }
 #pragma unroll
-    for (int q = 0; q < kSepBatch; ++q) acc = sep_mfma(a[q], b[q], acc);
-  }
-  const int fo = f0 + (lane & 15);
+    for (int q = 0; q < kSepBatch; ++q)
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int co = c0 + 4 * kk + r;
-    if (co < nc && fo < nf) H[(static_cast<size_t>(j) * kaz + co) * nf + fo] = acc[r];
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int g = 0; g < 2; ++g) acc[h][g] = sep_mfma(a[q][h], b[q][g], acc[h][g]);
+  }
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    const int fo = f0 + 16 * g + (lane & 15);
+    if (fo >= nf) continue;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = c0 + 16 * h + 4 * kk + r;
+        if (co < nc) H[(static_cast<size_t>(j) * kaz + co) * nf + fo] = acc[h][g][r];
+      }
   }
 }
 
@@ -223,8 +274,8 @@ void launch_synth_fwd_sep(const vis_field* f, const float* alm, float* img, hipS
   const int toff = b->lmax + kSepPad - L;   // T column of c = 0 (m = -L)
   {
     ProfScope ps(&f->prof, "k_alm_transpose", st);
-    dim3 grid(ceil_div(f->n_modes, 64), ceil_div(f->n_freq, 64));
-    k_alm_transpose<<<grid, 256, 0, st>>>(f->n_freq, f->n_modes, alm, f->scr.sep_at);
+    k_alm_transpose<<<ceil_div(f->n_modes, kTrModes), 256, 0, st>>>(f->n_freq, f->n_modes, alm,
+                                                                     f->scr.sep_at);
     check_launch("k_alm_transpose");
   }
   {
@@ -235,7 +286,7 @@ void launch_synth_fwd_sep(const vis_field* f, const float* alm, float* img, hipS
     check_launch("k_sep_leg_fwd");
   }
   ProfScope ps(&f->prof, "k_sep_az_fwd", st);
-  dim3 grid(ceil_div(b->nphi, 16), b->nz, ceil_div(f->n_freq, 16));
+  dim3 grid(ceil_div(b->nphi, 32), b->nz, ceil_div(f->n_freq, 32));
   k_sep_az_fwd<<<grid, 64, 0, st>>>(b->nphi, f->n_freq, f->kaz, 2 * L + 1, toff, b->sep_tt, f->scr.sep_g,
                                     f->tab.vidx, f->nv_pad, img);
   check_launch("k_sep_az_fwd");
@@ -255,7 +306,7 @@ void launch_synth_adj_sep(const vis_field* f, const float* dimg, float* grad_alm
   }
   {
     ProfScope ps(&f->prof, "k_sep_az_adj", st);
-    dim3 grid(ceil_div(2 * L + 1, 16), b->nz, ceil_div(f->n_freq, 16));
+    dim3 grid(ceil_div(2 * L + 1, 32), b->nz, ceil_div(f->n_freq, 32));
     k_sep_az_adj<<<grid, 64, 0, st>>>(b->nphi, f->n_freq, f->kaz, 2 * L + 1, b->kaz_t, toff, b->sep_t,
                                       f->scr.sep_dfull, f->scr.sep_g);
     check_launch("k_sep_az_adj");
