@@ -337,11 +337,31 @@ k_reduce_grads(int nt, int nf, int nant, int nfpart, int with_chi2, const double
   if (blockIdx.x + 1 < gridDim.x) {
     const int idx = blockIdx.x * 1024 + tid;
     if (idx >= nf * nant || grad_gains == nullptr) return;
+    // eight independent partial sums (times t = q mod 8), combined in order:
+    // eight loads in flight per thread instead of one chain of nt
+    const size_t stride = static_cast<size_t>(nf) * nant;
+    float2 p[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) p[q] = make_float2(0.f, 0.f);
+    int t = 0;
+    for (; t + 8 <= nt; t += 8) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float2 v = g_part[static_cast<size_t>(t + q) * stride + idx];
+        p[q].x += v.x;
+        p[q].y += v.y;
+      }
+    }
+    for (int q = 0; t < nt; ++t, ++q) {
+      const float2 v = g_part[static_cast<size_t>(t) * stride + idx];
+      p[q].x += v.x;
+      p[q].y += v.y;
+    }
     float2 s = make_float2(0.f, 0.f);
-    for (int t = 0; t < nt; ++t) {
-      const float2 v = g_part[static_cast<size_t>(t) * nf * nant + idx];
-      s.x += v.x;
-      s.y += v.y;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      s.x += p[q].x;
+      s.y += p[q].y;
     }
     grad_gains[idx] = s;
     return;

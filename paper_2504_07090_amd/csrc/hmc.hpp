@@ -6,7 +6,7 @@
 namespace bv {
 
 constexpr int kHmcThreads = 256;
-constexpr int kHmcPerBlock = 4096;   // parameters per elementwise block
+constexpr int kHmcPerBlock = 1024;   // parameters per elementwise block (4 per thread)
 constexpr int kGainBlockMax = 256;   // largest dense gain block (2 n_ant)
 constexpr int kGainBlockPad = 16;    // dense gain blocks are padded to a multiple of this
 constexpr int kNutsMaxDepth = 10;    // NUTS doublings (at most 2^10 - 1 leapfrog steps)
