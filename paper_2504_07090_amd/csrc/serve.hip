@@ -184,8 +184,11 @@ struct Tick {
 
 // Pinned host staging + device table slots, one per in-flight tick.
 struct Slot {
-  HmcTask* host_tasks = nullptr;     // pinned: [4][max_batch] task tables
-  int* host_blk = nullptr;           // pinned: [kPrefixes][max_batch + 1] block prefixes
+  // pinned, one allocation laid out like the device copy (task tables, then
+  // prefixes) so a tick uploads both with one copy
+  HmcTask* host_tasks = nullptr;     // [4][max_batch] task tables (owns the allocation)
+  int* host_blk = nullptr;           // [kPrefixes][max_batch + 1] block prefixes (inside it)
+  size_t table_bytes = 0;
   HmcState* host_states = nullptr;   // pinned: [max_batch] read-back
   HmcTask* dev_tasks = nullptr;      // in the arena
   int* dev_blk = nullptr;
@@ -372,10 +375,8 @@ void hmc_server::enqueue(Tick& t) {
   int* rst_blk_host = S.host_blk + 2 * (nb + 1);
   std::memcpy(rst_blk_host, rst_blk.data(), sizeof(int) * (nrst + 1));
 
-  hip_or_throw(hipMemcpyAsync(S.dev_tasks, S.host_tasks, sizeof(HmcTask) * 4 * nb,
-                              hipMemcpyHostToDevice, stream), "task upload");
-  hip_or_throw(hipMemcpyAsync(S.dev_blk, S.host_blk, sizeof(int) * kPrefixes * (nb + 1),
-                              hipMemcpyHostToDevice, stream), "prefix upload");
+  hip_or_throw(hipMemcpyAsync(S.dev_tasks, S.host_tasks, S.table_bytes, hipMemcpyHostToDevice, stream),
+               "task table upload");
   if (hmc_tasks) launch_hmc_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
   if (nuts_tasks) launch_nuts_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
   launch_hmc_gainblk(S.dev_tasks, npre, S.dev_blk + 3 * (nb + 1), cpre, stream);
@@ -556,11 +557,11 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
       S.dev_tasks = reinterpret_cast<HmcTask*>(base + i * per);
       S.dev_blk = reinterpret_cast<int*>(base + i * per + task_bytes);
       S.dev_states = reinterpret_cast<HmcState*>(base + i * per + task_bytes + blk_bytes);
-      BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_tasks), sizeof(HmcTask) * 4 * nb));
-      BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_blk), sizeof(int) * kPrefixes * (nb + 1)));
+      S.table_bytes = task_bytes + blk_bytes;
+      BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_tasks), S.table_bytes));
+      S.host_blk = reinterpret_cast<int*>(reinterpret_cast<char*>(S.host_tasks) + task_bytes);
       BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_states), sizeof(HmcState) * nb));
-      std::memset(S.host_tasks, 0, sizeof(HmcTask) * 4 * nb);
-      std::memset(S.host_blk, 0, sizeof(int) * kPrefixes * (nb + 1));
+      std::memset(S.host_tasks, 0, S.table_bytes);
     }
     s->arena.init(base + reserve, arena_bytes - reserve);
     if (cfg->batched) {
@@ -577,7 +578,6 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
   if (st != VIS_OK && s != nullptr) {
     for (auto& S : s->slots) {
       if (S.host_tasks) (void)hipHostFree(S.host_tasks);
-      if (S.host_blk) (void)hipHostFree(S.host_blk);
       if (S.host_states) (void)hipHostFree(S.host_states);
     }
     delete s;
@@ -801,7 +801,6 @@ vis_status hmc_server_destroy(hmc_server* s) {
   if (s->ev_pre) (void)hipEventDestroy(s->ev_pre);
   for (auto& S : s->slots) {
     if (S.host_tasks) (void)hipHostFree(S.host_tasks);
-    if (S.host_blk) (void)hipHostFree(S.host_blk);
     if (S.host_states) (void)hipHostFree(S.host_states);
   }
   delete s;
