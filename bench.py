@@ -52,8 +52,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "f7564905f7f28ff5fb149b218bfc4dac806e1d405ec7e68befd39e2a398021d6",
-    "bytes_per_launch": {"k_fringe_adj": 586724206, "k_fringe_fwd": 202363640},
+    "sha256": "427c0371d840453b913dc2f3d0c709d982800d1552f4dcdb9b56fd2835b39eda",
+    "bytes_per_launch": {"k_fringe_adj": 581169593, "k_fringe_fwd": 187269291},
 }
 
 
