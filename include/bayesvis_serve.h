@@ -97,7 +97,8 @@ typedef struct {
    * H - H0 > 1000 or non-finite, discards that subtree and ends the
    * trajectory.  The chain moves to the proposal (hmc_result.accepted = 1 if
    * it differs from the start).  Step-size adaptation uses the mean over the
-   * leaves of min(1, exp(H0 - H)).  Requires gain_chol == NULL.            */
+   * leaves of min(1, exp(H0 - H)).  With gain_chol the velocities M^-1 p of
+   * the checks come from the same triangular solves as the drift.          */
   int32_t nuts_max_depth;
 } hmc_chain_init;
 
@@ -131,8 +132,10 @@ size_t hmc_chain_footprint_bytes(const vis_field* field);
  * factors: about 8 n_freq (2 n_ant)^2 bytes).                              */
 size_t hmc_chain_footprint_dense_gain_bytes(const vis_field* field);
 /* The same for a NUTS chain (adds the trajectory ends, candidate, proposal,
- * momentum sums and 20 checkpoint vectors: 32 vectors of the parameter length). */
+ * momentum sums and 20 checkpoint vectors: 32 vectors of the parameter length),
+ * and for a NUTS chain with gain_chol (also 13 velocity vectors).          */
 size_t hmc_chain_footprint_nuts_bytes(const vis_field* field);
+size_t hmc_chain_footprint_nuts_dense_gain_bytes(const vis_field* field);
 vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size_t arena_bytes,
                              void* stream, hmc_server** out);
 /* VIS_EAGAIN: the arena has no room for this chain now (retry after a release). */

@@ -145,14 +145,20 @@ __device__ __forceinline__ void nuts_ckpt_range(int leaf, int& lo, int& hi) {
   }
 }
 
-__device__ void nuts_elem(const HmcTask& T, int lb, double* lds) {
+__device__ void nuts_elem(const HmcTask& T, int lb, double* lds, int phase) {
   HmcState* st = T.st;
   const bool begin = (T.op & kOpBegin) != 0;
+  // gains of a chain with dense gain blocks: momentum draw, drift and kinetic
+  // energy come from k_hmc_gainblk, as do the velocities M^-1 p of the U-turn
+  // checks (phase 1 forms those dots once the current velocity exists)
+  const bool dense = T.lrow != nullptr;
+  if (phase == 1 && !(dense && (T.op & kOpNutsPost))) return;
   if (T.op & kOpNutsApply) {
     if (!st->act) return;                            // nothing decided this tick
   } else if (!begin && st->done) {
     return;                                          // finished: a no-op step
   }
+  const bool dots = phase == 1 || (!dense && (T.op & kOpNutsPost));
   const float eps = st->eps;
   float* V = T.nuts;
   const size_t vs = static_cast<size_t>(T.vstride);
@@ -173,7 +179,7 @@ __device__ void nuts_elem(const HmcTask& T, int lb, double* lds) {
             a_prop = st->act_prop, a_finish = st->act_finish, a_dir = st->act_dir;
   for (int i0 = beg + threadIdx.x * 4; i0 < beg + kHmcPerBlock; i0 += kHmcThreads * 4) {
     float z[4];
-    if ((T.op & kOpNutsPre) && begin)
+    if (phase == 0 && (T.op & kOpNutsPre) && begin)
       normals4(T.seed, T.stream, T.traj, static_cast<uint32_t>(i0 >> 2), z);
 #pragma unroll
     for (int el = 0; el < 4; ++el) {
@@ -181,51 +187,63 @@ __device__ void nuts_elem(const HmcTask& T, int lb, double* lds) {
       if (i >= T.len) break;
       if (i >= T.nalm && i < T.goff) continue;  // alignment padding: never touched
       const float mi = T.minv[i];
-      if (T.op & kOpNutsPre) {
+      const bool dg = dense && i >= T.goff && i < T.goff + T.ngain;
+      if (phase == 0 && (T.op & kOpNutsPre)) {
         float q = T.q[i], p = T.p[i], g = T.grad[i];
         if (begin) {
-          p = z[el] * rsqrtf(mi);
-          acc[kNutsDots + 2] += 0.5 * static_cast<double>(mi) * p * p;
           T.q0[i] = q;
           T.grad0[i] = g;
           vec(kNqL)[i] = q; vec(kNqR)[i] = q; vec(kNqP)[i] = q;
-          vec(kNpL)[i] = p; vec(kNpR)[i] = p;
           vec(kNgL)[i] = g; vec(kNgR)[i] = g; vec(kNgP)[i] = g;
-          vec(kNrho)[i] = p;
           vec(kNrhos)[i] = 0.f;
+          if (!dg) {   // dense gains: drawn, and their ends and sums set, by k_hmc_gainblk
+            p = z[el] * rsqrtf(mi);
+            acc[kNutsDots + 2] += 0.5 * static_cast<double>(mi) * p * p;
+            vec(kNpL)[i] = p; vec(kNpR)[i] = p;
+            vec(kNrho)[i] = p;
+          }
         } else if (leaf == 0) {   // a new subtree starts at the end on its side
           q = vec(dir > 0 ? kNqR : kNqL)[i];
           p = vec(dir > 0 ? kNpR : kNpL)[i];
           g = vec(dir > 0 ? kNgR : kNgL)[i];
           T.grad[i] = g;
         }
-        p -= 0.5f * e * g;
-        q += e * mi * p;
+        if (!dg) {
+          p -= 0.5f * e * g;
+          q += e * mi * p;
+        }
         T.q[i] = q;
         T.p[i] = p;
       }
-      if (T.op & kOpNutsPost) {
+      if (phase == 0 && (T.op & kOpNutsPost)) {
         const float q = T.q[i];
         const float g = grad_potential(T, i, q, acc[kNutsDots]);
         const float p = T.p[i] - 0.5f * e * g;
-        acc[kNutsDots + 1] += 0.5 * static_cast<double>(mi) * p * p;
+        if (!dg) acc[kNutsDots + 1] += 0.5 * static_cast<double>(mi) * p * p;
         T.grad[i] = g;
         T.p[i] = p;
+      }
+      if (dots) {
+        // velocity M^-1 of a momentum: stored for dense gains, minv p otherwise
+        const float p = T.p[i];
+        const float vnow = dg ? vec(kNvN)[i] : mi * p;
         const float rs = vec(kNrhos)[i] + p;   // subtree momentum sum with this leaf
 #pragma unroll
         for (int c = 0; c < kNutsMaxDepth; ++c) {
           if (c >= ck_lo && c <= ck_hi) {
             const float cp = vec(kNckp + c)[i];
+            const float vc = dg ? vec(kNckv + c)[i] : mi * cp;
             const float adj = rs - vec(kNckr + c)[i] + 0.5f * (cp - p);
-            acc[2 * c] += static_cast<double>(mi * cp) * adj;
-            acc[2 * c + 1] += static_cast<double>(mi * p) * adj;
+            acc[2 * c] += static_cast<double>(vc) * adj;
+            acc[2 * c + 1] += static_cast<double>(vnow) * adj;
           }
         }
         if (last) {   // whole-trajectory check, used if this leaf completes the subtree
           const float po = vec(dir > 0 ? kNpL : kNpR)[i];
+          const float vo = dg ? vec(dir > 0 ? kNvL : kNvR)[i] : mi * po;
           const float adj = vec(kNrho)[i] + rs - 0.5f * (po + p);
-          acc[2 * kNutsMaxDepth] += static_cast<double>(mi * po) * adj;
-          acc[2 * kNutsMaxDepth + 1] += static_cast<double>(mi * p) * adj;
+          acc[2 * kNutsMaxDepth] += static_cast<double>(vo) * adj;
+          acc[2 * kNutsMaxDepth + 1] += static_cast<double>(vnow) * adj;
         }
       }
       if (T.op & kOpNutsApply) {
@@ -238,6 +256,7 @@ __device__ void nuts_elem(const HmcTask& T, int lb, double* lds) {
         if (a_ckpt >= 0) {
           vec(kNckp + a_ckpt)[i] = p;
           vec(kNckr + a_ckpt)[i] = rs;
+          if (dg) vec(kNckv + a_ckpt)[i] = vec(kNvN)[i];
         }
         if (a_merge) {
           if (a_prop) {
@@ -249,6 +268,7 @@ __device__ void nuts_elem(const HmcTask& T, int lb, double* lds) {
           vec(a_dir > 0 ? kNqR : kNqL)[i] = q;
           vec(a_dir > 0 ? kNpR : kNpL)[i] = p;
           vec(a_dir > 0 ? kNgR : kNgL)[i] = g;
+          if (dg) vec(a_dir > 0 ? kNvR : kNvL)[i] = vec(kNvN)[i];
         } else {
           vec(kNrhos)[i] = rs;
         }
@@ -262,7 +282,7 @@ __device__ void nuts_elem(const HmcTask& T, int lb, double* lds) {
   if (T.op & kOpNutsApply) return;
   block_sum_n<kNutsDots + 3>(acc, lds);
   if (threadIdx.x != 0) return;
-  if ((T.op & kOpNutsPre) && begin) {
+  if (phase == 0 && (T.op & kOpNutsPre) && begin) {
     T.part_k0[lb] = acc[kNutsDots + 2];
     if (lb == 0) {
       st->u0 = st->u;
@@ -281,9 +301,11 @@ __device__ void nuts_elem(const HmcTask& T, int lb, double* lds) {
       st->act = 0;
     }
   }
-  if (T.op & kOpNutsPost) {
+  if (phase == 0 && (T.op & kOpNutsPost)) {
     T.part_u[lb] = acc[kNutsDots];
     T.part_k[lb] = acc[kNutsDots + 1];
+  }
+  if (dots) {
 #pragma unroll
     for (int k = 0; k < kNutsDots; ++k) T.part_nuts[static_cast<size_t>(lb) * kNutsDots + k] = acc[k];
   }
@@ -303,13 +325,13 @@ constexpr int kNutsOps = kOpNutsPre | kOpNutsPost | kOpNutsApply;
 
 // The NUTS element work; the same task tables as k_hmc_elem, whose tasks it skips.
 __global__ void __launch_bounds__(kHmcThreads)
-k_nuts_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__ blk0) {
+k_nuts_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__ blk0, int phase) {
   __shared__ double red_n[4 * (kNutsDots + 3)];
   const int k = find_task(blk0, ntask, blockIdx.x);
   const HmcTask T = tasks[k];
   const int lb = blockIdx.x - blk0[k];
   if (lb >= T.nblk || !(T.op & kNutsOps)) return;
-  nuts_elem(T, lb, red_n);
+  nuts_elem(T, lb, red_n, phase);
 }
 
 // One block handles kHmcPerBlock consecutive parameters of one chain.
@@ -485,13 +507,19 @@ k_hmc_gainblk(const HmcTask* __restrict__ tasks, int ntask, const int* __restric
   const HmcTask T = tasks[lo];
   const int f = b - chan0[lo];
   if (T.lrow == nullptr || f >= T.nchan) return;   // uniform over the wave
+  // NUTS chains: steps after the device ended the trajectory are no-ops, and
+  // the leapfrog runs in the doubling's direction
+  const bool nuts = T.nuts != nullptr;
+  if (nuts && !(T.op & kOpBegin) && T.st->done) return;
   const int lane = threadIdx.x;
   const int nb = T.nb, nb4 = T.nb4;
   const size_t mo = static_cast<size_t>(f) * nb4 * nb4;
   const float* lr = T.lrow + mo;
   const float* lc = T.lcol + mo;
   const int e0 = T.goff + f * nb;     // layout index of the block's first element
-  const float eps = T.st->eps;
+  const float eps = nuts && T.st->dir < 0 ? -T.st->eps : T.st->eps;
+  const bool kick = (T.op & (kOpKickDrift | kOpNutsPre)) != 0;
+  auto nvec = [&](int k) { return T.nuts + static_cast<size_t>(k) * T.vstride + e0; };
   float rd[4], p[4], x[4], y[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -517,8 +545,23 @@ k_hmc_gainblk(const HmcTask* __restrict__ tasks, int ntask, const int* __restric
     sweep<kSweepProduct>(lc, nb4, x, rd, p);   // p = L z0, K0 = |z0|^2 / 2
     k0 = wave_sum_f64(k0);
     if (lane == 0) T.part_k0g[f] = k0;
+    if (nuts) {
+      // both trajectory ends start here: momentum, momentum sum and velocity L^-T z0
+      sweep<kSweepBackward>(lr, nb4, x, rd, y);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * lane + r;
+        if (i < nb) {
+          nvec(kNpL)[i] = p[r];
+          nvec(kNpR)[i] = p[r];
+          nvec(kNrho)[i] = p[r];
+          nvec(kNvL)[i] = y[r];
+          nvec(kNvR)[i] = y[r];
+        }
+      }
+    }
   }
-  if (T.op & kOpKickDrift) {
+  if (kick) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 4 * lane + r;
@@ -533,8 +576,10 @@ k_hmc_gainblk(const HmcTask* __restrict__ tasks, int ntask, const int* __restric
       if (i < nb) T.q[e0 + i] += eps * x[r];
     }
   }
-  if (T.op & kOpEnd) {
-    // kinetic energy of the final momentum (after the closing half kick)
+  if (T.op & (kOpEnd | kOpNutsPost)) {
+    // kinetic energy of the momentum after the closing half kick (every NUTS
+    // leaf needs it; fixed-length HMC only at the trajectory end) and, for
+    // NUTS, the velocity L^-T z of the U-turn checks
 #pragma unroll
     for (int r = 0; r < 4; ++r) x[r] = p[r];
     sweep<kSweepForward>(lc, nb4, x, rd, y);
@@ -543,8 +588,16 @@ k_hmc_gainblk(const HmcTask* __restrict__ tasks, int ntask, const int* __restric
     for (int r = 0; r < 4; ++r) k += 0.5 * static_cast<double>(y[r]) * y[r];
     k = wave_sum_f64(k);
     if (lane == 0) T.part_kg[f] = k;
+    if (T.op & kOpNutsPost) {
+      sweep<kSweepBackward>(lr, nb4, y, rd, x);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * lane + r;
+        if (i < nb) nvec(kNvN)[i] = x[r];
+      }
+    }
   }
-  if (T.op & (kOpBegin | kOpKickDrift)) {
+  if ((T.op & kOpBegin) || kick) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 4 * lane + r;
@@ -597,6 +650,12 @@ __device__ void nuts_finalize(const HmcTask& T, double* lds) {
     v[kNutsDots] += T.part_u[b];
     v[kNutsDots + 1] += T.part_k[b];
     v[kNutsDots + 2] += T.part_k0[b];
+  }
+  if (T.lrow != nullptr) {   // kinetic energies of the dense gain blocks
+    for (int c = threadIdx.x; c < T.nchan; c += kHmcThreads) {
+      v[kNutsDots + 1] += T.part_kg[c];
+      v[kNutsDots + 2] += T.part_k0g[c];
+    }
   }
   block_sum_n<kNutsDots + 3>(v, lds);
   if (threadIdx.x != 0) return;
@@ -774,9 +833,9 @@ void launch_gain_mass_setup(const float* chol, int nchan, int nb, int nb4, float
 }
 
 void launch_nuts_elem(const HmcTask* tasks_dev, int ntask, const int* blk0_dev, int nblocks,
-                      hipStream_t st) {
+                      hipStream_t st, int phase) {
   if (ntask == 0 || nblocks == 0) return;
-  k_nuts_elem<<<nblocks, kHmcThreads, 0, st>>>(tasks_dev, ntask, blk0_dev);
+  k_nuts_elem<<<nblocks, kHmcThreads, 0, st>>>(tasks_dev, ntask, blk0_dev, phase);
   check_launch("k_nuts_elem");
 }
 

@@ -17,9 +17,13 @@ constexpr int kNutsDots = 2 * kNutsMaxDepth + 2;
 // ends (q, p, grad on the left and right), the subtree candidate and the
 // proposal (q, grad), the momentum sums of the trajectory and of the subtree
 // being built, then kNutsMaxDepth checkpoint momenta and momentum sums.
+// Chains with dense gain mass blocks also keep velocities M^-1 p of the gain
+// elements (of the current state, of both ends and of every checkpoint),
+// which the U-turn checks need and which only the block solves give.
 enum NutsVec : int {
   kNqL, kNpL, kNgL, kNqR, kNpR, kNgR, kNqC, kNgC, kNqP, kNgP, kNrho, kNrhos, kNckp,
-  kNckr = kNckp + kNutsMaxDepth, kNutsVecs = kNckr + kNutsMaxDepth
+  kNckr = kNckp + kNutsMaxDepth, kNutsVecs = kNckr + kNutsMaxDepth,
+  kNvN = kNutsVecs, kNvL, kNvR, kNckv, kNutsVecsDense = kNckv + kNutsMaxDepth
 };
 
 enum HmcOp : int {
@@ -103,8 +107,10 @@ void launch_gain_mass_setup(const float* chol, int nchan, int nb, int nb4, float
                             float* lcol, int* bad, hipStream_t st);
 // NUTS element work over the same task tables (skips fixed-length HMC tasks,
 // which k_hmc_elem handles and this kernel's tasks skip in turn).
+// phase 0: the task's own op; phase 1: the U-turn dot products of NUTS chains
+// with dense gain blocks (after k_hmc_gainblk has formed the current velocity).
 void launch_nuts_elem(const HmcTask* tasks_dev, int ntask, const int* blk0_dev, int nblocks,
-                      hipStream_t st);
+                      hipStream_t st, int phase = 0);
 void launch_hmc_finalize(const HmcTask* tasks_dev, int ntask, hipStream_t st);
 
 }  // namespace bv

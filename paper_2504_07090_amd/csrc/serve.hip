@@ -88,7 +88,8 @@ static ChainLayout chain_layout(const vis_field* f, bool dense_gains, bool nuts)
   }
   if (nuts) {
     L.vstride = static_cast<int>(round_up(L.len, 64));
-    L.off_nuts = at(sizeof(float) * static_cast<size_t>(kNutsVecs) * L.vstride);
+    const int nvec = dense_gains ? kNutsVecsDense : kNutsVecs;
+    L.off_nuts = at(sizeof(float) * static_cast<size_t>(nvec) * L.vstride);
     L.off_pnuts = at(sizeof(double) * static_cast<size_t>(L.nblk) * kNutsDots);
   }
   L.bytes = round_up(cv.used, 256);
@@ -295,7 +296,7 @@ void hmc_server::enqueue(Tick& t) {
   int* pre_chan = S.host_blk + 3 * (nb + 1);
   int* post_chan = S.host_blk + 4 * (nb + 1);
   int npre = 0, npost = 0, nrst = 0, bpre = 0, bpost = 0, cpre = 0, cpost = 0;
-  int nuts_tasks = 0, hmc_tasks = 0;
+  int nuts_tasks = 0, hmc_tasks = 0, nuts_dense = 0;
   std::vector<const Chain*> evs;
   for (const TickEntry& e : t.entries) {
     Chain* c = e.c;
@@ -338,6 +339,7 @@ void hmc_server::enqueue(Tick& t) {
     T.stream = c->stream;
     T.traj = static_cast<uint32_t>(e.traj < 0 ? 0 : e.traj);
     if (e.nuts) ++nuts_tasks; else ++hmc_tasks;
+    if (e.nuts && c->L.nchan > 0) ++nuts_dense;
     const bool is_init = e.init;
     // pre-evaluation: momentum draw at a trajectory start, then kick + drift
     if (!is_init) {
@@ -357,7 +359,9 @@ void hmc_server::enqueue(Tick& t) {
     fin[npost] = Q;
     npost++;
     bpost += Q.nblk;
-    if (e.ends) cpost += c->L.nchan;   // the gain blocks' final kinetic energy
+    // the gain blocks' kinetic energy: at a fixed-length trajectory's end, at
+    // every NUTS step (with the velocity of the U-turn checks)
+    if (e.ends || (e.nuts && !is_init)) cpost += c->L.nchan;
     if (e.ends || (e.nuts && !is_init)) {
       HmcTask R = T;
       R.op = e.nuts ? kOpNutsApply : kOpRestore;
@@ -405,6 +409,8 @@ void hmc_server::enqueue(Tick& t) {
   launch_hmc_elem(S.dev_tasks + nb, npost, S.dev_blk + (nb + 1), bpost, stream);
   if (nuts_tasks) launch_nuts_elem(S.dev_tasks + nb, npost, S.dev_blk + (nb + 1), bpost, stream);
   launch_hmc_gainblk(S.dev_tasks + nb, npost, S.dev_blk + 4 * (nb + 1), cpost, stream);
+  if (nuts_dense)   // U-turn dots of NUTS chains with dense gain blocks (need the velocities)
+    launch_nuts_elem(S.dev_tasks + nb, npost, S.dev_blk + (nb + 1), bpost, stream, 1);
   launch_hmc_finalize(S.dev_tasks + 2 * nb, npost, stream);
   if (hmc_tasks)
     launch_hmc_elem(S.dev_tasks + 3 * nb, nrst, S.dev_blk + 2 * (nb + 1), rst_blk[nrst], stream);
@@ -530,6 +536,11 @@ size_t hmc_chain_footprint_nuts_bytes(const vis_field* field) {
   return chain_layout(field, false, true).bytes;
 }
 
+size_t hmc_chain_footprint_nuts_dense_gain_bytes(const vis_field* field) {
+  if (field == nullptr) return 0;
+  return chain_layout(field, true, true).bytes;
+}
+
 vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size_t arena_bytes,
                              void* stream, hmc_server** out) {
   hmc_server* s = nullptr;
@@ -596,8 +607,6 @@ vis_status hmc_chain_admit(hmc_server* s, const hmc_chain_init* in, int32_t* cha
     const bool dense = in->gain_chol != nullptr;
     BV_REQUIRE(in->nuts_max_depth >= 0 && in->nuts_max_depth <= kNutsMaxDepth, VIS_EINVAL,
                "nuts_max_depth must be in [0, %d]", kNutsMaxDepth);
-    BV_REQUIRE(!(dense && in->nuts_max_depth > 0), VIS_EINVAL,
-               "NUTS chains take a diagonal mass (gain_chol must be NULL)");
     BV_REQUIRE(!dense || 2 * in->field->n_ant <= kGainBlockMax, VIS_EINVAL,
                "dense gain mass blocks hold at most %d antennas (field has %d)",
                kGainBlockMax / 2, in->field->n_ant);

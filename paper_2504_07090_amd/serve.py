@@ -47,7 +47,7 @@ class Stats(C.Structure):
 
 
 for _n in ("hmc_chain_footprint_bytes", "hmc_chain_footprint_dense_gain_bytes",
-           "hmc_chain_footprint_nuts_bytes"):
+           "hmc_chain_footprint_nuts_bytes", "hmc_chain_footprint_nuts_dense_gain_bytes"):
     getattr(_lib, _n).argtypes = [_vp]
     getattr(_lib, _n).restype = C.c_size_t
 _lib.hmc_server_create.argtypes = [C.POINTER(ServerConfig), _vp, C.c_size_t, _vp, C.POINTER(_vp)]
@@ -167,6 +167,8 @@ class Server:
 
     @staticmethod
     def footprint(field: V.Field, dense_gains: bool = False, nuts: bool = False) -> int:
+        if nuts and dense_gains:
+            return int(_lib.hmc_chain_footprint_nuts_dense_gain_bytes(field.handle))
         if nuts:
             return int(_lib.hmc_chain_footprint_nuts_bytes(field.handle))
         if dense_gains:

@@ -127,16 +127,18 @@ def test_trajectory_matches_oracle(mods, case):
         np.testing.assert_allclose(qg, q_or, rtol=1e-6)
 
 
-@pytest.mark.parametrize("case", ["depth_limit", "u_turn"])
+@pytest.mark.parametrize("case", ["depth_limit", "u_turn", "depth_limit_dense", "u_turn_dense"])
 def test_nuts_trajectories_match_oracle(mods, case):
     """Three consecutive NUTS trajectories from the same start, momentum stream
-    and diagonal mass: tree depth, leapfrog steps, whether the chain moved, H0
-    and H of the proposal agree with the FP64 oracle's NUTS, and so does the
-    position after each trajectory (to 1e-3 of the move).  "depth_limit": the
-    data posterior at eps 0.12, whose stiff directions keep trajectories going
-    to the 6-doubling limit; "u_turn": noise 300x larger (the prior dominates)
-    at eps 0.4 with 8 doublings allowed, where trajectories end by the
-    no-U-turn criterion after 63-127 steps."""
+    and mass: tree depth, leapfrog steps, whether the chain moved, H0 and H of
+    the proposal agree with the FP64 oracle's NUTS, and so does the position
+    after each trajectory (to 1e-3 of the move).  "depth_limit": the data
+    posterior at eps 0.12, whose stiff directions keep trajectories going to
+    the 6-doubling limit; "u_turn": noise 300x larger (the prior dominates) at
+    eps 0.4 with 8 doublings allowed, where trajectories end by the no-U-turn
+    criterion.  The "_dense" cases give every channel's gains a dense mass
+    block (App. B, the Gauss-Newton gain Hessian plus the prior), so that the
+    U-turn checks use velocities from the block triangular solves."""
     from oracle import nuts as onuts
     vis, serve = mods
     cfg = w.scaled(w.C0, lmax=4, n_freq=2, n_time=2)
@@ -145,7 +147,7 @@ def test_nuts_trajectories_match_oracle(mods, case):
     d = w.draw(cfg)
     of = model.Field(cfg)
     _, sig, data = model.make_data(of, d)
-    if case == "u_turn":
+    if case.startswith("u_turn"):
         sig *= 300.0
         eps, depth = 0.4, 8
     else:
@@ -160,6 +162,12 @@ def test_nuts_trajectories_match_oracle(mods, case):
         qp[i] += h
         hd[i] = (post.potential_and_grad(qp)[1][i] - g0[i]) / h
     minv_or = (1.0 / hd).astype(np.float32).astype(np.float64)
+    mass_or, chol32 = minv_or, None
+    if case.endswith("_dense"):
+        hg = ohmc.gain_gauss_newton_blocks(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), sig)
+        hg += np.eye(hg.shape[1])[None] / post.gvar
+        chol32 = np.linalg.cholesky(hg).astype(np.float32)   # the same factor on both sides
+        mass_or = ohmc.gain_block_mass(minv_or, chol32.astype(np.float64), cfg.n_freq * cfg.n_modes)
     seed, stream = 5, 2
     lay = serve.Layout(fld)
     nalm, ng = lay.nalm, lay.ngain
@@ -182,14 +190,15 @@ def test_nuts_trajectories_match_oracle(mods, case):
                     torch.tensor(to_lay(q_or), dtype=torch.float32, device="cuda"),
                     torch.tensor(minv_l, dtype=torch.float32, device="cuda"),
                     torch.tensor(d.alm_var, dtype=torch.float32, device="cuda"),
-                    cfg.gain_scatter, eps, 1, seed, stream, nuts_max_depth=depth)
+                    cfg.gain_scatter, eps, 1, seed, stream, nuts_max_depth=depth,
+                    gain_chol=None if chol32 is None else torch.tensor(chol32, device="cuda"))
     q, (u, g) = q_or, post.potential_and_grad(q_or)
     reasons = []
     for t in range(3):
         srv.submit(cid, 1)
         r = srv.wait(1)[0]
         qg = from_lay(srv.position(cid, lay.length, "cuda").double().cpu().numpy())
-        o = onuts.trajectory(q, u, g, eps, depth, minv_or, post.potential_and_grad, seed, stream, t,
+        o = onuts.trajectory(q, u, g, eps, depth, mass_or, post.potential_and_grad, seed, stream, t,
                              normal_index=idx)
         say("nuts traj", t, "oracle", o.depth, o.n_steps, o.moved, o.reason, o.h0, o.h_prop,
             "gpu", r["tree_depth"], r["n_grad"], r["accepted"], r["h0"], r["h1"], r["accept_stat"])
@@ -204,7 +213,7 @@ def test_nuts_trajectories_match_oracle(mods, case):
         q, u, g = o.q, o.u, o.g
         reasons.append(o.reason)
     srv.close()
-    assert ("turn" in reasons) == (case == "u_turn")
+    assert ("turn" in reasons) == case.startswith("u_turn")
 
 
 # (hex side, channels, times, lmax, precision, synthesis): every evaluation path
@@ -244,18 +253,20 @@ def _dense_gain_chol(lay, minv, n_freq, n_ant, seed):
 
 def test_alone_equals_mix(mods):
     """A chain's trajectories are bitwise identical alone and batched with others,
-    for a diagonal-mass chain, a chain with dense gain mass blocks and a NUTS
-    chain, and with one or two ticks in flight."""
+    for a diagonal-mass chain, a chain with dense gain mass blocks, a NUTS
+    chain and a NUTS chain with dense gain blocks, and with one or two ticks in
+    flight."""
     vis, serve = mods
     basis = _mixed_basis(vis)
     cfgs, flds = _mixed_fields(vis, basis)
     inputs = []
     for c, f in zip(cfgs, flds):
         inputs.append(_chain_inputs(vis, serve, f, c, w.draw(c)))
-    # chain 1 (37 antennas: 74-row blocks, padded to 80) has dense gain blocks;
-    # chain 3 runs NUTS
-    chols = {1: _dense_gain_chol(inputs[1][0], inputs[1][4], flds[1].n_freq, flds[1].n_ant, 17)}
-    nuts_depth = {3: 5}
+    # chains 1 and 4 (37 antennas: 74-row blocks, padded to 80) have dense gain
+    # blocks; chains 3 and 4 run NUTS
+    chols = {k: _dense_gain_chol(inputs[k][0], inputs[k][4], flds[k].n_freq, flds[k].n_ant, 17 + k)
+             for k in (1, 4)}
+    nuts_depth = {3: 5, 4: 4}
 
     def run(which, inflight=1):
         srv = serve.Server(256 << 20, max_chains=8, max_batch=8, inflight_ticks=inflight)
@@ -279,6 +290,7 @@ def test_alone_equals_mix(mods):
     alone, pos_a = run([0])
     alone1, pos_a1 = run([1])
     alone3, pos_a3 = run([3])
+    alone4, pos_a4 = run([4])
     mix, pos_m = run([0, 1, 2, 3, 4])
     # two ticks in flight (the next built while the current runs): same results
     mix2, pos_m2 = run([0, 1, 2, 3, 4], inflight=2)
@@ -288,8 +300,8 @@ def test_alone_equals_mix(mods):
             for key in ("trajectory", "accepted", "h0", "h1", "chi2", "eps", "n_grad", "tree_depth"):
                 assert ra[key] == rm[key], (k, key, "inflight 2")
         assert torch.equal(pos_m[k], pos_m2[k]), (k, "inflight 2")
-    assert all(r["tree_depth"] >= 1 for r in mix[3])
-    for k, al, pa in ((0, alone, pos_a), (1, alone1, pos_a1), (3, alone3, pos_a3)):
+    assert all(r["tree_depth"] >= 1 for k in (3, 4) for r in mix[k])
+    for k, al, pa in ((0, alone, pos_a), (1, alone1, pos_a1), (3, alone3, pos_a3), (4, alone4, pos_a4)):
         assert len(al[k]) == len(mix[k]) == 3
         for ra, rm in zip(al[k], mix[k]):
             for key in ("trajectory", "accepted", "h0", "h1", "chi2", "eps", "n_grad", "tree_depth"):
@@ -322,10 +334,8 @@ def test_dense_gain_mass_admission_checks(mods):
     bad[0, 7, 2] = float("nan")
     with pytest.raises(vis.VisError):
         srv.admit(flds[0], *ins[1:], 0.05, 0.1, 2, 5, 0, gain_chol=bad)
-    # NUTS takes a diagonal mass only, and at most 10 doublings
-    good = _dense_gain_chol(lay, ins[4], flds[0].n_freq, flds[0].n_ant, 3)
-    with pytest.raises(vis.VisError):
-        srv.admit(flds[0], *ins[1:], 0.05, 0.1, 2, 5, 0, gain_chol=good, nuts_max_depth=3)
+    # NUTS takes at most 10 doublings; with dense blocks it also keeps velocities
+    assert serve.Server.footprint(flds[0], True, True) > serve.Server.footprint(flds[0], False, True)
     with pytest.raises(vis.VisError):
         srv.admit(flds[0], *ins[1:], 0.05, 0.1, 2, 5, 0, nuts_max_depth=11)
     # the upper triangle is never read
