@@ -73,6 +73,20 @@ __device__ __forceinline__ float sum_xor32(float x) {
   return __uint_as_float(p[0]) + __uint_as_float(p[1]);
 }
 
+// 2^x on the hardware exponential unit (no denormal-range rescaling: the
+// beam factors it forms are only ever weights, and one below 2^-126 adds
+// nothing to a sum of beam-weighted terms).
+__device__ __forceinline__ float beam_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Element k of a per-wave array through a 32-bit byte offset (the base is
+// uniform over the wave, so the load takes the scalar-base form and no
+// per-lane 64-bit address arithmetic is needed).
+template <class V>
+__device__ __forceinline__ V at_u32(const V* base, int k) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) +
+                                     static_cast<uint32_t>(k) * static_cast<uint32_t>(sizeof(V)));
+}
+
 // Reduced phase of nu * p in cycles, in [-1/2, 1/2], formed in FP64.
 __device__ __forceinline__ float reduced_cycles(double nu, double p) {
   const double x = nu * p;
@@ -159,10 +173,9 @@ __device__ __forceinline__ void write_powers(float* As, float* Bs, int px, float
 template <int D>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(D <= 8 ? 4 : 2)))
 k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
-             const double* __restrict__ freq, const double* __restrict__ P1,
-             const double* __restrict__ P2, const float* __restrict__ TH2,
-             const int* __restrict__ tchunk_off, const int* __restrict__ tchunk,
-             const int2* __restrict__ ubl_nm, const float* __restrict__ img,
+             const double* __restrict__ freq, const double* P1, const double* P2,
+             const float* TH2, const int* __restrict__ tchunk_off,
+             const int* __restrict__ tchunk, const int2* __restrict__ ubl_nm, const float* img,
              const float* __restrict__ fwhm, float2* __restrict__ vu) {
   using T = Tile<D>;
   constexpr int RT = T::RT, W = T::W;
@@ -200,13 +213,13 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
   struct G { double p1, p2; float th, iv; };
   auto load = [&](int ci) {
     const int k = tchunk[ci] * kChunk + lane;
-    return G{p1t[k], p2t[k], tht[k], imf[k]};
+    return G{at_u32(p1t, k), at_u32(p2t, k), at_u32(tht, k), at_u32(imf, k)};
   };
   // powers of one chunk into LDS; `live` = 0 turns a padding pass into a no-op
   auto generate = [&](const G& g, float live) {
     const float x1 = reduced_cycles(nu, g.p1);
     const float x2 = reduced_cycles(nu, g.p2);
-    const float s = live * d_omega * exp2f(-g.th * kb) * g.iv;
+    const float s = live * d_omega * beam_exp2(-g.th * kb) * g.iv;
     float s1, c1, s2, c2;
     sincos_rev(x1, s1, c1);
     sincos_rev(x2, s2, c2);
@@ -230,33 +243,43 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
       }
     }
   };
-  if (cend > cbeg) {
-    generate(load(cbeg), 1.0f);
-    G gn = load(min(cbeg + 1, cend - 1));
+  // one chunk: the MFMAs of chunk ci (register operands) interleaved with the
+  // generation of chunk ci + 1 from `cur`, while chunk ci + 2's geometry loads
+  // into `nxt`; the loop below is unrolled by two so the two geometry sets
+  // swap roles without register copies
+  auto chunk_step = [&](int ci, const G& cur, G& nxt) {
+    nxt = load(min(ci + 2, cend - 1));
+    // keep the prefetch here: the sources are read-only, so the optimizer
+    // would otherwise re-issue the loads right before their use
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < RT; ++j)
+          acc[q % NACC][i][j] = mfma4(a[q][i], b[q][j], acc[q % NACC][i][j]);
+    generate(cur, ci + 1 < cend ? 1.0f : 0.0f);
+#pragma unroll
+    for (int q = 0; q < 16 * RT * RT; ++q) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, 8 / (RT * RT), 0);  // vector ALU
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // one LDS write (128-bit)
+    }
     wave_sync();
     operands();
     wave_sync();
-    for (int ci = cbeg; ci < cend; ++ci) {
-      const G gn2 = load(min(ci + 2, cend - 1));
-      // MFMAs of chunk ci (register operands) interleaved with chunk ci+1's generation
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-#pragma unroll
-        for (int i = 0; i < RT; ++i)
-#pragma unroll
-          for (int j = 0; j < RT; ++j)
-            acc[q % NACC][i][j] = mfma4(a[q][i], b[q][j], acc[q % NACC][i][j]);
-      generate(gn, ci + 1 < cend ? 1.0f : 0.0f);
-#pragma unroll
-      for (int q = 0; q < 16 * RT * RT; ++q) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
-        __builtin_amdgcn_sched_group_barrier(0x002, 8 / (RT * RT), 0);  // vector ALU
-        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // one LDS write (128-bit)
-      }
-      wave_sync();
-      operands();
-      wave_sync();
-      gn = gn2;
+  };
+  if (cend > cbeg) {
+    generate(load(cbeg), 1.0f);
+    G ga = load(min(cbeg + 1, cend - 1)), gb;
+    wave_sync();
+    operands();
+    wave_sync();
+    for (int ci = cbeg; ci < cend; ci += 2) {
+      chunk_step(ci, ga, gb);
+      if (ci + 1 >= cend) break;
+      chunk_step(ci + 1, gb, ga);
     }
   }
 #pragma unroll
@@ -315,14 +338,14 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
 // ------------------------------------------------------------------ adjoint --
 // One wavefront per (nu, chunk of 64 visible pixels); loops over the times at
 // which the chunk is above the horizon.  gco[t][nu] holds the coefficient
-// matrix in MFMA A-operand order followed by the axis coefficients.
+// matrix in MFMA A-operand order, then the alpha-axis accumulator inputs of
+// every (row tile, lane group), then the axis coefficients.
 template <int D>
 __global__ void __launch_bounds__(64)
 k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, double beam_ref,
-             const double* __restrict__ freq, const double* __restrict__ P1,
-             const double* __restrict__ P2, const float* __restrict__ TH2,
-             const int2* __restrict__ chunk_t, const float* __restrict__ img,
-             const float* __restrict__ fwhm, const float* __restrict__ gco,
+             const double* __restrict__ freq, const double* P1, const double* P2,
+             const float* TH2, const int2* __restrict__ chunk_t, const float* __restrict__ img,
+             const float* __restrict__ fwhm, const float* __restrict__ gco, const float* gco_lane,
              float* __restrict__ dimg, float* __restrict__ f_part) {
   using T = Tile<D>;
   constexpr int RT = T::RT, W = T::W;
@@ -348,50 +371,47 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
   float pz_i[4] = {0.f, 0.f, 0.f, 0.f}, pz_f[4] = {0.f, 0.f, 0.f, 0.f};
   __shared__ float2 BW[64];   // (B, B theta^2) of every pixel of the chunk at this t
   const size_t gst = static_cast<size_t>(nf) * gstride;
-  // software pipeline over t: the geometry and this lane's coefficients of
-  // time t + 1 load while time t is processed
+  // gco feeds the wave-uniform (scalar) loads of the axis coefficients;
+  // gco_lane, the same table, the per-lane loads of the prefetch below: a
+  // pointer not marked read-only-unaliased keeps the optimizer from moving
+  // those loads to their use in the next step (as it does for P1, P2, TH2)
   auto gco_at = [&](int t) { return gco + t * gst + static_cast<size_t>(f) * gstride; };
-  double np1 = P1[static_cast<size_t>(tr.x) * nvp + k];
-  double np2 = P2[static_cast<size_t>(tr.x) * nvp + k];
-  float nth = TH2[static_cast<size_t>(tr.x) * nvp + k];
-  f4 ngv[RT][RT], nx0[RT], nx1[RT];
-  auto load_coefficients = [&](int t) {
-    const float* G = gco_at(t);
+  auto gco_lane_at = [&](int t) { return gco_lane + t * gst + static_cast<size_t>(f) * gstride; };
+  // Software pipeline over t, unrolled by two so that the two register sets
+  // swap roles without copies: the geometry and this lane's coefficients of
+  // time t + 1 load while time t is processed.
+  struct Step {
+    double p1, p2;
+    float th2;
+    f4 gv[RT][RT];
+    // alpha-axis coefficients of this lane's rows 16 i + 4 (lane >> 4) + 0..3:
+    // (Re, -Im) of omega(n, 0) for the two powers n of those rows, stored in
+    // this order by the gains pass.  As the first MFMA's accumulator input
+    // they put sum_n Re[omega(n, 0) alpha^n] into the per-pixel dot with A.
+    f4 g1[RT];
+  };
+  auto load_step = [&](Step& S, int t) {
+    const size_t row = static_cast<size_t>(t) * nvp;   // uniform over the wave
+    S.p1 = at_u32(P1 + row, k);
+    S.p2 = at_u32(P2 + row, k);
+    S.th2 = at_u32(TH2 + row, k);
+    const float* G = gco_lane_at(t);
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
 #pragma unroll
       for (int kt = 0; kt < RT; ++kt)
-        ngv[i][kt] = *reinterpret_cast<const f4*>(G + ((i * RT + kt) * 64 + lane) * 4);
-      const int pn = 8 * i + 2 * (lane >> 4);
-      nx0[i] = *reinterpret_cast<const f4*>(G + NMAT + 4 * min(pn, D - 1));
-      nx1[i] = *reinterpret_cast<const f4*>(G + NMAT + 4 * min(pn + 1, D - 1));
+        S.gv[i][kt] = *reinterpret_cast<const f4*>(G + ((i * RT + kt) * 64 + lane) * 4);
+      S.g1[i] = *reinterpret_cast<const f4*>(G + NMAT + 16 * i + 4 * (lane >> 4));
     }
   };
-  load_coefficients(tr.x);
-  for (int t = tr.x; t <= tr.y; ++t) {
-    const double p1 = np1, p2 = np2;
-    const float th2 = nth;
+  auto step = [&](int t, const Step& S, Step& next) {
+    const double p1 = S.p1, p2 = S.p2;
+    const float th2 = S.th2;
     const float* G = gco_at(t);
-    f4 gv[RT][RT];
-    // alpha-axis coefficients of this lane's rows 16 i + 4 (lane >> 4) + 0..3,
-    // i.e. powers 8 i + 2 (lane >> 4) and the next: (Re, -Im) of omega(n, 0).
-    // Adding them to T = G Bb (through the first MFMA's accumulator input)
-    // puts sum_n Re[omega(n, 0) alpha^n] into the per-pixel dot with A.
-    f4 g1[RT];
-#pragma unroll
-    for (int i = 0; i < RT; ++i) {
-#pragma unroll
-      for (int kt = 0; kt < RT; ++kt) gv[i][kt] = ngv[i][kt];
-      const int pn = 8 * i + 2 * (lane >> 4);
-      g1[i] = f4{pn < D ? nx0[i][0] : 0.f, pn < D ? -nx0[i][1] : 0.f,
-                 pn + 1 < D ? nx1[i][0] : 0.f, pn + 1 < D ? -nx1[i][1] : 0.f};
-    }
-    if (t < tr.y) {
-      const size_t g = static_cast<size_t>(t + 1) * nvp + k;
-      np1 = P1[g]; np2 = P2[g]; nth = TH2[g];
-      load_coefficients(t + 1);
-    }
-    const float bm = exp2f(-th2 * kb);
+    // unconditional (the last step re-reads its own time) so that the waits
+    // for this step's operands never cover the loads just issued
+    load_step(next, min(t + 1, tr.y));
+    const float bm = beam_exp2(-th2 * kb);
     const float x1 = reduced_cycles(nu, p1);
     const float x2 = reduced_cycles(nu, p2);
     float s1, c1, s2, c2;
@@ -401,7 +421,7 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
     float zax = 0.f;
     write_powers<D, W>(As, Bs, lane, c1, s1, c2, s2, 1.0f,
                        [&](int n, float ar, float ai, float br, float bi) {
-                         const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 4 * n);
+                         const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 16 * RT + 4 * n);
                          zax += ax[2] * br - ax[3] * bi;
                        });
     BW[lane] = make_float2(bm, bm * th2);
@@ -432,7 +452,7 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int pg = 0; pg < 4; ++pg)
-            tacc[pg] = mfma4(gv[i][kt][s], bq[kt][pg][s], (kt == 0 && s == 0) ? g1[i] : tacc[pg]);
+            tacc[pg] = mfma4(S.gv[i][kt][s], bq[kt][pg][s], (kt == 0 && s == 0) ? S.g1[i] : tacc[pg]);
 #pragma unroll
       for (int pg = 0; pg < 4; ++pg) {
         const int px = 16 * pg + (lane & 15);
@@ -447,6 +467,13 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
     wave_sync();
     acc_i += bm * zax;
     acc_f += bm * th2 * zax;
+  };
+  Step sa, sb;
+  load_step(sa, tr.x);
+  for (int t = tr.x; t <= tr.y; t += 2) {
+    step(t, sa, sb);
+    if (t + 1 > tr.y) break;
+    step(t + 1, sb, sa);
   }
   // the four row groups of each pixel sit in lanes l, l ^ 16, l ^ 32, l ^ 48
 #pragma unroll
@@ -485,7 +512,7 @@ static void adj_d(const vis_field* f, const float* img, const float* fwhm, const
   BV_REQUIRE(f->dtile == D, VIS_EINVAL, "internal: adjoint tile mismatch");
   k_fringe_adj<D><<<nblk, 64, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_chunks, f->gstride,
                                        static_cast<float>(f->d_omega), f->beam_ref_hz, T.freq, T.p1,
-                                       T.p2, T.th2, T.chunk_t, img, fwhm, gco, dimg, f_part);
+                                       T.p2, T.th2, T.chunk_t, img, fwhm, gco, gco, dimg, f_part);
   check_launch("k_fringe_adj");
 }
 

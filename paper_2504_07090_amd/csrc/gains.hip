@@ -100,8 +100,18 @@ __device__ __forceinline__ void write_coefficients(const GainArgs& a, const floa
         else if (pr == 0 && pc == 1) val = wm.y - wp.y;
         else val = -wp.y - wm.y;
       }
-    } else if (e < nmat + 4 * a.dtile) {
-      const int idx = e - nmat, n = idx / 4 + 1, comp = idx & 3;
+    } else if (e < nmat + 16 * a.rt) {
+      // alpha-axis accumulator input of row tile i, lane group grp: rows
+      // 16 i + 4 grp + 0..3 are (Re, Im) of the powers n = 8 i + 2 grp + 1
+      // and n + 1, whose coefficients are (Re, -Im) of omega(n, 0)
+      const int idx = e - nmat, i = idx >> 4, grp = (idx >> 2) & 3, comp = idx & 3;
+      const int n = 8 * i + 2 * grp + (comp >> 1) + 1;
+      if (n <= a.dtile) {
+        const float2 w0 = omega(n, 0);
+        val = (comp & 1) ? -w0.y : w0.x;
+      }
+    } else if (e < nmat + 16 * a.rt + 4 * a.dtile) {
+      const int idx = e - nmat - 16 * a.rt, n = idx / 4 + 1, comp = idx & 3;
       const float2 w0 = comp < 2 ? omega(n, 0) : omega(0, n);
       val = (comp & 1) ? w0.y : w0.x;
     }

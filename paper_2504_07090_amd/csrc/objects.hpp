@@ -150,7 +150,7 @@ int fringe_tile_extent(int extent);
 inline int fringe_tiles(int dtile) { return (2 * dtile + 15) / 16; }
 inline int adj_coef_stride(int dtile) {
   const int rt = fringe_tiles(dtile);
-  return static_cast<int>(round_up(rt * rt * 256 + 4 * dtile, 64));
+  return static_cast<int>(round_up(rt * rt * 256 + 16 * rt + 4 * dtile, 64));
 }
 
 // Delay-filtered likelihood: scratch carved from the caller's work buffer
