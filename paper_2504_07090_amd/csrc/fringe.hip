@@ -162,16 +162,22 @@ __device__ __forceinline__ void write_powers(float* As, float* Bs, int px, float
 }
 
 // ------------------------------------------------------------------ forward --
-// One wavefront per (t, nu); loops over the pixel chunks visible at t.
-// Software pipeline per chunk: the MFMA operands of chunk k are read from LDS
-// into registers, then the 16 MFMAs of chunk k are interleaved with the
-// vector-ALU generation of chunk k+1's powers (written to LDS), so the matrix
-// and vector pipes work at the same time; geometry is loaded two chunks ahead.
-// Four resident waves per SIMD (<= 128 VGPRs) for extents up to 8, so a
-// 61-dish field's 64 x 60 (nu, t) waves are all resident at once instead of
-// leaving a second, mostly idle round of waves.
+// One block of kFwdWaves wavefronts per (t, nu); wave w takes every
+// kFwdWaves-th pixel chunk visible at t, starting at chunk w, and the block
+// adds the waves' partial tiles in a fixed order at the end.  Splitting a
+// (t, nu) over the four SIMDs of a CU balances the SIMDs: with one wave per
+// (t, nu), a 61-dish field's 3840 waves over 1024 SIMDs leave a quarter of
+// the SIMDs with 4 waves and the rest with 3, and the kernel lasts as long
+// as the busiest.  Software pipeline per chunk: the MFMA operands of chunk k
+// are read from LDS into registers, then the 16 MFMAs of chunk k are
+// interleaved with the vector-ALU generation of the wave's next chunk
+// (written to LDS); geometry is loaded two of the wave's chunks ahead.  Four
+// resident waves per SIMD (<= 128 VGPRs) for extents up to 8.
+constexpr int kFwdWaves = 4;
+
 template <int D>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(D <= 8 ? 4 : 2)))
+__global__ void __launch_bounds__(64 * kFwdWaves)
+__attribute__((amdgpu_waves_per_eu(D <= 8 ? 4 : 2)))
 k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
              const double* __restrict__ freq, const double* P1, const double* P2,
              const float* TH2, const int* __restrict__ tchunk_off,
@@ -179,11 +185,14 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
              const float* __restrict__ fwhm, float2* __restrict__ vu) {
   using T = Tile<D>;
   constexpr int RT = T::RT, W = T::W;
-  __shared__ __attribute__((aligned(16))) float As[64 * W];
-  __shared__ __attribute__((aligned(16))) float Bs[64 * W];
-  const int lane = threadIdx.x;
+  __shared__ __attribute__((aligned(16))) float As_all[kFwdWaves][64 * W];
+  __shared__ __attribute__((aligned(16))) float Bs_all[kFwdWaves][64 * W];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  float* As = As_all[wv];   // this wave's operand rows
+  float* Bs = Bs_all[wv];
   const int L = xcd_logical(blockIdx.x, gridDim.x);
-  if (L >= nf * nt) return;
+  if (L >= nf * nt) return;   // uniform over the block
   const int t = L / nf, f = L - t * nf;
   const double nu = freq[f];
   const float sig = static_cast<float>(fwhm[0] * (beam_ref / nu) * kFwhmToSigma);
@@ -232,14 +241,23 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
                        });
   };
   float a[16][RT], b[16][RT];
+  // MFMA step q reads row px = 4 q + (lane >> 4); the swizzle of row px
+  // depends on q only through q & 1, so two per-lane offsets per column tile
+  // plus a constant 8 W per step pair address every read (the constant goes
+  // into the instruction's offset field instead of an address register)
+  int ofs[2][RT];
+#pragma unroll
+  for (int e = 0; e < 2; ++e)
+#pragma unroll
+    for (int i = 0; i < RT; ++i) ofs[e][i] = lds_at<W>(4 * e + (lane >> 4), 16 * i + (lane & 15));
   auto operands = [&]() {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int px = 4 * q + (lane >> 4);
 #pragma unroll
       for (int i = 0; i < RT; ++i) {
-        a[q][i] = As[lds_at<W>(px, 16 * i + (lane & 15))];
-        b[q][i] = Bs[lds_at<W>(px, 16 * i + (lane & 15))];
+        const int o = ofs[q & 1][i] + (q >> 1) * 8 * W;
+        a[q][i] = As[o];
+        b[q][i] = Bs[o];
       }
     }
   };
@@ -247,8 +265,9 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
   // generation of chunk ci + 1 from `cur`, while chunk ci + 2's geometry loads
   // into `nxt`; the loop below is unrolled by two so the two geometry sets
   // swap roles without register copies
+  constexpr int S = kFwdWaves;   // chunk stride of one wave
   auto chunk_step = [&](int ci, const G& cur, G& nxt) {
-    nxt = load(min(ci + 2, cend - 1));
+    nxt = load(min(ci + 2 * S, cend - 1));
     // keep the prefetch here: the sources are read-only, so the optimizer
     // would otherwise re-issue the loads right before their use
     asm volatile("" ::: "memory");
@@ -259,7 +278,7 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
 #pragma unroll
         for (int j = 0; j < RT; ++j)
           acc[q % NACC][i][j] = mfma4(a[q][i], b[q][j], acc[q % NACC][i][j]);
-    generate(cur, ci + 1 < cend ? 1.0f : 0.0f);
+    generate(cur, ci + S < cend ? 1.0f : 0.0f);
 #pragma unroll
     for (int q = 0; q < 16 * RT * RT; ++q) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
@@ -270,16 +289,17 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
     operands();
     wave_sync();
   };
-  if (cend > cbeg) {
-    generate(load(cbeg), 1.0f);
-    G ga = load(min(cbeg + 1, cend - 1)), gb;
+  const int c0 = cbeg + wv;
+  if (c0 < cend) {   // uniform over the wave
+    generate(load(c0), 1.0f);
+    G ga = load(min(c0 + S, cend - 1)), gb;
     wave_sync();
     operands();
     wave_sync();
-    for (int ci = cbeg; ci < cend; ci += 2) {
+    for (int ci = c0; ci < cend; ci += 2 * S) {
       chunk_step(ci, ga, gb);
-      if (ci + 1 >= cend) break;
-      chunk_step(ci + 1, gb, ga);
+      if (ci + S >= cend) break;
+      chunk_step(ci + S, gb, ga);
     }
   }
 #pragma unroll
@@ -292,32 +312,47 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
       bxi[n] += __shfl_xor(bxi[n], o);
     }
   }
-  // P tile to LDS (reuse As as a W x W matrix), axis sums in Bs
-  float* P = As;
+  // this wave's P tile to its LDS rows (reused as a W x W matrix), its axis
+  // sums to its Bs rows
+  {
+    float* Pw = As;
 #pragma unroll
-  for (int i = 0; i < RT; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
-    for (int j = 0; j < RT; ++j)
+      for (int j = 0; j < RT; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        float sum = acc[0][i][j][r];
+        for (int r = 0; r < 4; ++r) {
+          float sum = acc[0][i][j][r];
 #pragma unroll
-        for (int h = 1; h < NACC; ++h) sum += acc[h][i][j][r];
-        P[(16 * i + 4 * (lane >> 4) + r) * W + 16 * j + (lane & 15)] = sum;
+          for (int h = 1; h < NACC; ++h) sum += acc[h][i][j][r];
+          Pw[(16 * i + 4 * (lane >> 4) + r) * W + 16 * j + (lane & 15)] = sum;
+        }
+    float* AXw = Bs;  // [D][4]: axr, axi, bxr, bxi
+    if (lane == 0) {
+#pragma unroll
+      for (int n = 0; n < D; ++n) {
+        AXw[4 * n] = axr[n];
+        AXw[4 * n + 1] = axi[n];
+        AXw[4 * n + 2] = bxr[n];
+        AXw[4 * n + 3] = bxi[n];
       }
-  float* AX = Bs;  // [D][4]: axr, axi, bxr, bxi
-  if (lane == 0) {
-#pragma unroll
-    for (int n = 0; n < D; ++n) {
-      AX[4 * n] = axr[n];
-      AX[4 * n + 1] = axi[n];
-      AX[4 * n + 2] = bxr[n];
-      AX[4 * n + 3] = bxi[n];
     }
   }
-  wave_sync();
+  __syncthreads();
+  // the block's totals, waves added in index order, into the last wave's
+  // rows beyond the tiles (W x W + 4 D floats fit in one wave's 64 W)
+  float* P = Bs_all[kFwdWaves - 1] + 4 * D;
+  float* AX = Bs_all[kFwdWaves - 1] + 4 * D + W * W;
+  static_assert(8 * D + W * W <= 64 * W, "tile totals exceed one wave's rows");
+  for (int e = threadIdx.x; e < W * W + 4 * D; e += 64 * kFwdWaves) {
+    float sum = 0.f;
+#pragma unroll
+    for (int w = 0; w < kFwdWaves; ++w) sum += e < W * W ? As_all[w][e] : Bs_all[w][e - W * W];
+    if (e < W * W) P[e] = sum; else AX[e - W * W] = sum;
+  }
+  __syncthreads();
   float2* out = vu + (static_cast<size_t>(t) * nf + f) * nubl;
-  for (int u = lane; u < nubl; u += 64) {
+  for (int u = threadIdx.x; u < nubl; u += 64 * kFwdWaves) {
     const int2 nm = ubl_nm[u];
     float2 v;
     if (nm.x == 0) {
@@ -497,7 +532,7 @@ static void fwd_d(const vis_field* f, const float* img, const float* fwhm, float
   const int nblk = static_cast<int>(round_up(static_cast<long>(f->n_freq) * f->n_time, 8));
   const auto& T = f->tab;
   ProfScope ps(&f->prof, "k_fringe_fwd", st);
-  k_fringe_fwd<D><<<nblk, 64, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_ubl,
+  k_fringe_fwd<D><<<nblk, 64 * kFwdWaves, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_ubl,
                                        static_cast<float>(f->d_omega), f->beam_ref_hz, T.freq, T.p1,
                                        T.p2, T.th2, T.tchunk_off, T.tchunk, T.ubl_nm, img, fwhm, vu);
   check_launch("k_fringe_fwd");
