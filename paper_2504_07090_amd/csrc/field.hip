@@ -409,8 +409,8 @@ static void fill_shape(vis_field* f, const vis_basis* basis, const vis_field_des
       f->n_cu = ncu;
   }
   f->dtile = fringe_tile_extent(g.extent);
-  f->gstride = adj_coef_stride(f->dtile);
   f->precision = d->precision;
+  f->gstride = adj_coef_stride(f->dtile, fringe_split(f));
   f->synthesis = d->synthesis;
   f->kaz = static_cast<int>(round_up(2 * d->lmax + 1, 4));
   f->d_omega = 4.0 * kPi / basis->n_pix;

@@ -161,6 +161,88 @@ __device__ __forceinline__ void write_powers(float* As, float* Bs, int px, float
   }
 }
 
+// ------------------------------------------------- split-precision helpers --
+// Split-precision fields run the fringe products on FP16 MFMA as hi + lo
+// pairs (x ~ hi + lo, hi = fp16(x), lo = fp16(x - hi)), three products
+// hi hi + hi lo + lo hi accumulated in FP32: about 22 significant bits per
+// product instead of FP32's 24, at a sixth of the matrix-core time.
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma_h32(h8 a, h8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_h16(h4 a, h4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// hi halves of (x0, x1) packed into one register (round toward zero; the lo
+// half carries the rest exactly enough either way)
+__device__ __forceinline__ uint32_t split_hi2(float x0, float x1) {
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x0, x1));
+}
+// lo halves fp16(x0 - hi0), fp16(x1 - hi1): one mixed-precision FMA each
+// (hi read as FP16 from its half of `hi`, the difference rounded once to
+// FP16 into the low or high half of the result)
+__device__ __forceinline__ uint32_t split_lo2(float x0, float x1, uint32_t hi) {
+  uint32_t r;
+  asm("v_fma_mixlo_f16 %0, %2, -1.0, %1 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(x0), "v"(hi));
+  asm("v_fma_mixhi_f16 %0, %2, -1.0, %1 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+      : "+v"(r) : "v"(x1), "v"(hi));
+  return r;
+}
+
+// LDS row strides (32-bit words) of the split B operand of the adjoint: rows
+// of W halves padded so that the 16-byte (hi) and 8-byte (lo) operand reads of
+// 16 consecutive pixel rows fall on distinct banks
+template <int W> struct SplitRows {
+  static constexpr int BH = W / 2 + 4;
+  static constexpr int BL = W / 2 + 2;
+};
+
+// Powers of one pixel for the split adjoint: alpha^n in FP32 into its As row
+// (as write_powers), beta^m as FP16 hi + lo pairs into its Bh / Bl rows.
+template <int D, int W, class Visit>
+__device__ __forceinline__ void write_powers_split(float* As, uint32_t* Bh, uint32_t* Bl, int px,
+                                                   float c1, float s1, float c2, float s2,
+                                                   Visit visit) {
+  using R = SplitRows<W>;
+  float av[W];
+  uint32_t bh[W / 2], bl[W / 2];
+  float ar0 = 1.f, ai0 = 0.f, ar = c1, ai = -s1;
+  float br0 = 1.f, bi0 = 0.f, br = c2, bi = -s2;
+  const float t1 = 2.f * c1, t2 = 2.f * c2;
+#pragma unroll
+  for (int n = 0; n < D; ++n) {
+    av[2 * n] = ar;
+    av[2 * n + 1] = ai;
+    bh[n] = split_hi2(br, bi);
+    bl[n] = split_lo2(br, bi, bh[n]);
+    visit(n, ar, ai, br, bi);
+    const float nar = t1 * ar - ar0, nai = t1 * ai - ai0;
+    const float nbr = t2 * br - br0, nbi = t2 * bi - bi0;
+    ar0 = ar; ai0 = ai; br0 = br; bi0 = bi;
+    ar = nar; ai = nai; br = nbr; bi = nbi;
+  }
+#pragma unroll
+  for (int r = 2 * D; r < W; ++r) av[r] = 0.f;
+#pragma unroll
+  for (int n = D; n < W / 2; ++n) bh[n] = bl[n] = 0u;
+#pragma unroll
+  for (int g = 0; g < W / 4; ++g) {
+    const int o = px * W + ((g ^ swz<W>(px)) << 2);
+    *reinterpret_cast<f4*>(As + o) = f4{av[4 * g], av[4 * g + 1], av[4 * g + 2], av[4 * g + 3]};
+  }
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+  for (int g = 0; g < W / 8; ++g)
+    *reinterpret_cast<u4*>(Bh + px * R::BH + 4 * g) = u4{bh[4 * g], bh[4 * g + 1], bh[4 * g + 2], bh[4 * g + 3]};
+#pragma unroll
+  for (int g = 0; g < W / 4; ++g)
+    *reinterpret_cast<u2*>(Bl + px * R::BL + 2 * g) = u2{bl[2 * g], bl[2 * g + 1]};
+}
+
 // ------------------------------------------------------------------ forward --
 // One block of kFwdWaves wavefronts per (t, nu); wave w takes every
 // kFwdWaves-th pixel chunk visible at t, starting at chunk w, and the block
@@ -374,8 +456,16 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
 // One wavefront per (nu, chunk of 64 visible pixels); loops over the times at
 // which the chunk is above the horizon.  gco[t][nu] holds the coefficient
 // matrix in MFMA A-operand order, then the alpha-axis accumulator inputs of
-// every (row tile, lane group), then the axis coefficients.
-template <int D>
+// every (row tile, lane group), then the axis coefficients (and, SPLIT, the
+// inverse of the power-of-two scale of the FP16 coefficients).
+//
+// SPLIT: T = G Bb runs on FP16 MFMA, per 16 x 16 tile one K = 32 product
+// [G_hi | G_lo] [B_hi; B_hi] and one K = 16 product G_hi B_lo; the coefficient
+// operands come ready from the gains pass, only beta^m is split here.
+template <int RT, bool SPLIT> struct AdjCoef { f4 gv[RT][RT]; };
+template <int RT> struct AdjCoef<RT, true> { h8 ga[RT][RT]; h4 gb[RT][RT]; };
+
+template <int D, bool SPLIT>
 __global__ void __launch_bounds__(64)
 k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, double beam_ref,
              const double* __restrict__ freq, const double* P1, const double* P2,
@@ -383,10 +473,14 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
              const float* __restrict__ fwhm, const float* __restrict__ gco, const float* gco_lane,
              float* __restrict__ dimg, float* __restrict__ f_part) {
   using T = Tile<D>;
+  using R = SplitRows<T::W>;
   constexpr int RT = T::RT, W = T::W;
-  constexpr int NMAT = RT * RT * 256;
+  constexpr int NMAT = RT * RT * (SPLIT ? 384 : 256);
   __shared__ __attribute__((aligned(16))) float As[64 * W];
-  __shared__ __attribute__((aligned(16))) float Bs[64 * W];
+  // FP32 B operand rows, or (SPLIT) the hi rows followed by the lo rows
+  __shared__ __attribute__((aligned(16))) float Bs[SPLIT ? 64 * (R::BH + R::BL) : 64 * W];
+  uint32_t* Bh = reinterpret_cast<uint32_t*>(Bs);
+  uint32_t* Bl = Bh + 64 * R::BH;
   const int lane = threadIdx.x;
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nf * nchunks) return;
@@ -415,10 +509,9 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
   // Software pipeline over t, unrolled by two so that the two register sets
   // swap roles without copies: the geometry and this lane's coefficients of
   // time t + 1 load while time t is processed.
-  struct Step {
+  struct Step : AdjCoef<RT, SPLIT> {
     double p1, p2;
     float th2;
-    f4 gv[RT][RT];
     // alpha-axis coefficients of this lane's rows 16 i + 4 (lane >> 4) + 0..3:
     // (Re, -Im) of omega(n, 0) for the two powers n of those rows, stored in
     // this order by the gains pass.  As the first MFMA's accumulator input
@@ -434,8 +527,14 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
 #pragma unroll
-      for (int kt = 0; kt < RT; ++kt)
-        S.gv[i][kt] = *reinterpret_cast<const f4*>(G + ((i * RT + kt) * 64 + lane) * 4);
+      for (int kt = 0; kt < RT; ++kt) {
+        if constexpr (SPLIT) {
+          S.ga[i][kt] = *reinterpret_cast<const h8*>(G + ((i * RT + kt) * 64 + lane) * 4);
+          S.gb[i][kt] = *reinterpret_cast<const h4*>(G + RT * RT * 256 + ((i * RT + kt) * 64 + lane) * 2);
+        } else {
+          S.gv[i][kt] = *reinterpret_cast<const f4*>(G + ((i * RT + kt) * 64 + lane) * 4);
+        }
+      }
       S.g1[i] = *reinterpret_cast<const f4*>(G + NMAT + 16 * i + 4 * (lane >> 4));
     }
   };
@@ -454,12 +553,19 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
     sincos_rev(x2, s2, c2);
     // beta-axis terms of this lane's pixel: sum_n Re[omega(0, n) beta^n]
     float zax = 0.f;
-    write_powers<D, W>(As, Bs, lane, c1, s1, c2, s2, 1.0f,
-                       [&](int n, float ar, float ai, float br, float bi) {
-                         const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 16 * RT + 4 * n);
-                         zax += ax[2] * br - ax[3] * bi;
-                       });
-    BW[lane] = make_float2(bm, bm * th2);
+    auto visit = [&](int n, float ar, float ai, float br, float bi) {
+      const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 16 * RT + 4 * n);
+      zax += ax[2] * br - ax[3] * bi;
+    };
+    if constexpr (SPLIT) {
+      write_powers_split<D, W>(As, Bh, Bl, lane, c1, s1, c2, s2, visit);
+      // T comes out scaled by the coefficients' power of two: the weights undo it
+      const float isc = G[NMAT + 16 * RT + 4 * D];
+      BW[lane] = make_float2(bm * isc, bm * th2 * isc);
+    } else {
+      write_powers<D, W>(As, Bs, lane, c1, s1, c2, s2, 1.0f, visit);
+      BW[lane] = make_float2(bm, bm * th2);
+    }
     wave_sync();
     float2 bw[4];
 #pragma unroll
@@ -471,23 +577,46 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
     // in MFMA step s (the coefficient layout uses the same order), so its four
     // steps' values are one 16-byte read of group l >> 4 of its pixel's row
     // (conflict-free; four scalar reads of rows 16 apart would share banks)
-    f4 bq[RT][4];
+    // SPLIT: lane l supplies, for pixel 16 pg + (l & 15), the hi halves of
+    // columns 16 kt + 8 ((l >> 4) & 1) + 0..7 (K = 32 product: lane groups 0, 1
+    // meet G_hi, groups 2, 3 meet G_lo) and the lo halves of columns
+    // 16 kt + 4 (l >> 4) + 0..3 (K = 16 product)
+    f4 bq[SPLIT ? 1 : RT][4];
+    h8 bh8[SPLIT ? RT : 1][4];
+    h4 bl4[SPLIT ? RT : 1][4];
 #pragma unroll
     for (int kt = 0; kt < RT; ++kt)
 #pragma unroll
-      for (int pg = 0; pg < 4; ++pg)
-        bq[kt][pg] = *reinterpret_cast<const f4*>(
-            Bs + lds_at<W>(16 * pg + (lane & 15), 16 * kt + 4 * (lane >> 4)));
+      for (int pg = 0; pg < 4; ++pg) {
+        const int px = 16 * pg + (lane & 15);
+        if constexpr (SPLIT) {
+          bh8[kt][pg] = *reinterpret_cast<const h8*>(Bh + px * R::BH + 8 * kt + 4 * ((lane >> 4) & 1));
+          bl4[kt][pg] = *reinterpret_cast<const h4*>(Bl + px * R::BL + 8 * kt + 2 * (lane >> 4));
+        } else {
+          bq[kt][pg] = *reinterpret_cast<const f4*>(Bs + lds_at<W>(px, 16 * kt + 4 * (lane >> 4)));
+        }
+      }
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
       f4 tacc[4];
+      if constexpr (SPLIT) {
 #pragma unroll
-      for (int kt = 0; kt < RT; ++kt)
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int kt = 0; kt < RT; ++kt) {
 #pragma unroll
           for (int pg = 0; pg < 4; ++pg)
-            tacc[pg] = mfma4(S.gv[i][kt][s], bq[kt][pg][s], (kt == 0 && s == 0) ? S.g1[i] : tacc[pg]);
+            tacc[pg] = mfma_h32(S.ga[i][kt], bh8[kt][pg], kt == 0 ? S.g1[i] : tacc[pg]);
+#pragma unroll
+          for (int pg = 0; pg < 4; ++pg) tacc[pg] = mfma_h16(S.gb[i][kt], bl4[kt][pg], tacc[pg]);
+        }
+      } else {
+#pragma unroll
+        for (int kt = 0; kt < RT; ++kt)
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int pg = 0; pg < 4; ++pg)
+              tacc[pg] = mfma4(S.gv[i][kt][s], bq[kt][pg][s], (kt == 0 && s == 0) ? S.g1[i] : tacc[pg]);
+      }
 #pragma unroll
       for (int pg = 0; pg < 4; ++pg) {
         const int px = 16 * pg + (lane & 15);
@@ -545,9 +674,10 @@ static void adj_d(const vis_field* f, const float* img, const float* fwhm, const
   const auto& T = f->tab;
   ProfScope ps(&f->prof, "k_fringe_adj", st);
   BV_REQUIRE(f->dtile == D, VIS_EINVAL, "internal: adjoint tile mismatch");
-  k_fringe_adj<D><<<nblk, 64, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_chunks, f->gstride,
-                                       static_cast<float>(f->d_omega), f->beam_ref_hz, T.freq, T.p1,
-                                       T.p2, T.th2, T.chunk_t, img, fwhm, gco, gco, dimg, f_part);
+  auto kern = fringe_split(f) ? k_fringe_adj<D, true> : k_fringe_adj<D, false>;
+  kern<<<nblk, 64, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_chunks, f->gstride,
+                            static_cast<float>(f->d_omega), f->beam_ref_hz, T.freq, T.p1, T.p2,
+                            T.th2, T.chunk_t, img, fwhm, gco, gco, dimg, f_part);
   check_launch("k_fringe_adj");
 }
 

@@ -45,6 +45,7 @@ struct GainArgs {
   float2* g_part;
   const int* ulut;
   int dr, dtile, rt, gstride;
+  int split;   // the adjoint multiplies the coefficients as FP16 hi + lo pairs
   int tslab;   // consecutive times per block
 };
 
@@ -65,13 +66,36 @@ __host__ __device__ inline int lanes_per_item(int n) {
   return w;
 }
 
+// FP16 hi + lo pair of x: x ~ hi + lo with hi = fp16(x), lo = fp16(x - hi).
+__device__ __forceinline__ void split_f16(float x, _Float16& hi, _Float16& lo) {
+  hi = static_cast<_Float16>(x);
+  lo = static_cast<_Float16>(x - static_cast<float>(hi));
+}
+__device__ __forceinline__ float pack_f16(_Float16 a, _Float16 b) {
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(float, h2{a, b});
+}
+
 // Adjoint coefficients of one (t, nu) slice from the collapsed omega in LDS.
-// Entry ((i * rt + kt) * 64 + l) * 4 + s holds G[r][c], r = 16 i + (l & 15),
-// c = 16 kt + 4 s + (l >> 4), with r = 2 (n - 1) + (Re / Im of alpha^n),
-// c = 2 (m - 1) + (Re / Im of beta^m):
+// The coefficient matrix G[r][c], r = 16 i + (row in tile) = 2 (n - 1) + (Re /
+// Im of alpha^n), c = 16 kt + (column in tile) = 2 (m - 1) + (Re / Im of beta^m):
 //   G = w+r + w-r (Re Re), w-r - w+r (Im Im), w-i - w+i (Re Im), -w+i - w-i (Im Re),
-// w+- = omega(n, +-m).  After rt*rt*256 entries follow, for n = 1..dtile,
-// (omega(n, 0).re, omega(n, 0).im, omega(0, n).re, omega(0, n).im).
+// w+- = omega(n, +-m).
+//
+// FP32 layout: entry ((i * rt + kt) * 64 + l) * 4 + s holds G[r][c] with
+// r = 16 i + (l & 15), c = 16 kt + 4 (l >> 4) + s (lane l's A operand of the
+// four FP32 MFMA steps of tile (i, kt)).  Then the alpha-axis accumulator
+// inputs (16 rt floats, below), then for n = 1..dtile (omega(n, 0).re,
+// omega(n, 0).im, omega(0, n).re, omega(0, n).im).
+//
+// Split layout (a.split): G is scaled by a power of two s (|s G| < 2^14) and
+// stored as FP16 hi + lo pairs.  Per tile (i, kt), 64 lanes x 8 halves: lane
+// l = (row l & 15, group g = l >> 4) holds, in slot j, hi(s G[r][16 kt + 8 g + j])
+// for g < 2 and lo(s G[r][16 kt + 8 (g - 2) + j]) for g >= 2 (the A operand of
+// one K = 32 MFMA against [B_hi; B_hi], giving G_hi B_hi + G_lo B_hi).  Then
+// per tile 64 lanes x 4 halves: hi(s G[r][16 kt + 4 g + j]) (the A operand of
+// one K = 16 MFMA against B_lo).  Then the alpha-axis inputs times s, the axis
+// coefficients (unscaled) and 1 / s.
 __device__ __forceinline__ void write_coefficients(const GainArgs& a, const float2* om,
                                                    const int* ulut, size_t slice, int tid) {
   const int lw = 2 * a.dr + 1;
@@ -80,25 +104,66 @@ __device__ __forceinline__ void write_coefficients(const GainArgs& a, const floa
     const int u = ulut[n1 * lw + n2 + a.dr];
     return u >= 0 ? om[u] : make_float2(0.f, 0.f);
   };
+  auto gval = [&](int r, int c) {
+    const int n = (r >> 1) + 1, m = (c >> 1) + 1;
+    if (n > a.dtile || m > a.dtile) return 0.f;
+    const float2 wp = omega(n, m), wm = omega(n, -m);
+    const int pr = r & 1, pc = c & 1;
+    if (pr == 0 && pc == 0) return wp.x + wm.x;
+    if (pr == 1 && pc == 1) return wm.x - wp.x;
+    if (pr == 0 && pc == 1) return wm.y - wp.y;
+    return -wp.y - wm.y;
+  };
+  // split layout: power-of-two scale from the largest |omega| component
+  // (|G| <= 2 max |omega|), found by the whole block
+  float scale = 1.0f;
+  if (a.split) {
+    __shared__ float red_max[4];
+    float mx = 0.f;
+    for (int u = tid; u < a.nubl; u += blockDim.x) mx = fmaxf(mx, fmaxf(fabsf(om[u].x), fabsf(om[u].y)));
+    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if ((tid & 63) == 0) red_max[tid >> 6] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(red_max[0], red_max[1]), fmaxf(red_max[2], red_max[3]));
+    __syncthreads();   // red_max is reused by the next slice of this block
+    if (mx > 0.f && isfinite(mx)) {
+      int ex;
+      frexpf(2.0f * mx, &ex);   // 2 mx < 2^ex
+      scale = ldexpf(1.0f, 14 - ex);
+    }
+  }
   float* G = a.gco + slice * a.gstride;
-  const int nmat = a.rt * a.rt * 256;
+  const int ntile = a.rt * a.rt;
+  const int nmat = ntile * (a.split ? 384 : 256);
   for (int e = tid; e < a.gstride; e += blockDim.x) {
     float val = 0.f;
     if (e < nmat) {
-      const int s4 = e & 3, l = (e >> 2) & 63, blk = e >> 8;
-      const int i = blk / a.rt, kt = blk - i * a.rt;
-      // lane l feeds row l & 15 and, in MFMA step s4, column 4 (l >> 4) + s4 of
-      // the 16-column block kt (the adjoint reads its B operand for the four
-      // steps as one 16-byte LDS load)
-      const int r = 16 * i + (l & 15), c = 16 * kt + 4 * (l >> 4) + s4;
-      const int n = (r >> 1) + 1, m = (c >> 1) + 1;
-      if (n <= a.dtile && m <= a.dtile) {
-        const float2 wp = omega(n, m), wm = omega(n, -m);
-        const int pr = r & 1, pc = c & 1;
-        if (pr == 0 && pc == 0) val = wp.x + wm.x;
-        else if (pr == 1 && pc == 1) val = wm.x - wp.x;
-        else if (pr == 0 && pc == 1) val = wm.y - wp.y;
-        else val = -wp.y - wm.y;
+      if (!a.split) {
+        const int s4 = e & 3, l = (e >> 2) & 63, blk = e >> 8;
+        const int i = blk / a.rt, kt = blk - i * a.rt;
+        // lane l feeds row l & 15 and, in MFMA step s4, column 4 (l >> 4) + s4 of
+        // the 16-column block kt (the adjoint reads its B operand for the four
+        // steps as one 16-byte LDS load)
+        val = gval(16 * i + (l & 15), 16 * kt + 4 * (l >> 4) + s4);
+      } else if (e < ntile * 256) {
+        // K = 32 operand: two halves (slots 2 q, 2 q + 1) per float
+        const int q = e & 3, l = (e >> 2) & 63, blk = e >> 8;
+        const int i = blk / a.rt, kt = blk - i * a.rt, g = l >> 4, r = 16 * i + (l & 15);
+        const int c = 16 * kt + 8 * (g & 1) + 2 * q;
+        _Float16 h0, l0, h1, l1;
+        split_f16(scale * gval(r, c), h0, l0);
+        split_f16(scale * gval(r, c + 1), h1, l1);
+        val = g < 2 ? pack_f16(h0, h1) : pack_f16(l0, l1);
+      } else {
+        // K = 16 operand: hi halves, slots 2 q, 2 q + 1
+        const int e2 = e - ntile * 256;
+        const int q = e2 & 1, l = (e2 >> 1) & 63, blk = e2 >> 7;
+        const int i = blk / a.rt, kt = blk - i * a.rt, g = l >> 4, r = 16 * i + (l & 15);
+        const int c = 16 * kt + 4 * g + 2 * q;
+        _Float16 h0, l0, h1, l1;
+        split_f16(scale * gval(r, c), h0, l0);
+        split_f16(scale * gval(r, c + 1), h1, l1);
+        val = pack_f16(h0, h1);
       }
     } else if (e < nmat + 16 * a.rt) {
       // alpha-axis accumulator input of row tile i, lane group grp: rows
@@ -108,12 +173,14 @@ __device__ __forceinline__ void write_coefficients(const GainArgs& a, const floa
       const int n = 8 * i + 2 * grp + (comp >> 1) + 1;
       if (n <= a.dtile) {
         const float2 w0 = omega(n, 0);
-        val = (comp & 1) ? -w0.y : w0.x;
+        val = scale * ((comp & 1) ? -w0.y : w0.x);
       }
     } else if (e < nmat + 16 * a.rt + 4 * a.dtile) {
       const int idx = e - nmat - 16 * a.rt, n = idx / 4 + 1, comp = idx & 3;
       const float2 w0 = comp < 2 ? omega(n, 0) : omega(0, n);
       val = (comp & 1) ? w0.y : w0.x;
+    } else if (a.split && e == nmat + 16 * a.rt + 4 * a.dtile) {
+      val = 1.0f / scale;
     }
     G[e] = val;
   }
@@ -417,6 +484,7 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
   a.dtile = f->dtile;
   a.rt = fringe_tiles(f->dtile);
   a.gstride = f->gstride;
+  a.split = fringe_split(f);
   const size_t lds = sizeof(float2) * (f->n_ant + 2 * f->n_ubl);
   BV_REQUIRE(lds <= 48 * 1024, VIS_EINVAL, "field too large for the gains pass LDS budget");
   const size_t lds_sorted = lds + 3 * sizeof(float2) * f->n_bl +

@@ -148,9 +148,11 @@ void launch_fringe_adj(const vis_field* f, const float* img, const float* fwhm, 
 // layout of the adjoint coefficient table that the gains pass writes.
 int fringe_tile_extent(int extent);
 inline int fringe_tiles(int dtile) { return (2 * dtile + 15) / 16; }
-inline int adj_coef_stride(int dtile) {
+// Split-precision fields run the fringe products as FP16 hi + lo pairs.
+inline bool fringe_split(const vis_field* f) { return f->precision != VIS_FP32; }
+inline int adj_coef_stride(int dtile, bool split) {
   const int rt = fringe_tiles(dtile);
-  return static_cast<int>(round_up(rt * rt * 256 + 16 * rt + 4 * dtile, 64));
+  return static_cast<int>(round_up(rt * rt * (split ? 384 : 256) + 16 * rt + 4 * dtile + 1, 64));
 }
 
 // Delay-filtered likelihood: scratch carved from the caller's work buffer
