@@ -52,8 +52,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "427c0371d840453b913dc2f3d0c709d982800d1552f4dcdb9b56fd2835b39eda",
-    "bytes_per_launch": {"k_fringe_adj": 581169593, "k_fringe_fwd": 187269291},
+    "sha256": "22bdd8745e9bfbedc6f83fe13b9a8851da5e61f1a6eb1341f01148a7ae6047a8",
+    "bytes_per_launch": {"k_fringe_adj": 750402606, "k_fringe_fwd": 430161136},
 }
 
 
@@ -218,6 +218,9 @@ def main():
     ap.add_argument("--synthesis", default="separable", choices=["separable", "dense"],
                     help="sky synthesis of the timed chain (separable: FP32 only)")
     ap.add_argument("--serve-chains", type=int, default=64)
+    ap.add_argument("--inflight-ticks", type=int, default=1, choices=[1, 2],
+                    help="serving ticks in flight for the timed chain (2: the next tick is "
+                         "built and queued while the current one runs)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -246,7 +249,8 @@ def main():
     warm = make_chain(vis, serve, torch, basis, cfg, prec, synth)
     timed = make_chain(vis, serve, torch, basis, cfg, prec, synth)
     fld = timed[0]
-    srv = serve.Server(serve.Server.footprint(fld) * 2 + (64 << 20), max_chains=2, max_batch=2)
+    srv = serve.Server(serve.Server.footprint(fld) * 2 + (64 << 20), max_chains=2, max_batch=2,
+                       inflight_ticks=args.inflight_ticks)
     fldw, dataw, sigw, q0w, minvw, cvarw, _ = warm
     cw = srv.admit(fldw, dataw, sigw, q0w, minvw, cvarw, cfg.gain_scatter, EPS,
                    max(1, args.warmup), seed=1, stream_id=0)
@@ -337,7 +341,7 @@ def main():
                    "n_ant": fld.n_ant, "n_bl": fld.n_bl, "n_ubl": fld.n_ubl,
                    "n_pix": fld.info.n_pix, "n_pix_visible": nv, "lmax": cfg.lmax,
                    "n_freq": cfg.n_freq, "n_time": cfg.n_time, "fwd_macs": fld.fwd_macs,
-                   "leapfrog_steps": args.steps},
+                   "leapfrog_steps": args.steps, "inflight_ticks": args.inflight_ticks},
         "grad_evals_per_s": 1e3 / ms,
         "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
         "kernel_ms": per,
