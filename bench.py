@@ -52,8 +52,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "22bdd8745e9bfbedc6f83fe13b9a8851da5e61f1a6eb1341f01148a7ae6047a8",
-    "bytes_per_launch": {"k_fringe_adj": 750402606, "k_fringe_fwd": 430161136},
+    "sha256": "5810a33dbd7bce4722e58a5081e56d17bb4fa34b236db99a8f0a211ba1a4e2ec",
+    "bytes_per_launch": {"k_fringe_adj": 199089375, "k_fringe_fwd": 271978204},
 }
 
 

@@ -101,6 +101,20 @@ __device__ __forceinline__ int xcd_logical(int bid, int nblocks) {
   return (bid & 7) * per + (bid >> 3);
 }
 
+// Logical index L -> (outer o, inner i) of an n_o x n_i grid, visited in
+// tiles of to outers x ti inners (outer-major inside a tile), so that the
+// blocks resident on one XCD at a time share few outer and few inner rows
+// (geometry rows per outer, image or coefficient rows per inner) and both fit
+// its L2.  A bijection for L < n_o n_i.
+__device__ __forceinline__ void tile_map(int L, int n_o, int n_i, int to, int ti, int& o, int& i) {
+  const int og = L / (to * n_i), o0 = og * to, tog = min(to, n_o - o0);
+  int local = L - og * to * n_i;
+  const int ig = local / (tog * ti), i0 = ig * ti, tig = min(ti, n_i - i0);
+  local -= ig * tog * ti;
+  o = o0 + local / tig;
+  i = i0 + local % tig;
+}
+
 template <int D>
 struct Tile {
   static constexpr int RT = (2 * D + 15) / 16;  // 16-wide MFMA tiles per side
@@ -275,7 +289,8 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
   float* Bs = Bs_all[wv];
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nf * nt) return;   // uniform over the block
-  const int t = L / nf, f = L - t * nf;
+  int t, f;
+  tile_map(L, nt, nf, 4, 32, t, f);   // 128 resident blocks per XCD: 4 times x 32 channels
   const double nu = freq[f];
   const float sig = static_cast<float>(fwhm[0] * (beam_ref / nu) * kFwhmToSigma);
   const float kb = 1.0f / (2.0f * sig * sig * static_cast<float>(kLn2));
@@ -484,7 +499,8 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
   const int lane = threadIdx.x;
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   if (L >= nf * nchunks) return;
-  const int chunk = L / nf, f = L - chunk * nf;
+  int chunk, f;
+  tile_map(L, nchunks, nf, 32, 16, chunk, f);   // 512 resident waves per XCD: 32 chunks x 16 channels
   const double nu = freq[f];
   const float fw = fwhm[0];
   const float sig = static_cast<float>(fw * (beam_ref / nu) * kFwhmToSigma);
