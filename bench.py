@@ -315,6 +315,10 @@ def main():
         sep_nuts = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32,
                                  max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
                                  nuts_depth=5)
+        log("serving: batched, FP32 separable synthesis, NUTS with dense gain mass blocks")
+        sep_nuts_dg = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32,
+                                    max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
+                                    dense_gains=True, nuts_depth=5)
         log("serving: per-chain FP32 baseline (dense synthesis), one request per tick")
         base = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32, max_batch=1)
         del ins
@@ -322,6 +326,7 @@ def main():
                    "batched_" + args.serve_precision: fast, "batched_fp32_separable": sep,
                    "batched_fp32_separable_dense_gain_mass": sep_dg,
                    "batched_fp32_separable_nuts": sep_nuts,
+                   "batched_fp32_separable_nuts_dense_gain_mass": sep_nuts_dg,
                    "per_chain_fp32": base,
                    "speedup": fast["grad_evals_per_s"] / base["grad_evals_per_s"],
                    "speedup_separable": sep["grad_evals_per_s"] / base["grad_evals_per_s"]}
