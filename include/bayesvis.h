@@ -73,6 +73,10 @@ typedef enum {
   VIS_ENUMERIC = -6    /* non-finite value detected */
 } vis_status;
 
+/* Split precisions: the dense synthesis runs as three hi/lo products on
+ * 16-bit MFMA with FP32 accumulation, and so does the adjoint fringe GEMM
+ * (FP16 hi/lo, coefficients scaled by a power of two per (t, nu)); the
+ * forward fringe stays FP32 (its operands would need a 2-byte transpose). */
 typedef enum {
   VIS_FP32 = 1,        /* FP32 MFMA synthesis, FP32 fringe */
   VIS_BF16X3 = 2,      /* synthesis as bf16 hi/lo split products on MFMA, FP32 accumulate */
