@@ -8,7 +8,10 @@ residual + FP64 chi^2, residual collapse and gain gradient, adjoint fringe
 contraction, adjoint synthesis, prior terms + kick, FP64 energy partials
 (and the Metropolis test at the end of the trajectory).  The timed chain has
 exactly `--steps` leapfrog steps; its initial gradient is evaluated before
-timing starts.  Inputs are synthetic (seeded) and resident in HBM.
+timing starts.  Inputs are synthetic (seeded) and resident in HBM.  The step
+rate is timed without instrumentation; a second trajectory of the same length
+with HIP events around every kernel gives the per-kernel durations (the
+roofline's dominant kernel) and `ms_per_step_instrumented`.
 
 Headline value: fwd+adjoint complex MAC/s, one MAC being one term of the
 fringe sum for one (unique baseline, pixel above the horizon, channel, time),
@@ -18,8 +21,8 @@ Serving (`serving` key): 64 concurrent chains on uneven hex fields
 (19-127 dishes, 16-128 channels, 10-120 times, lmax 30-100), one trajectory
 of 20 leapfrog steps each, through the batched server with split-precision
 (bf16 hi/lo) dense synthesis and with FP32 separable synthesis (also with
-dense per-channel gain mass blocks, App. B, and as No-U-Turn trajectories of
-at most 31 steps), against the
+dense per-channel gain mass blocks, App. B, as No-U-Turn trajectories of at
+most 31 steps, and as No-U-Turn trajectories with dense gain blocks), against the
 same request stream through the plain FP32 dense path one request per tick:
 gradient evaluations per second and request latency p50/p99.
 
@@ -257,11 +260,9 @@ def main():
     srv.submit(cw, 1)
     srv.wait(1, timeout_s=300)
     fld, data, sigma, q0, minv, cvar, lay = timed
-    vis.profile_enable(fld, True)
     ct = srv.admit(fld, data, sigma, q0, minv, cvar, cfg.gain_scatter, EPS, args.steps,
                    seed=2, stream_id=1)
     wait_requests(srv, 1 + max(1, args.warmup) + 1)   # warm-up chain + the timed chain's initial gradient
-    vis.profile_read(fld, reset=True)
     srv.stats(reset=True)
     log("timed trajectory of", args.steps, "leapfrog steps")
     torch.cuda.synchronize()
@@ -271,12 +272,27 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = srv.stats()
+    # Per-kernel durations come from a second trajectory of the same length
+    # with a HIP event pair around every kernel of the evaluation; the events
+    # idle the GPU for a few microseconds at each kernel boundary, so the step
+    # rate above is taken without them.
+    log("instrumented trajectory (per-kernel HIP events)")
+    vis.profile_enable(fld, True)
+    vis.profile_read(fld, reset=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    srv.submit(ct, 1)
+    res2 = srv.wait(1, timeout_s=600)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     ktimes = vis.profile_read(fld, reset=True)
     vis.profile_enable(fld, False)
     srv.close()
-    if res[0]["status"] != 0:
-        raise RuntimeError(f"timed chain failed: {res[0]}")
+    for r in (res[0], res2[0]):
+        if r["status"] != 0:
+            raise RuntimeError(f"timed chain failed: {r}")
     ms = (t1 - t0) * 1e3 / args.steps
+    ms_instr = (t3 - t2) * 1e3 / args.steps
     macs = 2.0 * fld.fwd_macs
     value = macs / (ms * 1e-3)
     log("ms/step", ms, "result", res[0])
@@ -348,6 +364,7 @@ def main():
                    "n_freq": cfg.n_freq, "n_time": cfg.n_time, "fwd_macs": fld.fwd_macs,
                    "leapfrog_steps": args.steps, "inflight_ticks": args.inflight_ticks},
         "grad_evals_per_s": 1e3 / ms,
+        "ms_per_step_instrumented": ms_instr,
         "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
         "kernel_ms": per,
         "roofline": roof,
