@@ -214,8 +214,8 @@ def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--serve-precision", default="bf16x3", choices=["bf16x3", "fp16x3"])
     ap.add_argument("--synthesis", default="separable", choices=["separable", "dense"],
