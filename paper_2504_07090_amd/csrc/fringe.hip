@@ -20,9 +20,11 @@
 // in registers and LDS; nothing of size pixels x baselines touches HBM.
 //
 // Phase accuracy: x = nu (e . s) / c is formed in FP64 and reduced to
-// [-1/2, 1/2] before rounding to FP32, and the powers alpha^n, n <= D, are
-// built by repeated complex multiplication, so the phase error of every term
-// stays at the FP32 rounding level of a number below one cycle times D.
+// [-1/2, 1/2] before rounding to FP32, and the powers alpha^n, n <= D, come
+// from the three-term recurrence u_{n+1} = 2 cos(theta) u_n - u_{n-1}.  A
+// rounding error made at step k reaches step n multiplied by
+// sin((n - k) theta) / sin(theta), at most n - k in size, so the error of
+// alpha^n stays below about n^2 / 2 FP32 roundings (32 at n = 8).
 //
 // The adjoint (transpose over the reals) of the same map, for coefficients
 // omega_u = dL/dRe V_u - i dL/dIm V_u (formed by the gains pass), is
@@ -134,12 +136,6 @@ template <int W>
 __device__ __forceinline__ int lds_at(int px, int col) {
   return px * W + ((((col >> 2) ^ swz<W>(px))) << 2) + (col & 3);
 }
-
-// Geometry of one (time, visible pixel) entry.
-struct Geo {
-  double p1, p2;
-  float th2;
-};
 
 // Powers alpha^n (n = 1..D) and beta^m w (m = 1..D) of one pixel into its LDS
 // rows (row px of As / Bs, zero padding up to W); visit(n, alpha^n, beta^n w)
