@@ -128,8 +128,8 @@ __device__ __forceinline__ void write_coefficients(const GainArgs& a, const floa
     __syncthreads();   // red_max is reused by the next slice of this block
     if (mx > 0.f && isfinite(mx)) {
       int ex;
-      frexpf(2.0f * mx, &ex);   // 2 mx < 2^ex
-      scale = ldexpf(1.0f, 14 - ex);
+      frexpf(mx, &ex);   // mx < 2^ex, so |G| <= 2 mx < 2^(ex + 1)
+      scale = ldexpf(1.0f, min(100, 13 - ex));
     }
   }
   float* G = a.gco + slice * a.gstride;
