@@ -55,8 +55,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "5810a33dbd7bce4722e58a5081e56d17bb4fa34b236db99a8f0a211ba1a4e2ec",
-    "bytes_per_launch": {"k_fringe_adj": 199089375, "k_fringe_fwd": 271978204},
+    "sha256": "64639fd89d2bea6ee57daf0b53523afbee1529fd561d8a9cb80993c37db3e148",
+    "bytes_per_launch": {"k_fringe_adj": 199097695, "k_fringe_fwd": 272013517},
 }
 
 
