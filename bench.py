@@ -108,6 +108,98 @@ def cpu_baseline(cfg, chan: int = 37):
                        f"elementwise NumPy single-threaded, BLAS {blas_threads} threads")}
 
 
+def timed_reps(torch, fn, reps):
+    """Median wall time (ms) of fn() over reps calls, each bracketed by a sync."""
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def extras_bench(vis, torch, fld, cfg, data, sigma, reps=20):
+    """The delay-filtered likelihood and map-making on the timed chain's field:
+    median time per call, per-kernel times (HIP events, a separate set of
+    calls) and the roofline of each row's dominant kernel; the FP64 oracle and
+    the GPU timed beside it on the small 16-dish workload."""
+    import numpy as np
+    from oracle import filter as ofl, mapmaking as omm, model
+    from paper_2504_07090_amd import workload as w
+    d = w.draw(cfg)
+    alm = torch.tensor(d.alm, dtype=torch.float32, device="cuda")
+    g = torch.tensor(d.gains, dtype=torch.complex64, device="cuda")
+    fw = torch.tensor([w.fwhm_ref_rad(cfg)], dtype=torch.float32, device="cuda")
+    filt = vis.Filter(w.frequencies(cfg))
+    nvis = cfg.n_time * cfg.n_freq * fld.n_bl
+    out = {}
+
+    def kernel_times(fn, n=5):
+        vis.profile_enable(fld, True)
+        vis.profile_read(fld, reset=True)
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        kt = vis.profile_read(fld, reset=True)
+        vis.profile_enable(fld, False)
+        return {k: v[1] / max(1, v[0]) for k, v in kt.items()}
+
+    # delay-filtered chi^2 + gradient: the filter GEMMs over frequency read the
+    # data and model and write the weighted residual (3 x 8 B per visibility),
+    # then read it and write the cotangent (2 x 8 B); 2 nf^2 flop per real
+    # column and time, 10.7 flop/B: HBM-bound
+    ffn = lambda: vis.chi2_filtered_and_grad(fld, filt, data, sigma, alm, g, fw)
+    ffn()
+    ms_f = timed_reps(torch, ffn, reps)
+    kf = kernel_times(ffn)
+    kr = kf.get("k_filter_resid", float("nan"))
+    roof_f = {"bound": "hbm", "kernel": "k_filter_resid", "kernel_ms": kr, "unit": "GB/s",
+              "achieved": 3.0 * 8.0 * nvis / (kr * 1e-3) / 1e9, "peak": PEAK["hbm_gbs"]}
+    roof_f["frac"] = roof_f["achieved"] / roof_f["peak"]
+    out["delay_filtered_chi2_grad"] = {"ms": ms_f, "kernel_ms": kf, "roofline": roof_f,
+                                       "flop_per_launch": 2.0 * cfg.n_freq ** 2 * 2 * fld.n_bl * cfg.n_time}
+    # map-making: collapse onto unique baselines, the adjoint fringe contraction
+    # (same MAC count as the forward), the closed-form normalisation
+    mfn = lambda: vis.make_map(fld, data, g, fw)
+    mfn()
+    ms_m = timed_reps(torch, mfn, reps)
+    km = kernel_times(mfn)
+    ka = km.get("k_fringe_adj", float("nan"))
+    roof_m = {"bound": "mfma", "kernel": "k_fringe_adj", "kernel_ms": ka, "unit": "TFLOP/s",
+              "achieved": 4.0 * fld.fwd_macs / (ka * 1e-3) / 1e12, "peak": PEAK["fp32_mfma_tflops"]}
+    roof_m["frac"] = roof_m["achieved"] / roof_m["peak"]
+    out["map_making"] = {"ms": ms_m, "kernel_ms": km, "roofline": roof_m}
+    # the oracle beside the GPU on the 16-dish workload (8 channels, 4 times)
+    c0 = w.C0
+    b0 = vis.basis_for(c0)
+    f0 = vis.Field.from_config(b0, c0)
+    of = model.Field(c0)
+    d0 = w.draw(c0)
+    _, s0, y0 = model.make_data(of, d0)
+    fr0 = w.frequencies(c0)
+    t0 = time.perf_counter()
+    ofl.chi2_filtered_and_grad(of, y0, s0, ofl.delay_filter(fr0), d0.alm, d0.gains, w.fwhm_ref_rad(c0))
+    t_of = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    omm.dirty_map(of, y0, d0.gains, w.fwhm_ref_rad(c0))
+    t_om = (time.perf_counter() - t0) * 1e3
+    a0 = torch.tensor(d0.alm, dtype=torch.float32, device="cuda")
+    g0 = torch.tensor(d0.gains, dtype=torch.complex64, device="cuda")
+    fw0 = torch.tensor([w.fwhm_ref_rad(c0)], dtype=torch.float32, device="cuda")
+    y0d = torch.tensor(np.ascontiguousarray(y0), dtype=torch.complex64, device="cuda")
+    filt0 = vis.Filter(fr0)
+    g_of = timed_reps(torch, lambda: vis.chi2_filtered_and_grad(f0, filt0, y0d, s0, a0, g0, fw0), reps)
+    g_om = timed_reps(torch, lambda: vis.make_map(f0, y0d, g0, fw0), reps)
+    out["oracle_beside_gpu_16dish"] = {
+        "workload": c0.name, "unit": "ms per call",
+        "delay_filtered_chi2_grad": {"oracle_ms": t_of, "gpu_ms": g_of},
+        "map_making": {"oracle_ms": t_om, "gpu_ms": g_om}}
+    return out
+
+
 def make_chain(vis, serve, torch, basis, cfg, prec, synthesis=0):
     """Field, synthetic data, inverse mass and prior for one chain of config cfg."""
     from paper_2504_07090_amd import workload as w
@@ -226,6 +318,9 @@ def main():
                          "built and queued while the current one runs)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the delay-filtered likelihood and map-making measurements "
+                         "(also skipped with --no-serve, as in the profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -314,6 +409,11 @@ def main():
     roof["kernel"] = dom
     roof["kernel_ms"] = dom_ms
 
+    extras = None
+    if not args.no_serve and not args.no_extras:
+        log("extras: delay-filtered likelihood and map-making on the timed field")
+        extras = extras_bench(vis, torch, fld, cfg, data, sigma)
+
     serving = None
     if not args.no_serve:
         log("serving: building", args.serve_chains, "uneven chains")
@@ -369,6 +469,7 @@ def main():
         "kernel_ms": per,
         "roofline": roof,
         "serving": serving,
+        "extras": extras,
         "cpu_baseline": cpu,
     }
     if args.calibrate_copy:

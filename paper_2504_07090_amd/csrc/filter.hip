@@ -12,10 +12,9 @@
 //     Rf = F r                              (GEMM nu x nu' x 2 n_bl per time)
 //     chi^2 = sum Rf^2 / N~_nu,             W = Rf / N~_nu
 //     c = -2 F^T W                          (GEMM, the cotangent dL/dm)
-// both GEMMs on v_mfma_f32_16x16x4_f32 with one 16 x 16 output tile per
-// wavefront: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
-// D[i][j] in lane j + 16 (i / 4), register i % 4.  The chi^2 terms are summed
-// per wavefront in FP64 and totalled in a fixed order.
+// both GEMMs on v_mfma_f32_16x16x4_f32 (A[i][k] in lane i + 16 k, B[k][j] in
+// lane j + 16 k, D[i][j] in lane j + 16 (i / 4), register i % 4).  The chi^2
+// terms are summed per wavefront in FP64 and totalled in a fixed order.
 #include <cmath>
 #include <vector>
 
@@ -88,71 +87,114 @@ static void build_filter(int n, const double* freq, double tau, double eps, std:
 }
 
 // --------------------------------------------------------------- kernels --
-// Rf[t][nu][x] = sum_k F[nu][k] (d - m)[t][k][x];  W = Rf / N~;  part = per-wave chi^2.
-// grid (ceil(nx / 16), ceil(nf / 16), nt), one wavefront per block.
+// Both GEMMs stream the visibility-sized operands once, so they are bound by
+// HBM, not by the matrix cores: one wavefront per (time, 16 CT columns, 64
+// rows) keeps a 64 x 16 CT output block in registers (4 x CT tiles of
+// 16 x 16), reads each operand row segment once as 8-byte vectors, and loops
+// over all nf rows of the contraction, 16 per step with all the step's loads
+// in flight together.  In tile c, lane j holds column
+// x0 + 32 (c >> 1) + 2 j + (c & 1), so one 8-byte load per lane feeds two
+// tiles and every store is an 8-byte pair of adjacent columns.
+//
+// RESID: Rf = F (d - m);  W = Rf / N~;  part = chi^2 of the wave's block.
+// COT:   cot = -2 F^T W.
+constexpr int kFilterColTiles = 4;
+
+template <bool RESID, int CT>
 __global__ void __launch_bounds__(64)
-k_filter_resid(int nf, int nx, float inv_sig2, const float* __restrict__ F, const float* __restrict__ fft,
-               const float* __restrict__ d, const float* __restrict__ m, float* __restrict__ W,
-               double* __restrict__ part) {
-  const int x0 = blockIdx.x * 16, n0 = blockIdx.y * 16, t = blockIdx.z;
-  const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
-  const int row = min(n0 + i, nf - 1), col = min(x0 + i, nx - 1);
+k_filter_gemm(int nf, int nx, float inv_sig2, const float* __restrict__ F, const float* __restrict__ fft,
+              const float* x_a, const float* x_b, float* __restrict__ out, double* __restrict__ part) {
+  constexpr int NH = CT / 2;   // 8-byte loads per lane and contraction row
+  const int x0 = blockIdx.x * 16 * CT, n0 = blockIdx.y * 64, t = blockIdx.z;
+  const int lane = threadIdx.x, j = lane & 15, kk = lane >> 4;
   const size_t tb = static_cast<size_t>(t) * nf * nx;
-  f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < nf; k0 += 16) {
-    float a[4], b[4];
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  f4 acc[4][CT];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[r][c] = f4{0.f, 0.f, 0.f, 0.f};
+  int arow[4];   // this lane's A row in each row tile (clamped: rows past nf are never stored)
+#pragma unroll
+  for (int r = 0; r < 4; ++r) arow[r] = min(n0 + 16 * r + j, nf - 1);
+  bool colok[NH];
+  int xc[NH];
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+    xc[h] = x0 + 32 * h + 2 * j;   // even, and nx is even: the pair is whole or absent
+    colok[h] = xc[h] < nx;
+  }
+  // operand rows k0 + 4 q + kk of one 16-row step and the filter entries
+  // they meet, loaded unconditionally from clamped addresses so that all
+  // loads of a step are in flight together (a load under a branch is waited
+  // for before the branch ends); entries outside the matrix are zeroed when
+  // the step uses them
+  struct Rows { f2 a[4][NH], b[RESID ? 4 : 1][NH]; float f[4][4]; };
+  auto load_b = [&](int k0, Rows& R) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int k = k0 + 4 * q + kk;
-      const bool ok = k < nf;
-      const size_t o = tb + static_cast<size_t>(k) * nx + col;
-      a[q] = ok ? F[static_cast<size_t>(row) * nf + k] : 0.f;
-      b[q] = ok ? d[o] - m[o] : 0.f;
+      const int k = min(k0 + 4 * q + kk, nf - 1);
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        const size_t o = tb + static_cast<size_t>(k) * nx + min(xc[h], nx - 2);
+        R.a[q][h] = *reinterpret_cast<const f2*>(x_a + o);
+        if (RESID) R.b[q][h] = *reinterpret_cast<const f2*>(x_b + o);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        R.f[q][r] = RESID ? F[static_cast<size_t>(arow[r]) * nf + k] : F[static_cast<size_t>(k) * nf + arow[r]];
+    }
+  };
+  auto step = [&](int k0, const Rows& R) {
+    f2 b[4][NH];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool kok = k0 + 4 * q + kk < nf;
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        const f2 v = RESID ? R.a[q][h] - R.b[RESID ? q : 0][h] : R.a[q][h];
+        b[q][h] = kok && colok[h] ? v : f2{0.f, 0.f};
+      }
+    }
+    float a[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool kok = k0 + 4 * q + kk < nf;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[q][r] = kok ? R.f[q][r] : 0.f;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q], acc, 0, 0, 0);
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][r], b[q][c >> 1][c & 1], acc[r][c], 0, 0, 0);
+  };
+  for (int k0 = 0; k0 < nf; k0 += 16) {
+    Rows R;
+    load_b(k0, R);   // all loads of the step in flight at once
+    step(k0, R);
   }
   double chi = 0.0;
-  const int xo = x0 + (lane & 15);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int nu = n0 + 4 * kk + r;
-    if (nu < nf && xo < nx) {
-      const float w = inv_sig2 / fft[nu];
-      chi += static_cast<double>(acc[r]) * acc[r] * w;
-      W[tb + static_cast<size_t>(nu) * nx + xo] = acc[r] * w;
-    }
-  }
-  for (int o = 32; o >= 1; o >>= 1) chi += __shfl_xor(chi, o);
-  if (lane == 0) part[(static_cast<size_t>(t) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = chi;
-}
-
-// cot[t][nu'][x] = -2 sum_nu F[nu][nu'] W[t][nu][x];  grid as above.
-__global__ void __launch_bounds__(64)
-k_filter_cot(int nf, int nx, const float* __restrict__ F, const float* __restrict__ W,
-             float* __restrict__ cot) {
-  const int x0 = blockIdx.x * 16, n0 = blockIdx.y * 16, t = blockIdx.z;
-  const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
-  const int row = min(n0 + i, nf - 1), col = min(x0 + i, nx - 1);
-  const size_t tb = static_cast<size_t>(t) * nf * nx;
-  f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < nf; k0 += 16) {
-    float a[4], b[4];
+  for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int k = k0 + 4 * q + kk;
-      const bool ok = k < nf;
-      a[q] = ok ? F[static_cast<size_t>(k) * nf + row] : 0.f;
-      b[q] = ok ? W[tb + static_cast<size_t>(k) * nx + col] : 0.f;
+      const int nu = n0 + 16 * r + 4 * kk + q;
+      if (nu >= nf) continue;
+      const float w = RESID ? inv_sig2 / fft[nu] : -2.0f;
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        if (!colok[h]) continue;
+        const float v0 = acc[r][2 * h][q], v1 = acc[r][2 * h + 1][q];
+        if (RESID) chi += (static_cast<double>(v0) * v0 + static_cast<double>(v1) * v1) * w;
+        *reinterpret_cast<f2*>(out + tb + static_cast<size_t>(nu) * nx + xc[h]) = f2{v0 * w, v1 * w};
+      }
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], b[q], acc, 0, 0, 0);
-  }
-  const int xo = x0 + (lane & 15);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int nu = n0 + 4 * kk + r;
-    if (nu < nf && xo < nx) cot[tb + static_cast<size_t>(nu) * nx + xo] = -2.0f * acc[r];
+  if (RESID) {
+    for (int o = 32; o >= 1; o >>= 1) chi += __shfl_xor(chi, o);
+    if (lane == 0) part[(static_cast<size_t>(t) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = chi;
   }
 }
 
@@ -177,7 +219,8 @@ __global__ void __launch_bounds__(1024) k_sum_f64(long n, const double* __restri
 FilteredWork carve_filtered_work(const vis_field* f, void* work, size_t bytes) {
   const size_t nvis = static_cast<size_t>(f->n_time) * f->n_freq * f->n_bl;
   FilteredWork w;
-  w.nparts = static_cast<long>(f->n_time) * ceil_div(f->n_freq, 16) * ceil_div(2L * f->n_bl, 16);
+  w.nparts = static_cast<long>(f->n_time) * ceil_div(f->n_freq, 64) *
+             ceil_div(2L * f->n_bl, 16L * kFilterColTiles);
   Carver cv{static_cast<char*>(work), bytes, 0};
   w.m = cv.take<float2>(nvis);
   w.w = cv.take<float2>(nvis);
@@ -195,13 +238,13 @@ void launch_filter_chi2(const vis_field* f, const vis_filter* flt, const float2*
                         const FilteredWork& w, double* chi2, hipStream_t st) {
   check_filter(f, flt);
   const int nx = 2 * f->n_bl;
-  dim3 grid(ceil_div(nx, 16), ceil_div(f->n_freq, 16), f->n_time);
+  dim3 grid(ceil_div(nx, 16 * kFilterColTiles), ceil_div(f->n_freq, 64), f->n_time);
   {
     ProfScope ps(&f->prof, "k_filter_resid", st);
-    k_filter_resid<<<grid, 64, 0, st>>>(f->n_freq, nx, 1.0f / (sigma_n * sigma_n), flt->F, flt->fft,
-                                        reinterpret_cast<const float*>(data),
-                                        reinterpret_cast<const float*>(w.m),
-                                        reinterpret_cast<float*>(w.w), w.part);
+    k_filter_gemm<true, kFilterColTiles><<<grid, 64, 0, st>>>(f->n_freq, nx, 1.0f / (sigma_n * sigma_n), flt->F, flt->fft,
+                                             reinterpret_cast<const float*>(data),
+                                             reinterpret_cast<const float*>(w.m),
+                                             reinterpret_cast<float*>(w.w), w.part);
     check_launch("k_filter_resid");
   }
   ProfScope ps(&f->prof, "k_sum_f64", st);
@@ -212,10 +255,11 @@ void launch_filter_chi2(const vis_field* f, const vis_filter* flt, const float2*
 void launch_filter_cot(const vis_field* f, const vis_filter* flt, const FilteredWork& w, hipStream_t st) {
   check_filter(f, flt);
   const int nx = 2 * f->n_bl;
-  dim3 grid(ceil_div(nx, 16), ceil_div(f->n_freq, 16), f->n_time);
+  dim3 grid(ceil_div(nx, 16 * kFilterColTiles), ceil_div(f->n_freq, 64), f->n_time);
   ProfScope ps(&f->prof, "k_filter_cot", st);
-  k_filter_cot<<<grid, 64, 0, st>>>(f->n_freq, nx, flt->F, reinterpret_cast<const float*>(w.w),
-                                    reinterpret_cast<float*>(w.m));
+  k_filter_gemm<false, kFilterColTiles><<<grid, 64, 0, st>>>(f->n_freq, nx, 0.f, flt->F, nullptr,
+                                            reinterpret_cast<const float*>(w.w), nullptr,
+                                            reinterpret_cast<float*>(w.m), nullptr);
   check_launch("k_filter_cot");
 }
 

@@ -30,9 +30,12 @@ def _params(d, cfg, scale=1.0):
     return alm, g, fw
 
 
-@pytest.mark.parametrize("synthesis", [0, 1], ids=["dense", "separable"])
-def test_filtered_chi2_and_gradient_match_oracle(vis, synthesis):
-    cfg = w.scaled(w.C0, array="hex", array_size=4, n_freq=32, n_time=3, lmax=12,
+@pytest.mark.parametrize("synthesis,side,nf", [(0, 4, 32), (1, 4, 32), (1, 3, 13), (0, 3, 70)],
+                         ids=["dense", "separable", "ragged13", "two_row_blocks70"])
+def test_filtered_chi2_and_gradient_match_oracle(vis, synthesis, side, nf):
+    """13 channels leave a ragged contraction and row block, 70 channels need
+    two 64-row blocks; 19 dishes (342 real columns) a ragged column block."""
+    cfg = w.scaled(w.C0, array="hex", array_size=side, n_freq=nf, n_time=3, lmax=12,
                    freq_lo_hz=120e6, freq_hi_hz=130e6)
     basis = vis.Basis(cfg.grid_nz, cfg.grid_nphi, cfg.lmax, 1 | vis.STORAGE_SEPARABLE)
     fld = vis.Field.from_config(basis, cfg, vis.VIS_FP32, synthesis)
