@@ -26,6 +26,11 @@ most 31 steps, and as No-U-Turn trajectories with dense gain blocks), against th
 same request stream through the plain FP32 dense path one request per tick:
 gradient evaluations per second and request latency p50/p99.
 
+Extras (`extras` key; skipped with --no-serve unless --extras): the
+delay-filtered likelihood and map-making on the timed field, with the
+roofline of each one's dominant kernel, and the FP64 oracle timed beside the
+GPU for both on the 16-dish workload.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -321,6 +326,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the delay-filtered likelihood and map-making measurements "
                          "(also skipped with --no-serve, as in the profiling runs)")
+    ap.add_argument("--extras", action="store_true",
+                    help="run those measurements even with --no-serve")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with a 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -410,7 +417,7 @@ def main():
     roof["kernel_ms"] = dom_ms
 
     extras = None
-    if not args.no_serve and not args.no_extras:
+    if args.extras or (not args.no_serve and not args.no_extras):
         log("extras: delay-filtered likelihood and map-making on the timed field")
         extras = extras_bench(vis, torch, fld, cfg, data, sigma)
 
