@@ -59,19 +59,6 @@ __device__ __forceinline__ void normals4(uint64_t seed, uint32_t stream, uint32_
   }
 }
 
-__device__ double block_sum(double v, double* red) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
-  __syncthreads();
-  for (int o = kHmcThreads / 2; o > 0; o >>= 1) {
-    if (tid < o) red[tid] += red[tid + o];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
-  return r;
-}
-
 // grad U at element i from the chi^2 gradient and the priors; adds the prior
 // part of U to acc_u.
 __device__ __forceinline__ float grad_potential(const HmcTask& T, int i, float q, double& acc_u) {
@@ -122,7 +109,9 @@ __device__ void block_sum_n(double v[N], double* lds) {
 // against checkpoints popcount(n >> 1) - ones + 1 .. popcount(n >> 1).  A span
 // with end momenta p_a, p_b and momentum sum r turns when
 // (M^-1 p_a).(r - (p_a + p_b)/2) <= 0 or (M^-1 p_b).(r - (p_a + p_b)/2) <= 0.
-// Only diagonal masses are supported here.
+// With dense gain mass blocks the velocities M^-1 p of the gain elements come
+// from k_hmc_gainblk's triangular solves and are stored for the trajectory
+// ends and the checkpoints (the elementwise kernels never form them).
 
 __device__ __forceinline__ int nuts_direction(const HmcTask& T, int j) {
   const uint4 x = philox10(make_uint4(static_cast<uint32_t>(j), T.traj, T.stream, 2u),
@@ -337,7 +326,7 @@ k_nuts_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict_
 // One block handles kHmcPerBlock consecutive parameters of one chain.
 __global__ void __launch_bounds__(kHmcThreads)
 k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__ blk0) {
-  __shared__ double red[kHmcThreads];
+  __shared__ double red[4 * 3];   // block_sum_n<3> wave totals
   const int k = find_task(blk0, ntask, blockIdx.x);
   const HmcTask T = tasks[k];
   const int lb = blockIdx.x - blk0[k];
@@ -390,9 +379,9 @@ k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__
     }
   }
   if (T.op & kOpRestore) return;
-  const double su = block_sum(acc_u, red);
-  const double sk = block_sum(acc_k, red);
-  const double sk0 = block_sum(acc_k0, red);
+  double sums[3] = {acc_u, acc_k, acc_k0};
+  block_sum_n<3>(sums, red);   // fixed order: wave butterflies, then the four wave totals
+  const double su = sums[0], sk = sums[1], sk0 = sums[2];
   if (threadIdx.x == 0) {
     if (T.op & (kOpPost | kOpInit)) T.part_u[lb] = su;
     if (T.op & kOpPost) T.part_k[lb] = sk;
@@ -749,7 +738,7 @@ __device__ void nuts_finalize(const HmcTask& T, double* lds) {
 // end of a trajectory, step-size adaptation.
 __global__ void __launch_bounds__(kHmcThreads)
 k_hmc_finalize(const HmcTask* __restrict__ tasks) {
-  __shared__ double red[kHmcThreads];
+  __shared__ double red[4 * 3];   // block_sum_n<3> wave totals
   __shared__ double red_n[4 * (kNutsDots + 3)];
   const HmcTask T = tasks[blockIdx.x];
   HmcState* st = T.st;
@@ -771,9 +760,11 @@ k_hmc_finalize(const HmcTask* __restrict__ tasks) {
       sk0 += T.part_k0g[f];
     }
   }
-  su = block_sum(su, red);
-  sk = block_sum(sk, red);
-  sk0 = block_sum(sk0, red);
+  double sums[3] = {su, sk, sk0};
+  block_sum_n<3>(sums, red);
+  su = sums[0];
+  sk = sums[1];
+  sk0 = sums[2];
   if (threadIdx.x != 0) return;
   const double u = 0.5 * st->chi2 + su;
   st->u = u;
