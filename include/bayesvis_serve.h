@@ -119,7 +119,8 @@ typedef struct {
 
 typedef struct {
   int64_t requests;            /* chi^2 + gradient requests completed */
-  double p50_ms, p99_ms, max_ms; /* request latency: tick enqueue -> result visible to the host */
+  double p10_ms, p50_ms, p90_ms, p99_ms, max_ms; /* request latency: tick enqueue -> result
+                                                   visible to the host; nearest-rank percentiles */
   int64_t arena_free_bytes;
   int32_t live_chains;
 } hmc_stats;

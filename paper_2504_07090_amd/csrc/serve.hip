@@ -778,7 +778,9 @@ vis_status hmc_server_stats(hmc_server* s, hmc_stats* out, int32_t reset) {
       return static_cast<double>(v[i]) * 1e-6;
     };
     out->requests = static_cast<int64_t>(s->n_requests);
+    out->p10_ms = pct(0.10);
     out->p50_ms = pct(0.50);
+    out->p90_ms = pct(0.90);
     out->p99_ms = pct(0.99);
     out->max_ms = v.empty() ? 0.0 : static_cast<double>(v.back()) * 1e-6;
     size_t used = 0;

@@ -42,8 +42,8 @@ class Result(C.Structure):
 
 
 class Stats(C.Structure):
-    _fields_ = [("requests", C.c_int64), ("p50_ms", C.c_double), ("p99_ms", C.c_double),
-                ("max_ms", C.c_double), ("arena_free_bytes", C.c_int64), ("live_chains", C.c_int32)]
+    _fields_ = [("requests", C.c_int64), ("p10_ms", C.c_double), ("p50_ms", C.c_double),
+                ("p90_ms", C.c_double), ("p99_ms", C.c_double), ("max_ms", C.c_double), ("arena_free_bytes", C.c_int64), ("live_chains", C.c_int32)]
 
 
 for _n in ("hmc_chain_footprint_bytes", "hmc_chain_footprint_dense_gain_bytes",

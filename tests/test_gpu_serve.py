@@ -421,7 +421,7 @@ def test_latency_stats_recorded(mods):
     srv.submit(c, 2)
     srv.wait(2)
     st = srv.stats()
-    assert st["requests"] == 1 + 2 * 3 and 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    assert st["requests"] == 1 + 2 * 3 and 0 < st["p10_ms"] <= st["p50_ms"] <= st["p90_ms"] <= st["p99_ms"] <= st["max_ms"]
     srv.close()
 
 
