@@ -19,7 +19,14 @@
 // v_mfma_f32_16x16x4_f32: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
 // D[i][j] in lane j + 16 (i / 4), register i % 4.  Operands come straight
 // from the small, cache-resident tables; K is unrolled so the loads of
-// several MFMAs are in flight together.
+// several MFMAs are in flight together.  The azimuthal stages, whose K runs
+// over 2 lmax + 1 or nphi, also issue the next batch's loads into a second
+// register set before the current batch's MFMAs (the loop is unrolled by two so
+// the sets swap roles without copies, and a scheduling barrier keeps the
+// batch's loads together); those loads use indices clamped into the tables and
+// are always issued (a load under a divergent branch is waited for where the
+// branch ends), and terms past the end of K are removed by zeroing one operand
+// at the MFMA.
 #include "objects.hpp"
 
 namespace bv {
@@ -106,8 +113,8 @@ k_sep_leg_fwd(int nz, int nf, int lmax, int blmax, int kaz, const float* __restr
 // 16 x 16 tiles (rows = channels, columns = pixels), so every operand load
 // feeds two MFMAs.
 __global__ void __launch_bounds__(64)
-k_sep_az_fwd(int nphi, int nf, int kaz, int nc, int toff, const float* __restrict__ Tt,
-             const float* __restrict__ G, const int* __restrict__ vidx, int nvp, float* __restrict__ img) {
+k_sep_az_fwd(int nphi, int nf, int kaz, int nc, int toff, const float* Tt,
+             const float* G, const int* __restrict__ vidx, int nvp, float* __restrict__ img) {
   const int k0 = blockIdx.x * 32, j = blockIdx.y, f0 = blockIdx.z * 32;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const float* grow[2];
@@ -122,24 +129,42 @@ k_sep_az_fwd(int nphi, int nf, int kaz, int nc, int toff, const float* __restric
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int g = 0; g < 2; ++g) acc[h][g] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int c0 = 0; c0 < nc; c0 += kSepStep) {
+  struct Batch {
     float a[kSepBatch][2], b[kSepBatch][2];
+  };
+  auto load = [&](int c0, Batch& B) {
 #pragma unroll
     for (int q = 0; q < kSepBatch; ++q) {
-      const int c = c0 + 4 * q + kk;
-      const bool ok = c < nc;
+      const int c = min(c0 + 4 * q + kk, nc - 1);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        a[q][h] = ok ? grow[h][static_cast<size_t>(c) * nf] : 0.f;
-        b[q][h] = ok ? tcol[h][static_cast<size_t>(c) * nphi] : 0.f;
+        B.a[q][h] = grow[h][static_cast<size_t>(c) * nf];
+        B.b[q][h] = tcol[h][static_cast<size_t>(c) * nphi];
       }
     }
+  };
+  auto mma = [&](int c0, const Batch& B) {
 #pragma unroll
-    for (int q = 0; q < kSepBatch; ++q)
+    for (int q = 0; q < kSepBatch; ++q) {
+      const bool ok = c0 + 4 * q + kk < nc;
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h) {
+        const float av = ok ? B.a[q][h] : 0.f;
 #pragma unroll
-        for (int g = 0; g < 2; ++g) acc[h][g] = sep_mfma(a[q][h], b[q][g], acc[h][g]);
+        for (int g = 0; g < 2; ++g) acc[h][g] = sep_mfma(av, B.b[q][g], acc[h][g]);
+      }
+    }
+  };
+  Batch B0, B1;
+  load(0, B0);
+  for (int c0 = 0; c0 < nc; c0 += 2 * kSepStep) {
+    load(c0 + kSepStep, B1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(c0, B0);
+    if (c0 + kSepStep >= nc) break;
+    load(c0 + 2 * kSepStep, B0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(c0 + kSepStep, B1);
   }
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
@@ -182,8 +207,8 @@ k_sep_scatter(int npix, int nf, int nvp, const int* __restrict__ vidx, const flo
 // grid (ceil(nc / 32), nz, ceil(nf / 32)); each wave computes a 2 x 2 block of
 // 16 x 16 tiles (rows = c, columns = channels).
 __global__ void __launch_bounds__(64)
-k_sep_az_adj(int nphi, int nf, int kaz, int nc, int kaz_t, int toff, const float* __restrict__ T,
-             const float* __restrict__ dfull, float* __restrict__ H) {
+k_sep_az_adj(int nphi, int nf, int kaz, int nc, int kaz_t, int toff, const float* T,
+             const float* dfull, float* __restrict__ H) {
   const int c0 = blockIdx.x * 32, j = blockIdx.y, f0 = blockIdx.z * 32;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const float* trow[2];
@@ -198,24 +223,42 @@ k_sep_az_adj(int nphi, int nf, int kaz, int nc, int kaz_t, int toff, const float
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int g = 0; g < 2; ++g) acc[h][g] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < nphi; k0 += kSepStep) {
+  struct Batch {
     float a[kSepBatch][2], b[kSepBatch][2];
+  };
+  auto load = [&](int k0, Batch& B) {
 #pragma unroll
     for (int q = 0; q < kSepBatch; ++q) {
-      const int k = k0 + 4 * q + kk;
-      const bool ok = k < nphi;
+      const int k = min(k0 + 4 * q + kk, nphi - 1);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        a[q][h] = ok ? trow[h][static_cast<size_t>(k) * kaz_t] : 0.f;
-        b[q][h] = ok ? drow[h][static_cast<size_t>(k) * nf] : 0.f;
+        B.a[q][h] = trow[h][static_cast<size_t>(k) * kaz_t];
+        B.b[q][h] = drow[h][static_cast<size_t>(k) * nf];
       }
     }
+  };
+  auto mma = [&](int k0, const Batch& B) {
 #pragma unroll
-    for (int q = 0; q < kSepBatch; ++q)
+    for (int q = 0; q < kSepBatch; ++q) {
+      const bool ok = k0 + 4 * q + kk < nphi;
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < 2; ++h) {
+        const float av = ok ? B.a[q][h] : 0.f;
 #pragma unroll
-        for (int g = 0; g < 2; ++g) acc[h][g] = sep_mfma(a[q][h], b[q][g], acc[h][g]);
+        for (int g = 0; g < 2; ++g) acc[h][g] = sep_mfma(av, B.b[q][g], acc[h][g]);
+      }
+    }
+  };
+  Batch B0, B1;
+  load(0, B0);
+  for (int k0 = 0; k0 < nphi; k0 += 2 * kSepStep) {
+    load(k0 + kSepStep, B1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(k0, B0);
+    if (k0 + kSepStep >= nphi) break;
+    load(k0 + 2 * kSepStep, B0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(k0 + kSepStep, B1);
   }
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
