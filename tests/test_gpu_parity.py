@@ -400,6 +400,32 @@ def test_separable_lmax_prefix_and_hex7(vis):
         assert np.all(err <= 1e-5)
 
 
+def test_separable_ragged_grid_gradient(vis):
+    """A 24 x 80 grid: 80 columns are 2.5 K batches of the azimuthal adjoint and
+    2 l max + 1 = 23 rows one partial batch of the forward, so both stages end
+    on a batch that is cut short."""
+    cfg = w.scaled(w.C0, grid_nz=24, grid_nphi=80, lmax=11, n_freq=3, n_time=2)
+    basis, fld = _sep_field(vis, cfg)
+    d = w.draw(cfg)
+    of = model.Field(cfg)
+    ref = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg))
+    alm, g, fw = _dev_params(d, cfg)
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    err = chan_rel_err(m, ref)
+    rng = np.random.default_rng(5)
+    sig = 0.05 * float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+    data = ref + sig * (rng.normal(size=ref.shape) + 1j * rng.normal(size=ref.shape)) / np.sqrt(2)
+    alm, g, fw = _dev_params(d, cfg, alm_scale=1.2)
+    x2, ga, gg, gf = vis.chi2_and_grad(fld, torch.tensor(data, dtype=torch.complex64, device="cuda"),
+                                       sig, alm, g, fw)
+    rx2, rga, rgg, rgf = model.chi2_and_grad(of, data, sig, d.alm * 1.2, d.gains, w.fwhm_ref_rad(cfg))
+    e = [rel_norm(ga.cpu().numpy(), rga), rel_norm(gg.cpu().numpy(), rgg),
+         abs(float(gf) - rgf) / abs(rgf), abs(float(x2) - rx2) / rx2]
+    say("separable 24x80 forward err", err, "grad errs (a, g, F, chi2)", e)
+    assert np.all(err <= 1e-5)
+    assert max(e) <= 2e-4
+
+
 def test_separable_rejected_without_tables_or_in_split_precision(vis, c0):
     cfg, basis, *_ = c0     # FP32 Y only, no factor tables
     with pytest.raises(vis.VisError):
