@@ -216,6 +216,12 @@ def test_invalid_inputs_raise(vis, c0):
     with pytest.raises(vis.VisError):
         e = w.lattice_basis(cfg)
         vis.Field(basis, [[0, 0], [1, 0]], e[0], e[1], [150e6], [0.0], -0.5, 5, precision=4)
+    # empty and degenerate descriptors: no channel, no time, a single dish (no baseline)
+    e = w.lattice_basis(cfg)
+    for ants, fr, ls in [([[0, 0], [1, 0]], [], [0.0]), ([[0, 0], [1, 0]], [150e6], []),
+                         ([[0, 0]], [150e6], [0.0])]:
+        with pytest.raises(vis.VisError):
+            vis.Field(basis, ants, e[0], e[1], fr, ls, -0.5, 5)
 
 
 @pytest.fixture(scope="module")
