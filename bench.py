@@ -61,7 +61,7 @@ TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
     "sha256": "64639fd89d2bea6ee57daf0b53523afbee1529fd561d8a9cb80993c37db3e148",
-    "bytes_per_launch": {"k_fringe_adj": 199670059, "k_fringe_fwd": 271919661},
+    "bytes_per_launch": {"k_fringe_adj": 199359155, "k_fringe_fwd": 271652732},
 }
 
 

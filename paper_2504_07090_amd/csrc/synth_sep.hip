@@ -37,6 +37,34 @@ __device__ __forceinline__ f4 sep_mfma(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Blocks are dealt round-robin over the 8 XCDs (block b to XCD b % 8).  The
+// block's linear index is mapped to a logical one such that each XCD runs one
+// contiguous range of logical blocks (the tail that does not fill all eight
+// keeps its index): a bijection on [0, blocks).  Each stage decodes the
+// logical index with the blocks that share operand rows adjacent, so those
+// rows come from one XCD's L2 instead of being fetched once per XCD (the
+// forward Legendre stage keeps the launch order).
+__device__ __forceinline__ int sep_xcd_logical() {
+  const int total = gridDim.x * gridDim.y * gridDim.z;
+  const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int per = total / 8;
+  return b >= 8 * per ? b : (b % 8) * per + b / 8;
+}
+
+// (x, y, z) block coordinates of logical block L with y and z fastest (the
+// Legendre stages: every block of one m shares that m's table rows).
+__device__ __forceinline__ int3 sep_blocks_m_major(int L) {
+  const int nyz = gridDim.y * gridDim.z, yz = L % nyz;
+  return make_int3(L / nyz, yz % gridDim.y, yz / gridDim.y);
+}
+
+// (x, y, z) of logical block L with x fastest (the azimuthal stages: the
+// column or c tiles of one ring and channel tile share that ring's rows).
+__device__ __forceinline__ int3 sep_blocks_x_fastest(int L) {
+  const int yz = L / gridDim.x;
+  return make_int3(L % gridDim.x, yz % gridDim.y, yz / gridDim.y);
+}
+
 constexpr int kSepBatch = 8;              // MFMAs whose operand loads are issued together
 constexpr int kSepStep = 4 * kSepBatch;   // K covered per batch
 
@@ -76,6 +104,9 @@ k_alm_transpose(int nf, int nm, const float* __restrict__ a, float* __restrict__
 __global__ void __launch_bounds__(64)
 k_sep_leg_fwd(int nz, int nf, int lmax, int blmax, int kaz, const float* __restrict__ lam,
               const int* __restrict__ loff, const float* __restrict__ at, float* __restrict__ G) {
+  // blocks in launch order: grouping an m's blocks on one XCD, as the adjoint
+  // does, measured slower here (the rows shorten with |m|, so contiguous m
+  // ranges leave the XCDs unevenly loaded)
   const int m = static_cast<int>(blockIdx.x) - lmax, am = m < 0 ? -m : m;
   const int j0 = blockIdx.y * 16, f0 = blockIdx.z * 16;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
@@ -115,7 +146,8 @@ k_sep_leg_fwd(int nz, int nf, int lmax, int blmax, int kaz, const float* __restr
 __global__ void __launch_bounds__(64)
 k_sep_az_fwd(int nphi, int nf, int kaz, int nc, int toff, const float* Tt,
              const float* G, const int* __restrict__ vidx, int nvp, float* __restrict__ img) {
-  const int k0 = blockIdx.x * 32, j = blockIdx.y, f0 = blockIdx.z * 32;
+  const int3 bk = sep_blocks_x_fastest(sep_xcd_logical());
+  const int k0 = bk.x * 32, j = bk.y, f0 = bk.z * 32;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const float* grow[2];
   const float* tcol[2];
@@ -209,7 +241,8 @@ k_sep_scatter(int npix, int nf, int nvp, const int* __restrict__ vidx, const flo
 __global__ void __launch_bounds__(64)
 k_sep_az_adj(int nphi, int nf, int kaz, int nc, int kaz_t, int toff, const float* T,
              const float* dfull, float* __restrict__ H) {
-  const int c0 = blockIdx.x * 32, j = blockIdx.y, f0 = blockIdx.z * 32;
+  const int3 bk = sep_blocks_x_fastest(sep_xcd_logical());
+  const int c0 = bk.x * 32, j = bk.y, f0 = bk.z * 32;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const float* trow[2];
   const float* drow[2];
@@ -280,8 +313,9 @@ k_sep_az_adj(int nphi, int nf, int kaz, int nc, int kaz_t, int toff, const float
 __global__ void __launch_bounds__(64)
 k_sep_leg_adj(int nz, int nf, int nm, int lmax, int blmax, int kaz, const float* __restrict__ lam,
               const int* __restrict__ loff, const float* __restrict__ H, float* __restrict__ grad) {
-  const int m = static_cast<int>(blockIdx.x) - lmax, am = m < 0 ? -m : m;
-  const int l0 = am + 16 * static_cast<int>(blockIdx.y), f0 = blockIdx.z * 16;
+  const int3 bk = sep_blocks_m_major(sep_xcd_logical());
+  const int m = bk.x - lmax, am = m < 0 ? -m : m;
+  const int l0 = am + 16 * bk.y, f0 = bk.z * 16;
   if (l0 > lmax) return;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const int l = min(l0 + i, lmax), f = min(f0 + i, nf - 1);
