@@ -15,6 +15,12 @@ One trajectory is L leapfrog steps of size eps,
 followed by a Metropolis test accepting with probability min(1, exp(H0 - H1)),
 H = U + K.
 
+App. B, step-size adaptation: after each trajectory the step size eps is
+divided by 1.2 when the trajectory's acceptance probability falls below 0.2,
+and otherwise multiplied by 1.2 but never beyond the originally tuned eps0;
+it carries over from one trajectory to the next (``adapt_step``,
+``run_chain``).
+
 The potential (Sec. 2.3, eq. posterior) is
     U = chi^2 / 2 + sum a^2 / (2 C) + sum |g - 1|^2 / (2 s_g^2 / 2),
 a Gaussian prior of variance C(l, nu) on every sky coefficient, a Gaussian
@@ -176,6 +182,46 @@ def trajectory(q0: np.ndarray, u0: float, grad0: np.ndarray, eps: float, n_steps
     return q0, u0, grad0, False, h0, h1
 
 
+def accept_probability(h0: float, h1: float) -> float:
+    """min(1, exp(H0 - H1)); 0 for a non-finite energy (a divergence)."""
+    if not (math.isfinite(h0) and math.isfinite(h1)):
+        return 0.0
+    return math.exp(min(0.0, h0 - h1))
+
+
+def adapt_step(eps: float, eps0: float, accept_prob: float, threshold: float = 0.2,
+               factor: float = 1.2) -> float:
+    """App. B, step-size adaptation: a trajectory whose acceptance probability is
+    below the threshold shrinks the step, eps / 1.2; any other grows it,
+    min(eps0, 1.2 eps).  Reading: "below" is strict, so a probability equal to
+    the threshold grows the step."""
+    if accept_prob < threshold:
+        return eps / factor
+    return min(eps0, factor * eps)
+
+
+def run_chain(q0: np.ndarray, eps0: float, n_steps: int, minv, potential_and_grad: Callable,
+              seed: int, stream: int, n_traj: int, adapt: bool = True,
+              normal_index: np.ndarray = None):
+    """n_traj consecutive HMC transitions from q0 (trajectory indices 0 .. n_traj-1 of
+    the Philox stream), the step adapted after each one when ``adapt`` (App. B).
+    Returns (q, U, grad, records); record k holds the step size trajectory k used,
+    its acceptance probability, the accept decision, H0 and H1."""
+    mass = _as_mass(minv)
+    q = np.asarray(q0, dtype=np.float64)
+    u, g = potential_and_grad(q)
+    eps = eps0
+    recs = []
+    for t in range(n_traj):
+        q, u, g, acc, h0, h1 = trajectory(q, u, g, eps, n_steps, mass, potential_and_grad,
+                                          seed, stream, t, normal_index)
+        prob = accept_probability(h0, h1)
+        recs.append({"eps": eps, "accept_prob": prob, "accepted": acc, "h0": h0, "h1": h1})
+        if adapt:
+            eps = adapt_step(eps, eps0, prob)
+    return q, u, g, recs
+
+
 def gain_gauss_newton_blocks(field: model.Field, alm: np.ndarray, gains: np.ndarray,
                              fwhm: float, sigma_n: float) -> np.ndarray:
     """Per-channel Gauss-Newton Hessian of chi^2 / 2 in the real gain components,
@@ -198,6 +244,55 @@ def gain_gauss_newton_blocks(field: model.Field, alm: np.ndarray, gains: np.ndar
         j = np.stack(cols, axis=1)
         out[f] = (j.conj().T @ j).real / sigma_n ** 2
     return out
+
+
+def hutchinson_probe(shape, seed: int, probe: int) -> np.ndarray:
+    """Complex probe z[t][nu][bl] with unit-variance real and imaginary parts:
+    visibility v (row-major index) takes normals 2v (real) and 2v + 1 (imaginary)
+    of the Philox stream (seed, stream 0, traj = probe, purpose 5)."""
+    n = int(np.prod(shape))
+    x = philox.normals(2 * n, seed, 0, probe, purpose=5)
+    return (x[0::2] + 1j * x[1::2]).reshape(shape)
+
+
+def gauss_newton_diag(field: model.Field, alm: np.ndarray, gains: np.ndarray, fwhm: float,
+                      sigma_n: float, n_probes: int, seed: int) -> np.ndarray:
+    """Diagonal of the Gauss-Newton Hessian of chi^2 / 2, diag(J^T J) / sigma_n^2,
+    with J the Jacobian of the real and imaginary parts of the model visibilities
+    (Sec. 4.2 and App. B: the mass matrix approximates the posterior Hessian).
+    Sky coefficients and F: the Hutchinson estimate mean_k (J^T z_k)^2, z_k the
+    Philox probes of ``hutchinson_probe`` (E[z z^T] = I, so the mean tends to the
+    diagonal); J^T z is the adjoint of the model with cotangent z.  Gains: the
+    exact diagonal, for either real component of g_i,
+        sum over baselines (i, j) and times of |g_j|^2 |V_ij|^2,
+    V the visibility without gains.  Returned in the oracle's parameter layout."""
+    c = field.cfg
+    shape = (c.n_time, c.n_freq, field.n_ant * (field.n_ant - 1) // 2)
+    acc = np.zeros(c.n_freq * c.n_modes + 2 * c.n_freq * field.n_ant + 1)
+    for k in range(n_probes):
+        z = hutchinson_probe(shape, seed, k)
+        ga, gg, gf = model.adjoint(field, alm, gains, fwhm, z)
+        v = pack(ga, gg, gf)
+        acc += v * v
+    h = acc / n_probes / sigma_n ** 2
+    _, v, _ = model.forward(field, alm, gains, fwhm, return_parts=True)
+    v2 = np.sum(np.abs(v) ** 2, axis=0)                         # [nu][bl], summed over times
+    g2 = np.abs(gains) ** 2
+    hg = np.zeros((c.n_freq, field.n_ant))
+    for b, (i, j) in enumerate(field.pairs):
+        hg[:, i] += g2[:, j] * v2[:, b]
+        hg[:, j] += g2[:, i] * v2[:, b]
+    na = c.n_freq * c.n_modes
+    h[na:na + 2 * c.n_freq * field.n_ant] = np.repeat(hg.ravel(), 2) / sigma_n ** 2
+    return h
+
+
+def prior_precision_diag(alm_var: np.ndarray, n_ant: int, gain_scatter: float) -> np.ndarray:
+    """Diagonal of the prior's contribution to the Hessian of U: 1 / C for every
+    sky coefficient, 2 / s_g^2 for every real gain component, 0 for F (flat)."""
+    nf = alm_var.shape[0]
+    return np.concatenate([1.0 / alm_var.ravel(),
+                           np.full(2 * nf * n_ant, 2.0 / gain_scatter ** 2), [0.0]])
 
 
 def gain_block_mass(minv: np.ndarray, chol: np.ndarray, goff: int) -> BlockMass:

@@ -35,6 +35,8 @@ plainly over a stored trajectory (every state kept; no checkpoint tricks):
   max_depth doublings, ends it.
 * The chain moves to the proposal (there is no separate Metropolis test).
   The adaptation statistic is the mean over all leaves of min(1, exp(H0 - H)).
+* App. B's step-size adaptation (``hmc.adapt_step``) takes that mean as the
+  trajectory's acceptance probability (``run_chain``).
 """
 from __future__ import annotations
 
@@ -154,3 +156,24 @@ def trajectory(q0: np.ndarray, u0: float, g0: np.ndarray, eps: float, max_depth:
     moved = prop.q is not q0
     return Result(prop.q, prop.u, prop.g, h0, prop.h, moved, n_steps, depth,
                   float(np.mean(acc)) if acc else 0.0, reason)
+
+
+def run_chain(q0: np.ndarray, eps0: float, max_depth: int, minv, potential_and_grad: Callable,
+              seed: int, stream: int, n_traj: int, adapt: bool = True,
+              normal_index: np.ndarray = None):
+    """n_traj consecutive NUTS transitions from q0 (trajectory indices 0 .. n_traj-1),
+    the step adapted after each one when ``adapt`` (App. B), with the mean over the
+    leaves of min(1, exp(H0 - H)) as the acceptance probability.  Returns
+    (q, U, grad, records): the step size each trajectory used and its Result."""
+    q = np.asarray(q0, dtype=np.float64)
+    u, g = potential_and_grad(q)
+    eps = eps0
+    recs = []
+    for t in range(n_traj):
+        r = trajectory(q, u, g, eps, max_depth, minv, potential_and_grad, seed, stream, t,
+                       normal_index)
+        recs.append({"eps": eps, "result": r})
+        q, u, g = r.q, r.u, r.g
+        if adapt:
+            eps = hmc.adapt_step(eps, eps0, r.accept_stat)
+    return q, u, g, recs

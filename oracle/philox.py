@@ -46,12 +46,14 @@ def unit_open(x: int) -> float:
     return (x + 0.5) * 2.0 ** -32
 
 
-def normals(n: int, seed: int, stream: int, traj: int) -> np.ndarray:
-    """n standard normals; block k uses counter (k, traj, stream, 0), key (seed lo, seed hi)."""
+def normals(n: int, seed: int, stream: int, traj: int, purpose: int = 0) -> np.ndarray:
+    """n standard normals; block k uses counter (k, traj, stream, purpose), key
+    (seed lo, seed hi).  Purpose 0 draws HMC momenta; purpose 5 draws the probe
+    vectors of the Hutchinson mass-matrix estimate (``traj`` = probe index)."""
     key = (seed & MASK, (seed >> 32) & MASK)
     out = np.empty(4 * ((n + 3) // 4))
     for k in range(len(out) // 4):
-        x = philox4x32_10((k, traj, stream, 0), key)
+        x = philox4x32_10((k, traj, stream, purpose), key)
         for h in range(2):
             u1, u2 = unit_open(x[2 * h]), unit_open(x[2 * h + 1])
             r = math.sqrt(-2.0 * math.log(u1))

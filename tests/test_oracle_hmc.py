@@ -37,8 +37,7 @@ def test_leapfrog_harmonic_oscillator_closed_form():
     assert abs(p1[0] - (-eps * k * (1 - eps * eps * k / 4) * q0[0] + a * p0[0])) < 1e-15
 
 
-@pytest.fixture(scope="module")
-def tiny_posterior():
+def _tiny():
     cfg = w.scaled(w.C0, lmax=2, n_freq=2, n_time=2, grid_nz=16, grid_nphi=48)
     f = model.Field(cfg)
     d = w.draw(cfg)
@@ -54,6 +53,11 @@ def tiny_posterior():
         qp[i] += h
         hdiag[i] = (post.potential_and_grad(qp)[1][i] - g0[i]) / h
     return post, q0, 1.0 / hdiag
+
+
+@pytest.fixture(scope="module")
+def tiny_posterior():
+    return _tiny()
 
 
 def test_posterior_gradient_fd(tiny_posterior):
@@ -256,3 +260,160 @@ def test_planted_transposed_draw_is_caught(monkeypatch):
     monkeypatch.setattr(hmc.BlockMass, "draw", draw)
     with pytest.raises(AssertionError):
         test_block_mass_momentum_covariance()
+
+
+# ---- step-size adaptation (App. B) ----
+
+def test_adapt_step_scripted_sequence():
+    """App. B: below 0.2 acceptance the step shrinks to eps / 1.2; otherwise it
+    grows to 1.2 eps but never past the originally tuned eps0.  A scripted
+    sequence of acceptance probabilities gives these steps, written out by hand
+    from the rule with eps0 = 1."""
+    probs = [0.05, 0.1, 0.5, 0.7, 0.9, 0.19, 0.2, 0.0]
+    expect = [1 / 1.2, 1 / 1.44, 1 / 1.2, 1.0, 1.0, 1 / 1.2, 1.0, 1 / 1.2]
+    eps, got = 1.0, []
+    for a in probs:
+        eps = hmc.adapt_step(eps, 1.0, a)
+        got.append(eps)
+    assert np.max(np.abs(np.array(got) - np.array(expect))) <= 1e-15
+
+
+def test_run_chain_matches_oscillator_closed_form():
+    """Adapted HMC on a 40-dimensional unit oscillator U = |q|^2 / 2 with unit
+    mass: every trajectory of n leapfrog steps is the n-th power of the 2 x 2
+    leapfrog matrix [[1 - e^2/2, e], [-e (1 - e^2/4), 1 - e^2/2]] applied to
+    each (q_i, p_i); the acceptance probability, Metropolis decision and next
+    step follow from the closed form.  The run shrinks the step twice, grows it
+    and reaches the eps0 cap, so both branches of the rule are exercised."""
+    d, eps0, n, seed, stream = 40, 1.4, 3, 3, 1
+    pg = lambda q: (0.5 * float(q @ q), q.copy())
+    q0 = np.linspace(-1.0, 1.0, d)
+    _, _, _, recs = hmc.run_chain(q0, eps0, n, np.ones(d), pg, seed, stream, 8)
+    q, eps = q0.copy(), eps0
+    shrunk = grown = 0
+    for t, r in enumerate(recs):
+        p = philox.normals(d, seed, stream, t)
+        m = np.array([[1 - eps ** 2 / 2, eps], [-eps * (1 - eps ** 2 / 4), 1 - eps ** 2 / 2]])
+        mn = np.linalg.matrix_power(m, n)
+        q1 = mn[0, 0] * q + mn[0, 1] * p
+        p1 = mn[1, 0] * q + mn[1, 1] * p
+        h0 = 0.5 * (q @ q + p @ p)
+        h1 = 0.5 * (q1 @ q1 + p1 @ p1)
+        prob = min(1.0, math.exp(h0 - h1))
+        acc = philox.accept_uniform(seed, stream, t) < prob
+        assert r["eps"] == pytest.approx(eps, rel=1e-14)
+        assert r["h0"] == pytest.approx(h0, rel=1e-12) and r["h1"] == pytest.approx(h1, rel=1e-12)
+        assert r["accept_prob"] == pytest.approx(prob, rel=1e-10, abs=1e-300)
+        assert r["accepted"] == acc
+        if acc:
+            q = q1
+        if prob < 0.2:
+            eps, shrunk = eps / 1.2, shrunk + 1
+        else:
+            eps, grown = min(eps0, 1.2 * eps), grown + 1
+    assert shrunk >= 2 and grown >= 2
+    assert any(r["eps"] < eps0 / 1.3 for r in recs)
+
+
+def test_nuts_run_chain_chains_states_and_adapts():
+    """NUTS with adaptation: each trajectory starts where the previous one ended,
+    and its step is the App. B update of the previous step with the previous
+    trajectory's mean leaf acceptance as the acceptance probability."""
+    from oracle import nuts
+    d = 10
+    pg = lambda q: (0.5 * float(q @ q), q.copy())
+    q0 = np.linspace(-1.0, 1.0, d)
+    eps0 = 1.6
+    _, _, _, recs = nuts.run_chain(q0, eps0, 4, np.ones(d), pg, 7, 2, 6)
+    q, eps = q0, eps0
+    branches = set()
+    for t, rec in enumerate(recs):
+        u, g = pg(q)
+        ref = nuts.trajectory(q, u, g, eps, 4, np.ones(d), pg, 7, 2, t)
+        assert rec["eps"] == eps
+        assert rec["result"].accept_stat == ref.accept_stat and np.array_equal(rec["result"].q, ref.q)
+        branches.add(ref.accept_stat < 0.2)
+        eps = eps / 1.2 if ref.accept_stat < 0.2 else min(eps0, 1.2 * eps)
+        q = ref.q
+    assert branches == {True, False}
+
+
+def test_planted_grow_on_reject_is_caught(monkeypatch):
+    """Multiplying by 1.2 after a poor trajectory (and dividing after a good one)
+    breaks the scripted-sequence pin; so does dropping the eps0 cap."""
+    monkeypatch.setattr(hmc, "adapt_step",
+                        lambda eps, eps0, a, threshold=0.2, factor=1.2:
+                        min(eps0, eps * factor) if a < threshold else eps / factor)
+    with pytest.raises(AssertionError):
+        test_adapt_step_scripted_sequence()
+    monkeypatch.setattr(hmc, "adapt_step",
+                        lambda eps, eps0, a, threshold=0.2, factor=1.2:
+                        eps / factor if a < threshold else factor * eps)
+    with pytest.raises(AssertionError):
+        test_adapt_step_scripted_sequence()
+
+
+# ---- diagonal mass matrix: Gauss-Newton diagonal (Sec. 4.2, App. B) ----
+
+def _exact_jtj_diag(post, q0):
+    """diag(J^T J) from the explicit Jacobian: the model is linear in every sky
+    coefficient (column = model of a unit coefficient, gains and F fixed) and F
+    takes a central difference (O(h^2) error)."""
+    f = post.field
+    nf, nm, na = post.shape
+    alm, gains, fw = hmc.unpack(q0, nf, nm, na)
+    out = np.empty(nf * nm + 1)
+    for k in range(nf * nm):
+        e = np.zeros(nf * nm)
+        e[k] = 1.0
+        col = model.forward(f, e.reshape(nf, nm), gains, fw)
+        out[k] = np.sum(np.abs(col) ** 2)
+    h = 1e-5 * fw
+    col = (model.forward(f, alm, gains, fw + h) - model.forward(f, alm, gains, fw - h)) / (2 * h)
+    out[-1] = np.sum(np.abs(col) ** 2)
+    return out
+
+
+def test_gauss_newton_diag_gains_equal_dense_block_diagonal(tiny_posterior):
+    """The closed-form gain entries equal the diagonals of the Gauss-Newton gain
+    blocks, whose Jacobian comes from central differences of the forward model."""
+    post, q0, _ = tiny_posterior
+    nf, nm, na = post.shape
+    alm, gains, fw = hmc.unpack(q0, nf, nm, na)
+    h = hmc.gauss_newton_diag(post.field, alm, gains, fw, post.sigma_n, 1, seed=3)
+    blocks = hmc.gain_gauss_newton_blocks(post.field, alm, gains, fw, post.sigma_n)
+    ref = np.concatenate([np.diag(b) for b in blocks])
+    got = h[nf * nm:nf * nm + 2 * nf * na]
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(ref)
+
+
+def test_gauss_newton_diag_hutchinson_converges(tiny_posterior):
+    """With K Gaussian probes each sky / F entry is the mean of K draws of
+    (J^T z)^2 ~ (J^T J)_kk chi^2_1, so it lies within a few sqrt(2 / K) of the
+    exact diagonal; the mean ratio over the 19 entries is tighter."""
+    post, q0, _ = tiny_posterior
+    nf, nm, na = post.shape
+    alm, gains, fw = hmc.unpack(q0, nf, nm, na)
+    k = 400
+    h = hmc.gauss_newton_diag(post.field, alm, gains, fw, post.sigma_n, k, seed=11)
+    est = np.concatenate([h[:nf * nm], h[-1:]]) * post.sigma_n ** 2
+    ratio = est / _exact_jtj_diag(post, q0)
+    sd = math.sqrt(2.0 / k)
+    assert np.max(np.abs(ratio - 1)) < 5 * sd
+    assert abs(np.mean(ratio) - 1) < 2.5 * sd
+
+
+def test_planted_real_only_probe_is_caught(monkeypatch):
+    """Probes without an imaginary part see only half of J^T J: the Hutchinson pin fails."""
+    orig = hmc.hutchinson_probe
+    monkeypatch.setattr(hmc, "hutchinson_probe",
+                        lambda shape, seed, probe: orig(shape, seed, probe).real + 0j)
+    with pytest.raises(AssertionError):
+        test_gauss_newton_diag_hutchinson_converges(_tiny())
+
+
+def test_prior_precision_diag():
+    var = np.array([[2.0, 4.0], [0.5, 1.0]])
+    p = hmc.prior_precision_diag(var, 3, 0.05)
+    assert np.allclose(p[:4], [0.5, 0.25, 2.0, 1.0])
+    assert np.allclose(p[4:16], 2.0 / 0.05 ** 2) and p[-1] == 0.0 and p.size == 17
