@@ -220,11 +220,8 @@ def make_chain(vis, serve, torch, basis, cfg, prec, synthesis=0):
                                                       device="cuda")).contiguous()
     del m
     lay = serve.Layout(fld)
-    h = serve.diag_hessian(fld, alm, g, fw, sigma, n_probes=16)
     cvar = torch.tensor(d.alm_var, dtype=torch.float32, device="cuda")
-    h[:lay.nalm] += 1.0 / cvar.reshape(-1).double()
-    h[lay.goff:lay.goff + lay.ngain] += 2.0 / cfg.gain_scatter ** 2
-    minv = (1.0 / h).float().contiguous()
+    _, minv = serve.mass_diag(fld, alm, g, fw, sigma, cvar, cfg.gain_scatter, n_probes=16)
     # start slightly off the truth: 1% of the prior width
     gen = torch.Generator(device="cuda")
     gen.manual_seed(cfg.seed)
@@ -269,8 +266,8 @@ def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=
     if dense_gains:
         for c, ((cfg, _, data, sigma, q0, minv, cvar), fld) in enumerate(zip(inputs, flds)):
             alm, g, fw = serve.Layout(fld).unpack(q0)
-            chols[c] = serve.gain_mass_chol(fld, alm.contiguous(), g.contiguous(), fw.contiguous(),
-                                            sigma, cfg.gain_scatter)
+            chols[c] = serve.gain_mass_blocks(fld, alm.contiguous(), g.contiguous(),
+                                              fw.contiguous(), sigma, cfg.gain_scatter)
     fp = sum(serve.Server.footprint(f, dense_gains, nuts_depth > 0) for f in flds)
     srv = serve.Server(fp + (64 << 20), max_chains=n_chains, max_batch=max_batch,
                        batched=1 if max_batch > 1 else 0)

@@ -11,6 +11,56 @@
 extern "C" {
 #endif
 
+/* ------------------------------------------------------ mass matrices --
+ * Set-up of a chain's mass matrix (Sec. 4.2: the sampler is preconditioned
+ * with an approximation of the Hessian of -log posterior; App. B: only the
+ * Cholesky factor of a dense mass is needed).  The likelihood part is the
+ * Gauss-Newton Hessian of U = chi^2 / 2, J^T J / sigma_n^2, with J the
+ * Jacobian of the real and imaginary parts of the model visibilities of
+ * vis_forward at (alm, gains, fwhm); the prior adds 1 / C for each sky
+ * coefficient (alm_prior_var C, may be NULL for none), 2 / s_g^2 for each real
+ * gain component (gain_prior_sigma s_g, 0 for none) and nothing for the flat F.
+ * All pointers are device pointers in the layouts of bayesvis.h; `work` is
+ * device scratch of at least hmc_mass_work_bytes(field) bytes owned by the
+ * caller (not kept between calls).  The field's evaluation scratch is used,
+ * so the calls are ordered with the field's other evaluations on `stream`.
+ * Nothing is synchronised.  VIS_EINVAL: null pointers, sigma_n not positive
+ * and finite, gain_prior_sigma negative; VIS_ENOMEM: work too small.       */
+vis_status hmc_mass_work_bytes(const vis_field* field, size_t* bytes);
+
+/* hmc_mass_diag: the diagonal h of the Gauss-Newton Hessian plus the prior
+ * precision, and minv = 1 / h, both device float arrays in the server's
+ * parameter layout (hmc_chain_init; padding entries get h = minv = 1); either
+ * output may be NULL.  Sky coefficients and F take the Hutchinson estimate
+ * mean_k (J^T z_k)^2 / sigma_n^2 over n_probes (1 .. 4096) complex probes
+ * z_k with unit normal real and imaginary parts: probe k of visibility v
+ * (row-major [n_time][n_freq][n_bl]) takes normals 2v, 2v + 1 of the Philox
+ * stream with counter (v / 2, k, 0, 5) and key = seed (Box-Muller as for the
+ * momenta); J^T z_k is the vis_adjoint pass with cotangent z_k.  The gains
+ * take the exact diagonal: for both real components of g_a(nu),
+ * sum over baselines (a, b) and times of |g_b|^2 |V_ab|^2 / sigma_n^2, V the
+ * visibility without gains.  Accumulated in FP64.                          */
+vis_status hmc_mass_diag(const vis_field* field, const float* alm, const vis_c64* gains,
+                         const float* fwhm, float sigma_n, const float* alm_prior_var,
+                         float gain_prior_sigma, int32_t n_probes, uint64_t seed, float* hdiag,
+                         float* minv, void* work, size_t work_bytes, void* stream);
+
+/* hmc_gain_mass_blocks: per channel nu the dense Gauss-Newton block of the
+ * gains (components in layout order Re g_0, Im g_0, Re g_1, ...) plus
+ * 2 / s_g^2 I, M_nu = H_nu + 2 / s_g^2 I, and its lower Cholesky factor
+ * M_nu = L_nu L_nu^T, written to chol [n_freq][2 n_ant][2 n_ant] (float,
+ * row-major, zero above the diagonal) as hmc_chain_init.gain_chol expects.
+ * For baseline (i, j) and w = g_i g_j sum_t |V_ij|^2 / sigma_n^2:
+ * H[Re g_i][Re g_j] = Re w, H[Im g_i][Im g_j] = -Re w,
+ * H[Re g_i][Im g_j] = H[Im g_i][Re g_j] = Im w (symmetric), the diagonal as in
+ * hmc_mass_diag.  Assembled and factored in FP64 on the device, one workgroup
+ * per channel; a non-positive pivot (only with gain_prior_sigma = 0 and a
+ * degenerate field, or non-finite inputs) leaves NaN in that channel's factor,
+ * which hmc_chain_admit then refuses.  VIS_EINVAL also: 2 n_ant > 256.       */
+vis_status hmc_gain_mass_blocks(const vis_field* field, const float* alm, const vis_c64* gains,
+                                const float* fwhm, float sigma_n, float gain_prior_sigma,
+                                float* chol, void* work, size_t work_bytes, void* stream);
+
 /* ------------------------------------------------------------- serving --
  * Continuous-batching HMC server (Sec. 4.2, App. B with a diagonal mass
  * matrix, optionally with dense per-channel gain blocks; fixed-length

@@ -206,7 +206,8 @@ def run_chain(q0: np.ndarray, eps0: float, n_steps: int, minv, potential_and_gra
     """n_traj consecutive HMC transitions from q0 (trajectory indices 0 .. n_traj-1 of
     the Philox stream), the step adapted after each one when ``adapt`` (App. B).
     Returns (q, U, grad, records); record k holds the step size trajectory k used,
-    its acceptance probability, the accept decision, H0 and H1."""
+    its acceptance probability, the accept decision, H0, H1 and the position
+    after the transition."""
     mass = _as_mass(minv)
     q = np.asarray(q0, dtype=np.float64)
     u, g = potential_and_grad(q)
@@ -216,7 +217,8 @@ def run_chain(q0: np.ndarray, eps0: float, n_steps: int, minv, potential_and_gra
         q, u, g, acc, h0, h1 = trajectory(q, u, g, eps, n_steps, mass, potential_and_grad,
                                           seed, stream, t, normal_index)
         prob = accept_probability(h0, h1)
-        recs.append({"eps": eps, "accept_prob": prob, "accepted": acc, "h0": h0, "h1": h1})
+        recs.append({"eps": eps, "accept_prob": prob, "accepted": acc, "h0": h0, "h1": h1,
+                     "q": q.copy()})
         if adapt:
             eps = adapt_step(eps, eps0, prob)
     return q, u, g, recs

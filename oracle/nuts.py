@@ -78,9 +78,15 @@ class State:
     h: float
 
 
-def turns(mass, p_a: np.ndarray, p_b: np.ndarray, rho: np.ndarray) -> bool:
+def turns(mass, p_a: np.ndarray, p_b: np.ndarray, rho: np.ndarray, margins=None) -> bool:
     adj = rho - 0.5 * (p_a + p_b)
-    return float(mass.velocity(p_a) @ adj) <= 0.0 or float(mass.velocity(p_b) @ adj) <= 0.0
+    va, vb = mass.velocity(p_a), mass.velocity(p_b)
+    da, db = float(va @ adj), float(vb @ adj)
+    if margins is not None:
+        na = np.linalg.norm(adj)
+        margins.append(abs(da) / max(np.linalg.norm(va) * na, 1e-300))
+        margins.append(abs(db) / max(np.linalg.norm(vb) * na, 1e-300))
+    return da <= 0.0 or db <= 0.0
 
 
 @dataclass
@@ -95,6 +101,11 @@ class Result:
     depth: int          # doublings attempted (the last one may have been discarded)
     accept_stat: float
     reason: str         # "turn", "subtree-turn", "divergent" or "max-depth"
+    # smallest distance of any random or threshold decision from its boundary
+    # (leaf and merge draws: |u - p| / p; U-turn checks: |v . adj| / (|v| |adj|);
+    # divergence: |H - H0 - 1000| / 1000); a diagnostic for comparisons with
+    # lower-precision implementations, not part of the method
+    min_margin: float = math.inf
 
 
 def trajectory(q0: np.ndarray, u0: float, g0: np.ndarray, eps: float, max_depth: int,
@@ -110,6 +121,7 @@ def trajectory(q0: np.ndarray, u0: float, g0: np.ndarray, eps: float, max_depth:
     acc = []
     reason = "max-depth"
     depth = 0
+    margins = []
     for j in range(max_depth):
         depth = j + 1
         v = direction(seed, stream, traj, j)
@@ -126,18 +138,22 @@ def trajectory(q0: np.ndarray, u0: float, g0: np.ndarray, eps: float, max_depth:
             acc.append(min(1.0, math.exp(min(0.0, h0 - h))) if math.isfinite(h) else 0.0)
             cur = State(q, p, g, u, h)
             sub.append(cur)
+            if math.isfinite(h):
+                margins.append(abs(h - h0 - DIVERGENCE) / DIVERGENCE)
             if not math.isfinite(h) or h - h0 > DIVERGENCE:
                 ok, reason = False, "divergent"
                 break
             lw = h0 - h
             log_w_sub = np.logaddexp(log_w_sub, lw)
-            if leaf_uniform(seed, stream, traj, s) < math.exp(lw - log_w_sub):
+            pl, ul = math.exp(lw - log_w_sub), leaf_uniform(seed, stream, traj, s)
+            margins.append(abs(ul - pl) / max(pl, 1e-300))
+            if ul < pl:
                 cand = cur
             m = 2
             while (n + 1) % m == 0:
                 span = sub[n + 1 - m:n + 1]
                 rho = np.sum([x.p for x in span], axis=0)
-                if turns(mass, span[0].p, span[-1].p, rho):
+                if turns(mass, span[0].p, span[-1].p, rho, margins):
                     ok, reason = False, "subtree-turn"
                     break
                 m *= 2
@@ -145,17 +161,20 @@ def trajectory(q0: np.ndarray, u0: float, g0: np.ndarray, eps: float, max_depth:
                 break
         if not ok:
             break
-        if merge_uniform(seed, stream, traj, j) < math.exp(min(0.0, log_w_sub - log_w)):
+        pm, um = math.exp(min(0.0, log_w_sub - log_w)), merge_uniform(seed, stream, traj, j)
+        margins.append(abs(um - pm) / max(pm, 1e-300))
+        if um < pm:
             prop = cand
         log_w = np.logaddexp(log_w, log_w_sub)
         traj_states = (traj_states + sub) if v > 0 else (sub[::-1] + traj_states)
         rho = np.sum([x.p for x in traj_states], axis=0)
-        if turns(mass, traj_states[0].p, traj_states[-1].p, rho):
+        if turns(mass, traj_states[0].p, traj_states[-1].p, rho, margins):
             reason = "turn"
             break
     moved = prop.q is not q0
     return Result(prop.q, prop.u, prop.g, h0, prop.h, moved, n_steps, depth,
-                  float(np.mean(acc)) if acc else 0.0, reason)
+                  float(np.mean(acc)) if acc else 0.0, reason,
+                  min(margins) if margins else math.inf)
 
 
 def run_chain(q0: np.ndarray, eps0: float, max_depth: int, minv, potential_and_grad: Callable,

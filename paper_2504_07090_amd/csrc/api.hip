@@ -11,6 +11,10 @@ void check_field(const vis_field* f) {
   BV_REQUIRE(f != nullptr, VIS_EINVAL, "null field");
 }
 
+}  // namespace
+
+namespace bv {
+
 void forward_core(const vis_field* f, const float* alm, const float* fwhm, hipStream_t s) {
   launch_synth_fwd(f, alm, f->scr.img, s);
   launch_fringe_fwd(f, f->scr.img, fwhm, f->scr.vu, s);
@@ -26,7 +30,7 @@ void adjoint_tail(const vis_field* f, const float* fwhm, float* grad_alm, float2
   if (grad_alm != nullptr) launch_synth_adj(f, f->scr.dimg, grad_alm, s);
 }
 
-}  // namespace
+}  // namespace bv
 
 extern "C" {
 

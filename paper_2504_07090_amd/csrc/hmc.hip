@@ -16,48 +16,9 @@
 // run in a fixed order, so a chain's trajectory does not depend on which
 // other chains share its batch.
 #include "hmc.hpp"
+#include "philox.hpp"
 
 namespace bv {
-
-// ---------------------------------------------------------------- Philox --
-__device__ __forceinline__ uint4 philox_round(uint4 c, uint2 k) {
-  const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-  const uint32_t hi0 = __umulhi(m0, c.x), lo0 = m0 * c.x;
-  const uint32_t hi1 = __umulhi(m1, c.z), lo1 = m1 * c.z;
-  return make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
-}
-
-__device__ uint4 philox10(uint4 c, uint2 k) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k.x += 0x9E3779B9u;
-      k.y += 0xBB67AE85u;
-    }
-    c = philox_round(c, k);
-  }
-  return c;
-}
-
-__device__ __forceinline__ double unit_open(uint32_t x) {
-  return (static_cast<double>(x) + 0.5) * 2.3283064365386963e-10;  // 2^-32
-}
-
-// Normals 4j .. 4j+3 of the (trajectory, stream) momentum sequence.
-__device__ __forceinline__ void normals4(uint64_t seed, uint32_t stream, uint32_t traj, uint32_t j,
-                                         float z[4]) {
-  const uint4 x = philox10(make_uint4(j, traj, stream, 0u),
-                           make_uint2(static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32)));
-  const uint32_t w[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const float r = sqrtf(-2.0f * logf(static_cast<float>(unit_open(w[2 * h]))));
-    float s, c;
-    sincospif(2.0f * static_cast<float>(unit_open(w[2 * h + 1])), &s, &c);
-    z[2 * h] = r * c;
-    z[2 * h + 1] = r * s;
-  }
-}
 
 // grad U at element i from the chi^2 gradient and the priors; adds the prior
 // part of U to acc_u.

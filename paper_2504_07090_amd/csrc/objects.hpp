@@ -182,4 +182,12 @@ void launch_reduce_grads(const vis_field* f, bool with_chi2, const double* chi_p
                          double* chi2, const float2* g_part, float2* grad_gains,
                          const float* f_part, float* grad_fwhm, hipStream_t st);
 
+// The evaluation sequences shared by the entry points: sky synthesis and the
+// forward fringe pass into the field's scratch (img, vu); and, once the gains
+// pass has written the adjoint coefficients and gain partials, the adjoint
+// fringe pass, the gradient reductions and the adjoint synthesis.
+void forward_core(const vis_field* f, const float* alm, const float* fwhm, hipStream_t s);
+void adjoint_tail(const vis_field* f, const float* fwhm, float* grad_alm, float2* grad_gains,
+                  float* grad_fwhm, bool with_chi2, double* chi2, hipStream_t s);
+
 }  // namespace bv

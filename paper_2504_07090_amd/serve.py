@@ -2,8 +2,8 @@
 
 The server keeps every chain's state in a caller-provided device arena and
 runs leapfrog steps as batched kernel launches on a worker thread inside the
-library.  Helpers here pack parameter vectors in the server's layout and
-estimate a diagonal mass matrix from the library's adjoint.
+library.  Helpers here pack parameter vectors in the server's layout and call
+the library's mass-matrix set-up (hmc_mass_diag, hmc_gain_mass_blocks).
 """
 from __future__ import annotations
 
@@ -50,6 +50,11 @@ for _n in ("hmc_chain_footprint_bytes", "hmc_chain_footprint_dense_gain_bytes",
            "hmc_chain_footprint_nuts_bytes", "hmc_chain_footprint_nuts_dense_gain_bytes"):
     getattr(_lib, _n).argtypes = [_vp]
     getattr(_lib, _n).restype = C.c_size_t
+_lib.hmc_mass_work_bytes.argtypes = [_vp, C.POINTER(C.c_size_t)]
+_lib.hmc_mass_diag.argtypes = [_vp, _vp, _vp, _vp, C.c_float, _vp, C.c_float, C.c_int32,
+                               C.c_uint64, _vp, _vp, _vp, C.c_size_t, _vp]
+_lib.hmc_gain_mass_blocks.argtypes = [_vp, _vp, _vp, _vp, C.c_float, C.c_float, _vp, _vp,
+                                      C.c_size_t, _vp]
 _lib.hmc_server_create.argtypes = [C.POINTER(ServerConfig), _vp, C.c_size_t, _vp, C.POINTER(_vp)]
 _lib.hmc_chain_admit.argtypes = [_vp, C.POINTER(ChainInit), C.POINTER(C.c_int32)]
 _lib.hmc_submit.argtypes = [_vp, C.c_int32, C.c_int32]
@@ -58,7 +63,8 @@ _lib.hmc_chain_position.argtypes = [_vp, C.c_int32, _vp, _vp]
 _lib.hmc_chain_release.argtypes = [_vp, C.c_int32]
 _lib.hmc_server_stats.argtypes = [_vp, C.POINTER(Stats), C.c_int32]
 _lib.hmc_server_destroy.argtypes = [_vp]
-for _n in ("hmc_server_create", "hmc_chain_admit", "hmc_submit", "hmc_poll", "hmc_chain_position",
+for _n in ("hmc_mass_work_bytes", "hmc_mass_diag", "hmc_gain_mass_blocks", "hmc_server_create",
+           "hmc_chain_admit", "hmc_submit", "hmc_poll", "hmc_chain_position",
            "hmc_chain_release", "hmc_server_stats", "hmc_server_destroy"):
     getattr(_lib, _n).restype = C.c_int
 
@@ -89,67 +95,51 @@ class Layout:
         return alm, g, q[-1:]
 
 
-def diag_hessian(field: V.Field, alm, gains, fwhm, sigma_n: float, n_probes: int = 8,
-                 seed: int = 0) -> torch.Tensor:
-    """Hutchinson estimate of diag(J^T J) / sigma_n^2 (the Gauss-Newton diagonal of chi^2 / 2).
+def _mass_work(field: V.Field) -> torch.Tensor:
+    n = C.c_size_t()
+    V._check(_lib.hmc_mass_work_bytes(field.handle, C.byref(n)), "hmc_mass_work_bytes")
+    return torch.empty(n.value, dtype=torch.uint8, device=field.device)
 
-    For z with unit-variance real and imaginary parts, vis_adjoint(dvis = z)
-    returns J^T z, and E[(J^T z)^2] = diag(J^T J).  Returned in the server's
-    parameter layout (padding entries set to 1).
-    """
+
+def mass_diag(field: V.Field, alm, gains, fwhm, sigma_n: float,
+              alm_prior_var: Optional[torch.Tensor] = None, gain_prior_sigma: float = 0.0,
+              n_probes: int = 8, seed: int = 0):
+    """(hdiag, minv) in the server's parameter layout from hmc_mass_diag: the
+    Gauss-Newton diagonal of chi^2 / 2 (Hutchinson probes for the sky and F,
+    exact for the gains) plus the prior precisions, and its inverse."""
     lay = Layout(field)
-    g = torch.Generator(device=alm.device)
-    g.manual_seed(seed)
-    acc = torch.zeros(lay.length, dtype=torch.float64, device=alm.device)
-    shape = (field.n_time, field.n_freq, field.n_bl)
-    for _ in range(n_probes):
-        z = torch.complex(torch.randn(shape, generator=g, device=alm.device),
-                          torch.randn(shape, generator=g, device=alm.device))
-        ga, gg, gf = V.adjoint(field, alm, gains, fwhm, z)
-        v = lay.pack(ga, gg, gf).double()
-        acc += v * v
-    h = acc / n_probes / (sigma_n ** 2)
-    h[lay.nalm:lay.goff] = 1.0
-    return h
+    V._need(alm, "alm", torch.float32, (field.n_freq, field.n_modes), field.device)
+    V._need(gains, "gains", torch.complex64, (field.n_freq, field.n_ant), field.device)
+    V._need(fwhm, "fwhm", torch.float32, (1,), field.device)
+    if alm_prior_var is not None:
+        V._need(alm_prior_var, "alm_prior_var", torch.float32, (field.n_freq, field.n_modes),
+                field.device)
+    work = _mass_work(field)
+    h = torch.empty(lay.length, dtype=torch.float32, device=field.device)
+    minv = torch.empty_like(h)
+    V._check(_lib.hmc_mass_diag(field.handle, V._ptr(alm), V._ptr(gains), V._ptr(fwhm), sigma_n,
+                                V._ptr(alm_prior_var), gain_prior_sigma, n_probes, seed, V._ptr(h),
+                                V._ptr(minv), V._ptr(work), work.numel(), C.c_void_p(V._stream())),
+             "hmc_mass_diag")
+    return h, minv
 
 
-def gain_mass_chol(field: V.Field, alm, gains, fwhm, sigma_n: float,
-                   gain_prior_sigma: float) -> torch.Tensor:
-    """Cholesky factors [n_freq][2 n_ant][2 n_ant] (float32, device) of dense
-    per-channel gain mass blocks M_f = H_f + (2 / s_g^2) I, with H_f the
-    Gauss-Newton Hessian of chi^2 / 2 in the real gain components (App. B: the
-    mass matrix approximates the Hessian; every antenna pair couples through its
-    baseline).  With V_ij = g_i conj(g_j) M_ij and M the model without gains
-    (from vis_forward with unit gains), summed over times:
-        H[x_i, x_i] = H[y_i, y_i] = sum over i's baselines of |g_other|^2 |M|^2,
-        H[x_i, x_j] = -H[y_i, y_j] = Re w,  H[x_i, y_j] = H[y_i, x_j] = Im w,
-        w = g_i g_j |M_ij|^2,
-    all over sigma_n^2.  Set-up code for the chain's mass matrix, not part of a
-    leapfrog step."""
-    na, nf = field.n_ant, field.n_freq
-    m = V.forward(field, alm, torch.ones_like(gains), fwhm)
-    m2 = (m.abs().double() ** 2).sum(0)                       # [f][bl], sum over times
-    del m
-    iu = torch.triu_indices(na, na, 1, device=gains.device)   # baselines (i, j), i < j, in order
-    i, j = iu[0], iu[1]
-    g = gains.to(torch.complex128)
-    gi, gj = g[:, i], g[:, j]
-    d = torch.zeros(nf, na, dtype=torch.float64, device=gains.device)
-    d.index_add_(1, i, (gj.abs() ** 2) * m2)
-    d.index_add_(1, j, (gi.abs() ** 2) * m2)
-    wv = gi * gj * m2
-    h = torch.zeros(nf, 2 * na, 2 * na, dtype=torch.float64, device=gains.device)
-    k = torch.arange(na, device=gains.device)
-    h[:, 2 * k, 2 * k] = d
-    h[:, 2 * k + 1, 2 * k + 1] = d
-    for a, b in ((i, j), (j, i)):
-        h[:, 2 * a, 2 * b] = wv.real
-        h[:, 2 * a + 1, 2 * b + 1] = -wv.real
-        h[:, 2 * a, 2 * b + 1] = wv.imag
-        h[:, 2 * a + 1, 2 * b] = wv.imag
-    h /= sigma_n ** 2
-    h += (2.0 / gain_prior_sigma ** 2) * torch.eye(2 * na, dtype=torch.float64, device=gains.device)
-    return torch.linalg.cholesky(h.cpu()).float().to(gains.device).contiguous()
+def gain_mass_blocks(field: V.Field, alm, gains, fwhm, sigma_n: float,
+                     gain_prior_sigma: float) -> torch.Tensor:
+    """Cholesky factors [n_freq][2 n_ant][2 n_ant] (float32, device) of the dense
+    per-channel gain mass blocks from hmc_gain_mass_blocks: the Gauss-Newton gain
+    Hessian of chi^2 / 2 plus 2 / s_g^2 I (App. B)."""
+    V._need(alm, "alm", torch.float32, (field.n_freq, field.n_modes), field.device)
+    V._need(gains, "gains", torch.complex64, (field.n_freq, field.n_ant), field.device)
+    V._need(fwhm, "fwhm", torch.float32, (1,), field.device)
+    work = _mass_work(field)
+    nb = 2 * field.n_ant
+    chol = torch.empty(field.n_freq, nb, nb, dtype=torch.float32, device=field.device)
+    V._check(_lib.hmc_gain_mass_blocks(field.handle, V._ptr(alm), V._ptr(gains), V._ptr(fwhm),
+                                       sigma_n, gain_prior_sigma, V._ptr(chol), V._ptr(work),
+                                       work.numel(), C.c_void_p(V._stream())),
+             "hmc_gain_mass_blocks")
+    return chol
 
 
 class Server:

@@ -43,6 +43,9 @@ def test_make_map_matches_oracle(vis, name, cfg, synthesis):
     m, wt = m.cpu().numpy(), wt.cpu().numpy()
     e_m = np.linalg.norm(m - ref_map, axis=1) / np.linalg.norm(ref_map, axis=1)
     e_w = np.max(np.abs(wt - ref_w)) / np.max(ref_w)
-    say("map", name, "per-channel rel err", e_m, "weight", e_w)
+    # element-wise: max over pixels |error| / rms of the channel's map
+    e_x = np.max(np.abs(m - ref_map), axis=1) / np.sqrt(np.mean(ref_map ** 2, axis=1))
+    say("map", name, "per-channel rel err", e_m, "element-wise", e_x, "weight", e_w)
     assert np.all(e_m <= 1e-5) and e_w <= 1e-5
+    assert np.all(e_x <= 1e-4)
     assert np.all(m[ref_w == 0] == 0.0)

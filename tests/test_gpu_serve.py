@@ -33,12 +33,9 @@ def _chain_inputs(vis, serve, fld, cfg, d, sigma=None, data=None, scale=1.0):
         data = (m + sigma * math.sqrt(2) * torch.tensor(d.noise_unit, dtype=torch.complex64,
                                                         device="cuda")).contiguous()
     q0 = lay.pack(alm, g, fw)
-    h = serve.diag_hessian(fld, alm, g, fw, sigma, n_probes=8)
-    # prior precisions on the diagonal as well
-    h[:lay.nalm] += 1.0 / torch.tensor(d.alm_var, device="cuda").reshape(-1).double()
-    h[lay.goff:lay.goff + lay.ngain] += 2.0 / cfg.gain_scatter ** 2
-    minv = (1.0 / h).float().contiguous()
     cvar = torch.tensor(d.alm_var, dtype=torch.float32, device="cuda")
+    # Gauss-Newton diagonal plus the prior precisions, from the library
+    _, minv = serve.mass_diag(fld, alm, g, fw, sigma, cvar, cfg.gain_scatter, n_probes=8)
     return lay, data, sigma, q0, minv, cvar
 
 
@@ -253,9 +250,9 @@ def _dense_gain_chol(lay, minv, n_freq, n_ant, seed):
 
 def test_alone_equals_mix(mods):
     """A chain's trajectories are bitwise identical alone and batched with others,
-    for a diagonal-mass chain, a chain with dense gain mass blocks, a NUTS
-    chain and a NUTS chain with dense gain blocks, and with one or two ticks in
-    flight."""
+    for a diagonal-mass chain, a chain with dense gain mass blocks, a bf16x3
+    chain, a NUTS chain (fp16x3) and a NUTS chain with dense gain blocks, and
+    with one or two ticks in flight."""
     vis, serve = mods
     basis = _mixed_basis(vis)
     cfgs, flds = _mixed_fields(vis, basis)
@@ -291,6 +288,7 @@ def test_alone_equals_mix(mods):
     alone1, pos_a1 = run([1])
     alone3, pos_a3 = run([3])
     alone4, pos_a4 = run([4])
+    alone2, pos_a2 = run([2])
     mix, pos_m = run([0, 1, 2, 3, 4])
     # two ticks in flight (the next built while the current runs): same results
     mix2, pos_m2 = run([0, 1, 2, 3, 4], inflight=2)
@@ -301,7 +299,8 @@ def test_alone_equals_mix(mods):
                 assert ra[key] == rm[key], (k, key, "inflight 2")
         assert torch.equal(pos_m[k], pos_m2[k]), (k, "inflight 2")
     assert all(r["tree_depth"] >= 1 for k in (3, 4) for r in mix[k])
-    for k, al, pa in ((0, alone, pos_a), (1, alone1, pos_a1), (3, alone3, pos_a3), (4, alone4, pos_a4)):
+    for k, al, pa in ((0, alone, pos_a), (1, alone1, pos_a1), (2, alone2, pos_a2), (3, alone3, pos_a3),
+                      (4, alone4, pos_a4)):
         assert len(al[k]) == len(mix[k]) == 3
         for ra, rm in zip(al[k], mix[k]):
             for key in ("trajectory", "accepted", "h0", "h1", "chi2", "eps", "n_grad", "tree_depth"):
@@ -425,10 +424,10 @@ def test_latency_stats_recorded(mods):
     srv.close()
 
 
-def test_gain_mass_chol_matches_oracle_gauss_newton(mods):
-    """The set-up helper's dense gain mass equals the oracle's Gauss-Newton gain
-    blocks (Jacobian by central differences of the FP64 forward model) plus the
-    prior precision."""
+def test_gain_mass_blocks_match_oracle_gauss_newton(mods):
+    """hmc_gain_mass_blocks (assembled and factored on the device) gives factors
+    whose products equal the oracle's Gauss-Newton gain blocks (Jacobian by
+    central differences of the FP64 forward model) plus the prior precision."""
     vis, serve = mods
     cfg = w.scaled(w.C0, array="hex", array_size=3, lmax=6, n_freq=3, n_time=2,
                    freq_lo_hz=120e6, freq_hi_hz=130e6)
@@ -440,12 +439,211 @@ def test_gain_mass_chol_matches_oracle_gauss_newton(mods):
     fw = w.fwhm_ref_rad(cfg)
     ref = ohmc.gain_gauss_newton_blocks(of, d.alm, d.gains, fw, sig)
     ref += np.eye(ref.shape[1])[None] * 2.0 / cfg.gain_scatter ** 2
-    l = serve.gain_mass_chol(fld, torch.tensor(d.alm, dtype=torch.float32, device="cuda"),
-                             torch.tensor(d.gains, dtype=torch.complex64, device="cuda"),
-                             torch.tensor([fw], dtype=torch.float32, device="cuda"), sig,
-                             cfg.gain_scatter).double().cpu().numpy()
+    l = serve.gain_mass_blocks(fld, torch.tensor(d.alm, dtype=torch.float32, device="cuda"),
+                               torch.tensor(d.gains, dtype=torch.complex64, device="cuda"),
+                               torch.tensor([fw], dtype=torch.float32, device="cuda"), sig,
+                               cfg.gain_scatter).double().cpu().numpy()
     got = l @ np.transpose(l, (0, 2, 1))
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     say("gain mass rel err", err)
     assert err <= 1e-5
     assert np.allclose(l, np.tril(l))
+
+
+# ---------------------------------------------------------------- mass matrices --
+
+def test_mass_diag_matches_oracle(mods):
+    """hmc_mass_diag against the oracle's Gauss-Newton diagonal with the same Philox
+    probes (Hutchinson for the sky and F, the closed form for the gains) plus the
+    prior precisions, entry by entry; minv is its inverse and the padding is 1."""
+    vis, serve = mods
+    cfg = w.scaled(w.C0, lmax=6, n_freq=3, n_time=2)
+    basis = vis.basis_for(cfg)
+    fld = vis.Field.from_config(basis, cfg)
+    d = w.draw(cfg)
+    of = model.Field(cfg)
+    fw = w.fwhm_ref_rad(cfg)
+    sig, k, seed = 0.21, 8, 21
+    ref = ohmc.gauss_newton_diag(of, d.alm, d.gains, fw, sig, k, seed) \
+        + ohmc.prior_precision_diag(d.alm_var, of.n_ant, cfg.gain_scatter)
+    lay = serve.Layout(fld)
+    h, minv = serve.mass_diag(fld, torch.tensor(d.alm, dtype=torch.float32, device="cuda"),
+                              torch.tensor(d.gains, dtype=torch.complex64, device="cuda"),
+                              torch.tensor([fw], dtype=torch.float32, device="cuda"), sig,
+                              torch.tensor(d.alm_var, dtype=torch.float32, device="cuda"),
+                              cfg.gain_scatter, n_probes=k, seed=seed)
+    h = h.double().cpu().numpy()
+    minv = minv.double().cpu().numpy()
+    got = np.concatenate([h[:lay.nalm], h[lay.goff:lay.goff + lay.ngain], h[-1:]])
+    rel = np.abs(got - ref) / np.abs(ref)
+    say("mass diag rel err: sky", rel[:lay.nalm].max(), "gains", rel[lay.nalm:-1].max(),
+        "F", rel[-1])
+    assert np.all(rel <= 1e-4)
+    assert np.all(h[lay.nalm:lay.goff] == 1.0) and np.all(minv[lay.nalm:lay.goff] == 1.0)
+    assert np.max(np.abs(minv * h - 1.0)) <= 1e-6
+
+
+C0_FULL_CHAIN = {}
+
+
+def _c0_full(mods):
+    """C0 at full size (16 dishes, lmax 20, 8 ch, 4 t): 3785 parameters, 3841 in
+    the server's padded layout, so four 1024-parameter elementwise blocks; the
+    inverse mass is the oracle's Gauss-Newton diagonal plus the prior (an input
+    to both sides, rounded to FP32 on both)."""
+    if not C0_FULL_CHAIN:
+        cfg = w.C0
+        of = model.Field(cfg)
+        d = w.draw(cfg)
+        _, sig, data = model.make_data(of, d)
+        post = ohmc.Posterior(of, data, sig, d.alm_var, cfg.gain_scatter)
+        fw = w.fwhm_ref_rad(cfg)
+        q = ohmc.pack(d.alm, d.gains, fw)
+        h = ohmc.gauss_newton_diag(of, d.alm, d.gains, fw, sig, 8, seed=21) \
+            + ohmc.prior_precision_diag(d.alm_var, of.n_ant, cfg.gain_scatter)
+        minv = (1.0 / h).astype(np.float32).astype(np.float64)
+        hg = ohmc.gain_gauss_newton_blocks(of, d.alm, d.gains, fw, sig)
+        hg += np.eye(hg.shape[1])[None] / post.gvar
+        chol32 = np.linalg.cholesky(hg).astype(np.float32)
+        C0_FULL_CHAIN.update(cfg=cfg, of=of, d=d, sig=sig, data=data, post=post, q=q, minv=minv,
+                             chol32=chol32)
+    return C0_FULL_CHAIN
+
+
+def _admit_c0_full(vis, serve, c, dense, eps0, n_leapfrog, seed, stream, nuts_depth=0):
+    cfg = c["cfg"]
+    basis = vis.basis_for(cfg)
+    fld = vis.Field.from_config(basis, cfg)
+    lay = serve.Layout(fld)
+    nalm, ng = lay.nalm, lay.ngain
+    assert (lay.length + 1023) // 1024 >= 4
+
+    def to_lay(v):
+        out = np.zeros(lay.length)
+        out[:nalm] = v[:nalm]
+        out[lay.goff:lay.goff + ng] = v[nalm:nalm + ng]
+        out[-1] = v[-1]
+        return out
+
+    minv_l = to_lay(c["minv"])
+    minv_l[nalm:lay.goff] = 1.0
+    srv = serve.Server(128 << 20, max_chains=2, max_batch=2)
+    cid = srv.admit(fld, torch.tensor(c["data"], dtype=torch.complex64, device="cuda"), c["sig"],
+                    torch.tensor(to_lay(c["q"]), dtype=torch.float32, device="cuda"),
+                    torch.tensor(minv_l, dtype=torch.float32, device="cuda"),
+                    torch.tensor(c["d"].alm_var, dtype=torch.float32, device="cuda"),
+                    cfg.gain_scatter, eps0, n_leapfrog, seed, stream, adapt_step=True,
+                    gain_chol=torch.tensor(c["chol32"], device="cuda") if dense else None,
+                    nuts_max_depth=nuts_depth)
+    idx = np.concatenate([np.arange(nalm), lay.goff + np.arange(ng), [lay.length - 1]])
+
+    def from_lay(v):
+        return np.concatenate([v[:nalm], v[lay.goff:lay.goff + ng], v[-1:]])
+
+    return srv, cid, lay, idx, from_lay
+
+
+def _oracle_mass(c, dense):
+    if not dense:
+        return c["minv"]
+    cfg = c["cfg"]
+    return ohmc.gain_block_mass(c["minv"], c["chol32"].astype(np.float64), cfg.n_freq * cfg.n_modes)
+
+
+@pytest.mark.parametrize("dense", [False, True], ids=["diagonal", "dense_gains"])
+def test_adaptive_hmc_multiblock_matches_oracle(mods, dense):
+    """Six adapted HMC trajectories (App. B step-size rule) on a four-block chain
+    against the oracle's run_chain from the same start, mass and Philox streams:
+    the step each trajectory used, the accept decision, H0 and H1 and the
+    position after each trajectory.  eps0 = 0.1 is unstable for this field's
+    stiffest directions, so the step shrinks after the poor trajectories and
+    grows back (capped at eps0) after good ones."""
+    vis, serve = mods
+    c = _c0_full(mods)
+    # stream 29 keeps every accept decision and every comparison with the 0.2
+    # threshold more than 10% away from its boundary (checked with the oracle)
+    eps0, nl, seed, stream = 0.1, 5, 11, 29
+    srv, cid, lay, idx, from_lay = _admit_c0_full(vis, serve, c, dense, eps0, nl, seed, stream)
+    _, _, _, recs = ohmc.run_chain(c["q"], eps0, nl, _oracle_mass(c, dense),
+                                   c["post"].potential_and_grad, seed, stream, 6, normal_index=idx)
+    q_prev, err_prev = c["q"], 0.0
+    branches = set()
+    for t, rec in enumerate(recs):
+        srv.submit(cid, 1)
+        r = srv.wait(1)[0]
+        qg = from_lay(srv.position(cid, lay.length, "cuda").double().cpu().numpy())
+        from oracle import philox
+        un = philox.accept_uniform(seed, stream, t)
+        dh = rec["h1"] - rec["h0"]
+        say("adaptive hmc", "dense" if dense else "diag", t, "oracle eps", rec["eps"], "prob",
+            rec["accept_prob"], "u", un, "acc", rec["accepted"], "dH", dh,
+            "gpu eps", r["eps"], "prob", r["accept_stat"], "acc", r["accepted"], "dH", r["h1"] - r["h0"])
+        # the case is chosen away from both decision boundaries (FP32 energies move
+        # the probability by ~1% at this H ~ 7400)
+        p = rec["accept_prob"]
+        assert abs(p - 0.2) > 0.03 * 0.2 and abs(un - p) > 0.03 * max(p, 1e-300)
+        assert r["status"] == 0 and r["trajectory"] == t
+        assert abs(r["eps"] - rec["eps"]) <= 1e-5 * rec["eps"]
+        assert bool(r["accepted"]) == bool(rec["accepted"])
+        assert abs(r["h0"] - rec["h0"]) <= 1e-4 * abs(rec["h0"])
+        if dh < 30:
+            assert abs(r["h1"] - rec["h1"]) <= 1e-4 * abs(rec["h1"])
+            assert abs((r["h1"] - r["h0"]) - dh) <= 0.05 + 1e-2 * abs(dh)
+            # consistent with that energy bound: exp(0.05) - 1 ~ 5% of the probability
+            assert abs(r["accept_stat"] - p) <= 0.06 * p + 1e-3
+        else:
+            # an unstable trajectory: both sides reject with a vanishing probability
+            assert r["h1"] - r["h0"] > 20 or not math.isfinite(r["h1"])
+        # the GPU chain carries its earlier deviation (err_prev) into this trajectory
+        move = np.linalg.norm(rec["q"] - q_prev)
+        err = np.linalg.norm(qg - rec["q"])
+        assert err <= 1e-3 * move + 1.5 * err_prev + 1e-7 * np.linalg.norm(q_prev)
+        q_prev, err_prev = rec["q"], err
+        branches.add(rec["accept_prob"] < 0.2)
+    srv.close()
+    assert branches == {True, False}
+    assert min(rec["eps"] for rec in recs) < eps0 / 1.3   # two reductions in a row
+
+
+@pytest.mark.parametrize("dense", [False, True], ids=["diagonal", "dense_gains"])
+def test_adaptive_nuts_multiblock_matches_oracle(mods, dense):
+    """Five adapted NUTS trajectories (at most 4 doublings) on the four-block chain
+    against the oracle's NUTS run_chain: tree depth, leapfrog steps, whether the
+    chain moved, H0 and H of the proposal, the mean-leaf acceptance statistic,
+    the adapted step and the position after each trajectory.  The U-turn dot
+    products and energies are reduced over all four elementwise blocks; with
+    dense gain blocks the checks use velocities from the block solves."""
+    from oracle import nuts as onuts
+    vis, serve = mods
+    c = _c0_full(mods)
+    # stream 29 keeps every leaf, merge, U-turn and divergence decision of the
+    # oracle's trajectories more than 8% from its boundary (oracle min_margin)
+    eps0, depth, seed, stream = 0.12, 4, 5, 29
+    srv, cid, lay, idx, from_lay = _admit_c0_full(vis, serve, c, dense, eps0, 1, seed, stream,
+                                                  nuts_depth=depth)
+    _, _, _, recs = onuts.run_chain(c["q"], eps0, depth, _oracle_mass(c, dense),
+                                    c["post"].potential_and_grad, seed, stream, 5, normal_index=idx)
+    q_prev, err_prev = c["q"], 0.0
+    branches = set()
+    for t, rec in enumerate(recs):
+        o = rec["result"]
+        srv.submit(cid, 1)
+        r = srv.wait(1)[0]
+        qg = from_lay(srv.position(cid, lay.length, "cuda").double().cpu().numpy())
+        say("adaptive nuts", "dense" if dense else "diag", t, "oracle", rec["eps"], o.depth,
+            o.n_steps, o.moved, o.reason, o.accept_stat, "gpu", r["eps"], r["tree_depth"],
+            r["n_grad"], r["accepted"], r["accept_stat"])
+        assert abs(o.accept_stat - 0.2) > 0.01 and o.min_margin > 0.03
+        assert r["status"] == 0 and r["trajectory"] == t
+        assert abs(r["eps"] - rec["eps"]) <= 1e-5 * rec["eps"]
+        assert (r["tree_depth"], r["n_grad"], bool(r["accepted"])) == (o.depth, o.n_steps, o.moved)
+        assert abs(r["h0"] - o.h0) <= 1e-4 * abs(o.h0)
+        assert abs(r["h1"] - o.h_prop) <= 1e-4 * abs(o.h_prop)
+        assert abs(r["accept_stat"] - o.accept_stat) <= 0.06 * o.accept_stat + 2e-3
+        move = np.linalg.norm(o.q - q_prev)
+        err = np.linalg.norm(qg - o.q)
+        assert err <= 1e-3 * move + 1.5 * err_prev + 1e-7 * np.linalg.norm(q_prev)
+        q_prev, err_prev = o.q, err
+        branches.add(o.accept_stat < 0.2)
+    srv.close()
+    assert branches == {True, False}

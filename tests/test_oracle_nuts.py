@@ -86,7 +86,7 @@ def test_harmonic_oscillator_turns_near_half_period():
 
 def test_planted_flipped_turn_sign_is_caught(monkeypatch):
     orig = nuts.turns
-    monkeypatch.setattr(nuts, "turns", lambda m, a, b, r: not orig(m, a, b, r))
+    monkeypatch.setattr(nuts, "turns", lambda m, a, b, r, margins=None: not orig(m, a, b, r))
     with pytest.raises(AssertionError):
         test_harmonic_oscillator_turns_near_half_period()
 
