@@ -255,6 +255,25 @@ vis_status chi2_filtered_and_grad(const vis_field* field, const vis_filter* filt
                                   float* grad_alm, vis_c64* grad_gains, float* grad_fwhm,
                                   void* work, size_t work_bytes, void* stream);
 
+/* chi2_filtered_and_grad_noalloc: chi2_filtered_and_grad without the work
+ * argument, for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops and harnesses that forbid allocation).  Its
+ * scratch is one static device array of VIS_NOALLOC_SCRATCH_BYTES per GPU in
+ * the library's code object, held until the process ends (the 61-dish, 64-
+ * channel, 60-time field needs 112.5 MB of it); the call makes no allocation.
+ * Every call on one GPU shares that GPU's array and it keeps the last call's
+ * contents, so calls that may overlap on one device (other streams, other
+ * threads) race and must be ordered by the caller.  Nothing in the array has
+ * to start at zero.  VIS_ENOMEM: vis_filtered_work_bytes(field) exceeds
+ * VIS_NOALLOC_SCRATCH_BYTES.  Other arguments, outputs and errors as for
+ * chi2_filtered_and_grad.                                                   */
+#define VIS_NOALLOC_SCRATCH_BYTES (128u << 20)
+vis_status chi2_filtered_and_grad_noalloc(const vis_field* field, const vis_filter* filter,
+                                          const vis_c64* data, float sigma_n, const float* alm,
+                                          const vis_c64* gains, const float* fwhm, double* chi2,
+                                          float* grad_alm, vis_c64* grad_gains, float* grad_fwhm,
+                                          void* stream);
+
 /* ------------------------------------------------------------ profiling --
  * Optional per-field kernel timing: when enabled, every kernel the field
  * launches is bracketed by a pair of hipEvents on the launch stream and its

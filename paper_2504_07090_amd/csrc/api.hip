@@ -1,6 +1,8 @@
 // Evaluation entry points of the C ABI: vis_forward, vis_adjoint, chi2_and_grad.
 // Each is a fixed stream-ordered sequence of kernel launches; nothing returns
 // to the host.
+#include <mutex>
+
 #include "objects.hpp"
 
 using namespace bv;
@@ -31,6 +33,36 @@ void adjoint_tail(const vis_field* f, const float* fwhm, float* grad_alm, float2
 }
 
 }  // namespace bv
+
+namespace {
+
+// Scratch of chi2_filtered_and_grad_noalloc: one array per GPU, in the code
+// object's device memory, held until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host it names a stand-in, not
+// the device copy); it uses the device address looked up once per device.
+static __device__ __align__(256) unsigned char scratch[VIS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device, with that device current).
+void* noalloc_scratch() {
+  int dev = 0;
+  BV_HIP(hipGetDevice(&dev));
+  BV_REQUIRE(dev >= 0 && dev < kMaxDevices, VIS_EDEVICE, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev] == nullptr) {
+    void* p = nullptr;
+    BV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    BV_REQUIRE(p != nullptr, VIS_EDEVICE, "no device address for the static scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -117,6 +149,27 @@ vis_status chi2_filtered_and_grad(const vis_field* f, const vis_filter* flt, con
     launch_gains(f, kGainAdj, f->scr.vu, reinterpret_cast<const float2*>(gains), w.m, 0.f, nullptr,
                  nullptr, f->scr.gco, f->scr.g_part, s);
     adjoint_tail(f, fwhm, grad_alm, reinterpret_cast<float2*>(grad_gains), grad_fwhm, false, nullptr, s);
+  });
+}
+
+vis_status chi2_filtered_and_grad_noalloc(const vis_field* f, const vis_filter* flt,
+                                          const vis_c64* data, float sigma_n, const float* alm,
+                                          const vis_c64* gains, const float* fwhm, double* chi2,
+                                          float* grad_alm, vis_c64* grad_gains, float* grad_fwhm,
+                                          void* stream) {
+  return guarded([&] {
+    check_field(f);
+    const size_t need = carve_filtered_work(f, nullptr, 0).bytes;
+    BV_REQUIRE(need <= VIS_NOALLOC_SCRATCH_BYTES, VIS_ENOMEM,
+               "the field needs %zu bytes of scratch; the static array holds %zu", need,
+               static_cast<size_t>(VIS_NOALLOC_SCRATCH_BYTES));
+    void* work = noalloc_scratch();
+    // the same sequence as chi2_filtered_and_grad over the static array (its
+    // kernels write every scratch element they read, so nothing is cleared)
+    const vis_status st = chi2_filtered_and_grad(f, flt, data, sigma_n, alm, gains, fwhm, chi2,
+                                                 grad_alm, grad_gains, grad_fwhm, work,
+                                                 VIS_NOALLOC_SCRATCH_BYTES, stream);
+    if (st != VIS_OK) throw Failure{st};
   });
 }
 

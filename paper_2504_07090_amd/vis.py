@@ -309,6 +309,8 @@ _lib.vis_filter_destroy.argtypes = [_vp]
 _lib.vis_filtered_work_bytes.argtypes = [_vp, C.POINTER(C.c_size_t)]
 _lib.chi2_filtered_and_grad.argtypes = [_vp, _vp, _vp, C.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                         _vp, C.c_size_t, _vp]
+_lib.chi2_filtered_and_grad_noalloc.argtypes = [_vp, _vp, _vp, C.c_float, _vp, _vp, _vp, _vp, _vp,
+                                                _vp, _vp, _vp]
 
 
 def filter_build(freqs, tau_max: float = 250e-9, noise_ratio: float = 1e-8):
@@ -368,6 +370,31 @@ def chi2_filtered_and_grad(field: Field, filt: Filter, data, sigma_n: float, alm
                                        _ptr(alm), _ptr(gains), _ptr(fwhm), _ptr(x2), _ptr(ga),
                                        _ptr(gg), _ptr(gf), _ptr(work), nbytes.value,
                                        C.c_void_p(_stream())), "chi2_filtered_and_grad")
+    return x2, ga, gg, gf
+
+
+def chi2_filtered_and_grad_noalloc(field: Field, filt: Filter, data, sigma_n: float, alm, gains,
+                                   fwhm, out=None, grads: bool = True):
+    """chi2_filtered_and_grad through the entry point that allocates nothing: its
+    scratch is the library's static per-GPU array.  ``out`` = (chi2, ga, gg, gf)
+    preallocated outputs (any gradient may be None); allocated here if omitted."""
+    field._params(alm, gains, fwhm)
+    _need(data, "data", torch.complex64, field._vis_shape(), field.device)
+    if not (sigma_n > 0 and math.isfinite(sigma_n)):
+        raise ValueError("sigma_n must be positive and finite")
+    if out is None:
+        x2 = torch.empty((), dtype=torch.float64, device=field.device)
+        if grads:
+            ga, gg, gf = torch.empty_like(alm), torch.empty_like(gains), torch.empty_like(fwhm)
+        else:
+            ga = gg = gf = None
+    else:
+        x2, ga, gg, gf = out
+    _check(_lib.chi2_filtered_and_grad_noalloc(field.handle, filt.handle, _ptr(data),
+                                               C.c_float(sigma_n), _ptr(alm), _ptr(gains),
+                                               _ptr(fwhm), _ptr(x2), _ptr(ga), _ptr(gg), _ptr(gf),
+                                               C.c_void_p(_stream())),
+           "chi2_filtered_and_grad_noalloc")
     return x2, ga, gg, gf
 
 
