@@ -85,32 +85,95 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, chan: int = 37):
-    """Oracle chi^2 + gradient for one channel of the workload (all times), FP64."""
-    import numpy as np
-    from oracle import model
-    from paper_2504_07090_amd import workload as w
+# The oracle's sample of the 61-dish workload: 16 channels spread over the band
+# (both ends, both 32-channel tiles of the forward kernel's map) x 2 consecutive
+# times each, one (channel, time block) per single-threaded worker process.
+CPU_SAMPLE_CHANNELS = [0, 4, 9, 13, 18, 22, 27, 31, 32, 36, 41, 45, 50, 54, 59, 63]
+CPU_SAMPLE_TIMES = 2
+
+
+def _oracle_sample(task):
+    """FP64 oracle chi^2 + gradient of one (channel, time block) of the 61-dish
+    workload, single-threaded; returns its MAC count, the timed seconds, and the
+    model visibilities, cotangent and gradient for the GPU comparison."""
+    f, t0, nt = task
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        import numpy as np
+        from oracle import model
+        from paper_2504_07090_amd import workload as w
+        cfg = w.C1
+        d = w.draw(cfg)
+        fw = w.fwhm_ref_rad(cfg)
+        of = model.Field(w.scaled(cfg, n_time=nt, lst0_rad=float(w.lsts(cfg)[t0])))
+        m = model.forward(of, d.alm, d.gains, fw, chans=[f])
+        sig = model.noise_sigma(cfg, m)
+        data = m + sig * math.sqrt(2) * d.noise_unit[t0:t0 + nt, [f], :]
+        t1 = time.perf_counter()
+        _, ga, gg, _ = model.chi2_and_grad(of, data, sig, d.alm, d.gains, fw, chans=[f])
+        t2 = time.perf_counter()
+        macs = 2.0 * len(of.ubl_ij) * float(np.sum(of.up))   # forward + adjoint
+        cot = -2.0 * (data - m) / sig ** 2
+        return macs, t2 - t1, m[:, 0], cot[:, 0], ga[0], gg[0]
+
+
+def cpu_baseline_run():
+    """The oracle on a process pool over (channel, time block) samples, before the
+    GPU is touched (the workers are forked).  Wall time of the pool is the
+    baseline; every worker is single-threaded, so `cores` = workers."""
+    import multiprocessing as mp
     try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        blas_threads = os.cpu_count() or 1
-    d = w.draw(cfg)
-    of = model.Field(cfg)
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    workers = max(1, min(16, ncpu, len(CPU_SAMPLE_CHANNELS)))
+    tasks = [(f, (7 * k) % (60 - CPU_SAMPLE_TIMES), CPU_SAMPLE_TIMES)
+             for k, f in enumerate(CPU_SAMPLE_CHANNELS)]
     t0 = time.perf_counter()
-    m = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg), chans=[chan])
-    sig = model.noise_sigma(cfg, m)
-    data = m + sig * math.sqrt(2) * d.noise_unit[:, [chan], :]
-    t1 = time.perf_counter()
-    model.chi2_and_grad(of, data, sig, d.alm, d.gains, w.fwhm_ref_rad(cfg), chans=[chan])
-    t2 = time.perf_counter()
-    macs = 2.0 * len(of.ubl_ij) * float(np.sum(of.up))  # fwd + adjoint, one channel
-    return {"value": macs / (t2 - t1), "unit": "complex MAC/s", "cores": int(blas_threads),
-            "kind": "oracle",
-            "sample": (f"FP64 NumPy oracle chi^2 + analytic gradient of channel {chan} of 64, all "
-                       f"{cfg.n_time} times, {len(of.ubl_ij)} unique baselines, full grid: "
-                       f"{t2 - t1:.1f} s (data generation {t1 - t0:.1f} s not timed); "
-                       f"elementwise NumPy single-threaded, BLAS {blas_threads} threads")}
+    with mp.get_context("fork").Pool(workers) as pool:
+        out = pool.map(_oracle_sample, tasks)
+    wall = time.perf_counter() - t0
+    macs = sum(o[0] for o in out)
+    busy = sum(o[1] for o in out)
+    base = {"value": macs / wall, "unit": "complex MAC/s", "cores": workers, "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle chi^2 + analytic gradient of {len(tasks)} (channel, "
+                       f"{CPU_SAMPLE_TIMES}-time block) samples of the 61-dish workload (channels "
+                       f"{CPU_SAMPLE_CHANNELS}), one single-threaded worker process per sample, "
+                       f"{workers} at a time: {wall:.1f} s wall for {macs:.3e} complex MACs "
+                       f"({busy:.1f} s of timed worker time; per core {macs / busy:.3e} MAC/s)")}
+    return base, tasks, out
+
+
+def oracle_errors(vis, torch, fld, cfg, tasks, out):
+    """Per sampled channel: GPU visibilities and the GPU adjoint of the oracle's
+    chi^2 cotangent against the oracle, normwise and element-wise."""
+    import numpy as np
+    from paper_2504_07090_amd import workload as w
+    d = w.draw(cfg, with_noise=False)
+    alm = torch.tensor(d.alm, dtype=torch.float32, device="cuda")
+    g = torch.tensor(d.gains, dtype=torch.complex64, device="cuda")
+    fw = torch.tensor([w.fwhm_ref_rad(cfg)], dtype=torch.float32, device="cuda")
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    cot = np.zeros((cfg.n_time, cfg.n_freq, fld.n_bl), dtype=np.complex64)
+    for (f, t0, nt), o in zip(tasks, out):
+        cot[t0:t0 + nt, f] = o[3]
+    ga, gg, _ = vis.adjoint(fld, alm, g, fw, torch.tensor(cot, device="cuda"))
+    ga, gg = ga.cpu().numpy(), gg.cpu().numpy()
+    rows = {}
+    for (f, t0, nt), o in zip(tasks, out):
+        ref, got = o[2], m[t0:t0 + nt, f]
+        rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+        rows[str(f)] = {
+            "times": [t0, t0 + nt - 1],
+            "vis_rel": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "vis_max_over_rms": float(np.max(np.abs(got - ref)) / rms),
+            "grad_alm_rel": float(np.linalg.norm(ga[f] - o[4]) / np.linalg.norm(o[4])),
+            "grad_gain_rel": float(np.linalg.norm(gg[f] - o[5]) / np.linalg.norm(o[5]))}
+    worst = {k: max(r[k] for r in rows.values())
+             for k in ("vis_rel", "vis_max_over_rms", "grad_alm_rel", "grad_gain_rel")}
+    return {"per_channel": rows, "worst": worst,
+            "note": "timed field against the FP64 oracle on the cpu_baseline samples; gradients "
+                    "are the adjoint of the oracle's chi^2 cotangent of each sample"}
 
 
 def timed_reps(torch, fn, reps):
@@ -252,7 +315,7 @@ def serving_inputs(vis, serve, torch, basis, n_chains):
 
 
 def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=20, synthesis=0,
-                  dense_gains=False, nuts_depth=0):
+                  dense_gains=False, nuts_depth=0, batched=None):
     """One trajectory of n_leapfrog steps per chain; all chains submitted at once.
     dense_gains: every chain gets dense per-channel gain mass blocks (the
     Gauss-Newton gain Hessian plus the prior, built before timing).
@@ -269,8 +332,9 @@ def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=
             chols[c] = serve.gain_mass_blocks(fld, alm.contiguous(), g.contiguous(),
                                               fw.contiguous(), sigma, cfg.gain_scatter)
     fp = sum(serve.Server.footprint(f, dense_gains, nuts_depth > 0) for f in flds)
-    srv = serve.Server(fp + (64 << 20), max_chains=n_chains, max_batch=max_batch,
-                       batched=1 if max_batch > 1 else 0)
+    if batched is None:
+        batched = 1 if max_batch > 1 else 0
+    srv = serve.Server(fp + (64 << 20), max_chains=n_chains, max_batch=max_batch, batched=batched)
     ids = []
     for c, ((cfg, _, data, sigma, q0, minv, cvar), fld) in enumerate(zip(inputs, flds)):
         ids.append(srv.admit(fld, data, sigma, q0, minv, cvar, cfg.gain_scatter, EPS, n_leapfrog,
@@ -298,7 +362,9 @@ def serving_bench(vis, serve, torch, basis, inputs, prec, max_batch, n_leapfrog=
     out = {"grad_evals_per_s": st["requests"] / (t1 - t0), "p10_ms": st["p10_ms"],
            "p50_ms": st["p50_ms"], "p90_ms": st["p90_ms"], "p99_ms": st["p99_ms"],
            "requests": st["requests"], "wall_s": t1 - t0,
-           "complex_macs_per_s": macs / (t1 - t0), "acceptance": acc, "max_batch": max_batch}
+           "complex_macs_per_s": macs / (t1 - t0), "acceptance": acc, "max_batch": max_batch,
+           "evaluation_launches": {0: "one chain after another", 1: "batched grids",
+                                   2: "per chain on several streams"}[batched]}
     if nuts_depth:
         out.update({"trajectory_grad_evals_per_s": sum(steps) / (t1 - t0),
                     "mean_steps": sum(steps) / len(steps), "max_depth": nuts_depth,
@@ -320,6 +386,10 @@ def main():
                     help="serving ticks in flight for the timed chain (2: the next tick is "
                          "built and queued while the current one runs)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-modes", default="split,separable,multistream,dense_gains,nuts,"
+                    "nuts_dense_gains,per_chain",
+                    help="serving runs to measure (comma list; the speed-ups need split, "
+                         "separable and per_chain)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the delay-filtered likelihood and map-making measurements "
@@ -333,6 +403,13 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    cpu = samples = None
+    if not args.no_cpu_baseline:
+        # before the GPU is initialised: the pool forks
+        log("cpu baseline (oracle on a process pool over channel / time samples)")
+        cpu, sample_tasks, sample_out = cpu_baseline_run()
+        samples = (sample_tasks, sample_out)
 
     import torch
     from paper_2504_07090_amd import serve, vis, workload as w
@@ -352,8 +429,10 @@ def main():
     warm = make_chain(vis, serve, torch, basis, cfg, prec, synth)
     timed = make_chain(vis, serve, torch, basis, cfg, prec, synth)
     fld = timed[0]
+    # one chain per tick: its kernels launch one by one (batched=0), so the
+    # per-field kernel timers can bracket each of them
     srv = serve.Server(serve.Server.footprint(fld) * 2 + (64 << 20), max_chains=2, max_batch=2,
-                       inflight_ticks=args.inflight_ticks)
+                       batched=0, inflight_ticks=args.inflight_ticks)
     fldw, dataw, sigw, q0w, minvw, cvarw, _ = warm
     cw = srv.admit(fldw, dataw, sigw, q0w, minvw, cvarw, cfg.gain_scatter, EPS,
                    max(1, args.warmup), seed=1, stream_id=0)
@@ -423,39 +502,52 @@ def main():
     if not args.no_serve:
         log("serving: building", args.serve_chains, "uneven chains")
         ins = serving_inputs(vis, serve, torch, basis, args.serve_chains)
-        log("serving: batched,", args.serve_precision, "dense synthesis")
-        fast = serving_bench(vis, serve, torch, basis, ins, sprec, max_batch=args.serve_chains)
-        log("serving: batched, FP32 separable synthesis")
-        sep = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32, max_batch=args.serve_chains,
-                            synthesis=vis.VIS_SYNTH_SEPARABLE)
-        log("serving: batched, FP32 separable synthesis, dense gain mass blocks")
-        sep_dg = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32,
-                               max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
-                               dense_gains=True)
-        log("serving: batched, FP32 separable synthesis, NUTS (at most 5 doublings)")
-        sep_nuts = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32,
-                                 max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
-                                 nuts_depth=5)
-        log("serving: batched, FP32 separable synthesis, NUTS with dense gain mass blocks")
-        sep_nuts_dg = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32,
-                                    max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
-                                    dense_gains=True, nuts_depth=5)
-        log("serving: per-chain FP32 baseline (dense synthesis), one request per tick")
-        base = serving_bench(vis, serve, torch, basis, ins, vis.VIS_FP32, max_batch=1)
-        del ins
-        serving = {"chains": args.serve_chains, "leapfrog_steps": 20,
-                   "batched_" + args.serve_precision: fast, "batched_fp32_separable": sep,
-                   "batched_fp32_separable_dense_gain_mass": sep_dg,
-                   "batched_fp32_separable_nuts": sep_nuts,
-                   "batched_fp32_separable_nuts_dense_gain_mass": sep_nuts_dg,
-                   "per_chain_fp32": base,
-                   "speedup": fast["grad_evals_per_s"] / base["grad_evals_per_s"],
-                   "speedup_separable": sep["grad_evals_per_s"] / base["grad_evals_per_s"]}
+        modes = set(args.serve_modes.split(","))
+        runs = {}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, one channel)")
-        cpu = cpu_baseline(cfg)
+        def sb(name, label, **kw):
+            if name in modes:
+                log("serving:", label)
+                runs[name] = serving_bench(vis, serve, torch, basis, ins, **kw)
+
+        sb("split", f"batched, {args.serve_precision}, dense synthesis", prec=sprec,
+           max_batch=args.serve_chains)
+        sb("separable", "batched, FP32 separable synthesis", prec=vis.VIS_FP32,
+           max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE)
+        sb("multistream", "FP32 separable synthesis, each chain's kernels on their own (4 streams)",
+           prec=vis.VIS_FP32, max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
+           batched=2)
+        sb("dense_gains", "batched, FP32 separable synthesis, dense gain mass blocks",
+           prec=vis.VIS_FP32, max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
+           dense_gains=True)
+        sb("nuts", "batched, FP32 separable synthesis, NUTS (at most 5 doublings)",
+           prec=vis.VIS_FP32, max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
+           nuts_depth=5)
+        sb("nuts_dense_gains", "batched, FP32 separable synthesis, NUTS with dense gain mass blocks",
+           prec=vis.VIS_FP32, max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE,
+           dense_gains=True, nuts_depth=5)
+        sb("per_chain", "per-chain FP32 baseline (dense synthesis), one request per tick",
+           prec=vis.VIS_FP32, max_batch=1)
+        del ins
+        names = {"split": "batched_" + args.serve_precision, "separable": "batched_fp32_separable",
+                 "multistream": "multistream_fp32_separable",
+                 "dense_gains": "batched_fp32_separable_dense_gain_mass",
+                 "nuts": "batched_fp32_separable_nuts",
+                 "nuts_dense_gains": "batched_fp32_separable_nuts_dense_gain_mass",
+                 "per_chain": "per_chain_fp32"}
+        serving = {"chains": args.serve_chains, "leapfrog_steps": 20}
+        serving.update({names[k]: v for k, v in runs.items()})
+        if "per_chain" in runs:
+            base = runs["per_chain"]["grad_evals_per_s"]
+            if "split" in runs:
+                serving["speedup"] = runs["split"]["grad_evals_per_s"] / base
+            if "separable" in runs:
+                serving["speedup_separable"] = runs["separable"]["grad_evals_per_s"] / base
+
+    errors = None
+    if samples is not None:
+        log("errors against the oracle on its samples")
+        errors = oracle_errors(vis, torch, fld, cfg, *samples)
 
     line = {
         "metric": "fwd+adjoint complex MAC/s; batched-HMC grad evals/s + p50/p99 latency",
@@ -476,6 +568,7 @@ def main():
         "roofline": roof,
         "serving": serving,
         "extras": extras,
+        "error_vs_oracle": errors,
         "cpu_baseline": cpu,
     }
     if args.calibrate_copy:

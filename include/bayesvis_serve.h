@@ -74,7 +74,8 @@ vis_status hmc_gain_mass_blocks(const vis_field* field, const float* alm, const 
  * steps and accepts with probability min(1, exp(H0 - H1)) (uniform from
  * counter (0xFFFFFFFF, trajectory, stream, 1)).  Each leapfrog step is one
  * chi^2 + gradient request; a worker thread batches the pending requests of
- * all chains into one sequence of batched kernel launches per tick, and
+ * all chains into one sequence of batched kernel launches per tick (the
+ * evaluations too, with batched = 1), and
  * admits new chains while others are in flight when the arena has room.
  * If adapt_step is set, after each trajectory eps <- eps / 1.2 when the
  * acceptance probability is below 0.2, else eps <- min(eps0, 1.2 eps)
@@ -93,8 +94,14 @@ typedef struct hmc_server hmc_server;
 typedef struct {
   int32_t max_chains;          /* request-table capacity, >= 1 */
   int32_t max_batch;           /* requests per tick, >= 1 */
-  int32_t batched;             /* 1: a tick's evaluations overlap on several streams;
-                                  0: they run one after another on the server stream */
+  int32_t batched;             /* 1: batched launches: every kernel of the evaluation
+                                  sequence runs as one grid over all chains of the tick
+                                  (one grid per kernel instantiation and stage); each
+                                  chain's workgroups compute exactly what its own launch
+                                  would;
+                                  2: each chain's sequence is launched on its own, the
+                                  chains spread over several streams;
+                                  0: one chain after another on the server stream */
   int32_t inflight_ticks;       /* ticks queued on the device at once: 0 or 1 = one (the host
                                   builds the next tick after the current one completes),
                                   2 = two (the next tick is built and queued while the

@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libbayesvis.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["field.hip", "synth.hip", "synth_split.hip", "synth_sep.hip", "fringe.hip", "gains.hip", "filter.hip", "mapmaking.hip", "api.hip",
-           "hmc.hip", "serve.hip", "mass.hip"]
+           "hmc.hip", "serve.hip", "mass.hip", "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # MFMA operands and results in ordinary VGPRs (on gfx950 they share one

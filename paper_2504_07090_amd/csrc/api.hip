@@ -3,6 +3,7 @@
 // to the host.
 #include <mutex>
 
+#include "batch.hpp"
 #include "objects.hpp"
 
 using namespace bv;
@@ -18,18 +19,29 @@ void check_field(const vis_field* f) {
 namespace bv {
 
 void forward_core(const vis_field* f, const float* alm, const float* fwhm, hipStream_t s) {
-  launch_synth_fwd(f, alm, f->scr.img, s);
-  launch_fringe_fwd(f, f->scr.img, fwhm, f->scr.vu, s);
+  { StageScope sc(kStageSynthFwd); launch_synth_fwd(f, alm, f->scr.img, s); }
+  { StageScope sc(kStageFringeFwd); launch_fringe_fwd(f, f->scr.img, fwhm, f->scr.vu, s); }
 }
 
 void adjoint_tail(const vis_field* f, const float* fwhm, float* grad_alm, float2* grad_gains,
                   float* grad_fwhm, bool with_chi2, double* chi2, hipStream_t s) {
-  launch_reduce_grads(f, with_chi2, f->scr.chi_part, chi2, f->scr.g_part, grad_gains,
-                      f->scr.f_part, nullptr, s);
-  launch_fringe_adj(f, f->scr.img, fwhm, f->scr.gco, f->scr.dimg, f->scr.f_part, s);
-  if (grad_fwhm != nullptr)
+  {
+    StageScope sc(kStageReduce);
+    launch_reduce_grads(f, with_chi2, f->scr.chi_part, chi2, f->scr.g_part, grad_gains,
+                        f->scr.f_part, nullptr, s);
+  }
+  {
+    StageScope sc(kStageFringeAdj);
+    launch_fringe_adj(f, f->scr.img, fwhm, f->scr.gco, f->scr.dimg, f->scr.f_part, s);
+  }
+  if (grad_fwhm != nullptr) {
+    StageScope sc(kStageReduceF);
     launch_reduce_grads(f, false, nullptr, nullptr, nullptr, nullptr, f->scr.f_part, grad_fwhm, s);
-  if (grad_alm != nullptr) launch_synth_adj(f, f->scr.dimg, grad_alm, s);
+  }
+  if (grad_alm != nullptr) {
+    StageScope sc(kStageSynthAdj);
+    launch_synth_adj(f, f->scr.dimg, grad_alm, s);
+  }
 }
 
 }  // namespace bv
@@ -109,6 +121,7 @@ vis_status chi2_and_grad(const vis_field* f, const vis_c64* data, float sigma_n,
                  f->scr.gco, f->scr.g_part, s);
     const bool any_grad = grad_alm || grad_gains || grad_fwhm;
     if (!any_grad) {
+      StageScope sc(kStageReduce);
       launch_reduce_grads(f, true, f->scr.chi_part, chi2, nullptr, nullptr, nullptr, nullptr, s);
       return;
     }

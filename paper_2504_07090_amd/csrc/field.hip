@@ -11,6 +11,7 @@
 #include <utility>
 #include <vector>
 
+#include "batch.hpp"
 #include "objects.hpp"
 
 namespace bv {
@@ -61,7 +62,8 @@ Profiler::~Profiler() {
 }
 
 ProfScope::ProfScope(Profiler* p_, const char* n, hipStream_t s) : p(p_), name(n), st(s) {
-  if (p && p->on) {
+  // a recorded (batched) launch runs later as part of a shared grid: no timing
+  if (p && p->on && thread_recorder() == nullptr) {
     a = p->get();
     BV_HIP(hipEventRecord(a, st));
   }

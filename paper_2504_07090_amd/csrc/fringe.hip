@@ -33,6 +33,7 @@
 // with G built from omega(n, +m), omega(n, -m); it runs as the GEMM
 // T[r][p] = sum_c G[r][c] Bb[c][p] on MFMA followed by a per-pixel dot with A.
 // dL/dI(p, nu) = dOmega sum_t B Z and dL/dF = dOmega sum (dB/dF) I Z follow.
+#include "batch.hpp"
 #include "objects.hpp"
 
 namespace bv {
@@ -267,14 +268,44 @@ __device__ __forceinline__ void write_powers_split(float* As, uint32_t* Bh, uint
 // resident waves per SIMD (<= 128 VGPRs) for extents up to 8.
 constexpr int kFwdWaves = 4;
 
+struct FwdArgs {
+  int nf, nt, nvp, nubl;
+  float d_omega;
+  double beam_ref;
+  const double* freq;
+  const double* P1;
+  const double* P2;
+  const float* TH2;
+  const int* tchunk_off;
+  const int* tchunk;
+  const int2* ubl_nm;
+  const float* img;
+  const float* fwhm;
+  float2* vu;
+};
+
 template <int D>
-__global__ void __launch_bounds__(64 * kFwdWaves)
-__attribute__((amdgpu_waves_per_eu(D <= 8 ? 4 : 2)))
-k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
-             const double* __restrict__ freq, const double* P1, const double* P2,
-             const float* TH2, const int* __restrict__ tchunk_off,
-             const int* __restrict__ tchunk, const int2* __restrict__ ubl_nm, const float* img,
-             const float* __restrict__ fwhm, float2* __restrict__ vu) {
+struct KFringeFwd {
+  using Args = FwdArgs;
+  static constexpr int kThreads = 64 * kFwdWaves, kWaves = D <= 8 ? 4 : 2;
+  static __device__ void run(const FwdArgs& args, const Blk& B);
+};
+
+template <int D>
+__device__ void KFringeFwd<D>::run(const FwdArgs& args, const Blk& B) {
+  const int nf = args.nf, nt = args.nt, nvp = args.nvp, nubl = args.nubl;
+  const float d_omega = args.d_omega;
+  const double beam_ref = args.beam_ref;
+  const double* __restrict__ freq = args.freq;
+  const double* P1 = args.P1;
+  const double* P2 = args.P2;
+  const float* TH2 = args.TH2;
+  const int* __restrict__ tchunk_off = args.tchunk_off;
+  const int* __restrict__ tchunk = args.tchunk;
+  const int2* __restrict__ ubl_nm = args.ubl_nm;
+  const float* img = args.img;
+  const float* __restrict__ fwhm = args.fwhm;
+  float2* __restrict__ vu = args.vu;
   using T = Tile<D>;
   constexpr int RT = T::RT, W = T::W;
   __shared__ __attribute__((aligned(16))) float As_all[kFwdWaves][64 * W];
@@ -283,7 +314,7 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   float* As = As_all[wv];   // this wave's operand rows
   float* Bs = Bs_all[wv];
-  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int L = xcd_logical(B.x, B.nx);
   if (L >= nf * nt) return;   // uniform over the block
   int t, f;
   tile_map(L, nt, nf, 4, 32, t, f);   // 128 resident blocks per XCD: 4 times x 32 channels
@@ -476,13 +507,46 @@ k_fringe_fwd(int nf, int nt, int nvp, int nubl, float d_omega, double beam_ref,
 template <int RT, bool SPLIT> struct AdjCoef { f4 gv[RT][RT]; };
 template <int RT> struct AdjCoef<RT, true> { h8 ga[RT][RT]; h4 gb[RT][RT]; };
 
+struct AdjArgs {
+  int nf, nt, nvp, nchunks, gstride;
+  float d_omega;
+  double beam_ref;
+  const double* freq;
+  const double* P1;
+  const double* P2;
+  const float* TH2;
+  const int2* chunk_t;
+  const float* img;
+  const float* fwhm;
+  const float* gco;
+  const float* gco_lane;
+  float* dimg;
+  float* f_part;
+};
+
 template <int D, bool SPLIT>
-__global__ void __launch_bounds__(64)
-k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, double beam_ref,
-             const double* __restrict__ freq, const double* P1, const double* P2,
-             const float* TH2, const int2* __restrict__ chunk_t, const float* __restrict__ img,
-             const float* __restrict__ fwhm, const float* __restrict__ gco, const float* gco_lane,
-             float* __restrict__ dimg, float* __restrict__ f_part) {
+struct KFringeAdj {
+  using Args = AdjArgs;
+  static constexpr int kThreads = 64, kWaves = 1;
+  static __device__ void run(const AdjArgs& args, const Blk& B);
+};
+
+template <int D, bool SPLIT>
+__device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
+  const int nf = args.nf, nvp = args.nvp, nchunks = args.nchunks, gstride = args.gstride;
+  const float d_omega = args.d_omega;
+  const double beam_ref = args.beam_ref;
+  const double* __restrict__ freq = args.freq;
+  const double* P1 = args.P1;
+  const double* P2 = args.P2;
+  const float* TH2 = args.TH2;
+  const int2* __restrict__ chunk_t = args.chunk_t;
+  const float* __restrict__ img = args.img;
+  const float* __restrict__ fwhm = args.fwhm;
+  const float* __restrict__ gco = args.gco;
+  const float* gco_lane = args.gco_lane;
+  float* __restrict__ dimg = args.dimg;
+  float* __restrict__ f_part = args.f_part;
   using T = Tile<D>;
   using R = SplitRows<T::W>;
   constexpr int RT = T::RT, W = T::W;
@@ -493,7 +557,7 @@ k_fringe_adj(int nf, int nt, int nvp, int nchunks, int gstride, float d_omega, d
   uint32_t* Bh = reinterpret_cast<uint32_t*>(Bs);
   uint32_t* Bl = Bh + 64 * R::BH;
   const int lane = threadIdx.x;
-  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int L = xcd_logical(B.x, B.nx);
   if (L >= nf * nchunks) return;
   int chunk, f;
   tile_map(L, nchunks, nf, 32, 16, chunk, f);   // 512 resident waves per XCD: 32 chunks x 16 channels
@@ -673,10 +737,10 @@ static void fwd_d(const vis_field* f, const float* img, const float* fwhm, float
   const int nblk = static_cast<int>(round_up(static_cast<long>(f->n_freq) * f->n_time, 8));
   const auto& T = f->tab;
   ProfScope ps(&f->prof, "k_fringe_fwd", st);
-  k_fringe_fwd<D><<<nblk, 64 * kFwdWaves, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_ubl,
-                                       static_cast<float>(f->d_omega), f->beam_ref_hz, T.freq, T.p1,
-                                       T.p2, T.th2, T.tchunk_off, T.tchunk, T.ubl_nm, img, fwhm, vu);
-  check_launch("k_fringe_fwd");
+  const FwdArgs a{f->n_freq, f->n_time, f->nv_pad, f->n_ubl, static_cast<float>(f->d_omega),
+                  f->beam_ref_hz, T.freq, T.p1, T.p2, T.th2, T.tchunk_off, T.tchunk, T.ubl_nm,
+                  img, fwhm, vu};
+  launch_k<KFringeFwd<D>>(dim3(nblk), 0, a, st, "k_fringe_fwd");
 }
 
 template <int D>
@@ -686,11 +750,13 @@ static void adj_d(const vis_field* f, const float* img, const float* fwhm, const
   const auto& T = f->tab;
   ProfScope ps(&f->prof, "k_fringe_adj", st);
   BV_REQUIRE(f->dtile == D, VIS_EINVAL, "internal: adjoint tile mismatch");
-  auto kern = fringe_split(f) ? k_fringe_adj<D, true> : k_fringe_adj<D, false>;
-  kern<<<nblk, 64, 0, st>>>(f->n_freq, f->n_time, f->nv_pad, f->n_chunks, f->gstride,
-                            static_cast<float>(f->d_omega), f->beam_ref_hz, T.freq, T.p1, T.p2,
-                            T.th2, T.chunk_t, img, fwhm, gco, gco, dimg, f_part);
-  check_launch("k_fringe_adj");
+  const AdjArgs a{f->n_freq, f->n_time, f->nv_pad, f->n_chunks, f->gstride,
+                  static_cast<float>(f->d_omega), f->beam_ref_hz, T.freq, T.p1, T.p2, T.th2,
+                  T.chunk_t, img, fwhm, gco, gco, dimg, f_part};
+  if (fringe_split(f))
+    launch_k<KFringeAdj<D, true>>(dim3(nblk), 0, a, st, "k_fringe_adj");
+  else
+    launch_k<KFringeAdj<D, false>>(dim3(nblk), 0, a, st, "k_fringe_adj");
 }
 
 #define BV_DISPATCH_EXTENT(ext, CALL)          \

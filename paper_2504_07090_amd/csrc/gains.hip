@@ -13,6 +13,7 @@
 //   dL/dg_a = sum_{(a, j)} c_aj g_j conj(V_aj) + sum_{(i, a)} conj(c_ia) g_i V_ia.
 // One 256-thread block per (t, nu) keeps the gains and unique visibilities of
 // that slice in LDS; every reduction runs in a fixed order.
+#include "batch.hpp"
 #include "objects.hpp"
 
 namespace bv {
@@ -202,7 +203,14 @@ __device__ __forceinline__ void write_coefficients(const GainArgs& a, const floa
 constexpr int kGainsMaxPerThread = 8;
 
 template <bool SORTED>
-__global__ void __launch_bounds__(256) k_gains(GainArgs a) {
+struct KGains {
+  using Args = GainArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const GainArgs& a, const Blk& B);
+};
+
+template <bool SORTED>
+__device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
   extern __shared__ float2 sm[];
   float2* g = sm;              // [nant]
   float2* v = sm + a.nant;     // [nubl]
@@ -211,8 +219,8 @@ __global__ void __launch_bounds__(256) k_gains(GainArgs a) {
   float2* ta = tu + a.nbl;     // [2 nbl] antenna terms in a_list order (SORTED)
   int* ulut = reinterpret_cast<int*>(ta + 2 * a.nbl);   // SORTED: LDS copy of the lookup
   __shared__ double red[4];
-  const int f = blockIdx.x, tid = threadIdx.x;
-  const int t0 = blockIdx.y * a.tslab, t1 = min(a.nt, t0 + a.tslab);
+  const int f = B.x, tid = threadIdx.x;
+  const int t0 = B.y * a.tslab, t1 = min(a.nt, t0 + a.tslab);
   const int nlut = (a.dr + 1) * (2 * a.dr + 1);
   for (int i = tid; i < a.nant; i += 256) g[i] = a.gains[static_cast<size_t>(f) * a.nant + i];
   if (SORTED)
@@ -406,13 +414,33 @@ __device__ double block_sum(const T* __restrict__ x, int n, double* red) {
 
 // grad_gains[f][a] = sum_t g_part[t][f][a]; block (nblk-1) also totals chi^2
 // and dL/dF in FP64.
-__global__ void __launch_bounds__(1024)
-k_reduce_grads(int nt, int nf, int nant, int nfpart, int with_chi2, const double* __restrict__ chi_part,
-               double* chi2, const float2* __restrict__ g_part, float2* grad_gains,
-               const float* __restrict__ f_part, float* grad_fwhm) {
+struct ReduceArgs {
+  int nt, nf, nant, nfpart, with_chi2;
+  const double* chi_part;
+  double* chi2;
+  const float2* g_part;
+  float2* grad_gains;
+  const float* f_part;
+  float* grad_fwhm;
+};
+
+struct KReduceGrads {
+  using Args = ReduceArgs;
+  static constexpr int kThreads = 1024, kWaves = 1;
+  static __device__ void run(const ReduceArgs& a, const Blk& B);
+};
+
+__device__ void KReduceGrads::run(const ReduceArgs& a, const Blk& B) {
+  const int nt = a.nt, nf = a.nf, nant = a.nant, nfpart = a.nfpart, with_chi2 = a.with_chi2;
+  const double* __restrict__ chi_part = a.chi_part;
+  double* chi2 = a.chi2;
+  const float2* __restrict__ g_part = a.g_part;
+  float2* grad_gains = a.grad_gains;
+  const float* __restrict__ f_part = a.f_part;
+  float* grad_fwhm = a.grad_fwhm;
   const int tid = threadIdx.x;
-  if (blockIdx.x + 1 < gridDim.x) {
-    const int idx = blockIdx.x * 1024 + tid;
+  if (B.x + 1 < B.nx) {
+    const int idx = B.x * 1024 + tid;
     if (idx >= nf * nant || grad_gains == nullptr) return;
     // eight independent partial sums (times t = q mod 8), combined in order:
     // eight loads in flight per thread instead of one chain of nt
@@ -490,19 +518,19 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
   const size_t lds_sorted = lds + 3 * sizeof(float2) * f->n_bl +
                             sizeof(int) * (f->extent + 1) * (2 * f->extent + 1);
   ProfScope ps(&f->prof, "k_gains", st);
+  StageScope sc(kStageGains);
   if (mode != kGainFwd && lds_sorted <= kGainsSortedLds && f->n_bl <= 256 * kGainsMaxPerThread &&
       f->n_ubl <= 256) {
     // enough times per block that the grid is about one round of resident blocks
     const long slots = static_cast<long>(f->n_cu) * std::max<long>(1, (160 * 1024) / static_cast<long>(lds_sorted + 64));
     a.tslab = std::max(1, std::min(f->n_time, ceil_div(static_cast<long>(f->n_time) * f->n_freq, slots)));
     dim3 grid(f->n_freq, ceil_div(f->n_time, a.tslab));
-    k_gains<true><<<grid, 256, lds_sorted, st>>>(a);
+    launch_k<KGains<true>>(grid, lds_sorted, a, st, "k_gains");
   } else {
     a.tslab = 1;
     dim3 grid(f->n_freq, f->n_time);
-    k_gains<false><<<grid, 256, lds, st>>>(a);
+    launch_k<KGains<false>>(grid, lds, a, st, "k_gains");
   }
-  check_launch("k_gains");
 }
 
 void launch_reduce_grads(const vis_field* f, bool with_chi2, const double* chi_part, double* chi2,
@@ -510,10 +538,9 @@ void launch_reduce_grads(const vis_field* f, bool with_chi2, const double* chi_p
                          float* grad_fwhm, hipStream_t st) {
   const int nblk = (grad_gains != nullptr ? ceil_div(static_cast<long>(f->n_freq) * f->n_ant, 1024) : 0) + 1;
   ProfScope ps(&f->prof, "k_reduce_grads", st);
-  k_reduce_grads<<<nblk, 1024, 0, st>>>(f->n_time, f->n_freq, f->n_ant, f->n_freq * f->n_chunks,
-                                       with_chi2 ? 1 : 0, chi_part, chi2, g_part, grad_gains,
-                                       f_part, grad_fwhm);
-  check_launch("k_reduce_grads");
+  const ReduceArgs a{f->n_time, f->n_freq, f->n_ant, f->n_freq * f->n_chunks, with_chi2 ? 1 : 0,
+                     chi_part, chi2, g_part, grad_gains, f_part, grad_fwhm};
+  launch_k<KReduceGrads>(dim3(nblk), 0, a, st, "k_reduce_grads");
 }
 
 }  // namespace bv

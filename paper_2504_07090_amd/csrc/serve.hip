@@ -26,6 +26,7 @@
 #include <thread>
 #include <vector>
 
+#include "batch.hpp"
 #include "hmc.hpp"
 
 #include "../../include/bayesvis_serve.h"
@@ -194,13 +195,25 @@ struct Slot {
   HmcTask* dev_tasks = nullptr;      // in the arena
   int* dev_blk = nullptr;
   HmcState* dev_states = nullptr;    // finalize output, [max_batch]
+  // argument tables and workgroup entries of the batched evaluation launches
+  unsigned char* host_batch = nullptr;   // pinned
+  unsigned char* dev_batch = nullptr;    // in the arena
+  size_t batch_bytes = 0;
 };
 
 constexpr int kSlots = 3;
 // block prefixes of a tick: pre, post and restore/apply elementwise launches,
 // then the channel prefixes of the pre and post gain-block launches
 constexpr int kPrefixes = 5;
-constexpr int kSubStreams = 4;   // evaluation streams of a batched tick (hardware queues)
+constexpr int kSubStreams = 4;   // evaluation streams of a multi-stream tick (hardware queues)
+// staging of the batched evaluation launches: at most this many launches per
+// evaluation, each with an argument block of at most LaunchRec::args bytes
+constexpr int kMaxLaunchesPerEval = 16;
+inline size_t batch_stage_bytes(int max_batch) {
+  return round_up(static_cast<size_t>(max_batch) * kMaxLaunchesPerEval *
+                      (sizeof(LaunchRec::args) + sizeof(BatchEntry) + 64) +
+                  64 * 1024, 256);
+}
 
 }  // namespace bv
 
@@ -384,9 +397,37 @@ void hmc_server::enqueue(Tick& t) {
   if (hmc_tasks) launch_hmc_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
   if (nuts_tasks) launch_nuts_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
   launch_hmc_gainblk(S.dev_tasks, npre, S.dev_blk + 3 * (nb + 1), cpre, stream);
-  // evaluations: in a batched tick the chains' evaluation sequences run on
-  // several streams so the kernels of different fields overlap on the device
-  const int nsub = (cfg.batched && evs.size() > 1) ? std::min<int>(kSubStreams, evs.size()) : 0;
+  // evaluations.  Batched (cfg.batched == 1): every kernel of the evaluation
+  // sequence runs as one grid over all chains of the tick that need it (one
+  // grid per kernel instantiation, stage by stage).  Multi-stream
+  // (cfg.batched == 2): each chain's sequence is launched on its own, spread
+  // over several streams so that kernels of different fields overlap.
+  if (cfg.batched == 1 && !evs.empty()) {
+    Recorder rec;
+    struct Install {
+      explicit Install(Recorder* r) { thread_recorder() = r; }
+      ~Install() { thread_recorder() = nullptr; }
+    };
+    {
+      Install in(&rec);
+      for (const Chain* c : evs) {
+        rec.begin_eval();
+        const float* q = c->ptr(c->L.off_q);
+        float* g = c->ptr(c->L.off_gchi);
+        const vis_status s = chi2_and_grad(
+            c->field, reinterpret_cast<const vis_c64*>(c->data), c->sigma_n, q,
+            reinterpret_cast<const vis_c64*>(q + c->L.goff), q + c->L.len - 1, &c->st()->chi2, g,
+            reinterpret_cast<vis_c64*>(g + c->L.goff), g + c->L.len - 1, stream);
+        if (s != VIS_OK) throw Failure{s};
+      }
+    }
+    hipEvent_t evs_b[kSubStreams + 1];
+    for (int i = 0; i < kSubStreams; ++i) evs_b[i] = ev_sub[i];
+    evs_b[kSubStreams] = ev_pre;
+    run_batched(rec, S.host_batch, S.dev_batch, S.batch_bytes, stream, kSubStreams, sub, evs_b);
+    evs.clear();
+  }
+  const int nsub = (cfg.batched == 2 && evs.size() > 1) ? std::min<int>(kSubStreams, evs.size()) : 0;
   if (nsub > 0) {
     hip_or_throw(hipEventRecord(ev_pre, stream), "event record");
     for (int i = 0; i < nsub; ++i) hip_or_throw(hipStreamWaitEvent(sub[i], ev_pre, 0), "stream wait");
@@ -550,6 +591,7 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
     BV_REQUIRE(cfg->max_batch >= 1 && cfg->max_batch <= 1024, VIS_EINVAL, "max_batch out of range");
     BV_REQUIRE(cfg->inflight_ticks >= 0 && cfg->inflight_ticks <= kSlots - 1, VIS_EINVAL,
                "inflight_ticks must be 0, 1 or 2");
+    BV_REQUIRE(cfg->batched >= 0 && cfg->batched <= 2, VIS_EINVAL, "batched must be 0, 1 or 2");
     s = new hmc_server();
     s->cfg = *cfg;
     s->depth = cfg->inflight_ticks == 2 ? 2 : 1;
@@ -558,7 +600,8 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
     const size_t task_bytes = round_up(sizeof(HmcTask) * 4 * nb, 256);
     const size_t blk_bytes = round_up(sizeof(int) * kPrefixes * (nb + 1), 256);
     const size_t st_bytes = round_up(sizeof(HmcState) * nb, 256);
-    const size_t per = task_bytes + blk_bytes + st_bytes;
+    const size_t bb = cfg->batched == 1 ? batch_stage_bytes(nb) : 0;
+    const size_t per = task_bytes + blk_bytes + st_bytes + bb;
     const size_t reserve = kSlots * per;
     BV_REQUIRE(arena_bytes > reserve, VIS_ENOMEM, "arena smaller than the %zu-byte tick tables",
                reserve);
@@ -573,9 +616,14 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
       S.host_blk = reinterpret_cast<int*>(reinterpret_cast<char*>(S.host_tasks) + task_bytes);
       BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_states), sizeof(HmcState) * nb));
       std::memset(S.host_tasks, 0, S.table_bytes);
+      if (bb > 0) {
+        S.dev_batch = reinterpret_cast<unsigned char*>(base + i * per + task_bytes + blk_bytes + st_bytes);
+        S.batch_bytes = bb;
+        BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_batch), bb));
+      }
     }
     s->arena.init(base + reserve, arena_bytes - reserve);
-    if (cfg->batched) {
+    if (cfg->batched != 0) {
       for (int i = 0; i < kSubStreams; ++i) {
         BV_HIP(hipStreamCreateWithFlags(&s->sub[i], hipStreamNonBlocking));
         BV_HIP(hipEventCreateWithFlags(&s->ev_sub[i], hipEventDisableTiming));
@@ -590,6 +638,7 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
     for (auto& S : s->slots) {
       if (S.host_tasks) (void)hipHostFree(S.host_tasks);
       if (S.host_states) (void)hipHostFree(S.host_states);
+      if (S.host_batch) (void)hipHostFree(S.host_batch);
     }
     delete s;
   }
@@ -813,6 +862,7 @@ vis_status hmc_server_destroy(hmc_server* s) {
   for (auto& S : s->slots) {
     if (S.host_tasks) (void)hipHostFree(S.host_tasks);
     if (S.host_states) (void)hipHostFree(S.host_states);
+    if (S.host_batch) (void)hipHostFree(S.host_batch);
   }
   delete s;
   return VIS_OK;

@@ -13,6 +13,7 @@
 //
 // MFMA v_mfma_f32_16x16x4_f32 operand layout (wave64):
 //   A[i][k]: lane i + 16 k;  B[k][j]: lane j + 16 k;  D[i][j]: lane j + 16 (i / 4), register i % 4.
+#include "batch.hpp"
 #include "objects.hpp"
 
 namespace bv {
@@ -25,9 +26,30 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
 
 // apad[f][c] = alm[f][c] for f < nf, c < nm, else 0 (rows of kpad floats,
 // 64 rows per 64-row tile), so the GEMMs load aligned, unconditional vectors.
-__global__ void __launch_bounds__(256)
-k_pad_alm(int nf, int nm, int kpad, int nrows, const float* __restrict__ alm, float* __restrict__ apad) {
-  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+struct PadAlmArgs {
+  int nf;
+  int nm;
+  int kpad;
+  int nrows;
+  const float* alm;
+  float* apad;
+};
+
+struct KPadAlm {
+  using Args = PadAlmArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const PadAlmArgs& args_, const Blk& B_);
+};
+
+__device__ void KPadAlm::run(const PadAlmArgs& args_, const Blk& B_) {
+  int nf = args_.nf;
+  int nm = args_.nm;
+  int kpad = args_.kpad;
+  int nrows = args_.nrows;
+  const float* __restrict__ alm = args_.alm;
+  float* __restrict__ apad = args_.apad;
+
+  const long idx = static_cast<long>(B_.x) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<long>(nrows) * kpad) return;
   const int f = static_cast<int>(idx / kpad), c = static_cast<int>(idx - static_cast<long>(f) * kpad);
   apad[idx] = (f < nf && c < nm) ? alm[static_cast<size_t>(f) * nm + c] : 0.f;
@@ -38,8 +60,7 @@ void pad_alm(const vis_field* f, const float* alm, hipStream_t st) {
   const int nrows = static_cast<int>(round_up(f->n_freq, 64));
   const long n = static_cast<long>(nrows) * kpad;
   ProfScope ps(&f->prof, "k_pad_alm", st);
-  k_pad_alm<<<ceil_div(n, 256), 256, 0, st>>>(f->n_freq, f->n_modes, kpad, nrows, alm, f->scr.apad);
-  check_launch("k_pad_alm");
+  launch_k<KPadAlm>(ceil_div(n, 256), 0, PadAlmArgs{f->n_freq, f->n_modes, kpad, nrows, alm, f->scr.apad}, st, "k_pad_alm");
 }
 
 // part[s][f][k] = sum_{c in split s, c < nm} alm[f][c] Y[vpix[k]][c]
@@ -48,16 +69,42 @@ void pad_alm(const vis_field* f, const float* alm, hipStream_t st) {
 // fixed order afterwards.  Three-stage pipeline: step t is computed from LDS
 // buffer t % 3 while step t+1 is stored into the next buffer and step t+3 is
 // being fetched into registers, so two compute phases cover each load.
-__global__ void __launch_bounds__(256)
-k_synth_fwd_f32(int nf, int nm, int nvp, int kpad, int kps, const float* __restrict__ apad,
-                const float* __restrict__ Y, const int* __restrict__ vpix, float* __restrict__ part) {
+struct SynthFwdF32Args {
+  int nf;
+  int nm;
+  int nvp;
+  int kpad;
+  int kps;
+  const float* apad;
+  const float* Y;
+  const int* vpix;
+  float* part;
+};
+
+struct KSynthFwdF32 {
+  using Args = SynthFwdF32Args;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const SynthFwdF32Args& args_, const Blk& B_);
+};
+
+__device__ void KSynthFwdF32::run(const SynthFwdF32Args& args_, const Blk& B_) {
+  int nf = args_.nf;
+  int nm = args_.nm;
+  int nvp = args_.nvp;
+  int kpad = args_.kpad;
+  int kps = args_.kps;
+  const float* __restrict__ apad = args_.apad;
+  const float* __restrict__ Y = args_.Y;
+  const int* __restrict__ vpix = args_.vpix;
+  float* __restrict__ part = args_.part;
+
   // pitch 34: the operand reads (16 rows x 4 columns per instruction) land on
   // 2 row + column, distinct over each half-wavefront
   __shared__ __attribute__((aligned(16))) float As[3][64][34];
   __shared__ __attribute__((aligned(16))) float Bs[3][64][34];
   typedef float f2 __attribute__((ext_vector_type(2)));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64, split = blockIdx.z;
+  const int n0 = B_.x * 64, m0 = B_.y * 64, split = B_.z;
   const int kbeg = split * kps, kend = min(nm, kbeg + kps);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = tid >> 2, lk = (tid & 3) * 8;
@@ -142,9 +189,26 @@ k_synth_fwd_f32(int nf, int nm, int nvp, int kpad, int kps, const float* __restr
 }
 
 // img[f][k] = sum_s part[s][f][k], fixed order over s.
-__global__ void __launch_bounds__(256)
-k_sum_fwd_splits(int nsplit, long n, const float* __restrict__ part, float* __restrict__ img) {
-  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+struct SumFwdSplitsArgs {
+  int nsplit;
+  long n;
+  const float* part;
+  float* img;
+};
+
+struct KSumFwdSplits {
+  using Args = SumFwdSplitsArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const SumFwdSplitsArgs& args_, const Blk& B_);
+};
+
+__device__ void KSumFwdSplits::run(const SumFwdSplitsArgs& args_, const Blk& B_) {
+  int nsplit = args_.nsplit;
+  long n = args_.n;
+  const float* __restrict__ part = args_.part;
+  float* __restrict__ img = args_.img;
+
+  const long idx = static_cast<long>(B_.x) * blockDim.x + threadIdx.x;
   if (idx >= n) return;
   float s = 0.f;
   for (int q = 0; q < nsplit; ++q) s += part[q * n + idx];
@@ -154,14 +218,38 @@ k_sum_fwd_splits(int nsplit, long n, const float* __restrict__ part, float* __re
 // part[s][f][c] = sum_{k in split s} dimg[f][k] Y[vpix[k]][c]
 // Block tile 64 (f) x 64 (c), K step 16 pixels, three-stage pipeline as in
 // the forward.
-__global__ void __launch_bounds__(256)
-k_synth_adj_f32(int nf, int nvp, int kpad, int kps, const float* __restrict__ dimg,
-                const float* __restrict__ Y, const int* __restrict__ vpix, float* __restrict__ part) {
+struct SynthAdjF32Args {
+  int nf;
+  int nvp;
+  int kpad;
+  int kps;
+  const float* dimg;
+  const float* Y;
+  const int* vpix;
+  float* part;
+};
+
+struct KSynthAdjF32 {
+  using Args = SynthAdjF32Args;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const SynthAdjF32Args& args_, const Blk& B_);
+};
+
+__device__ void KSynthAdjF32::run(const SynthAdjF32Args& args_, const Blk& B_) {
+  int nf = args_.nf;
+  int nvp = args_.nvp;
+  int kpad = args_.kpad;
+  int kps = args_.kps;
+  const float* __restrict__ dimg = args_.dimg;
+  const float* __restrict__ Y = args_.Y;
+  const int* __restrict__ vpix = args_.vpix;
+  float* __restrict__ part = args_.part;
+
   __shared__ __attribute__((aligned(16))) float As[3][64][18];
   __shared__ __attribute__((aligned(16))) float Bs[3][16][80];
   typedef float f2 __attribute__((ext_vector_type(2)));
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64, split = blockIdx.z;
+  const int n0 = B_.x * 64, m0 = B_.y * 64, split = B_.z;
   const int kbeg = split * kps, kend = min(nvp, kbeg + kps);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = tid >> 2, lk = (tid & 3) * 4;      // A loads: row f, 4 pixels
@@ -235,10 +323,30 @@ k_synth_adj_f32(int nf, int nvp, int kpad, int kps, const float* __restrict__ di
 }
 
 // grad[f][c] = sum_s part[s][f][c] for c < nm, fixed order over s.
-__global__ void __launch_bounds__(256)
-k_reduce_splits(int nsplit, int nf, int nm, int kpad, const float* __restrict__ part,
-                float* __restrict__ grad) {
-  const long idx = static_cast<long>(blockIdx.x) * blockDim.x + threadIdx.x;
+struct ReduceSplitsArgs {
+  int nsplit;
+  int nf;
+  int nm;
+  int kpad;
+  const float* part;
+  float* grad;
+};
+
+struct KReduceSplits {
+  using Args = ReduceSplitsArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const ReduceSplitsArgs& args_, const Blk& B_);
+};
+
+__device__ void KReduceSplits::run(const ReduceSplitsArgs& args_, const Blk& B_) {
+  int nsplit = args_.nsplit;
+  int nf = args_.nf;
+  int nm = args_.nm;
+  int kpad = args_.kpad;
+  const float* __restrict__ part = args_.part;
+  float* __restrict__ grad = args_.grad;
+
+  const long idx = static_cast<long>(B_.x) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<long>(nf) * nm) return;
   const int f = static_cast<int>(idx / nm), c = static_cast<int>(idx - static_cast<long>(f) * nm);
   float s = 0.f;
@@ -266,17 +374,15 @@ void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStrea
     pad_alm(f, alm, st);
     dim3 grid(f->nv_pad / 64, ceil_div(f->n_freq, 64), nsplit);
     ProfScope ps(&f->prof, "k_synth_fwd_f32", st);
-    k_synth_fwd_f32<<<grid, 256, 0, st>>>(f->n_freq, f->n_modes, f->nv_pad, b->kpad, kps,
-                                           f->scr.apad, b->y32, f->tab.vpix, dst);
-    check_launch("k_synth_fwd_f32");
+    launch_k<KSynthFwdF32>(grid, 0, SynthFwdF32Args{f->n_freq, f->n_modes, f->nv_pad, b->kpad, kps,
+                                           f->scr.apad, b->y32, f->tab.vpix, dst}, st, "k_synth_fwd_f32");
   } else {
     launch_synth_fwd_split(f, alm, dst, nsplit, kps, st);
   }
   if (nsplit > 1) {
     const long n = static_cast<long>(f->n_freq) * f->nv_pad;
     ProfScope ps(&f->prof, "k_sum_fwd_splits", st);
-    k_sum_fwd_splits<<<ceil_div(n, 256), 256, 0, st>>>(nsplit, n, f->scr.a_part, img);
-    check_launch("k_sum_fwd_splits");
+    launch_k<KSumFwdSplits>(ceil_div(n, 256), 0, SumFwdSplitsArgs{nsplit, n, f->scr.a_part, img}, st, "k_sum_fwd_splits");
   }
 }
 
@@ -296,15 +402,13 @@ void launch_synth_adj(const vis_field* f, const float* dimg, float* grad_alm, hi
     const int ncol = static_cast<int>(round_up(f->n_modes, 64));
     dim3 grid(ncol / 64, ceil_div(f->n_freq, 64), nsplit);
     ProfScope ps(&f->prof, "k_synth_adj_f32", st);
-    k_synth_adj_f32<<<grid, 256, 0, st>>>(f->n_freq, f->nv_pad, b->kpad, kps, dimg, b->y32,
-                                           f->tab.vpix, f->scr.a_part);
-    check_launch("k_synth_adj_f32");
+    launch_k<KSynthAdjF32>(grid, 0, SynthAdjF32Args{f->n_freq, f->nv_pad, b->kpad, kps, dimg, b->y32,
+                                           f->tab.vpix, f->scr.a_part}, st, "k_synth_adj_f32");
   }
   const long n = static_cast<long>(f->n_freq) * f->n_modes;
   ProfScope ps(&f->prof, "k_reduce_splits", st);
-  k_reduce_splits<<<ceil_div(n, 256), 256, 0, st>>>(nsplit, f->n_freq, f->n_modes, b->kpad,
-                                                     f->scr.a_part, grad_alm);
-  check_launch("k_reduce_splits");
+  launch_k<KReduceSplits>(ceil_div(n, 256), 0, ReduceSplitsArgs{nsplit, f->n_freq, f->n_modes, b->kpad,
+                                                     f->scr.a_part, grad_alm}, st, "k_reduce_splits");
 }
 
 }  // namespace bv

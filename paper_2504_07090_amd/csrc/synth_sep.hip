@@ -27,6 +27,7 @@
 // are always issued (a load under a divergent branch is waited for where the
 // branch ends), and terms past the end of K are removed by zeroing one operand
 // at the MFMA.
+#include "batch.hpp"
 #include "objects.hpp"
 
 namespace bv {
@@ -44,25 +45,25 @@ __device__ __forceinline__ f4 sep_mfma(float a, float b, f4 c) {
 // logical index with the blocks that share operand rows adjacent, so those
 // rows come from one XCD's L2 instead of being fetched once per XCD (the
 // forward Legendre stage keeps the launch order).
-__device__ __forceinline__ int sep_xcd_logical() {
-  const int total = gridDim.x * gridDim.y * gridDim.z;
-  const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+__device__ __forceinline__ int sep_xcd_logical(const Blk& B) {
+  const int total = B.nx * B.ny * B.nz;
+  const int b = B.x + B.nx * (B.y + B.ny * B.z);
   const int per = total / 8;
   return b >= 8 * per ? b : (b % 8) * per + b / 8;
 }
 
 // (x, y, z) block coordinates of logical block L with y and z fastest (the
 // Legendre stages: every block of one m shares that m's table rows).
-__device__ __forceinline__ int3 sep_blocks_m_major(int L) {
-  const int nyz = gridDim.y * gridDim.z, yz = L % nyz;
-  return make_int3(L / nyz, yz % gridDim.y, yz / gridDim.y);
+__device__ __forceinline__ int3 sep_blocks_m_major(int L, const Blk& B) {
+  const int nyz = B.ny * B.nz, yz = L % nyz;
+  return make_int3(L / nyz, yz % B.ny, yz / B.ny);
 }
 
 // (x, y, z) of logical block L with x fastest (the azimuthal stages: the
 // column or c tiles of one ring and channel tile share that ring's rows).
-__device__ __forceinline__ int3 sep_blocks_x_fastest(int L) {
-  const int yz = L / gridDim.x;
-  return make_int3(L % gridDim.x, yz % gridDim.y, yz / gridDim.y);
+__device__ __forceinline__ int3 sep_blocks_x_fastest(int L, const Blk& B) {
+  const int yz = L / B.nx;
+  return make_int3(L % B.nx, yz % B.ny, yz / B.ny);
 }
 
 constexpr int kSepBatch = 8;              // MFMAs whose operand loads are issued together
@@ -73,10 +74,27 @@ constexpr int kSepStep = 4 * kSepBatch;   // K covered per batch
 // chip), so the Legendre stage reads 16 channels of one mode as one 64-byte
 // segment.
 constexpr int kTrModes = 16, kTrChans = 64;
-__global__ void __launch_bounds__(256)
-k_alm_transpose(int nf, int nm, const float* __restrict__ a, float* __restrict__ at) {
+struct AlmTransposeArgs {
+  int nf;
+  int nm;
+  const float* a;
+  float* at;
+};
+
+struct KAlmTranspose {
+  using Args = AlmTransposeArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const AlmTransposeArgs& args_, const Blk& B_);
+};
+
+__device__ void KAlmTranspose::run(const AlmTransposeArgs& args_, const Blk& B_) {
+  int nf = args_.nf;
+  int nm = args_.nm;
+  const float* __restrict__ a = args_.a;
+  float* __restrict__ at = args_.at;
+
   __shared__ float tile[kTrChans][kTrModes + 1];
-  const int m0 = blockIdx.x * kTrModes;
+  const int m0 = B_.x * kTrModes;
   const int t = threadIdx.x;
   for (int f0 = 0; f0 < nf; f0 += kTrChans) {
     // read: 16 consecutive modes of 16 channel rows per pass
@@ -101,14 +119,40 @@ k_alm_transpose(int nf, int nm, const float* __restrict__ a, float* __restrict__
 // In MFMA step q the lanes of group kk = lane / 16 take l = l0 + 8 kk + q, so
 // every lane reads eight consecutive l of its ring's Legendre row (two
 // 16-byte loads) and each group of 16 lanes one 64-byte segment of `at`.
-__global__ void __launch_bounds__(64)
-k_sep_leg_fwd(int nz, int nf, int lmax, int blmax, int kaz, const float* __restrict__ lam,
-              const int* __restrict__ loff, const float* __restrict__ at, float* __restrict__ G) {
+struct SepLegFwdArgs {
+  int nz;
+  int nf;
+  int lmax;
+  int blmax;
+  int kaz;
+  const float* lam;
+  const int* loff;
+  const float* at;
+  float* G;
+};
+
+struct KSepLegFwd {
+  using Args = SepLegFwdArgs;
+  static constexpr int kThreads = 64, kWaves = 1;
+  static __device__ void run(const SepLegFwdArgs& args_, const Blk& B_);
+};
+
+__device__ void KSepLegFwd::run(const SepLegFwdArgs& args_, const Blk& B_) {
+  int nz = args_.nz;
+  int nf = args_.nf;
+  int lmax = args_.lmax;
+  int blmax = args_.blmax;
+  int kaz = args_.kaz;
+  const float* __restrict__ lam = args_.lam;
+  const int* __restrict__ loff = args_.loff;
+  const float* __restrict__ at = args_.at;
+  float* __restrict__ G = args_.G;
+
   // blocks in launch order: grouping an m's blocks on one XCD, as the adjoint
   // does, measured slower here (the rows shorten with |m|, so contiguous m
   // ranges leave the XCDs unevenly loaded)
-  const int m = static_cast<int>(blockIdx.x) - lmax, am = m < 0 ? -m : m;
-  const int j0 = blockIdx.y * 16, f0 = blockIdx.z * 16;
+  const int m = static_cast<int>(B_.x) - lmax, am = m < 0 ? -m : m;
+  const int j0 = B_.y * 16, f0 = B_.z * 16;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const int j = min(j0 + i, nz - 1), f = min(f0 + i, nf - 1);
   const int lp = sep_lpad(blmax, am);
@@ -143,10 +187,38 @@ k_sep_leg_fwd(int nz, int nf, int lmax, int blmax, int kaz, const float* __restr
 // grid (ceil(nphi / 32), nz, ceil(nf / 32)); each wave computes a 2 x 2 block of
 // 16 x 16 tiles (rows = channels, columns = pixels), so every operand load
 // feeds two MFMAs.
-__global__ void __launch_bounds__(64)
-k_sep_az_fwd(int nphi, int nf, int kaz, int nc, int toff, const float* Tt,
-             const float* G, const int* __restrict__ vidx, int nvp, float* __restrict__ img) {
-  const int3 bk = sep_blocks_x_fastest(sep_xcd_logical());
+struct SepAzFwdArgs {
+  int nphi;
+  int nf;
+  int kaz;
+  int nc;
+  int toff;
+  const float* Tt;
+  const float* G;
+  const int* vidx;
+  int nvp;
+  float* img;
+};
+
+struct KSepAzFwd {
+  using Args = SepAzFwdArgs;
+  static constexpr int kThreads = 64, kWaves = 1;
+  static __device__ void run(const SepAzFwdArgs& args_, const Blk& B_);
+};
+
+__device__ void KSepAzFwd::run(const SepAzFwdArgs& args_, const Blk& B_) {
+  int nphi = args_.nphi;
+  int nf = args_.nf;
+  int kaz = args_.kaz;
+  int nc = args_.nc;
+  int toff = args_.toff;
+  const float* Tt = args_.Tt;
+  const float* G = args_.G;
+  const int* __restrict__ vidx = args_.vidx;
+  int nvp = args_.nvp;
+  float* __restrict__ img = args_.img;
+
+  const int3 bk = sep_blocks_x_fastest(sep_xcd_logical(B_), B_);
   const int k0 = bk.x * 32, j = bk.y, f0 = bk.z * 32;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const float* grow[2];
@@ -216,11 +288,31 @@ k_sep_az_fwd(int nphi, int nf, int kaz, int nc, int toff, const float* Tt,
 
 // dfull[p][nu] = dimg[nu][vidx[p]] (0 for pixels never above the horizon):
 // a 64 x 64 tile transposed through LDS so reads and writes are coalesced.
-__global__ void __launch_bounds__(256)
-k_sep_scatter(int npix, int nf, int nvp, const int* __restrict__ vidx, const float* __restrict__ dimg,
-              float* __restrict__ dfull) {
+struct SepScatterArgs {
+  int npix;
+  int nf;
+  int nvp;
+  const int* vidx;
+  const float* dimg;
+  float* dfull;
+};
+
+struct KSepScatter {
+  using Args = SepScatterArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const SepScatterArgs& args_, const Blk& B_);
+};
+
+__device__ void KSepScatter::run(const SepScatterArgs& args_, const Blk& B_) {
+  int npix = args_.npix;
+  int nf = args_.nf;
+  int nvp = args_.nvp;
+  const int* __restrict__ vidx = args_.vidx;
+  const float* __restrict__ dimg = args_.dimg;
+  float* __restrict__ dfull = args_.dfull;
+
   __shared__ float tile[64][65];
-  const int p0 = blockIdx.x * 64, f0 = blockIdx.y * 64, tid = threadIdx.x;
+  const int p0 = B_.x * 64, f0 = B_.y * 64, tid = threadIdx.x;
   const int tp = tid & 63, tr = tid >> 6;
   const int p = p0 + tp;
   const int slot = p < npix ? vidx[p] : -1;
@@ -238,10 +330,36 @@ k_sep_scatter(int npix, int nf, int nvp, const int* __restrict__ vidx, const flo
 // H[j][c][nu] = sum_k T[k][c + toff] dfull[j nphi + k][nu] for c < nc = 2 lmax + 1.
 // grid (ceil(nc / 32), nz, ceil(nf / 32)); each wave computes a 2 x 2 block of
 // 16 x 16 tiles (rows = c, columns = channels).
-__global__ void __launch_bounds__(64)
-k_sep_az_adj(int nphi, int nf, int kaz, int nc, int kaz_t, int toff, const float* T,
-             const float* dfull, float* __restrict__ H) {
-  const int3 bk = sep_blocks_x_fastest(sep_xcd_logical());
+struct SepAzAdjArgs {
+  int nphi;
+  int nf;
+  int kaz;
+  int nc;
+  int kaz_t;
+  int toff;
+  const float* T;
+  const float* dfull;
+  float* H;
+};
+
+struct KSepAzAdj {
+  using Args = SepAzAdjArgs;
+  static constexpr int kThreads = 64, kWaves = 1;
+  static __device__ void run(const SepAzAdjArgs& args_, const Blk& B_);
+};
+
+__device__ void KSepAzAdj::run(const SepAzAdjArgs& args_, const Blk& B_) {
+  int nphi = args_.nphi;
+  int nf = args_.nf;
+  int kaz = args_.kaz;
+  int nc = args_.nc;
+  int kaz_t = args_.kaz_t;
+  int toff = args_.toff;
+  const float* T = args_.T;
+  const float* dfull = args_.dfull;
+  float* __restrict__ H = args_.H;
+
+  const int3 bk = sep_blocks_x_fastest(sep_xcd_logical(B_), B_);
   const int c0 = bk.x * 32, j = bk.y, f0 = bk.z * 32;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const float* trow[2];
@@ -310,10 +428,38 @@ k_sep_az_adj(int nphi, int nf, int kaz, int nc, int kaz_t, int toff, const float
 // grad[nu][l^2 + l + m] = sum_j lambda_l|m|(z_j) H[j][m + lmax][nu], l = |m| .. lmax;
 // 16 lanes read 16 consecutive l of one ring row of the m-major Legendre table.
 // grid (2 lmax + 1, ceil((lmax + 1) / 16), ceil(nf / 16)); D rows = l, columns = channels.
-__global__ void __launch_bounds__(64)
-k_sep_leg_adj(int nz, int nf, int nm, int lmax, int blmax, int kaz, const float* __restrict__ lam,
-              const int* __restrict__ loff, const float* __restrict__ H, float* __restrict__ grad) {
-  const int3 bk = sep_blocks_m_major(sep_xcd_logical());
+struct SepLegAdjArgs {
+  int nz;
+  int nf;
+  int nm;
+  int lmax;
+  int blmax;
+  int kaz;
+  const float* lam;
+  const int* loff;
+  const float* H;
+  float* grad;
+};
+
+struct KSepLegAdj {
+  using Args = SepLegAdjArgs;
+  static constexpr int kThreads = 64, kWaves = 1;
+  static __device__ void run(const SepLegAdjArgs& args_, const Blk& B_);
+};
+
+__device__ void KSepLegAdj::run(const SepLegAdjArgs& args_, const Blk& B_) {
+  int nz = args_.nz;
+  int nf = args_.nf;
+  int nm = args_.nm;
+  int lmax = args_.lmax;
+  int blmax = args_.blmax;
+  int kaz = args_.kaz;
+  const float* __restrict__ lam = args_.lam;
+  const int* __restrict__ loff = args_.loff;
+  const float* __restrict__ H = args_.H;
+  float* __restrict__ grad = args_.grad;
+
+  const int3 bk = sep_blocks_m_major(sep_xcd_logical(B_), B_);
   const int m = bk.x - lmax, am = m < 0 ? -m : m;
   const int l0 = am + 16 * bk.y, f0 = bk.z * 16;
   if (l0 > lmax) return;
@@ -351,22 +497,19 @@ void launch_synth_fwd_sep(const vis_field* f, const float* alm, float* img, hipS
   const int toff = b->lmax + kSepPad - L;   // T column of c = 0 (m = -L)
   {
     ProfScope ps(&f->prof, "k_alm_transpose", st);
-    k_alm_transpose<<<ceil_div(f->n_modes, kTrModes), 256, 0, st>>>(f->n_freq, f->n_modes, alm,
-                                                                     f->scr.sep_at);
-    check_launch("k_alm_transpose");
+    launch_k<KAlmTranspose>(ceil_div(f->n_modes, kTrModes), 0, AlmTransposeArgs{f->n_freq, f->n_modes, alm,
+                                                                     f->scr.sep_at}, st, "k_alm_transpose");
   }
   {
     ProfScope ps(&f->prof, "k_sep_leg_fwd", st);
     dim3 grid(2 * L + 1, ceil_div(b->nz, 16), ceil_div(f->n_freq, 16));
-    k_sep_leg_fwd<<<grid, 64, 0, st>>>(b->nz, f->n_freq, L, b->lmax, f->kaz, b->sep_lam, b->sep_loff,
-                                       f->scr.sep_at, f->scr.sep_g);
-    check_launch("k_sep_leg_fwd");
+    launch_k<KSepLegFwd>(grid, 0, SepLegFwdArgs{b->nz, f->n_freq, L, b->lmax, f->kaz, b->sep_lam, b->sep_loff,
+                                       f->scr.sep_at, f->scr.sep_g}, st, "k_sep_leg_fwd");
   }
   ProfScope ps(&f->prof, "k_sep_az_fwd", st);
   dim3 grid(ceil_div(b->nphi, 32), b->nz, ceil_div(f->n_freq, 32));
-  k_sep_az_fwd<<<grid, 64, 0, st>>>(b->nphi, f->n_freq, f->kaz, 2 * L + 1, toff, b->sep_tt, f->scr.sep_g,
-                                    f->tab.vidx, f->nv_pad, img);
-  check_launch("k_sep_az_fwd");
+  launch_k<KSepAzFwd>(grid, 0, SepAzFwdArgs{b->nphi, f->n_freq, f->kaz, 2 * L + 1, toff, b->sep_tt, f->scr.sep_g,
+                                    f->tab.vidx, f->nv_pad, img}, st, "k_sep_az_fwd");
 }
 
 void launch_synth_adj_sep(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st) {
@@ -377,22 +520,19 @@ void launch_synth_adj_sep(const vis_field* f, const float* dimg, float* grad_alm
   {
     ProfScope ps(&f->prof, "k_sep_scatter", st);
     dim3 grid(ceil_div(b->n_pix, 64), ceil_div(f->n_freq, 64));
-    k_sep_scatter<<<grid, 256, 0, st>>>(b->n_pix, f->n_freq, f->nv_pad, f->tab.vidx, dimg,
-                                        f->scr.sep_dfull);
-    check_launch("k_sep_scatter");
+    launch_k<KSepScatter>(grid, 0, SepScatterArgs{b->n_pix, f->n_freq, f->nv_pad, f->tab.vidx, dimg,
+                                        f->scr.sep_dfull}, st, "k_sep_scatter");
   }
   {
     ProfScope ps(&f->prof, "k_sep_az_adj", st);
     dim3 grid(ceil_div(2 * L + 1, 32), b->nz, ceil_div(f->n_freq, 32));
-    k_sep_az_adj<<<grid, 64, 0, st>>>(b->nphi, f->n_freq, f->kaz, 2 * L + 1, b->kaz_t, toff, b->sep_t,
-                                      f->scr.sep_dfull, f->scr.sep_g);
-    check_launch("k_sep_az_adj");
+    launch_k<KSepAzAdj>(grid, 0, SepAzAdjArgs{b->nphi, f->n_freq, f->kaz, 2 * L + 1, b->kaz_t, toff, b->sep_t,
+                                      f->scr.sep_dfull, f->scr.sep_g}, st, "k_sep_az_adj");
   }
   ProfScope ps(&f->prof, "k_sep_leg_adj", st);
   dim3 grid(2 * L + 1, ceil_div(L + 1, 16), ceil_div(f->n_freq, 16));
-  k_sep_leg_adj<<<grid, 64, 0, st>>>(b->nz, f->n_freq, f->n_modes, L, b->lmax, f->kaz, b->sep_lam,
-                                     b->sep_loff, f->scr.sep_g, grad_alm);
-  check_launch("k_sep_leg_adj");
+  launch_k<KSepLegAdj>(grid, 0, SepLegAdjArgs{b->nz, f->n_freq, f->n_modes, L, b->lmax, f->kaz, b->sep_lam,
+                                     b->sep_loff, f->scr.sep_g, grad_alm}, st, "k_sep_leg_adj");
 }
 
 }  // namespace bv

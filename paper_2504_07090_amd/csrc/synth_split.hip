@@ -17,6 +17,7 @@
 //
 // v_mfma_f32_16x16x32_{bf16,f16}: lane l holds A[l % 16][8 (l / 16) + j] and
 // B[8 (l / 16) + j][l % 16], j = 0..7; D as for the other 16x16 MFMAs.
+#include "batch.hpp"
 #include "objects.hpp"
 
 namespace bv {
@@ -63,10 +64,27 @@ constexpr int kSplitCols = 2048;   // columns per block in the row-split kernels
 constexpr int kHP = 40;            // LDS pitch (16-bit elements) of a 32-wide K tile
 
 // pmax[r][ch] = max |src[r][c]| over the ch-th block of kSplitCols columns.
-__global__ void __launch_bounds__(256)
-k_row_absmax(int ncols, int ld, const float* __restrict__ src, float* __restrict__ pmax) {
+struct RowAbsmaxArgs {
+  int ncols;
+  int ld;
+  const float* src;
+  float* pmax;
+};
+
+struct KRowAbsmax {
+  using Args = RowAbsmaxArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const RowAbsmaxArgs& args_, const Blk& B_);
+};
+
+__device__ void KRowAbsmax::run(const RowAbsmaxArgs& args_, const Blk& B_) {
+  int ncols = args_.ncols;
+  int ld = args_.ld;
+  const float* __restrict__ src = args_.src;
+  float* __restrict__ pmax = args_.pmax;
+
   __shared__ float red[4];
-  const int ch = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+  const int ch = B_.x, r = B_.y, tid = threadIdx.x;
   const float* row = src + static_cast<size_t>(r) * ld;
   float m = 0.f;
   for (int c = ch * kSplitCols + tid; c < min(ncols, (ch + 1) * kSplitCols); c += 256)
@@ -75,17 +93,45 @@ k_row_absmax(int ncols, int ld, const float* __restrict__ src, float* __restrict
   if ((tid & 63) == 0) red[tid >> 6] = m;
   __syncthreads();
   if (tid == 0)
-    pmax[static_cast<size_t>(r) * gridDim.x + ch] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    pmax[static_cast<size_t>(r) * B_.nx + ch] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
 // Rows r < nrows of src (ncols valid columns) -> hi/lo rows of ld_dst
 // columns, zero beyond ncols and for rows nrows..gridDim.y-1; rscale[r] = 1/s.
+struct SplitRowsArgs {
+  int nrows;
+  int ncols;
+  int ld_src;
+  int ld_dst;
+  const float* src;
+  const float* pmax;
+  int nch;
+  unsigned short* hi;
+  unsigned short* lo;
+  float* rscale;
+};
+
 template <class Fmt>
-__global__ void __launch_bounds__(256)
-k_split_rows(int nrows, int ncols, int ld_src, int ld_dst, const float* __restrict__ src,
-             const float* __restrict__ pmax, int nch, unsigned short* __restrict__ hi,
-             unsigned short* __restrict__ lo, float* __restrict__ rscale) {
-  const int ch = blockIdx.x, r = blockIdx.y, tid = threadIdx.x;
+struct KSplitRows {
+  using Args = SplitRowsArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const SplitRowsArgs& args_, const Blk& B_);
+};
+
+template <class Fmt>
+__device__ void KSplitRows<Fmt>::run(const SplitRowsArgs& args_, const Blk& B_) {
+  int nrows = args_.nrows;
+  int ncols = args_.ncols;
+  int ld_src = args_.ld_src;
+  int ld_dst = args_.ld_dst;
+  const float* __restrict__ src = args_.src;
+  const float* __restrict__ pmax = args_.pmax;
+  int nch = args_.nch;
+  unsigned short* __restrict__ hi = args_.hi;
+  unsigned short* __restrict__ lo = args_.lo;
+  float* __restrict__ rscale = args_.rscale;
+
+  const int ch = B_.x, r = B_.y, tid = threadIdx.x;
   float s = 1.0f;
   if (Fmt::kScaled && r < nrows) {
     float m = 0.f;
@@ -108,16 +154,47 @@ k_split_rows(int nrows, int ncols, int ld_src, int ld_dst, const float* __restri
 
 // part[split][f][k] = sum_{c in split} a[f][c] Y[vpix[k]][c]; tile 64 (f) x 64 (k),
 // K step 32.  A: split coefficient rows [nf_pad][kpad], zero beyond the modes.
+struct SynthFwdSplitArgs {
+  int nf;
+  int nm;
+  int nvp;
+  int kpad;
+  int kps;
+  const unsigned short* Ahg;
+  const unsigned short* Alg;
+  const float* rscale;
+  const unsigned short* Yh;
+  const unsigned short* Yl;
+  const int* vpix;
+  float* part;
+};
+
 template <class Fmt>
-__global__ void __launch_bounds__(256)
-k_synth_fwd_split(int nf, int nm, int nvp, int kpad, int kps, const unsigned short* __restrict__ Ahg,
-                  const unsigned short* __restrict__ Alg, const float* __restrict__ rscale,
-                  const unsigned short* __restrict__ Yh, const unsigned short* __restrict__ Yl,
-                  const int* __restrict__ vpix, float* __restrict__ part) {
+struct KSynthFwdSplit {
+  using Args = SynthFwdSplitArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const SynthFwdSplitArgs& args_, const Blk& B_);
+};
+
+template <class Fmt>
+__device__ void KSynthFwdSplit<Fmt>::run(const SynthFwdSplitArgs& args_, const Blk& B_) {
+  int nf = args_.nf;
+  int nm = args_.nm;
+  int nvp = args_.nvp;
+  int kpad = args_.kpad;
+  int kps = args_.kps;
+  const unsigned short* __restrict__ Ahg = args_.Ahg;
+  const unsigned short* __restrict__ Alg = args_.Alg;
+  const float* __restrict__ rscale = args_.rscale;
+  const unsigned short* __restrict__ Yh = args_.Yh;
+  const unsigned short* __restrict__ Yl = args_.Yl;
+  const int* __restrict__ vpix = args_.vpix;
+  float* __restrict__ part = args_.part;
+
   __shared__ __attribute__((aligned(16))) unsigned short Ah[2][64 * kHP], Al[2][64 * kHP];
   __shared__ __attribute__((aligned(16))) unsigned short Bh[2][64 * kHP], Bl[2][64 * kHP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64, split = blockIdx.z;
+  const int n0 = B_.x * 64, m0 = B_.y * 64, split = B_.z;
   const int kbeg = split * kps, kend = min(nm, kbeg + kps);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = tid >> 2, lk = (tid & 3) * 8;
@@ -184,16 +261,45 @@ k_synth_fwd_split(int nf, int nm, int nvp, int kpad, int kps, const unsigned sho
 
 // part[split][f][c] = sum_{k in split} dimg[f][k] Y[vpix[k]][c]; tile 64 (f) x 64 (c),
 // K step 32.  A: split dL/dI rows [nf_pad][nvp].
+struct SynthAdjSplitArgs {
+  int nf;
+  int nvp;
+  int kpad;
+  int kps;
+  const unsigned short* Dh;
+  const unsigned short* Dl;
+  const float* rscale;
+  const unsigned short* Yh;
+  const unsigned short* Yl;
+  const int* vpix;
+  float* part;
+};
+
 template <class Fmt>
-__global__ void __launch_bounds__(256)
-k_synth_adj_split(int nf, int nvp, int kpad, int kps, const unsigned short* __restrict__ Dh,
-                  const unsigned short* __restrict__ Dl, const float* __restrict__ rscale,
-                  const unsigned short* __restrict__ Yh, const unsigned short* __restrict__ Yl,
-                  const int* __restrict__ vpix, float* __restrict__ part) {
+struct KSynthAdjSplit {
+  using Args = SynthAdjSplitArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const SynthAdjSplitArgs& args_, const Blk& B_);
+};
+
+template <class Fmt>
+__device__ void KSynthAdjSplit<Fmt>::run(const SynthAdjSplitArgs& args_, const Blk& B_) {
+  int nf = args_.nf;
+  int nvp = args_.nvp;
+  int kpad = args_.kpad;
+  int kps = args_.kps;
+  const unsigned short* __restrict__ Dh = args_.Dh;
+  const unsigned short* __restrict__ Dl = args_.Dl;
+  const float* __restrict__ rscale = args_.rscale;
+  const unsigned short* __restrict__ Yh = args_.Yh;
+  const unsigned short* __restrict__ Yl = args_.Yl;
+  const int* __restrict__ vpix = args_.vpix;
+  float* __restrict__ part = args_.part;
+
   __shared__ __attribute__((aligned(16))) unsigned short Ah[2][64 * kHP], Al[2][64 * kHP];
   __shared__ __attribute__((aligned(16))) unsigned short Bh[2][64 * kHP], Bl[2][64 * kHP];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n0 = blockIdx.x * 64, m0 = blockIdx.y * 64, split = blockIdx.z;
+  const int n0 = B_.x * 64, m0 = B_.y * 64, split = B_.z;
   const int kbeg = split * kps, kend = min(nvp, kbeg + kps);
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = tid >> 2, lk = (tid & 3) * 8;      // A: row f, 8 pixels
@@ -296,13 +402,11 @@ void split_rows(const vis_field* f, int ncols, int ld_src, int ld_dst, const flo
   const int nch_src = ceil_div(ncols, kSplitCols);
   if (Fmt::kScaled) {
     ProfScope ps(&f->prof, "k_row_absmax", st);
-    k_row_absmax<<<dim3(nch_src, nrows), 256, 0, st>>>(ncols, ld_src, src, f->scr.rmax);
-    check_launch("k_row_absmax");
+    launch_k<KRowAbsmax>(dim3(nch_src, nrows), 0, RowAbsmaxArgs{ncols, ld_src, src, f->scr.rmax}, st, "k_row_absmax");
   }
   ProfScope ps(&f->prof, "k_split_rows", st);
-  k_split_rows<Fmt><<<dim3(ceil_div(ld_dst, kSplitCols), nrows_pad), 256, 0, st>>>(
-      nrows, ncols, ld_src, ld_dst, src, f->scr.rmax, nch_src, hi, lo, f->scr.rscale);
-  check_launch("k_split_rows");
+  launch_k<KSplitRows<Fmt>>(dim3(ceil_div(ld_dst, kSplitCols), nrows_pad), 0, SplitRowsArgs{
+      nrows, ncols, ld_src, ld_dst, src, f->scr.rmax, nch_src, hi, lo, f->scr.rscale}, st, "k_split_rows");
 }
 
 template <class Fmt>
@@ -315,9 +419,8 @@ void fwd_split(const vis_field* f, const float* alm, float* dst, int nsplit, int
   split_rows<Fmt>(f, f->n_modes, f->n_modes, b->kpad, alm, ah, al, st);
   dim3 grid(f->nv_pad / 64, ceil_div(f->n_freq, 64), nsplit);
   ProfScope ps(&f->prof, Fmt::kScaled ? "k_synth_fwd_fp16x3" : "k_synth_fwd_bf16x3", st);
-  k_synth_fwd_split<Fmt><<<grid, 256, 0, st>>>(f->n_freq, f->n_modes, f->nv_pad, b->kpad, kps, ah, al,
-                                               f->scr.rscale, y.hi, y.lo, f->tab.vpix, dst);
-  check_launch("k_synth_fwd_split");
+  launch_k<KSynthFwdSplit<Fmt>>(grid, 0, SynthFwdSplitArgs{f->n_freq, f->n_modes, f->nv_pad, b->kpad, kps, ah, al,
+                                               f->scr.rscale, y.hi, y.lo, f->tab.vpix, dst}, st, "k_synth_fwd_split");
 }
 
 template <class Fmt>
@@ -331,9 +434,8 @@ void adj_split(const vis_field* f, const float* dimg, int kps, hipStream_t st) {
   const int ncol = static_cast<int>(round_up(f->n_modes, 64));
   dim3 grid(ncol / 64, ceil_div(f->n_freq, 64), f->asplit);
   ProfScope ps(&f->prof, Fmt::kScaled ? "k_synth_adj_fp16x3" : "k_synth_adj_bf16x3", st);
-  k_synth_adj_split<Fmt><<<grid, 256, 0, st>>>(f->n_freq, f->nv_pad, b->kpad, kps, dh, dl,
-                                               f->scr.rscale, y.hi, y.lo, f->tab.vpix, f->scr.a_part);
-  check_launch("k_synth_adj_split");
+  launch_k<KSynthAdjSplit<Fmt>>(grid, 0, SynthAdjSplitArgs{f->n_freq, f->nv_pad, b->kpad, kps, dh, dl,
+                                               f->scr.rscale, y.hi, y.lo, f->tab.vpix, f->scr.a_part}, st, "k_synth_adj_split");
 }
 
 }  // namespace

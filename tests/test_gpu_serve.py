@@ -251,8 +251,10 @@ def _dense_gain_chol(lay, minv, n_freq, n_ant, seed):
 def test_alone_equals_mix(mods):
     """A chain's trajectories are bitwise identical alone and batched with others,
     for a diagonal-mass chain, a chain with dense gain mass blocks, a bf16x3
-    chain, a NUTS chain (fp16x3) and a NUTS chain with dense gain blocks, and
-    with one or two ticks in flight."""
+    chain, a NUTS chain (fp16x3) and a NUTS chain with dense gain blocks, with
+    one or two ticks in flight, and whether the tick's evaluations run as
+    batched grids over all chains, one chain after another, or on several
+    streams."""
     vis, serve = mods
     basis = _mixed_basis(vis)
     cfgs, flds = _mixed_fields(vis, basis)
@@ -265,8 +267,9 @@ def test_alone_equals_mix(mods):
              for k in (1, 4)}
     nuts_depth = {3: 5, 4: 4}
 
-    def run(which, inflight=1):
-        srv = serve.Server(256 << 20, max_chains=8, max_batch=8, inflight_ticks=inflight)
+    def run(which, inflight=1, batched=1):
+        srv = serve.Server(256 << 20, max_chains=8, max_batch=8, inflight_ticks=inflight,
+                           batched=batched)
         ids = {}
         for k in which:
             lay, data, sig, q0, minv, cvar = inputs[k]
@@ -292,6 +295,16 @@ def test_alone_equals_mix(mods):
     mix, pos_m = run([0, 1, 2, 3, 4])
     # two ticks in flight (the next built while the current runs): same results
     mix2, pos_m2 = run([0, 1, 2, 3, 4], inflight=2)
+    # the chains' evaluations launched one by one (no batched grids) and on
+    # several streams: the batched grids compute exactly the same numbers
+    seq, pos_s = run([0, 1, 2, 3, 4], batched=0)
+    mst, pos_t = run([0, 1, 2, 3, 4], batched=2)
+    for other, opos, what in ((seq, pos_s, "one by one"), (mst, pos_t, "multi-stream")):
+        for k in range(5):
+            for ra, rm in zip(mix[k], other[k]):
+                for key in ("trajectory", "accepted", "h0", "h1", "chi2", "eps", "n_grad", "tree_depth"):
+                    assert ra[key] == rm[key], (k, key, what)
+            assert torch.equal(pos_m[k], opos[k]), (k, what)
     assert all(r["status"] == 0 for rs in mix.values() for r in rs)
     for k in range(5):
         for ra, rm in zip(mix[k], mix2[k]):
