@@ -386,8 +386,8 @@ def main():
                     help="serving ticks in flight for the timed chain (2: the next tick is "
                          "built and queued while the current one runs)")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-modes", default="split,separable,multistream,dense_gains,nuts,"
-                    "nuts_dense_gains,per_chain",
+    ap.add_argument("--serve-modes", default="split,split_separable,separable,multistream,"
+                    "dense_gains,nuts,nuts_dense_gains,per_chain",
                     help="serving runs to measure (comma list; the speed-ups need split, "
                          "separable and per_chain)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -420,8 +420,6 @@ def main():
     prec = precs[args.precision]
     sprec = precs[args.serve_precision]
     synth = vis.VIS_SYNTH_SEPARABLE if args.synthesis == "separable" else vis.VIS_SYNTH_DENSE
-    if synth == vis.VIS_SYNTH_SEPARABLE and prec != vis.VIS_FP32:
-        raise SystemExit("separable synthesis runs in FP32 only")
     log("basis + fields", cfg.name, args.synthesis, "synthesis")
     storage = (vis.STORAGE_SEPARABLE if synth == vis.VIS_SYNTH_SEPARABLE else vis.STORAGE_FOR[prec]) | \
         (0 if args.no_serve else 1 | vis.STORAGE_FOR[sprec] | vis.STORAGE_SEPARABLE)
@@ -512,6 +510,8 @@ def main():
 
         sb("split", f"batched, {args.serve_precision}, dense synthesis", prec=sprec,
            max_batch=args.serve_chains)
+        sb("split_separable", "batched, FP32 separable synthesis, fp16x3 adjoint fringe",
+           prec=vis.VIS_FP16X3, max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE)
         sb("separable", "batched, FP32 separable synthesis", prec=vis.VIS_FP32,
            max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE)
         sb("multistream", "FP32 separable synthesis, each chain's kernels on their own (4 streams)",
@@ -529,7 +529,9 @@ def main():
         sb("per_chain", "per-chain FP32 baseline (dense synthesis), one request per tick",
            prec=vis.VIS_FP32, max_batch=1)
         del ins
-        names = {"split": "batched_" + args.serve_precision, "separable": "batched_fp32_separable",
+        names = {"split": "batched_" + args.serve_precision,
+                 "split_separable": "batched_fp16x3_fringe_separable",
+                 "separable": "batched_fp32_separable",
                  "multistream": "multistream_fp32_separable",
                  "dense_gains": "batched_fp32_separable_dense_gain_mass",
                  "nuts": "batched_fp32_separable_nuts",
@@ -543,6 +545,8 @@ def main():
                 serving["speedup"] = runs["split"]["grad_evals_per_s"] / base
             if "separable" in runs:
                 serving["speedup_separable"] = runs["separable"]["grad_evals_per_s"] / base
+            if "split_separable" in runs:
+                serving["speedup_split_separable"] = runs["split_separable"]["grad_evals_per_s"] / base
 
     errors = None
     if samples is not None:

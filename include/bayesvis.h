@@ -90,7 +90,9 @@ typedef enum {
  *   Y(ring j, column k; l, m) = lambda_lm(z_j) T_m(alpha_k) (Sec. 3.2,
  *   eq. fg_separable), so I is a Legendre sum per (m, ring) followed by an
  *   azimuthal sum per ring; both run as FP32 MFMA GEMMs from small tables and
- *   Y itself is never read (needs basis storage bit 3; FP32 fields only).   */
+ *   Y itself is never read (needs basis storage bit 3).  The synthesis is FP32
+ *   at every field precision; with VIS_BF16X3 or VIS_FP16X3 only the adjoint
+ *   fringe GEMM runs as FP16 hi/lo products (the two are then the same).     */
 typedef enum {
   VIS_SYNTH_DENSE = 0,
   VIS_SYNTH_SEPARABLE = 1

@@ -232,7 +232,8 @@ static void validate_field(const vis_basis* basis, const vis_field_desc* d) {
   BV_REQUIRE(d->synthesis == VIS_SYNTH_DENSE || d->synthesis == VIS_SYNTH_SEPARABLE, VIS_EINVAL,
              "synthesis %d is not one of VIS_SYNTH_DENSE, VIS_SYNTH_SEPARABLE", d->synthesis);
   if (d->synthesis == VIS_SYNTH_SEPARABLE) {
-    BV_REQUIRE(d->precision == VIS_FP32, VIS_EINVAL, "separable synthesis runs in FP32 only");
+    // the separable synthesis itself runs in FP32 at every precision; a split
+    // precision then applies to the fringe products only
     BV_REQUIRE((basis->storage & 8u) != 0, VIS_EINVAL,
                "the basis was created without the separable factor tables (storage bit 3)");
   } else {
@@ -371,6 +372,7 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
     S.dsplit = cv.take<float>(nfp * nvp);
     S.rscale = cv.take<float>(nfp);
     S.rmax = cv.take<float>(nfp * ceil_div(std::max<long>(kpad, nvp), 2048));
+    S.fscale = cv.take<float>(nfq * kScaleParts);
   }
   S.vu = cv.take<float2>(nt * nfq * f->n_ubl);
   S.gco = cv.take<float>(nt * nfq * static_cast<size_t>(f->gstride));

@@ -254,6 +254,123 @@ __device__ __forceinline__ void write_powers_split(float* As, uint32_t* Bh, uint
     *reinterpret_cast<u2*>(Bl + px * R::BL + 2 * g) = u2{bl[2 * g], bl[2 * g + 1]};
 }
 
+// Forward split rows: each pixel row holds W halves (W / 2 words, pairs
+// (Re, Im) of one power) in 16-byte groups, group g stored at g ^ swz_h(px)
+// so that a wavefront's 16-byte row writes spread over the banks; four
+// consecutive rows (4 aligned to 4) share the swizzle, which is what the
+// transposing operand reads below assume.
+template <int W>
+__device__ __forceinline__ int swz_h(int px) {
+  return W == 16 ? ((px >> 3) & 1) : ((px >> 2) & 3);
+}
+
+// Powers of one pixel for the split forward: alpha^n and beta^m w as FP16
+// hi + lo pairs into its rows of Ah, Al (alpha) and Bh, Bl (beta); visit(n,
+// ...) sees the FP32 values (beta^m w as generated, w already scaled).
+template <int D, int W, class Visit>
+__device__ __forceinline__ void write_powers_fwd_split(uint32_t* Ah, uint32_t* Al, uint32_t* Bh,
+                                                       uint32_t* Bl, int px, float c1, float s1,
+                                                       float c2, float s2, float w, Visit visit) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  uint32_t ah[W / 2], al[W / 2], bh[W / 2], bl[W / 2];
+  float ar0 = 1.f, ai0 = 0.f, ar = c1, ai = -s1;
+  float br0 = w, bi0 = 0.f, br = c2 * w, bi = -s2 * w;
+  const float t1 = 2.f * c1, t2 = 2.f * c2;
+#pragma unroll
+  for (int n = 0; n < D; ++n) {
+    ah[n] = split_hi2(ar, ai);
+    al[n] = split_lo2(ar, ai, ah[n]);
+    bh[n] = split_hi2(br, bi);
+    bl[n] = split_lo2(br, bi, bh[n]);
+    visit(n, ar, ai, br, bi);
+    const float nar = t1 * ar - ar0, nai = t1 * ai - ai0;
+    const float nbr = t2 * br - br0, nbi = t2 * bi - bi0;
+    ar0 = ar; ai0 = ai; br0 = br; bi0 = bi;
+    ar = nar; ai = nai; br = nbr; bi = nbi;
+  }
+#pragma unroll
+  for (int n = D; n < W / 2; ++n) ah[n] = al[n] = bh[n] = bl[n] = 0u;
+#pragma unroll
+  for (int g = 0; g < W / 8; ++g) {
+    const int o = px * (W / 2) + ((g ^ swz_h<W>(px)) << 2);
+    *reinterpret_cast<u4*>(Ah + o) = u4{ah[4 * g], ah[4 * g + 1], ah[4 * g + 2], ah[4 * g + 3]};
+    *reinterpret_cast<u4*>(Al + o) = u4{al[4 * g], al[4 * g + 1], al[4 * g + 2], al[4 * g + 3]};
+    *reinterpret_cast<u4*>(Bh + o) = u4{bh[4 * g], bh[4 * g + 1], bh[4 * g + 2], bh[4 * g + 3]};
+    *reinterpret_cast<u4*>(Bl + o) = u4{bl[4 * g], bl[4 * g + 1], bl[4 * g + 2], bl[4 * g + 3]};
+  }
+}
+
+// One K = 32 FP16 MFMA operand (eight consecutive pixels of one row or
+// column per lane) of 16-column tile `tile` from rows stored pixel-major:
+// lane l (index j = l & 15 in its group, group g = l >> 4) needs values
+// [pix0 + 8 g .. + 7][16 tile + j].  ds_read_b64_tr_b16 gives lane j of a
+// 16-lane group element (j & 3) of the 4-half chunk addressed by lane
+// 4 k + (j >> 2), for k = 0..3; so lane j addresses row pix0 + 8 g + 4 h +
+// (j >> 2), halves 16 tile + 4 (j & 3) .. + 3, and the two reads (h = 0, 1)
+// give its eight pixels in order.
+typedef short s4 __attribute__((ext_vector_type(4)));
+template <int W>
+__device__ __forceinline__ h8 tr_operand(const uint32_t* base, int pix0, int tile, int lane) {
+  const int j = lane & 15, g = lane >> 4;
+  const int row0 = pix0 + 8 * g + (j >> 2);
+  const int col = 16 * tile + 4 * (j & 3);                 // halves
+  const int grp = col >> 3, within = (col & 7) >> 1;       // 16-byte group, word in group
+  s4 v[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int row = row0 + 4 * h;
+    const uint32_t* a = base + row * (W / 2) + ((grp ^ swz_h<W>(row)) << 2) + within;
+    v[h] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+        (__attribute__((address_space(3))) s4*)(reinterpret_cast<uintptr_t>(a)));
+  }
+  typedef short s8 __attribute__((ext_vector_type(8)));
+  const s8 c = s8{v[0][0], v[0][1], v[0][2], v[0][3], v[1][0], v[1][1], v[1][2], v[1][3]};
+  return __builtin_bit_cast(h8, c);
+}
+
+// Per-channel power-of-two scale of the split forward's beam-weighted sky.
+// k_chan_scale writes the maximum |I| of each of kScaleParts segments of a
+// channel's row; the forward kernel turns the channel's maxima into
+// scale = 2^(13 - e) with dOmega max |I| < 2^e (B <= 1), so that every
+// |dOmega B I scale| < 2^13 and its FP16 lo part stays a normal number.
+struct ChanScaleArgs {
+  int nvp;
+  const float* img;
+  float* part;   // [n_freq][kScaleParts]
+};
+
+struct KChanScale {
+  using Args = ChanScaleArgs;
+  static constexpr int kThreads = 256, kWaves = 1;
+  static __device__ void run(const ChanScaleArgs& a, const Blk& B) {
+    __shared__ float red[4];
+    const int seg = (a.nvp + kScaleParts - 1) / kScaleParts;
+    const int k0 = B.y * seg, k1 = min(a.nvp, k0 + seg);
+    const float* row = a.img + static_cast<size_t>(B.x) * a.nvp;
+    float m = 0.f;
+    for (int k = k0 + threadIdx.x; k < k1; k += 256) m = fmaxf(m, fabsf(row[k]));
+    for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      a.part[B.x * kScaleParts + B.y] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  }
+};
+
+__device__ __forceinline__ float chan_scale(const float* part, int f, float d_omega) {
+  float mx = 0.f;
+#pragma unroll
+  for (int q = 0; q < kScaleParts; ++q) mx = fmaxf(mx, part[f * kScaleParts + q]);
+  mx *= d_omega;
+  float sc = 1.0f;
+  if (mx > 0.f && isfinite(mx)) {
+    int e;
+    frexpf(mx, &e);   // mx < 2^e
+    sc = ldexpf(1.0f, max(-100, min(100, 13 - e)));
+  }
+  return sc;
+}
+
 // ------------------------------------------------------------------ forward --
 // One block of kFwdWaves wavefronts per (t, nu); wave w takes every
 // kFwdWaves-th pixel chunk visible at t, starting at chunk w, and the block
@@ -282,17 +399,21 @@ struct FwdArgs {
   const float* img;
   const float* fwhm;
   float2* vu;
+  const float* cscale;   // SPLIT: [n_freq][kScaleParts] segment maxima of |I|
 };
 
-template <int D>
+// SPLIT: the P tile runs on FP16 MFMA (K = 32) as three products of hi + lo
+// pairs, A_hi B_hi + A_lo B_hi + A_hi B_lo, accumulated in FP32; the beam-
+// weighted sky carries the channel's power-of-two scale, undone at the end.
+template <int D, bool SPLIT = false>
 struct KFringeFwd {
   using Args = FwdArgs;
   static constexpr int kThreads = 64 * kFwdWaves, kWaves = D <= 8 ? 4 : 2;
   static __device__ void run(const FwdArgs& args, const Blk& B);
 };
 
-template <int D>
-__device__ void KFringeFwd<D>::run(const FwdArgs& args, const Blk& B) {
+template <int D, bool SPLIT>
+__device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
   const int nf = args.nf, nt = args.nt, nvp = args.nvp, nubl = args.nubl;
   const float d_omega = args.d_omega;
   const double beam_ref = args.beam_ref;
@@ -314,11 +435,17 @@ __device__ void KFringeFwd<D>::run(const FwdArgs& args, const Blk& B) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   float* As = As_all[wv];   // this wave's operand rows
   float* Bs = Bs_all[wv];
+  // SPLIT: the same LDS as FP16 hi and lo row sets (64 rows of W halves each)
+  uint32_t* Ah = reinterpret_cast<uint32_t*>(As);
+  uint32_t* Al = Ah + 32 * W;
+  uint32_t* Bh = reinterpret_cast<uint32_t*>(Bs);
+  uint32_t* Bl = Bh + 32 * W;
   const int L = xcd_logical(B.x, B.nx);
   if (L >= nf * nt) return;   // uniform over the block
   int t, f;
   tile_map(L, nt, nf, 4, 32, t, f);   // 128 resident blocks per XCD: 4 times x 32 channels
   const double nu = freq[f];
+  const float csc = SPLIT ? chan_scale(args.cscale, f, d_omega) : 1.0f;   // power of two
   const float sig = static_cast<float>(fwhm[0] * (beam_ref / nu) * kFwhmToSigma);
   const float kb = 1.0f / (2.0f * sig * sig * static_cast<float>(kLn2));
 
@@ -356,15 +483,20 @@ __device__ void KFringeFwd<D>::run(const FwdArgs& args, const Blk& B) {
     float s1, c1, s2, c2;
     sincos_rev(x1, s1, c1);
     sincos_rev(x2, s2, c2);
-    write_powers<D, W>(As, Bs, lane, c1, s1, c2, s2, s,
-                       [&](int n, float ar, float ai, float br, float bi) {
-                         axr[n] += ar * s;
-                         axi[n] += ai * s;
-                         bxr[n] += br;
-                         bxi[n] += bi;
-                       });
+    auto visit = [&](int n, float ar, float ai, float br, float bi) {
+      axr[n] += ar * s;
+      axi[n] += ai * s;
+      bxr[n] += br;   // SPLIT: scaled by csc, undone after the loop
+      bxi[n] += bi;
+    };
+    if constexpr (SPLIT)
+      write_powers_fwd_split<D, W>(Ah, Al, Bh, Bl, lane, c1, s1, c2, s2, s * csc, visit);
+    else
+      write_powers<D, W>(As, Bs, lane, c1, s1, c2, s2, s, visit);
   };
-  float a[16][RT], b[16][RT];
+  float a[SPLIT ? 1 : 16][RT], b[SPLIT ? 1 : 16][RT];
+  // SPLIT operands of the two K = 32 steps of a chunk: hi and lo of A and B
+  h8 oah[SPLIT ? 2 : 1][RT], oal[SPLIT ? 2 : 1][RT], obh[SPLIT ? 2 : 1][RT], obl[SPLIT ? 2 : 1][RT];
   // MFMA step q reads row px = 4 q + (lane >> 4); the swizzle of row px
   // depends on q only through q & 1, so two per-lane offsets per column tile
   // plus a constant 8 W per step pair address every read (the constant goes
@@ -375,13 +507,25 @@ __device__ void KFringeFwd<D>::run(const FwdArgs& args, const Blk& B) {
 #pragma unroll
     for (int i = 0; i < RT; ++i) ofs[e][i] = lds_at<W>(4 * e + (lane >> 4), 16 * i + (lane & 15));
   auto operands = [&]() {
+    if constexpr (SPLIT) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+      for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-      for (int i = 0; i < RT; ++i) {
-        const int o = ofs[q & 1][i] + (q >> 1) * 8 * W;
-        a[q][i] = As[o];
-        b[q][i] = Bs[o];
+        for (int i = 0; i < RT; ++i) {
+          oah[ks][i] = tr_operand<W>(Ah, 32 * ks, i, lane);
+          oal[ks][i] = tr_operand<W>(Al, 32 * ks, i, lane);
+          obh[ks][i] = tr_operand<W>(Bh, 32 * ks, i, lane);
+          obl[ks][i] = tr_operand<W>(Bl, 32 * ks, i, lane);
+        }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+          const int o = ofs[q & 1][i] + (q >> 1) * 8 * W;
+          a[q][i] = As[o];
+          b[q][i] = Bs[o];
+        }
       }
     }
   };
@@ -395,19 +539,41 @@ __device__ void KFringeFwd<D>::run(const FwdArgs& args, const Blk& B) {
     // keep the prefetch here: the sources are read-only, so the optimizer
     // would otherwise re-issue the loads right before their use
     asm volatile("" ::: "memory");
+    if constexpr (SPLIT) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
+      for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-      for (int i = 0; i < RT; ++i)
+        for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < RT; ++j)
-          acc[q % NACC][i][j] = mfma4(a[q][i], b[q][j], acc[q % NACC][i][j]);
+          for (int j = 0; j < RT; ++j) {
+            acc[0][i][j] = mfma_h32(oah[ks][i], obh[ks][j], acc[0][i][j]);
+            acc[0][i][j] = mfma_h32(oal[ks][i], obh[ks][j], acc[0][i][j]);
+            acc[0][i][j] = mfma_h32(oah[ks][i], obl[ks][j], acc[0][i][j]);
+          }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int j = 0; j < RT; ++j)
+            acc[q % NACC][i][j] = mfma4(a[q][i], b[q][j], acc[q % NACC][i][j]);
+    }
     generate(cur, ci + S < cend ? 1.0f : 0.0f);
+    if constexpr (SPLIT) {
 #pragma unroll
-    for (int q = 0; q < 16 * RT * RT; ++q) {
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
-      __builtin_amdgcn_sched_group_barrier(0x002, 8 / (RT * RT), 0);  // vector ALU
-      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // one LDS write (128-bit)
+      for (int q = 0; q < 6 * RT * RT; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 16 / (RT * RT), 0);  // vector ALU
+        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // one LDS write (128-bit)
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16 * RT * RT; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 8 / (RT * RT), 0);  // vector ALU
+        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // one LDS write (128-bit)
+      }
     }
     wave_sync();
     operands();
@@ -426,6 +592,7 @@ __device__ void KFringeFwd<D>::run(const FwdArgs& args, const Blk& B) {
       chunk_step(ci + S, gb, ga);
     }
   }
+  const float inv_csc = 1.0f / csc;   // exact: a power of two
 #pragma unroll
   for (int n = 0; n < D; ++n) {
 #pragma unroll
@@ -434,6 +601,10 @@ __device__ void KFringeFwd<D>::run(const FwdArgs& args, const Blk& B) {
       axi[n] += __shfl_xor(axi[n], o);
       bxr[n] += __shfl_xor(bxr[n], o);
       bxi[n] += __shfl_xor(bxi[n], o);
+    }
+    if constexpr (SPLIT) {
+      bxr[n] *= inv_csc;
+      bxi[n] *= inv_csc;
     }
   }
   // this wave's P tile to its LDS rows (reused as a W x W matrix), its axis
@@ -449,6 +620,7 @@ __device__ void KFringeFwd<D>::run(const FwdArgs& args, const Blk& B) {
           float sum = acc[0][i][j][r];
 #pragma unroll
           for (int h = 1; h < NACC; ++h) sum += acc[h][i][j][r];
+          if constexpr (SPLIT) sum *= inv_csc;
           Pw[(16 * i + 4 * (lane >> 4) + r) * W + 16 * j + (lane & 15)] = sum;
         }
     float* AXw = Bs;  // [D][4]: axr, axi, bxr, bxi
@@ -736,11 +908,20 @@ template <int D>
 static void fwd_d(const vis_field* f, const float* img, const float* fwhm, float2* vu, hipStream_t st) {
   const int nblk = static_cast<int>(round_up(static_cast<long>(f->n_freq) * f->n_time, 8));
   const auto& T = f->tab;
+  const bool split = fringe_split(f);
+  if (split) {
+    ProfScope ps(&f->prof, "k_chan_scale", st);
+    launch_k<KChanScale>(dim3(f->n_freq, kScaleParts), 0,
+                         ChanScaleArgs{f->nv_pad, img, f->scr.fscale}, st, "k_chan_scale");
+  }
   ProfScope ps(&f->prof, "k_fringe_fwd", st);
   const FwdArgs a{f->n_freq, f->n_time, f->nv_pad, f->n_ubl, static_cast<float>(f->d_omega),
                   f->beam_ref_hz, T.freq, T.p1, T.p2, T.th2, T.tchunk_off, T.tchunk, T.ubl_nm,
-                  img, fwhm, vu};
-  launch_k<KFringeFwd<D>>(dim3(nblk), 0, a, st, "k_fringe_fwd");
+                  img, fwhm, vu, split ? f->scr.fscale : nullptr};
+  if (split)
+    launch_k<KFringeFwd<D, true>>(dim3(nblk), 0, a, st, "k_fringe_fwd");
+  else
+    launch_k<KFringeFwd<D, false>>(dim3(nblk), 0, a, st, "k_fringe_fwd");
 }
 
 template <int D>

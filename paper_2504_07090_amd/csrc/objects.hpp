@@ -74,6 +74,8 @@ struct FieldScratch {
                                    //   16-bit hi plane then the lo plane of dL/dI
   float* rscale = nullptr;         // split fields: [nf_pad] inverse row scales
   float* rmax = nullptr;           // split fields: [nf_pad][ceil(max(kpad, nv_pad) / 2048)]
+  float* fscale = nullptr;         // split fields: [n_freq][kScaleParts] maxima of |I|, from
+                                   //   which the forward fringe scales the weighted sky
   float* sep_g = nullptr;          // separable fields: [nz][kaz][n_freq] Legendre stage output
                                    //   (forward) or azimuthal stage output (adjoint)
   float* sep_dfull = nullptr;      // separable fields: [n_pix][n_freq] dL/dI on the full grid

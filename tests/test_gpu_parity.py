@@ -551,15 +551,43 @@ def test_separable_ragged_grid_gradient(vis):
     assert max(em) <= GRAD_ELEM_FP32
 
 
-def test_separable_rejected_without_tables_or_in_split_precision(vis, c0):
+def test_separable_rejected_without_tables(vis, c0):
     cfg, basis, *_ = c0     # FP32 Y only, no factor tables
     with pytest.raises(vis.VisError):
         vis.Field.from_config(basis, cfg, vis.VIS_FP32, vis.VIS_SYNTH_SEPARABLE)
     sb = vis.Basis(cfg.grid_nz, cfg.grid_nphi, cfg.lmax, vis.STORAGE_SEPARABLE)
     with pytest.raises(vis.VisError):
-        vis.Field.from_config(sb, cfg, vis.VIS_BF16X3, vis.VIS_SYNTH_SEPARABLE)
-    with pytest.raises(vis.VisError):
         vis.Field.from_config(sb, cfg, vis.VIS_FP32, vis.VIS_SYNTH_DENSE)   # no Y stored
+    with pytest.raises(vis.VisError):
+        vis.Field.from_config(sb, cfg, vis.VIS_BF16X3, vis.VIS_SYNTH_DENSE)
+
+
+@pytest.mark.parametrize("side", [4, 7])
+def test_separable_split_fringe_gradient(vis, side):
+    """Separable (FP32) synthesis with the split-precision adjoint fringe GEMM
+    (FP16 hi + lo): forward, adjoint and the chi^2 gradient against the oracle
+    at the split bar, for a 37-dish (extent 6) and a 127-dish (extent 12) field."""
+    cfg = w.scaled(w.C0, array="hex", array_size=side, n_freq=3, n_time=3,
+                   freq_lo_hz=120e6, freq_hi_hz=130e6, lmax=12)
+    basis = vis.Basis(cfg.grid_nz, cfg.grid_nphi, cfg.lmax, vis.STORAGE_SEPARABLE)
+    fld = vis.Field.from_config(basis, cfg, vis.VIS_FP16X3, vis.VIS_SYNTH_SEPARABLE)
+    assert fld.info.synthesis == vis.VIS_SYNTH_SEPARABLE and fld.info.precision == vis.VIS_FP16X3
+    d = w.draw(cfg)
+    of = model.Field(cfg)
+    ref = model.forward(of, d.alm, d.gains, w.fwhm_ref_rad(cfg))
+    alm, g, fw = _dev_params(d, cfg)
+    m = vis.forward(fld, alm, g, fw).cpu().numpy()
+    assert np.all(chan_rel_err(m, ref) <= 1e-4) and np.all(chan_max_err(m, ref) <= VIS_ELEM_SPLIT)
+    _, sig, data = model.make_data(of, d)
+    alm, g, fw = _dev_params(d, cfg, alm_scale=1.2)
+    x2, ga, gg, gf = vis.chi2_and_grad(fld, torch.tensor(np.ascontiguousarray(data), dtype=torch.complex64,
+                                                         device="cuda"), sig, alm, g, fw)
+    rx2, rga, rgg, rgf = model.chi2_and_grad(of, data, sig, d.alm * 1.2, d.gains, w.fwhm_ref_rad(cfg))
+    e = [rel_norm(ga.cpu().numpy(), rga), rel_norm(gg.cpu().numpy(), rgg),
+         abs(float(gf) - rgf) / abs(rgf), abs(float(x2) - rx2) / rx2]
+    em = [max_rel(ga.cpu().numpy(), rga), max_rel(gg.cpu().numpy(), rgg)]
+    say("separable + split fringe, hex side", side, "errs (a, g, F, chi2)", e, "element-wise", em)
+    assert max(e) <= 2e-3 and max(em) <= GRAD_ELEM_SPLIT
 
 
 def test_c1_separable_sampled(vis, c1, c1_ref, c1_adj_ref, c1_grad_ref):
