@@ -480,7 +480,9 @@ def main():
     nv = fld.info.n_pix_visible
     if dom.startswith("k_fringe"):
         work = 4.0 * fld.fwd_macs            # 2 FMA per complex x real MAC
-        roof = {"bound": "mfma", "peak": PEAK["fp32_mfma_tflops"]}
+        # split-precision fields run both fringe GEMMs on FP16 MFMA
+        roof = {"bound": "mfma", "peak": PEAK["fp32_mfma_tflops"] if prec == vis.VIS_FP32
+                else PEAK["fp16_mfma_tflops"]}
     else:
         work = 2.0 * cfg.n_freq * nv * fld.n_modes
         roof = {"bound": "mfma", "peak": PEAK["fp32_mfma_tflops"] if prec == vis.VIS_FP32
@@ -510,7 +512,7 @@ def main():
 
         sb("split", f"batched, {args.serve_precision}, dense synthesis", prec=sprec,
            max_batch=args.serve_chains)
-        sb("split_separable", "batched, FP32 separable synthesis, fp16x3 adjoint fringe",
+        sb("split_separable", "batched, FP32 separable synthesis, fp16x3 fringe",
            prec=vis.VIS_FP16X3, max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE)
         sb("separable", "batched, FP32 separable synthesis", prec=vis.VIS_FP32,
            max_batch=args.serve_chains, synthesis=vis.VIS_SYNTH_SEPARABLE)

@@ -337,10 +337,11 @@ static HostGeometry build_geometry(const vis_basis* basis, const vis_field_desc*
 static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
   const size_t nt = f->n_time, nfq = f->n_freq, nvp = f->nv_pad;
   auto& T = f->tab;
-  T.freq = cv.take<double>(nfq);
+  T.dnu = cv.take<float>(nfq);
+  T.sigr = cv.take<float>(nfq);
   T.vpix = cv.take<int>(nvp);
-  T.p1 = cv.take<double>(nt * nvp);
-  T.p2 = cv.take<double>(nt * nvp);
+  T.q1 = cv.take<float2>(nt * nvp);
+  T.q2 = cv.take<float2>(nt * nvp);
   T.th2 = cv.take<float>(nt * nvp);
   T.chunk_t = cv.take<int2>(f->n_chunks);
   T.tchunk_off = cv.take<int>(nt + 1);
@@ -601,10 +602,36 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
       ulut[g.ubl[u].first * (2 * D + 1) + g.ubl[u].second + D] = u;
     }
     auto& T = f->tab;
-    up(T.freq, freq, s);
+    // Phase tables: nu_f p = nu_c p + (nu_f - nu_c) p.  The large part is
+    // reduced modulo 1 here in FP64 (|y| <= 1/2, one rounding to FP32); the
+    // kernels add the small part with one FP32 fma, |nu_f - nu_c| p being at
+    // most half the band times the longest lattice delay.
+    double fmin = freq[0], fmax = freq[0];
+    for (double v : freq) {
+      fmin = std::min(fmin, v);
+      fmax = std::max(fmax, v);
+    }
+    const double nu_c = 0.5 * (fmin + fmax);
+    std::vector<float> dnu(f->n_freq), sigr(f->n_freq);
+    for (int k = 0; k < f->n_freq; ++k) {
+      dnu[k] = static_cast<float>(freq[k] - nu_c);
+      sigr[k] = static_cast<float>(desc->beam_ref_hz / freq[k] * kFwhmToSigma);
+    }
+    auto phase_table = [&](const std::vector<double>& p) {
+      std::vector<float2> q(p.size());
+      for (size_t i = 0; i < p.size(); ++i) {
+        const double x = nu_c * p[i];
+        q[i] = make_float2(static_cast<float>(x - std::rint(x)), static_cast<float>(p[i]));
+      }
+      return q;
+    };
+    up(T.dnu, dnu, s);
+    up(T.sigr, sigr, s);
     up(T.vpix, vpix, s);
-    up(T.p1, g.p1, s);
-    up(T.p2, g.p2, s);
+    // named: the host buffers of the copies stay alive until the stream is synchronised
+    const std::vector<float2> q1 = phase_table(g.p1), q2 = phase_table(g.p2);
+    up(T.q1, q1, s);
+    up(T.q2, q2, s);
     up(T.th2, g.th2, s);
     up(T.chunk_t, chunk_t, s);
     up(T.tchunk_off, g.tchunk_off, s);
@@ -620,11 +647,9 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
     up(T.ulut, ulut, s);
     // the padded tail of the sky scratch must stay finite (it is multiplied by a zero beam)
     BV_HIP(hipMemsetAsync(f->scr.img, 0, sizeof(float) * f->n_freq * f->nv_pad, s));
-    {
-      std::vector<int> vidx(basis->n_pix, -1);
-      for (int k = 0; k < f->nv; ++k) vidx[g.vpix[k]] = k;
-      up(T.vidx, vidx, s);
-    }
+    std::vector<int> vidx(basis->n_pix, -1);
+    for (int k = 0; k < f->nv; ++k) vidx[g.vpix[k]] = k;
+    up(T.vidx, vidx, s);
     if (f->synthesis == VIS_SYNTH_SEPARABLE) {
       // rows of the Legendre stage beyond 2 lmax + 1 are never written: keep them zero
       BV_HIP(hipMemsetAsync(f->scr.sep_g, 0,

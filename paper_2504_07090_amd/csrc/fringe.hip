@@ -90,10 +90,13 @@ __device__ __forceinline__ V at_u32(const V* base, int k) {
                                      static_cast<uint32_t>(k) * static_cast<uint32_t>(sizeof(V)));
 }
 
-// Reduced phase of nu * p in cycles, in [-1/2, 1/2], formed in FP64.
-__device__ __forceinline__ float reduced_cycles(double nu, double p) {
-  const double x = nu * p;
-  return static_cast<float>(x - rint(x));
+// Reduced phase of nu_f p in cycles, in [-1/2, 1/2], in FP32 from the
+// table entry q = (y, p), y = nu_c p reduced modulo 1 on the host in FP64,
+// and dnu = nu_f - nu_c: x = y + dnu p is at most a few cycles, so one fma
+// and one round-to-integer keep the error near one FP32 rounding of x.
+__device__ __forceinline__ float reduced_cycles(float dnu, float2 q) {
+  const float x = __builtin_fmaf(dnu, q.y, q.x);
+  return x - __builtin_rintf(x);
 }
 
 // Block index -> logical index so that consecutive logical indices share an
@@ -388,10 +391,10 @@ constexpr int kFwdWaves = 4;
 struct FwdArgs {
   int nf, nt, nvp, nubl;
   float d_omega;
-  double beam_ref;
-  const double* freq;
-  const double* P1;
-  const double* P2;
+  const float* dnu;
+  const float* sigr;
+  const float2* Q1;
+  const float2* Q2;
   const float* TH2;
   const int* tchunk_off;
   const int* tchunk;
@@ -416,10 +419,8 @@ template <int D, bool SPLIT>
 __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
   const int nf = args.nf, nt = args.nt, nvp = args.nvp, nubl = args.nubl;
   const float d_omega = args.d_omega;
-  const double beam_ref = args.beam_ref;
-  const double* __restrict__ freq = args.freq;
-  const double* P1 = args.P1;
-  const double* P2 = args.P2;
+  const float2* Q1 = args.Q1;
+  const float2* Q2 = args.Q2;
   const float* TH2 = args.TH2;
   const int* __restrict__ tchunk_off = args.tchunk_off;
   const int* __restrict__ tchunk = args.tchunk;
@@ -444,9 +445,9 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
   if (L >= nf * nt) return;   // uniform over the block
   int t, f;
   tile_map(L, nt, nf, 4, 32, t, f);   // 128 resident blocks per XCD: 4 times x 32 channels
-  const double nu = freq[f];
+  const float dnu = args.dnu[f];
   const float csc = SPLIT ? chan_scale(args.cscale, f, d_omega) : 1.0f;   // power of two
-  const float sig = static_cast<float>(fwhm[0] * (beam_ref / nu) * kFwhmToSigma);
+  const float sig = fwhm[0] * args.sigr[f];
   const float kb = 1.0f / (2.0f * sig * sig * static_cast<float>(kLn2));
 
   // NACC independent accumulator sets (consecutive MFMAs of a chunk go to
@@ -465,20 +466,20 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
   for (int n = 0; n < D; ++n) axr[n] = axi[n] = bxr[n] = bxi[n] = 0.f;
 
   const int cbeg = tchunk_off[t], cend = tchunk_off[t + 1];
-  const double* p1t = P1 + static_cast<size_t>(t) * nvp;
-  const double* p2t = P2 + static_cast<size_t>(t) * nvp;
+  const float2* q1t = Q1 + static_cast<size_t>(t) * nvp;
+  const float2* q2t = Q2 + static_cast<size_t>(t) * nvp;
   const float* tht = TH2 + static_cast<size_t>(t) * nvp;
   const float* imf = img + static_cast<size_t>(f) * nvp;
 
-  struct G { double p1, p2; float th, iv; };
+  struct G { float2 q1, q2; float th, iv; };
   auto load = [&](int ci) {
     const int k = tchunk[ci] * kChunk + lane;
-    return G{at_u32(p1t, k), at_u32(p2t, k), at_u32(tht, k), at_u32(imf, k)};
+    return G{at_u32(q1t, k), at_u32(q2t, k), at_u32(tht, k), at_u32(imf, k)};
   };
   // powers of one chunk into LDS; `live` = 0 turns a padding pass into a no-op
   auto generate = [&](const G& g, float live) {
-    const float x1 = reduced_cycles(nu, g.p1);
-    const float x2 = reduced_cycles(nu, g.p2);
+    const float x1 = reduced_cycles(dnu, g.q1);
+    const float x2 = reduced_cycles(dnu, g.q2);
     const float s = live * d_omega * beam_exp2(-g.th * kb) * g.iv;
     float s1, c1, s2, c2;
     sincos_rev(x1, s1, c1);
@@ -682,10 +683,10 @@ template <int RT> struct AdjCoef<RT, true> { h8 ga[RT][RT]; h4 gb[RT][RT]; };
 struct AdjArgs {
   int nf, nt, nvp, nchunks, gstride;
   float d_omega;
-  double beam_ref;
-  const double* freq;
-  const double* P1;
-  const double* P2;
+  const float* dnu;
+  const float* sigr;
+  const float2* Q1;
+  const float2* Q2;
   const float* TH2;
   const int2* chunk_t;
   const float* img;
@@ -707,10 +708,8 @@ template <int D, bool SPLIT>
 __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
   const int nf = args.nf, nvp = args.nvp, nchunks = args.nchunks, gstride = args.gstride;
   const float d_omega = args.d_omega;
-  const double beam_ref = args.beam_ref;
-  const double* __restrict__ freq = args.freq;
-  const double* P1 = args.P1;
-  const double* P2 = args.P2;
+  const float2* Q1 = args.Q1;
+  const float2* Q2 = args.Q2;
   const float* TH2 = args.TH2;
   const int2* __restrict__ chunk_t = args.chunk_t;
   const float* __restrict__ img = args.img;
@@ -733,9 +732,9 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
   if (L >= nf * nchunks) return;
   int chunk, f;
   tile_map(L, nchunks, nf, 32, 16, chunk, f);   // 512 resident waves per XCD: 32 chunks x 16 channels
-  const double nu = freq[f];
+  const float dnu = args.dnu[f];
   const float fw = fwhm[0];
-  const float sig = static_cast<float>(fw * (beam_ref / nu) * kFwhmToSigma);
+  const float sig = fw * args.sigr[f];
   const float kb = 1.0f / (2.0f * sig * sig * static_cast<float>(kLn2));
   const float kappa = 1.0f / (sig * sig * fw);   // dB/dF = B theta^2 kappa
   const int k = chunk * kChunk + lane;
@@ -758,7 +757,7 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
   // swap roles without copies: the geometry and this lane's coefficients of
   // time t + 1 load while time t is processed.
   struct Step : AdjCoef<RT, SPLIT> {
-    double p1, p2;
+    float2 q1, q2;
     float th2;
     // alpha-axis coefficients of this lane's rows 16 i + 4 (lane >> 4) + 0..3:
     // (Re, -Im) of omega(n, 0) for the two powers n of those rows, stored in
@@ -768,8 +767,8 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
   };
   auto load_step = [&](Step& S, int t) {
     const size_t row = static_cast<size_t>(t) * nvp;   // uniform over the wave
-    S.p1 = at_u32(P1 + row, k);
-    S.p2 = at_u32(P2 + row, k);
+    S.q1 = at_u32(Q1 + row, k);
+    S.q2 = at_u32(Q2 + row, k);
     S.th2 = at_u32(TH2 + row, k);
     const float* G = gco_lane_at(t);
 #pragma unroll
@@ -787,15 +786,15 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
     }
   };
   auto step = [&](int t, const Step& S, Step& next) {
-    const double p1 = S.p1, p2 = S.p2;
+    const float2 q1 = S.q1, q2 = S.q2;
     const float th2 = S.th2;
     const float* G = gco_at(t);
     // unconditional (the last step re-reads its own time) so that the waits
     // for this step's operands never cover the loads just issued
     load_step(next, min(t + 1, tr.y));
     const float bm = beam_exp2(-th2 * kb);
-    const float x1 = reduced_cycles(nu, p1);
-    const float x2 = reduced_cycles(nu, p2);
+    const float x1 = reduced_cycles(dnu, q1);
+    const float x2 = reduced_cycles(dnu, q2);
     float s1, c1, s2, c2;
     sincos_rev(x1, s1, c1);
     sincos_rev(x2, s2, c2);
@@ -916,7 +915,7 @@ static void fwd_d(const vis_field* f, const float* img, const float* fwhm, float
   }
   ProfScope ps(&f->prof, "k_fringe_fwd", st);
   const FwdArgs a{f->n_freq, f->n_time, f->nv_pad, f->n_ubl, static_cast<float>(f->d_omega),
-                  f->beam_ref_hz, T.freq, T.p1, T.p2, T.th2, T.tchunk_off, T.tchunk, T.ubl_nm,
+                  T.dnu, T.sigr, T.q1, T.q2, T.th2, T.tchunk_off, T.tchunk, T.ubl_nm,
                   img, fwhm, vu, split ? f->scr.fscale : nullptr};
   if (split)
     launch_k<KFringeFwd<D, true>>(dim3(nblk), 0, a, st, "k_fringe_fwd");
@@ -932,7 +931,7 @@ static void adj_d(const vis_field* f, const float* img, const float* fwhm, const
   ProfScope ps(&f->prof, "k_fringe_adj", st);
   BV_REQUIRE(f->dtile == D, VIS_EINVAL, "internal: adjoint tile mismatch");
   const AdjArgs a{f->n_freq, f->n_time, f->nv_pad, f->n_chunks, f->gstride,
-                  static_cast<float>(f->d_omega), f->beam_ref_hz, T.freq, T.p1, T.p2, T.th2,
+                  static_cast<float>(f->d_omega), T.dnu, T.sigr, T.q1, T.q2, T.th2,
                   T.chunk_t, img, fwhm, gco, gco, dimg, f_part};
   if (fringe_split(f))
     launch_k<KFringeAdj<D, true>>(dim3(nblk), 0, a, st, "k_fringe_adj");

@@ -77,6 +77,25 @@ __device__ __forceinline__ float pack_f16(_Float16 a, _Float16 b) {
   return __builtin_bit_cast(float, h2{a, b});
 }
 
+// Sum of x[e] for e = r.x, r.x + w, ... < r.y as four interleaved partial
+// sums (e, e + w, e + 2w, e + 3w), added in a fixed order at the end.
+__device__ __forceinline__ float2 lds_sum4(const float2* x, int2 r, int w) {
+  float2 p0 = make_float2(0.f, 0.f), p1 = p0, p2 = p0, p3 = p0;
+  int e = r.x;
+  for (; e + 3 * w < r.y; e += 4 * w) {
+    const float2 a = x[e], b = x[e + w], c = x[e + 2 * w], d = x[e + 3 * w];
+    p0.x += a.x; p0.y += a.y;
+    p1.x += b.x; p1.y += b.y;
+    p2.x += c.x; p2.y += c.y;
+    p3.x += d.x; p3.y += d.y;
+  }
+  for (; e < r.y; e += w) {
+    p0.x += x[e].x;
+    p0.y += x[e].y;
+  }
+  return make_float2((p0.x + p1.x) + (p2.x + p3.x), (p0.y + p1.y) + (p2.y + p3.y));
+}
+
 // Adjoint coefficients of one (t, nu) slice from the collapsed omega in LDS.
 // The coefficient matrix G[r][c], r = 16 i + (row in tile) = 2 (n - 1) + (Re /
 // Im of alpha^n), c = 16 kt + (column in tile) = 2 (m - 1) + (Re / Im of beta^m):
@@ -239,6 +258,16 @@ __device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
       }
     }
   }
+  // SORTED: the lane group of each unique baseline and antenna, and its list's
+  // range, are the same for every slice of the slab (one list per group:
+  // lanes_per_item(n) * n <= 256 for the n <= 256 this path admits)
+  const int wu = lanes_per_item(a.nubl), wa = lanes_per_item(a.nant);
+  const int u_mine = tid / wu, a_mine = tid / wa;
+  int2 u_rng = make_int2(0, 0), a_rng = make_int2(0, 0);
+  if (SORTED) {
+    if (u_mine < a.nubl) u_rng = make_int2(a.u_off[u_mine] + (tid & (wu - 1)), a.u_off[u_mine + 1]);
+    if (a_mine < a.nant) a_rng = make_int2(a.a_off[a_mine] + (tid & (wa - 1)), a.a_off[a_mine + 1]);
+  }
   auto omega_term = [&](bool neg, float2 c, float2 G) {
     return neg ? cmul(c, conjf2(G)) : cmul(conjf2(c), G);
   };
@@ -334,22 +363,26 @@ __device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
     __syncthreads();
     if (a.mode == kGainChi2 && tid == 0)
       a.chi_part[slice] = ((red[0] + red[1]) + (red[2] + red[3])) * static_cast<double>(a.inv_sig2);
-    {
+    if (SORTED) {
+      // one list per lane group (u_rng / a_rng, fixed for the whole slab);
+      // four interleaved partial sums keep four LDS reads in flight
+      const float2 o = group_sum(lds_sum4(tu, u_rng, wu), wu);
+      if (u_mine < a.nubl && (tid & (wu - 1)) == 0) om[u_mine] = o;
+      if (a.mode != kGainMap) {
+        const float2 s = group_sum(lds_sum4(ta, a_rng, wa), wa);
+        if (a_mine < a.nant && (tid & (wa - 1)) == 0) a.g_part[slice * a.nant + a_mine] = s;
+      }
+    } else {
       const int w = lanes_per_item(a.nubl), sub = tid & (w - 1);
       for (int base = 0; base < a.nubl; base += 256 / w) {
         const int u = base + tid / w;
         float2 o = make_float2(0.f, 0.f);
         if (u < a.nubl) {
           for (int e = a.u_off[u] + sub; e < a.u_off[u + 1]; e += w) {
-            float2 term;
-            if (SORTED) {
-              term = tu[e];
-            } else {
-              const int code = a.u_list[e];
-              const int k = code >> 1;
-              const float2 G = gprod(k);
-              term = omega_term(code & 1, cot_of(k, cmul(G, vis_of(k))), G);
-            }
+            const int code = a.u_list[e];
+            const int k = code >> 1;
+            const float2 G = gprod(k);
+            const float2 term = omega_term(code & 1, cot_of(k, cmul(G, vis_of(k))), G);
             o.x += term.x;
             o.y += term.y;
           }
@@ -357,30 +390,25 @@ __device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
         o = group_sum(o, w);
         if (u < a.nubl && sub == 0) om[u] = o;
       }
-    }
-    if (a.mode != kGainMap) {
-      const int w = lanes_per_item(a.nant), sub = tid & (w - 1);
-      for (int base = 0; base < a.nant; base += 256 / w) {
-        const int ant = base + tid / w;
-        float2 s = make_float2(0.f, 0.f);
-        if (ant < a.nant) {
-          for (int e = a.a_off[ant] + sub; e < a.a_off[ant + 1]; e += w) {
-            float2 term;
-            if (SORTED) {
-              term = ta[e];
-            } else {
+      if (a.mode != kGainMap) {
+        const int w2 = lanes_per_item(a.nant), sub2 = tid & (w2 - 1);
+        for (int base = 0; base < a.nant; base += 256 / w2) {
+          const int ant = base + tid / w2;
+          float2 s = make_float2(0.f, 0.f);
+          if (ant < a.nant) {
+            for (int e = a.a_off[ant] + sub2; e < a.a_off[ant + 1]; e += w2) {
               const int code = a.a_list[e];
               const int k = code >> 1;
               const int2 ij = a.bl_ant[k];
               const float2 vk = vis_of(k);
-              term = ant_term(code & 1, ij, cot_of(k, cmul(gprod(k), vk)), vk);
+              const float2 term = ant_term(code & 1, ij, cot_of(k, cmul(gprod(k), vk)), vk);
+              s.x += term.x;
+              s.y += term.y;
             }
-            s.x += term.x;
-            s.y += term.y;
           }
+          s = group_sum(s, w2);
+          if (ant < a.nant && sub2 == 0) a.g_part[slice * a.nant + ant] = s;
         }
-        s = group_sum(s, w);
-        if (ant < a.nant && sub == 0) a.g_part[slice * a.nant + ant] = s;
       }
     }
     __syncthreads();
@@ -520,7 +548,7 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
   ProfScope ps(&f->prof, "k_gains", st);
   StageScope sc(kStageGains);
   if (mode != kGainFwd && lds_sorted <= kGainsSortedLds && f->n_bl <= 256 * kGainsMaxPerThread &&
-      f->n_ubl <= 256) {
+      f->n_ubl <= 256 && f->n_ant <= 256) {
     // enough times per block that the grid is about one round of resident blocks
     const long slots = static_cast<long>(f->n_cu) * std::max<long>(1, (160 * 1024) / static_cast<long>(lds_sorted + 64));
     a.tslab = std::max(1, std::min(f->n_time, ceil_div(static_cast<long>(f->n_time) * f->n_freq, slots)));

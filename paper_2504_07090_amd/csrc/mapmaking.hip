@@ -22,14 +22,13 @@ constexpr float kMapWeightFloor = 1e-6f;
 // w[f][k] = (A^H A)_pp for visible slot k; one wavefront per (64-pixel chunk,
 // channel).  Also clears the channel maxima that k_map_wmax raises.
 __global__ void __launch_bounds__(64)
-k_map_weight(int nf, int nvp, int nant, double d_omega, double beam_ref, const double* __restrict__ freq,
+k_map_weight(int nf, int nvp, int nant, double d_omega, const float* __restrict__ sigr,
              const float* __restrict__ TH2, const int2* __restrict__ chunk_t,
              const float2* __restrict__ gains, const float* __restrict__ fwhm, float* __restrict__ w,
              unsigned* __restrict__ wmax) {
   const int chunk = blockIdx.x, f = blockIdx.y, lane = threadIdx.x;
   if (chunk == 0 && lane == 0) wmax[f] = 0u;
-  const double nu = freq[f];
-  const float sig = static_cast<float>(fwhm[0] * (beam_ref / nu) * kFwhmToSigma);
+  const float sig = fwhm[0] * sigr[f];
   const float kb = 1.0f / (2.0f * sig * sig * static_cast<float>(kLn2));
   double s2 = 0.0, s4 = 0.0;
   for (int a = lane; a < nant; a += 64) {
@@ -106,7 +105,7 @@ void launch_map_finish(const vis_field* f, const vis_c64* gains, const float* fw
   {
     ProfScope ps(&f->prof, "k_map_weight", st);
     k_map_weight<<<dim3(f->n_chunks, f->n_freq), 64, 0, st>>>(
-        f->n_freq, f->nv_pad, f->n_ant, f->d_omega, f->beam_ref_hz, f->tab.freq, f->tab.th2,
+        f->n_freq, f->nv_pad, f->n_ant, f->d_omega, f->tab.sigr, f->tab.th2,
         f->tab.chunk_t, reinterpret_cast<const float2*>(gains), fwhm, w, wmax);
     check_launch("k_map_weight");
   }

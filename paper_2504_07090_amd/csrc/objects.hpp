@@ -91,11 +91,13 @@ struct FieldScratch {
 
 // Immutable device tables of one field.
 struct FieldTables {
-  double* freq = nullptr;          // [n_freq] Hz
+  float* dnu = nullptr;            // [n_freq] nu_f - nu_c, Hz (nu_c: the field's reference frequency)
+  float* sigr = nullptr;           // [n_freq] beam sigma per unit FWHM: (nu_ref / nu_f) / (2 sqrt(2 ln 2))
   int* vpix = nullptr;             // [nv_pad] pixel index of each visible slot
   int* vidx = nullptr;             // [n_pix] visible slot of each pixel or -1
-  double* p1 = nullptr;            // [n_time][nv_pad] (e1 . s) / c, seconds
-  double* p2 = nullptr;            // [n_time][nv_pad] (e2 . s) / c
+  float2* q1 = nullptr;            // [n_time][nv_pad] (y, p) of lattice axis 1: p = (e1 . s) / c in
+                                   //   seconds, y = nu_c p - rint(nu_c p) (cycles, formed in FP64)
+  float2* q2 = nullptr;            // [n_time][nv_pad] the same for e2
   float* th2 = nullptr;            // [n_time][nv_pad] zenith angle^2, kBelowHorizon if U <= 0
   int2* chunk_t = nullptr;         // [n_chunks] first / last time the chunk is visible
   int* tchunk_off = nullptr;       // [n_time + 1] CSR of chunks active at each time
