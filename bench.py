@@ -60,8 +60,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "64639fd89d2bea6ee57daf0b53523afbee1529fd561d8a9cb80993c37db3e148",
-    "bytes_per_launch": {"k_fringe_adj": 199359155, "k_fringe_fwd": 271652732},
+    "sha256": "6d2a6ee6280f02f452f74a54358b12d09685efa484fd77f2fb2a5263518aeeec",
+    "bytes_per_launch": {"k_fringe_adj": 199664428, "k_fringe_fwd": 273535542},
 }
 
 
