@@ -355,6 +355,7 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
   T.a_list = cv.take<int>(2 * static_cast<size_t>(f->n_bl));
   T.ubl_nm = cv.take<int2>(f->n_ubl);
   T.ulut = cv.take<int>(static_cast<size_t>(f->extent + 1) * (2 * f->extent + 1));
+  T.cplan = cv.take<int4>(f->gstride);
   auto& S = f->scr;
   const size_t kpad = f->basis->kpad;
   const bool dense = f->synthesis == VIS_SYNTH_DENSE;
@@ -645,6 +646,8 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
     up(T.a_list, a_list, s);
     up(T.ubl_nm, ubl_nm, s);
     up(T.ulut, ulut, s);
+    const std::vector<int4> cplan = coef_plan(ulut, f->extent, f->dtile, fringe_split(f), f->gstride);
+    up(T.cplan, cplan, s);
     // the padded tail of the sky scratch must stay finite (it is multiplied by a zero beam)
     BV_HIP(hipMemsetAsync(f->scr.img, 0, sizeof(float) * f->n_freq * f->nv_pad, s));
     std::vector<int> vidx(basis->n_pix, -1);

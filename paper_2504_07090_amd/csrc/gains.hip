@@ -28,7 +28,7 @@ __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.
 constexpr size_t kGainsSortedLds = 64 * 1024;
 
 struct GainArgs {
-  int mode, nt, nf, nbl, nubl, nant;
+  int nt, nf, nbl, nubl, nant;
   float inv_sig2;
   const int2* bl_ant;
   const int* bl_u;
@@ -44,8 +44,8 @@ struct GainArgs {
   double* chi_part;
   float* gco;
   float2* g_part;
-  const int* ulut;
-  int dr, dtile, rt, gstride;
+  const int4* cplan;
+  int gstride;
   int split;   // the adjoint multiplies the coefficients as FP16 hi + lo pairs
   int tslab;   // consecutive times per block
 };
@@ -108,32 +108,126 @@ __device__ __forceinline__ float2 lds_sum4(const float2* x, int2 r, int w) {
 // inputs (16 rt floats, below), then for n = 1..dtile (omega(n, 0).re,
 // omega(n, 0).im, omega(0, n).re, omega(0, n).im).
 //
-// Split layout (a.split): G is scaled by a power of two s (|s G| < 2^14) and
-// stored as FP16 hi + lo pairs.  Per tile (i, kt), 64 lanes x 8 halves: lane
-// l = (row l & 15, group g = l >> 4) holds, in slot j, hi(s G[r][16 kt + 8 g + j])
-// for g < 2 and lo(s G[r][16 kt + 8 (g - 2) + j]) for g >= 2 (the A operand of
-// one K = 32 MFMA against [B_hi; B_hi], giving G_hi B_hi + G_lo B_hi).  Then
-// per tile 64 lanes x 4 halves: hi(s G[r][16 kt + 4 g + j]) (the A operand of
-// one K = 16 MFMA against B_lo).  Then the alpha-axis inputs times s, the axis
+// Split layout: G is scaled by a power of two s (|s G| < 2^14) and stored as
+// FP16 hi + lo pairs.  Per tile (i, kt), 64 lanes x 8 halves: lane l = (row
+// l & 15, group g = l >> 4) holds, in slot j, hi(s G[r][16 kt + 8 g + j]) for
+// g < 2 and lo(s G[r][16 kt + 8 (g - 2) + j]) for g >= 2 (the A operand of one
+// K = 32 MFMA against [B_hi; B_hi], giving G_hi B_hi + G_lo B_hi).  Then per
+// tile 64 lanes x 4 halves: hi(s G[r][16 kt + 4 g + j]) (the A operand of one
+// K = 16 MFMA against B_lo).  Then the alpha-axis inputs times s, the axis
 // coefficients (unscaled) and 1 / s.
-__device__ __forceinline__ void write_coefficients(const GainArgs& a, const float2* om,
-                                                   const int* ulut, size_t slice, int tid) {
-  const int lw = 2 * a.dr + 1;
-  auto omega = [&](int n1, int n2) {
-    if (n1 > a.dr || n2 > a.dr || n2 < -a.dr) return make_float2(0.f, 0.f);
-    const int u = ulut[n1 * lw + n2 + a.dr];
-    return u >= 0 ? om[u] : make_float2(0.f, 0.f);
+//
+// The layout depends only on the field, so where every entry comes from is
+// worked out once on the host (coef_plan): entry e holds one or two values
+// g = +-omega[a].c +- omega[b].c (c = Re or Im, either source may be absent),
+// combined as its kind says.
+enum CoefKind : int { kCoefZero = 0, kCoefPlain = 1, kCoefScaled = 2, kCoefPackHi = 3, kCoefPackLo = 4,
+                      kCoefInvScale = 5 };
+
+// One value of a plan entry: sources a, b (unique index + 1, 0 = none) in
+// `src`, and in `fl` the component (bit 0) and the negations of a (bit 1) and
+// b (bit 2).
+struct CoefTerm {
+  int a = 0, b = 0, comp = 0, na = 0, nb = 0;
+};
+
+static int4 pack_plan(int kind, const CoefTerm& t0, const CoefTerm& t1) {
+  int4 p;
+  p.x = t0.a | (t0.b << 16);
+  p.y = t1.a | (t1.b << 16);
+  p.z = kind | (t0.comp << 4) | (t0.na << 5) | (t0.nb << 6) | (t1.comp << 7) | (t1.na << 8) |
+        (t1.nb << 9);
+  p.w = 0;
+  return p;
+}
+
+std::vector<int4> coef_plan(const std::vector<int>& ulut, int extent, int dtile, bool split,
+                            int gstride) {
+  const int lw = 2 * extent + 1;
+  auto src = [&](int n1, int n2) {   // unique index + 1 of lattice (n1, n2), 0 if none
+    if (n1 > extent || n2 > extent || n2 < -extent) return 0;
+    const int u = ulut[n1 * lw + n2 + extent];
+    return u >= 0 ? u + 1 : 0;
   };
-  auto gval = [&](int r, int c) {
+  auto gterm = [&](int r, int c) {   // G[r][c] as +-omega(n, m).comp +- omega(n, -m).comp
+    CoefTerm t;
     const int n = (r >> 1) + 1, m = (c >> 1) + 1;
-    if (n > a.dtile || m > a.dtile) return 0.f;
-    const float2 wp = omega(n, m), wm = omega(n, -m);
+    if (n > dtile || m > dtile) return t;
+    t.a = src(n, m);
+    t.b = src(n, -m);
     const int pr = r & 1, pc = c & 1;
-    if (pr == 0 && pc == 0) return wp.x + wm.x;
-    if (pr == 1 && pc == 1) return wm.x - wp.x;
-    if (pr == 0 && pc == 1) return wm.y - wp.y;
-    return -wp.y - wm.y;
+    if (pr == 0 && pc == 0) {          // w+r + w-r
+      t.comp = 0;
+    } else if (pr == 1 && pc == 1) {   // w-r - w+r
+      t.comp = 0;
+      t.na = 1;
+    } else if (pr == 0 && pc == 1) {   // w-i - w+i
+      t.comp = 1;
+      t.na = 1;
+    } else {                           // -w+i - w-i
+      t.comp = 1;
+      t.na = 1;
+      t.nb = 1;
+    }
+    return t;
   };
+  const int rt = fringe_tiles(dtile);
+  const int ntile = rt * rt;
+  const int nmat = ntile * (split ? 384 : 256);
+  std::vector<int4> plan(gstride, pack_plan(kCoefZero, CoefTerm{}, CoefTerm{}));
+  for (int e = 0; e < gstride; ++e) {
+    if (e < nmat) {
+      if (!split) {
+        const int s4 = e & 3, l = (e >> 2) & 63, blk = e >> 8;
+        const int i = blk / rt, kt = blk - i * rt;
+        plan[e] = pack_plan(kCoefPlain, gterm(16 * i + (l & 15), 16 * kt + 4 * (l >> 4) + s4), CoefTerm{});
+      } else if (e < ntile * 256) {   // K = 32 operand: two halves per float
+        const int q = e & 3, l = (e >> 2) & 63, blk = e >> 8;
+        const int i = blk / rt, kt = blk - i * rt, g = l >> 4, r = 16 * i + (l & 15);
+        const int c = 16 * kt + 8 * (g & 1) + 2 * q;
+        plan[e] = pack_plan(g < 2 ? kCoefPackHi : kCoefPackLo, gterm(r, c), gterm(r, c + 1));
+      } else {                        // K = 16 operand: hi halves
+        const int e2 = e - ntile * 256;
+        const int q = e2 & 1, l = (e2 >> 1) & 63, blk = e2 >> 7;
+        const int i = blk / rt, kt = blk - i * rt, g = l >> 4, r = 16 * i + (l & 15);
+        const int c = 16 * kt + 4 * g + 2 * q;
+        plan[e] = pack_plan(kCoefPackHi, gterm(r, c), gterm(r, c + 1));
+      }
+    } else if (e < nmat + 16 * rt) {
+      // alpha-axis accumulator input of row tile i, lane group grp: rows
+      // 16 i + 4 grp + 0..3 are (Re, Im) of the powers n = 8 i + 2 grp + 1
+      // and n + 1, whose coefficients are (Re, -Im) of omega(n, 0)
+      const int idx = e - nmat, i = idx >> 4, grp = (idx >> 2) & 3, comp = idx & 3;
+      const int n = 8 * i + 2 * grp + (comp >> 1) + 1;
+      if (n <= dtile) {
+        CoefTerm t;
+        t.a = src(n, 0);
+        t.comp = comp & 1;
+        t.na = comp & 1;
+        plan[e] = pack_plan(kCoefScaled, t, CoefTerm{});
+      }
+    } else if (e < nmat + 16 * rt + 4 * dtile) {
+      const int idx = e - nmat - 16 * rt, n = idx / 4 + 1, comp = idx & 3;
+      CoefTerm t;
+      t.a = comp < 2 ? src(n, 0) : src(0, n);
+      t.comp = comp & 1;
+      plan[e] = pack_plan(kCoefPlain, t, CoefTerm{});
+    } else if (split && e == nmat + 16 * rt + 4 * dtile) {
+      plan[e] = pack_plan(kCoefInvScale, CoefTerm{}, CoefTerm{});
+    }
+  }
+  return plan;
+}
+
+__device__ __forceinline__ float coef_term(const float2* om, int src, int comp, int neg) {
+  if (src == 0) return 0.f;
+  const float2 o = om[src - 1];
+  const float v = comp ? o.y : o.x;
+  return neg ? -v : v;
+}
+
+__device__ __forceinline__ void write_coefficients(const GainArgs& a, const float2* om, size_t slice,
+                                                   int tid) {
   // split layout: power-of-two scale from the largest |omega| component
   // (|G| <= 2 max |omega|), found by the whole block
   float scale = 1.0f;
@@ -153,53 +247,24 @@ __device__ __forceinline__ void write_coefficients(const GainArgs& a, const floa
     }
   }
   float* G = a.gco + slice * a.gstride;
-  const int ntile = a.rt * a.rt;
-  const int nmat = ntile * (a.split ? 384 : 256);
   for (int e = tid; e < a.gstride; e += blockDim.x) {
+    const int4 p = a.cplan[e];
+    const int kind = p.z & 15;
+    const float g0 = coef_term(om, p.x & 0xffff, (p.z >> 4) & 1, (p.z >> 5) & 1) +
+                     coef_term(om, p.x >> 16, (p.z >> 4) & 1, (p.z >> 6) & 1);
     float val = 0.f;
-    if (e < nmat) {
-      if (!a.split) {
-        const int s4 = e & 3, l = (e >> 2) & 63, blk = e >> 8;
-        const int i = blk / a.rt, kt = blk - i * a.rt;
-        // lane l feeds row l & 15 and, in MFMA step s4, column 4 (l >> 4) + s4 of
-        // the 16-column block kt (the adjoint reads its B operand for the four
-        // steps as one 16-byte LDS load)
-        val = gval(16 * i + (l & 15), 16 * kt + 4 * (l >> 4) + s4);
-      } else if (e < ntile * 256) {
-        // K = 32 operand: two halves (slots 2 q, 2 q + 1) per float
-        const int q = e & 3, l = (e >> 2) & 63, blk = e >> 8;
-        const int i = blk / a.rt, kt = blk - i * a.rt, g = l >> 4, r = 16 * i + (l & 15);
-        const int c = 16 * kt + 8 * (g & 1) + 2 * q;
-        _Float16 h0, l0, h1, l1;
-        split_f16(scale * gval(r, c), h0, l0);
-        split_f16(scale * gval(r, c + 1), h1, l1);
-        val = g < 2 ? pack_f16(h0, h1) : pack_f16(l0, l1);
-      } else {
-        // K = 16 operand: hi halves, slots 2 q, 2 q + 1
-        const int e2 = e - ntile * 256;
-        const int q = e2 & 1, l = (e2 >> 1) & 63, blk = e2 >> 7;
-        const int i = blk / a.rt, kt = blk - i * a.rt, g = l >> 4, r = 16 * i + (l & 15);
-        const int c = 16 * kt + 4 * g + 2 * q;
-        _Float16 h0, l0, h1, l1;
-        split_f16(scale * gval(r, c), h0, l0);
-        split_f16(scale * gval(r, c + 1), h1, l1);
-        val = pack_f16(h0, h1);
-      }
-    } else if (e < nmat + 16 * a.rt) {
-      // alpha-axis accumulator input of row tile i, lane group grp: rows
-      // 16 i + 4 grp + 0..3 are (Re, Im) of the powers n = 8 i + 2 grp + 1
-      // and n + 1, whose coefficients are (Re, -Im) of omega(n, 0)
-      const int idx = e - nmat, i = idx >> 4, grp = (idx >> 2) & 3, comp = idx & 3;
-      const int n = 8 * i + 2 * grp + (comp >> 1) + 1;
-      if (n <= a.dtile) {
-        const float2 w0 = omega(n, 0);
-        val = scale * ((comp & 1) ? -w0.y : w0.x);
-      }
-    } else if (e < nmat + 16 * a.rt + 4 * a.dtile) {
-      const int idx = e - nmat - 16 * a.rt, n = idx / 4 + 1, comp = idx & 3;
-      const float2 w0 = comp < 2 ? omega(n, 0) : omega(0, n);
-      val = (comp & 1) ? w0.y : w0.x;
-    } else if (a.split && e == nmat + 16 * a.rt + 4 * a.dtile) {
+    if (kind == kCoefPlain) {
+      val = g0;
+    } else if (kind == kCoefScaled) {
+      val = scale * g0;
+    } else if (kind == kCoefPackHi || kind == kCoefPackLo) {
+      const float g1 = coef_term(om, p.y & 0xffff, (p.z >> 7) & 1, (p.z >> 8) & 1) +
+                       coef_term(om, p.y >> 16, (p.z >> 7) & 1, (p.z >> 9) & 1);
+      _Float16 h0, l0, h1, l1;
+      split_f16(scale * g0, h0, l0);
+      split_f16(scale * g1, h1, l1);
+      val = kind == kCoefPackHi ? pack_f16(h0, h1) : pack_f16(l0, l1);
+    } else if (kind == kCoefInvScale) {
       val = 1.0f / scale;
     }
     G[e] = val;
@@ -221,29 +286,27 @@ __device__ __forceinline__ void write_coefficients(const GainArgs& a, const floa
 // partial sums with a fixed butterfly, so every result has a fixed order.
 constexpr int kGainsMaxPerThread = 8;
 
-template <bool SORTED>
+template <bool SORTED, int MODE>
 struct KGains {
   using Args = GainArgs;
   static constexpr int kThreads = 256, kWaves = 1;
   static __device__ void run(const GainArgs& a, const Blk& B);
 };
 
-template <bool SORTED>
-__device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
+template <bool SORTED, int MODE>
+__device__ void KGains<SORTED, MODE>::run(const GainArgs& a, const Blk& B) {
+  static_assert(!(SORTED && MODE == kGainFwd), "the forward mode walks the baselines once");
+  constexpr bool kCot = MODE == kGainAdj || MODE == kGainMap;   // cotangent given
   extern __shared__ float2 sm[];
   float2* g = sm;              // [nant]
   float2* v = sm + a.nant;     // [nubl]
   float2* om = v + a.nubl;     // [nubl] collapsed coefficients omega_u
   float2* tu = om + a.nubl;    // [nbl] omega terms in u_list order (SORTED)
   float2* ta = tu + a.nbl;     // [2 nbl] antenna terms in a_list order (SORTED)
-  int* ulut = reinterpret_cast<int*>(ta + 2 * a.nbl);   // SORTED: LDS copy of the lookup
   __shared__ double red[4];
   const int f = B.x, tid = threadIdx.x;
   const int t0 = B.y * a.tslab, t1 = min(a.nt, t0 + a.tslab);
-  const int nlut = (a.dr + 1) * (2 * a.dr + 1);
   for (int i = tid; i < a.nant; i += 256) g[i] = a.gains[static_cast<size_t>(f) * a.nant + i];
-  if (SORTED)
-    for (int i = tid; i < nlut; i += 256) ulut[i] = a.ulut[i];
   int2 ij_r[SORTED ? kGainsMaxPerThread : 1];
   int uc_r[SORTED ? kGainsMaxPerThread : 1];
   int4 pos_r[SORTED ? kGainsMaxPerThread : 1];
@@ -271,8 +334,10 @@ __device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
   auto omega_term = [&](bool neg, float2 c, float2 G) {
     return neg ? cmul(c, conjf2(G)) : cmul(conjf2(c), G);
   };
-  auto ant_term = [&](int role, int2 ij, float2 c, float2 vk) {
-    return role ? cmul(cmul(conjf2(c), g[ij.x]), vk) : cmul(cmul(c, g[ij.y]), conjf2(vk));
+  // antenna terms through h = c conj(V): role 0 (antenna i of (i, j)) takes
+  // h g_j, role 1 (antenna j) takes conj(h) g_i
+  auto ant_term = [&](int role, int2 ij, float2 h) {
+    return role ? cmul(conjf2(h), g[ij.x]) : cmul(h, g[ij.y]);
   };
   // SORTED: the next slice's data and unique visibilities are loaded into
   // registers while the current one is processed
@@ -287,6 +352,14 @@ __device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
     if (tid < a.nubl) v_r = a.vu[sl * a.nubl + tid];
   };
   if (SORTED && t0 < t1) fetch(t0);
+  // residual r = d - m in FP32 (one rounding of a difference of two FP32
+  // values), its square summed in FP64
+  auto cot_from = [&](float2 dk, float2 m, double& acc) {
+    if (kCot) return dk;
+    const float rx = dk.x - m.x, ry = dk.y - m.y;
+    if (MODE == kGainChi2) acc += static_cast<double>(__builtin_fmaf(rx, rx, ry * ry));
+    return make_float2(-2.f * a.inv_sig2 * rx, -2.f * a.inv_sig2 * ry);
+  };
   for (int t = t0; t < t1; ++t) {
     const size_t slice = static_cast<size_t>(t) * a.nf + f;
     __syncthreads();   // the previous slice is done with v, om, tu, ta
@@ -310,23 +383,12 @@ __device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
       const int2 ij = a.bl_ant[k];
       return cmul(g[ij.x], conjf2(g[ij.y]));
     };
-    auto cot_of = [&](int k, float2 m) {
-      if (a.mode == kGainAdj || a.mode == kGainMap) return din[k];
-      return make_float2(-2.f * a.inv_sig2 * (din[k].x - m.x), -2.f * a.inv_sig2 * (din[k].y - m.y));
-    };
-    if (a.mode == kGainFwd) {
+    if (MODE == kGainFwd) {
       float2* out = a.vis_out + slice * a.nbl;
       for (int k = tid; k < a.nbl; k += 256) out[k] = cmul(gprod(k), vis_of(k));
       continue;
     }
     double acc = 0.0;
-    auto chi_term = [&](int k, float2 m) {
-      if (a.mode == kGainChi2) {
-        const double rx = static_cast<double>(din[k].x) - m.x;
-        const double ry = static_cast<double>(din[k].y) - m.y;
-        acc += rx * rx + ry * ry;
-      }
-    };
     if (SORTED) {
 #pragma unroll
       for (int q = 0; q < kGainsMaxPerThread; ++q) {
@@ -336,43 +398,36 @@ __device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
           const int ucode = uc_r[q];
           const float2 G = cmul(g[ij.x], conjf2(g[ij.y]));
           const float2 vk = ucode >= 0 ? v[ucode] : conjf2(v[~ucode]);
-          const float2 m = cmul(G, vk);
-          const float2 dk = dcur[q];
-          if (a.mode == kGainChi2) {
-            const double rx = static_cast<double>(dk.x) - m.x;
-            const double ry = static_cast<double>(dk.y) - m.y;
-            acc += rx * rx + ry * ry;
-          }
-          const float2 c = (a.mode == kGainAdj || a.mode == kGainMap)
-                               ? dk
-                               : make_float2(-2.f * a.inv_sig2 * (dk.x - m.x), -2.f * a.inv_sig2 * (dk.y - m.y));
+          const float2 c = cot_from(dcur[q], kCot ? make_float2(0.f, 0.f) : cmul(G, vk), acc);
           tu[pos_r[q].x] = omega_term(ucode < 0, c, G);
-          if (a.mode != kGainMap) {
-            ta[pos_r[q].y] = ant_term(0, ij, c, vk);
-            ta[pos_r[q].z] = ant_term(1, ij, c, vk);
+          if (MODE != kGainMap) {
+            const float2 h = cmul(c, conjf2(vk));
+            ta[pos_r[q].y] = ant_term(0, ij, h);
+            ta[pos_r[q].z] = ant_term(1, ij, h);
           }
         }
       }
-    } else if (a.mode == kGainChi2) {
-      for (int k = tid; k < a.nbl; k += 256) chi_term(k, cmul(gprod(k), vis_of(k)));
+    } else if (MODE == kGainChi2) {
+      for (int k = tid; k < a.nbl; k += 256) cot_from(din[k], cmul(gprod(k), vis_of(k)), acc);
     }
-    if (a.mode == kGainChi2) {
+    if (MODE == kGainChi2) {
       for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
       if ((tid & 63) == 0) red[tid >> 6] = acc;
     }
     __syncthreads();
-    if (a.mode == kGainChi2 && tid == 0)
+    if (MODE == kGainChi2 && tid == 0)
       a.chi_part[slice] = ((red[0] + red[1]) + (red[2] + red[3])) * static_cast<double>(a.inv_sig2);
     if (SORTED) {
-      // one list per lane group (u_rng / a_rng, fixed for the whole slab);
-      // four interleaved partial sums keep four LDS reads in flight
+      // one list per lane group; four interleaved partial sums keep four LDS
+      // reads in flight
       const float2 o = group_sum(lds_sum4(tu, u_rng, wu), wu);
       if (u_mine < a.nubl && (tid & (wu - 1)) == 0) om[u_mine] = o;
-      if (a.mode != kGainMap) {
-        const float2 s = group_sum(lds_sum4(ta, a_rng, wa), wa);
-        if (a_mine < a.nant && (tid & (wa - 1)) == 0) a.g_part[slice * a.nant + a_mine] = s;
+      if (MODE != kGainMap) {
+        const float2 sg = group_sum(lds_sum4(ta, a_rng, wa), wa);
+        if (a_mine < a.nant && (tid & (wa - 1)) == 0) a.g_part[slice * a.nant + a_mine] = sg;
       }
     } else {
+      double unused = 0.0;
       const int w = lanes_per_item(a.nubl), sub = tid & (w - 1);
       for (int base = 0; base < a.nubl; base += 256 / w) {
         const int u = base + tid / w;
@@ -382,7 +437,8 @@ __device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
             const int code = a.u_list[e];
             const int k = code >> 1;
             const float2 G = gprod(k);
-            const float2 term = omega_term(code & 1, cot_of(k, cmul(G, vis_of(k))), G);
+            const float2 c = cot_from(din[k], kCot ? make_float2(0.f, 0.f) : cmul(G, vis_of(k)), unused);
+            const float2 term = omega_term(code & 1, c, G);
             o.x += term.x;
             o.y += term.y;
           }
@@ -390,29 +446,30 @@ __device__ void KGains<SORTED>::run(const GainArgs& a, const Blk& B) {
         o = group_sum(o, w);
         if (u < a.nubl && sub == 0) om[u] = o;
       }
-      if (a.mode != kGainMap) {
+      if (MODE != kGainMap) {
         const int w2 = lanes_per_item(a.nant), sub2 = tid & (w2 - 1);
         for (int base = 0; base < a.nant; base += 256 / w2) {
           const int ant = base + tid / w2;
-          float2 s = make_float2(0.f, 0.f);
+          float2 sg = make_float2(0.f, 0.f);
           if (ant < a.nant) {
             for (int e = a.a_off[ant] + sub2; e < a.a_off[ant + 1]; e += w2) {
               const int code = a.a_list[e];
               const int k = code >> 1;
               const int2 ij = a.bl_ant[k];
               const float2 vk = vis_of(k);
-              const float2 term = ant_term(code & 1, ij, cot_of(k, cmul(gprod(k), vk)), vk);
-              s.x += term.x;
-              s.y += term.y;
+              const float2 c = cot_from(din[k], kCot ? make_float2(0.f, 0.f) : cmul(gprod(k), vk), unused);
+              const float2 term = ant_term(code & 1, ij, cmul(c, conjf2(vk)));
+              sg.x += term.x;
+              sg.y += term.y;
             }
           }
-          s = group_sum(s, w2);
-          if (ant < a.nant && sub2 == 0) a.g_part[slice * a.nant + ant] = s;
+          sg = group_sum(sg, w2);
+          if (ant < a.nant && sub2 == 0) a.g_part[slice * a.nant + ant] = sg;
         }
       }
     }
     __syncthreads();
-    write_coefficients(a, om, SORTED ? ulut : a.ulut, slice, tid);
+    write_coefficients(a, om, slice, tid);
   }
 }
 
@@ -514,7 +571,6 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
                   const float2* din, float sigma_n, float2* vis_out, double* chi_part, float* gco,
                   float2* g_part, hipStream_t st) {
   GainArgs a;
-  a.mode = mode;
   a.nt = f->n_time;
   a.nf = f->n_freq;
   a.nbl = f->n_bl;
@@ -535,16 +591,12 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
   a.chi_part = chi_part;
   a.gco = gco;
   a.g_part = g_part;
-  a.ulut = f->tab.ulut;
-  a.dr = f->extent;
-  a.dtile = f->dtile;
-  a.rt = fringe_tiles(f->dtile);
+  a.cplan = f->tab.cplan;
   a.gstride = f->gstride;
   a.split = fringe_split(f);
   const size_t lds = sizeof(float2) * (f->n_ant + 2 * f->n_ubl);
   BV_REQUIRE(lds <= 48 * 1024, VIS_EINVAL, "field too large for the gains pass LDS budget");
-  const size_t lds_sorted = lds + 3 * sizeof(float2) * f->n_bl +
-                            sizeof(int) * (f->extent + 1) * (2 * f->extent + 1);
+  const size_t lds_sorted = lds + 3 * sizeof(float2) * f->n_bl;
   ProfScope ps(&f->prof, "k_gains", st);
   StageScope sc(kStageGains);
   if (mode != kGainFwd && lds_sorted <= kGainsSortedLds && f->n_bl <= 256 * kGainsMaxPerThread &&
@@ -553,11 +605,23 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
     const long slots = static_cast<long>(f->n_cu) * std::max<long>(1, (160 * 1024) / static_cast<long>(lds_sorted + 64));
     a.tslab = std::max(1, std::min(f->n_time, ceil_div(static_cast<long>(f->n_time) * f->n_freq, slots)));
     dim3 grid(f->n_freq, ceil_div(f->n_time, a.tslab));
-    launch_k<KGains<true>>(grid, lds_sorted, a, st, "k_gains");
+    if (mode == kGainChi2)
+      launch_k<KGains<true, kGainChi2>>(grid, lds_sorted, a, st, "k_gains");
+    else if (mode == kGainAdj)
+      launch_k<KGains<true, kGainAdj>>(grid, lds_sorted, a, st, "k_gains");
+    else
+      launch_k<KGains<true, kGainMap>>(grid, lds_sorted, a, st, "k_gains");
   } else {
     a.tslab = 1;
     dim3 grid(f->n_freq, f->n_time);
-    launch_k<KGains<false>>(grid, lds, a, st, "k_gains");
+    if (mode == kGainFwd)
+      launch_k<KGains<false, kGainFwd>>(grid, lds, a, st, "k_gains");
+    else if (mode == kGainChi2)
+      launch_k<KGains<false, kGainChi2>>(grid, lds, a, st, "k_gains");
+    else if (mode == kGainAdj)
+      launch_k<KGains<false, kGainAdj>>(grid, lds, a, st, "k_gains");
+    else
+      launch_k<KGains<false, kGainMap>>(grid, lds, a, st, "k_gains");
   }
 }
 

@@ -112,6 +112,7 @@ struct FieldTables {
   int* a_list = nullptr;           // [2 n_bl] (bl << 1) | role (0: antenna is i, 1: is j)
   int2* ubl_nm = nullptr;          // [n_ubl] lattice (n1, n2), canonical
   int* ulut = nullptr;             // [(D+1) * (2D+1)] unique index of (n1, n2) or -1
+  int4* cplan = nullptr;           // [gstride] source plan of each adjoint coefficient entry
 };
 
 }  // namespace bv
@@ -179,6 +180,10 @@ void launch_filter_cot(const vis_field* f, const vis_filter* flt, const Filtered
 enum GainMode { kGainFwd = 0, kGainChi2 = 1, kGainAdj = 2, kGainMap = 3 };
 void launch_map_finish(const vis_field* f, const vis_c64* gains, const float* fwhm, float* map,
                        float* weight, hipStream_t st);
+// Where each entry of a (t, nu) slice of adjoint coefficients comes from
+// (the gains pass evaluates it from the slice's collapsed omega): see gains.hip.
+std::vector<int4> coef_plan(const std::vector<int>& ulut, int extent, int dtile, bool split,
+                            int gstride);
 void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const float2* gains,
                   const float2* data_or_dvis, float sigma_n, float2* vis_out, double* chi_part,
                   float* gco, float2* g_part, hipStream_t st);
