@@ -146,10 +146,9 @@ __device__ __forceinline__ int lds_at(int px, int col) {
 // sees every power while it is still in registers.  With alpha = exp(-i t),
 // alpha^(n+1) = 2 cos(t) alpha^n - alpha^(n-1) (the three-term recurrence of
 // cos(n t) and sin(n t)), one FMA per component; the same holds for beta^m w.
-template <int D, int W, class Visit>
-__device__ __forceinline__ void write_powers(float* As, float* Bs, int px, float c1, float s1,
-                                             float c2, float s2, float w, Visit visit) {
-  float av[W], bv[W];
+template <int D, class Visit>
+__device__ __forceinline__ void powers_f32(float* av, float* bv, float c1, float s1, float c2,
+                                           float s2, float w, Visit visit) {
   float ar0 = 1.f, ai0 = 0.f, ar = c1, ai = -s1;
   float br0 = w, bi0 = 0.f, br = c2 * w, bi = -s2 * w;
   const float t1 = 2.f * c1, t2 = 2.f * c2;
@@ -165,14 +164,24 @@ __device__ __forceinline__ void write_powers(float* As, float* Bs, int px, float
     ar0 = ar; ai0 = ai; br0 = br; bi0 = bi;
     ar = nar; ai = nai; br = nbr; bi = nbi;
   }
-#pragma unroll
-  for (int r = 2 * D; r < W; ++r) av[r] = bv[r] = 0.f;
+}
+template <int W>
+__device__ __forceinline__ void store_rows(float* As, float* Bs, int px, const float* av, const float* bv) {
 #pragma unroll
   for (int g = 0; g < W / 4; ++g) {
     const int o = px * W + ((g ^ swz<W>(px)) << 2);
     *reinterpret_cast<f4*>(As + o) = f4{av[4 * g], av[4 * g + 1], av[4 * g + 2], av[4 * g + 3]};
     *reinterpret_cast<f4*>(Bs + o) = f4{bv[4 * g], bv[4 * g + 1], bv[4 * g + 2], bv[4 * g + 3]};
   }
+}
+template <int D, int W, class Visit>
+__device__ __forceinline__ void write_powers(float* As, float* Bs, int px, float c1, float s1,
+                                             float c2, float s2, float w, Visit visit) {
+  float av[W], bv[W];
+  powers_f32<D>(av, bv, c1, s1, c2, s2, w, visit);
+#pragma unroll
+  for (int r = 2 * D; r < W; ++r) av[r] = bv[r] = 0.f;
+  store_rows<W>(As, Bs, px, av, bv);
 }
 
 // ------------------------------------------------- split-precision helpers --
@@ -216,13 +225,9 @@ template <int W> struct SplitRows {
 
 // Powers of one pixel for the split adjoint: alpha^n in FP32 into its As row
 // (as write_powers), beta^m as FP16 hi + lo pairs into its Bh / Bl rows.
-template <int D, int W, class Visit>
-__device__ __forceinline__ void write_powers_split(float* As, uint32_t* Bh, uint32_t* Bl, int px,
-                                                   float c1, float s1, float c2, float s2,
-                                                   Visit visit) {
-  using R = SplitRows<W>;
-  float av[W];
-  uint32_t bh[W / 2], bl[W / 2];
+template <int D, class Visit>
+__device__ __forceinline__ void powers_split_adj(float* av, uint32_t* bh, uint32_t* bl, float c1,
+                                                 float s1, float c2, float s2, Visit visit) {
   float ar0 = 1.f, ai0 = 0.f, ar = c1, ai = -s1;
   float br0 = 1.f, bi0 = 0.f, br = c2, bi = -s2;
   const float t1 = 2.f * c1, t2 = 2.f * c2;
@@ -238,10 +243,12 @@ __device__ __forceinline__ void write_powers_split(float* As, uint32_t* Bh, uint
     ar0 = ar; ai0 = ai; br0 = br; bi0 = bi;
     ar = nar; ai = nai; br = nbr; bi = nbi;
   }
-#pragma unroll
-  for (int r = 2 * D; r < W; ++r) av[r] = 0.f;
-#pragma unroll
-  for (int n = D; n < W / 2; ++n) bh[n] = bl[n] = 0u;
+}
+template <int W>
+__device__ __forceinline__ void store_rows_split_adj(float* As, uint32_t* Bh, uint32_t* Bl, int px,
+                                                     const float* av, const uint32_t* bh,
+                                                     const uint32_t* bl) {
+  using R = SplitRows<W>;
 #pragma unroll
   for (int g = 0; g < W / 4; ++g) {
     const int o = px * W + ((g ^ swz<W>(px)) << 2);
@@ -256,6 +263,19 @@ __device__ __forceinline__ void write_powers_split(float* As, uint32_t* Bh, uint
   for (int g = 0; g < W / 4; ++g)
     *reinterpret_cast<u2*>(Bl + px * R::BL + 2 * g) = u2{bl[2 * g], bl[2 * g + 1]};
 }
+template <int D, int W, class Visit>
+__device__ __forceinline__ void write_powers_split(float* As, uint32_t* Bh, uint32_t* Bl, int px,
+                                                   float c1, float s1, float c2, float s2,
+                                                   Visit visit) {
+  float av[W];
+  uint32_t bh[W / 2], bl[W / 2];
+  powers_split_adj<D>(av, bh, bl, c1, s1, c2, s2, visit);
+#pragma unroll
+  for (int r = 2 * D; r < W; ++r) av[r] = 0.f;
+#pragma unroll
+  for (int n = D; n < W / 2; ++n) bh[n] = bl[n] = 0u;
+  store_rows_split_adj<W>(As, Bh, Bl, px, av, bh, bl);
+}
 
 // Forward split rows: each pixel row holds W halves (W / 2 words, pairs
 // (Re, Im) of one power) in 16-byte groups, group g stored at g ^ swz_h(px)
@@ -268,14 +288,14 @@ __device__ __forceinline__ int swz_h(int px) {
 }
 
 // Powers of one pixel for the split forward: alpha^n and beta^m w as FP16
-// hi + lo pairs into its rows of Ah, Al (alpha) and Bh, Bl (beta); visit(n,
-// ...) sees the FP32 values (beta^m w as generated, w already scaled).
-template <int D, int W, class Visit>
-__device__ __forceinline__ void write_powers_fwd_split(uint32_t* Ah, uint32_t* Al, uint32_t* Bh,
-                                                       uint32_t* Bl, int px, float c1, float s1,
-                                                       float c2, float s2, float w, Visit visit) {
-  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-  uint32_t ah[W / 2], al[W / 2], bh[W / 2], bl[W / 2];
+// hi + lo pairs (one word per complex power) into ah, al (alpha) and bh, bl
+// (beta); visit(n, ...) sees the FP32 values (beta^m w as generated, w
+// already scaled).  store_rows_split writes a pixel's words to its rows of
+// Ah, Al, Bh, Bl.
+template <int D, class Visit>
+__device__ __forceinline__ void powers_split_fwd(uint32_t* ah, uint32_t* al, uint32_t* bh, uint32_t* bl,
+                                                 float c1, float s1, float c2, float s2, float w,
+                                                 Visit visit) {
   float ar0 = 1.f, ai0 = 0.f, ar = c1, ai = -s1;
   float br0 = w, bi0 = 0.f, br = c2 * w, bi = -s2 * w;
   const float t1 = 2.f * c1, t2 = 2.f * c2;
@@ -291,8 +311,12 @@ __device__ __forceinline__ void write_powers_fwd_split(uint32_t* Ah, uint32_t* A
     ar0 = ar; ai0 = ai; br0 = br; bi0 = bi;
     ar = nar; ai = nai; br = nbr; bi = nbi;
   }
-#pragma unroll
-  for (int n = D; n < W / 2; ++n) ah[n] = al[n] = bh[n] = bl[n] = 0u;
+}
+template <int W>
+__device__ __forceinline__ void store_rows_split(uint32_t* Ah, uint32_t* Al, uint32_t* Bh, uint32_t* Bl,
+                                                 int px, const uint32_t* ah, const uint32_t* al,
+                                                 const uint32_t* bh, const uint32_t* bl) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int g = 0; g < W / 8; ++g) {
     const int o = px * (W / 2) + ((g ^ swz_h<W>(px)) << 2);
@@ -405,6 +429,13 @@ struct FwdArgs {
   const float* cscale;   // SPLIT: [n_freq][kScaleParts] segment maxima of |I|
 };
 
+// Channels that share one 16 x 16 tile: a lattice extent D fills 2D of the
+// tile's rows and columns, so for D <= 4 the rows and columns of 16 / (2D)
+// channels are stacked and the tile's diagonal blocks are their P matrices
+// (the off-diagonal blocks pair one channel's alpha with another's beta and
+// are not read).  The MFMA work is shared; the generation is per channel.
+__host__ __device__ constexpr int fwd_channels_per_tile(int D) { return 2 * D <= 8 ? 16 / (2 * D) : 1; }
+
 // SPLIT: the P tile runs on FP16 MFMA (K = 32) as three products of hi + lo
 // pairs, A_hi B_hi + A_lo B_hi + A_hi B_lo, accumulated in FP32; the beam-
 // weighted sky carries the channel's power-of-two scale, undone at the end.
@@ -441,14 +472,27 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
   uint32_t* Al = Ah + 32 * W;
   uint32_t* Bh = reinterpret_cast<uint32_t*>(Bs);
   uint32_t* Bl = Bh + 32 * W;
+  constexpr int NCH = fwd_channels_per_tile(D);
+  static_assert(NCH == 1 || RT == 1, "stacked channels share one 16 x 16 tile");
+  const int nfg = (nf + NCH - 1) / NCH;   // channel groups
   const int L = xcd_logical(B.x, B.nx);
-  if (L >= nf * nt) return;   // uniform over the block
-  int t, f;
-  tile_map(L, nt, nf, 4, 32, t, f);   // 128 resident blocks per XCD: 4 times x 32 channels
-  const float dnu = args.dnu[f];
-  const float csc = SPLIT ? chan_scale(args.cscale, f, d_omega) : 1.0f;   // power of two
-  const float sig = fwhm[0] * args.sigr[f];
-  const float kb = 1.0f / (2.0f * sig * sig * static_cast<float>(kLn2));
+  if (L >= nfg * nt) return;   // uniform over the block
+  int t, fgrp;
+  tile_map(L, nt, nfg, 4, 32, t, fgrp);   // 128 resident blocks per XCD: 4 times x 32 channel groups
+  // channel c of the group: f = NCH fgrp + c; one past the band (an odd
+  // channel count) runs with zero weight and is not written
+  float dnu[NCH], csc[NCH], kb[NCH], chan_on[NCH];
+  const float* imf[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int fc = NCH * fgrp + c, fl = min(fc, nf - 1);
+    chan_on[c] = fc < nf ? 1.0f : 0.0f;
+    dnu[c] = args.dnu[fl];
+    csc[c] = SPLIT ? chan_scale(args.cscale, fl, d_omega) : 1.0f;   // power of two
+    const float sig = fwhm[0] * args.sigr[fl];
+    kb[c] = 1.0f / (2.0f * sig * sig * static_cast<float>(kLn2));
+    imf[c] = img + static_cast<size_t>(fl) * nvp;
+  }
 
   // NACC independent accumulator sets (consecutive MFMAs of a chunk go to
   // different sets); one set measured fastest at 61 dishes
@@ -461,39 +505,62 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
 #pragma unroll
       for (int j = 0; j < RT; ++j) acc[h][i][j] = f4{0.f, 0.f, 0.f, 0.f};
   // per-lane partial sums of alpha^n S and beta^m S (the axis baselines)
-  float axr[D], axi[D], bxr[D], bxi[D];
+  float axr[NCH][D], axi[NCH][D], bxr[NCH][D], bxi[NCH][D];
 #pragma unroll
-  for (int n = 0; n < D; ++n) axr[n] = axi[n] = bxr[n] = bxi[n] = 0.f;
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int n = 0; n < D; ++n) axr[c][n] = axi[c][n] = bxr[c][n] = bxi[c][n] = 0.f;
 
   const int cbeg = tchunk_off[t], cend = tchunk_off[t + 1];
   const float2* q1t = Q1 + static_cast<size_t>(t) * nvp;
   const float2* q2t = Q2 + static_cast<size_t>(t) * nvp;
   const float* tht = TH2 + static_cast<size_t>(t) * nvp;
-  const float* imf = img + static_cast<size_t>(f) * nvp;
 
-  struct G { float2 q1, q2; float th, iv; };
+  struct G { float2 q1, q2; float th, iv[NCH]; };
   auto load = [&](int ci) {
     const int k = tchunk[ci] * kChunk + lane;
-    return G{at_u32(q1t, k), at_u32(q2t, k), at_u32(tht, k), at_u32(imf, k)};
+    G g;
+    g.q1 = at_u32(q1t, k);
+    g.q2 = at_u32(q2t, k);
+    g.th = at_u32(tht, k);
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) g.iv[c] = at_u32(imf[c], k);
+    return g;
   };
-  // powers of one chunk into LDS; `live` = 0 turns a padding pass into a no-op
+  // powers of one chunk into LDS, channel c in rows and columns 2D c ..;
+  // `live` = 0 turns a padding pass into a no-op
   auto generate = [&](const G& g, float live) {
-    const float x1 = reduced_cycles(dnu, g.q1);
-    const float x2 = reduced_cycles(dnu, g.q2);
-    const float s = live * d_omega * beam_exp2(-g.th * kb) * g.iv;
-    float s1, c1, s2, c2;
-    sincos_rev(x1, s1, c1);
-    sincos_rev(x2, s2, c2);
-    auto visit = [&](int n, float ar, float ai, float br, float bi) {
-      axr[n] += ar * s;
-      axi[n] += ai * s;
-      bxr[n] += br;   // SPLIT: scaled by csc, undone after the loop
-      bxi[n] += bi;
-    };
-    if constexpr (SPLIT)
-      write_powers_fwd_split<D, W>(Ah, Al, Bh, Bl, lane, c1, s1, c2, s2, s * csc, visit);
-    else
-      write_powers<D, W>(As, Bs, lane, c1, s1, c2, s2, s, visit);
+    float av[SPLIT ? 1 : W], bv[SPLIT ? 1 : W];
+    uint32_t ah[SPLIT ? W / 2 : 1], al[SPLIT ? W / 2 : 1], bh[SPLIT ? W / 2 : 1], bl[SPLIT ? W / 2 : 1];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const float x1 = reduced_cycles(dnu[c], g.q1);
+      const float x2 = reduced_cycles(dnu[c], g.q2);
+      const float s = live * chan_on[c] * d_omega * beam_exp2(-g.th * kb[c]) * g.iv[c];
+      float s1, c1, s2, c2;
+      sincos_rev(x1, s1, c1);
+      sincos_rev(x2, s2, c2);
+      auto visit = [&](int n, float ar, float ai, float br, float bi) {
+        axr[c][n] += ar * s;
+        axi[c][n] += ai * s;
+        bxr[c][n] += br;   // SPLIT: scaled by csc, undone after the loop
+        bxi[c][n] += bi;
+      };
+      if constexpr (SPLIT)
+        powers_split_fwd<D>(ah + D * c, al + D * c, bh + D * c, bl + D * c, c1, s1, c2, s2,
+                            s * csc[c], visit);
+      else
+        powers_f32<D>(av + 2 * D * c, bv + 2 * D * c, c1, s1, c2, s2, s, visit);
+    }
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int n = NCH * D; n < W / 2; ++n) ah[n] = al[n] = bh[n] = bl[n] = 0u;
+      store_rows_split<W>(Ah, Al, Bh, Bl, lane, ah, al, bh, bl);
+    } else {
+#pragma unroll
+      for (int r = 2 * NCH * D; r < W; ++r) av[r] = bv[r] = 0.f;
+      store_rows<W>(As, Bs, lane, av, bv);
+    }
   };
   float a[SPLIT ? 1 : 16][RT], b[SPLIT ? 1 : 16][RT];
   // SPLIT operands of the two K = 32 steps of a chunk: hi and lo of A and B
@@ -593,19 +660,24 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
       chunk_step(ci + S, gb, ga);
     }
   }
-  const float inv_csc = 1.0f / csc;   // exact: a power of two
+  // channel of each tile row / column block (its scale is undone on its block)
+  float inv_csc[NCH];
 #pragma unroll
-  for (int n = 0; n < D; ++n) {
+  for (int c = 0; c < NCH; ++c) {
+    inv_csc[c] = 1.0f / csc[c];   // exact: a power of two
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      axr[n] += __shfl_xor(axr[n], o);
-      axi[n] += __shfl_xor(axi[n], o);
-      bxr[n] += __shfl_xor(bxr[n], o);
-      bxi[n] += __shfl_xor(bxi[n], o);
-    }
-    if constexpr (SPLIT) {
-      bxr[n] *= inv_csc;
-      bxi[n] *= inv_csc;
+    for (int n = 0; n < D; ++n) {
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        axr[c][n] += __shfl_xor(axr[c][n], o);
+        axi[c][n] += __shfl_xor(axi[c][n], o);
+        bxr[c][n] += __shfl_xor(bxr[c][n], o);
+        bxi[c][n] += __shfl_xor(bxi[c][n], o);
+      }
+      if constexpr (SPLIT) {
+        bxr[c][n] *= inv_csc[c];
+        bxi[c][n] *= inv_csc[c];
+      }
     }
   }
   // this wave's P tile to its LDS rows (reused as a W x W matrix), its axis
@@ -621,49 +693,66 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
           float sum = acc[0][i][j][r];
 #pragma unroll
           for (int h = 1; h < NACC; ++h) sum += acc[h][i][j][r];
-          if constexpr (SPLIT) sum *= inv_csc;
+          // column 16 j + (lane & 15) belongs to channel (lane & 15) / 2D
+          if constexpr (SPLIT) {
+            float isc = inv_csc[0];
+#pragma unroll
+            for (int c = 1; c < NCH; ++c)
+              if ((lane & 15) >= 2 * D * c) isc = inv_csc[c];
+            sum *= isc;
+          }
           Pw[(16 * i + 4 * (lane >> 4) + r) * W + 16 * j + (lane & 15)] = sum;
         }
-    float* AXw = Bs;  // [D][4]: axr, axi, bxr, bxi
+    float* AXw = Bs;  // [NCH][D][4]: axr, axi, bxr, bxi
     if (lane == 0) {
 #pragma unroll
-      for (int n = 0; n < D; ++n) {
-        AXw[4 * n] = axr[n];
-        AXw[4 * n + 1] = axi[n];
-        AXw[4 * n + 2] = bxr[n];
-        AXw[4 * n + 3] = bxi[n];
-      }
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int n = 0; n < D; ++n) {
+          AXw[4 * (D * c + n)] = axr[c][n];
+          AXw[4 * (D * c + n) + 1] = axi[c][n];
+          AXw[4 * (D * c + n) + 2] = bxr[c][n];
+          AXw[4 * (D * c + n) + 3] = bxi[c][n];
+        }
     }
   }
   __syncthreads();
   // the block's totals, waves added in index order, into the last wave's
-  // rows beyond the tiles (W x W + 4 D floats fit in one wave's 64 W)
-  float* P = Bs_all[kFwdWaves - 1] + 4 * D;
-  float* AX = Bs_all[kFwdWaves - 1] + 4 * D + W * W;
-  static_assert(8 * D + W * W <= 64 * W, "tile totals exceed one wave's rows");
-  for (int e = threadIdx.x; e < W * W + 4 * D; e += 64 * kFwdWaves) {
+  // rows beyond the tiles (W x W + 4 D NCH floats fit in one wave's 64 W)
+  constexpr int NAX = 4 * D * NCH;
+  float* P = Bs_all[kFwdWaves - 1] + NAX;
+  float* AX = Bs_all[kFwdWaves - 1] + NAX + W * W;
+  static_assert(2 * NAX + W * W <= 64 * W, "tile totals exceed one wave's rows");
+  for (int e = threadIdx.x; e < W * W + NAX; e += 64 * kFwdWaves) {
     float sum = 0.f;
 #pragma unroll
     for (int w = 0; w < kFwdWaves; ++w) sum += e < W * W ? As_all[w][e] : Bs_all[w][e - W * W];
     if (e < W * W) P[e] = sum; else AX[e - W * W] = sum;
   }
   __syncthreads();
-  float2* out = vu + (static_cast<size_t>(t) * nf + f) * nubl;
-  for (int u = threadIdx.x; u < nubl; u += 64 * kFwdWaves) {
-    const int2 nm = ubl_nm[u];
-    float2 v;
-    if (nm.x == 0) {
-      v = make_float2(AX[4 * (nm.y - 1) + 2], AX[4 * (nm.y - 1) + 3]);
-    } else if (nm.y == 0) {
-      v = make_float2(AX[4 * (nm.x - 1)], AX[4 * (nm.x - 1) + 1]);
-    } else {
-      const int m = nm.y > 0 ? nm.y : -nm.y;
-      const int r0 = 2 * (nm.x - 1), c0 = 2 * (m - 1);
-      const float p1 = P[r0 * W + c0], p3 = P[r0 * W + c0 + 1];
-      const float p4 = P[(r0 + 1) * W + c0], p2 = P[(r0 + 1) * W + c0 + 1];
-      v = nm.y > 0 ? make_float2(p1 - p2, p3 + p4) : make_float2(p1 + p2, p4 - p3);
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int fc = NCH * fgrp + c;
+    if (fc >= nf) break;   // uniform over the block
+    float2* out = vu + (static_cast<size_t>(t) * nf + fc) * nubl;
+    const float* AXc = AX + 4 * D * c;
+    const int off = 2 * D * c;   // the channel's diagonal block
+    for (int u = threadIdx.x; u < nubl; u += 64 * kFwdWaves) {
+      const int2 nm = ubl_nm[u];
+      float2 v;
+      if (nm.x == 0) {
+        v = make_float2(AXc[4 * (nm.y - 1) + 2], AXc[4 * (nm.y - 1) + 3]);
+      } else if (nm.y == 0) {
+        v = make_float2(AXc[4 * (nm.x - 1)], AXc[4 * (nm.x - 1) + 1]);
+      } else {
+        const int m = nm.y > 0 ? nm.y : -nm.y;
+        const int r0 = off + 2 * (nm.x - 1), c0 = off + 2 * (m - 1);
+        const float p1 = P[r0 * W + c0], p3 = P[r0 * W + c0 + 1];
+        const float p4 = P[(r0 + 1) * W + c0], p2 = P[(r0 + 1) * W + c0 + 1];
+        v = nm.y > 0 ? make_float2(p1 - p2, p3 + p4) : make_float2(p1 + p2, p4 - p3);
+      }
+      out[u] = v;
     }
-    out[u] = v;
   }
 }
 
@@ -697,6 +786,11 @@ struct AdjArgs {
   float* f_part;
 };
 
+// Channels that share one adjoint tile: for D = 4 two channels' coefficient
+// matrices sit on the diagonal blocks of the 16 x 16 tile (the gains pass
+// writes each channel's slice as usual; the kernel places them).
+__host__ __device__ constexpr int adj_channels_per_tile(int D) { return D == 4 ? 2 : 1; }
+
 template <int D, bool SPLIT>
 struct KFringeAdj {
   using Args = AdjArgs;
@@ -728,31 +822,52 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
   uint32_t* Bh = reinterpret_cast<uint32_t*>(Bs);
   uint32_t* Bl = Bh + 64 * R::BH;
   const int lane = threadIdx.x;
+  constexpr int NCH = adj_channels_per_tile(D);
+  static_assert(NCH == 1 || (D == 4 && RT == 1), "two stacked channels: D = 4 only");
+  const int nfg = (nf + NCH - 1) / NCH;   // channel groups
   const int L = xcd_logical(B.x, B.nx);
-  if (L >= nf * nchunks) return;
-  int chunk, f;
-  tile_map(L, nchunks, nf, 32, 16, chunk, f);   // 512 resident waves per XCD: 32 chunks x 16 channels
-  const float dnu = args.dnu[f];
-  const float fw = fwhm[0];
-  const float sig = fw * args.sigr[f];
-  const float kb = 1.0f / (2.0f * sig * sig * static_cast<float>(kLn2));
-  const float kappa = 1.0f / (sig * sig * fw);   // dB/dF = B theta^2 kappa
+  if (L >= nfg * nchunks) return;
+  int chunk, fgrp;
+  tile_map(L, nchunks, nfg, 32, 16, chunk, fgrp);   // 512 resident waves per XCD: 32 chunks x 16 channel groups
   const int k = chunk * kChunk + lane;
-  const float ival = img[static_cast<size_t>(f) * nvp + k];
+  const float fw = fwhm[0];
+  // channel c of the group: f = NCH fgrp + c (one past the band, for an odd
+  // channel count, gets zero coefficients and is not written)
+  int fch[NCH];
+  float dnu[NCH], kb[NCH], kappa[NCH], ival[NCH], acc_i[NCH], acc_f[NCH], chan_on[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int fc = NCH * fgrp + c;
+    fch[c] = min(fc, nf - 1);
+    chan_on[c] = fc < nf ? 1.0f : 0.0f;
+    dnu[c] = args.dnu[fch[c]];
+    const float sig = fw * args.sigr[fch[c]];
+    kb[c] = 1.0f / (2.0f * sig * sig * static_cast<float>(kLn2));
+    kappa[c] = 1.0f / (sig * sig * fw);   // dB/dF = B theta^2 kappa
+    ival[c] = img[static_cast<size_t>(fch[c]) * nvp + k];
+    acc_i[c] = acc_f[c] = 0.f;
+  }
+  // NCH > 1: the tile's row block r / 2D and column block belong to one
+  // channel each; a lane's coefficient operand is channel c's own operand of
+  // lane `lane - src_shift c` on the diagonal blocks and zero elsewhere, and
+  // its output rows 4 (lane >> 4) .. + 3 belong to channel (lane >> 4) / 2
+  const int c_row = NCH > 1 ? (lane & 15) / (2 * D) : 0;
+  const int c_out = NCH > 1 ? (lane >> 4) / (D / 2) : 0;
   const int2 tr = chunk_t[chunk];
-  float acc_i = 0.f, acc_f = 0.f;
   // Partial sums, over this lane's four rows of every row tile, of the core and
   // alpha-axis terms of the pixels of the four 16-pixel groups, weighted by B
   // and by B theta^2; reduced across the row groups once, after the time loop.
   float pz_i[4] = {0.f, 0.f, 0.f, 0.f}, pz_f[4] = {0.f, 0.f, 0.f, 0.f};
-  __shared__ float2 BW[64];   // (B, B theta^2) of every pixel of the chunk at this t
+  __shared__ float2 BW[NCH][64];   // (B, B theta^2) of every pixel of the chunk at this t
   const size_t gst = static_cast<size_t>(nf) * gstride;
   // gco feeds the wave-uniform (scalar) loads of the axis coefficients;
   // gco_lane, the same table, the per-lane loads of the prefetch below: a
   // pointer not marked read-only-unaliased keeps the optimizer from moving
   // those loads to their use in the next step (as it does for P1, P2, TH2)
-  auto gco_at = [&](int t) { return gco + t * gst + static_cast<size_t>(f) * gstride; };
-  auto gco_lane_at = [&](int t) { return gco_lane + t * gst + static_cast<size_t>(f) * gstride; };
+  auto gco_at = [&](int t, int c) { return gco + t * gst + static_cast<size_t>(fch[c]) * gstride; };
+  auto gco_lane_at = [&](int t, int c) {
+    return gco_lane + t * gst + static_cast<size_t>(fch[c]) * gstride;
+  };
   // Software pipeline over t, unrolled by two so that the two register sets
   // swap roles without copies: the geometry and this lane's coefficients of
   // time t + 1 load while time t is processed.
@@ -765,58 +880,89 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
     // they put sum_n Re[omega(n, 0) alpha^n] into the per-pixel dot with A.
     f4 g1[RT];
   };
+  // per-lane channel selection (NCH <= 2)
+  auto chan_of = [&](const int* arr, int c) { return NCH == 1 || c == 0 ? arr[0] : arr[NCH - 1]; };
   auto load_step = [&](Step& S, int t) {
     const size_t row = static_cast<size_t>(t) * nvp;   // uniform over the wave
     S.q1 = at_u32(Q1 + row, k);
     S.q2 = at_u32(Q2 + row, k);
     S.th2 = at_u32(TH2 + row, k);
-    const float* G = gco_lane_at(t);
+    const size_t tbase = static_cast<size_t>(t) * gst;
+    // the coefficient operand: this lane's row channel's slice; zero off the
+    // diagonal blocks and for a channel past the band
+    const float* Gr = gco_lane + tbase + static_cast<size_t>(chan_of(fch, c_row)) * gstride;
+    const float* Go = gco_lane + tbase + static_cast<size_t>(chan_of(fch, c_out)) * gstride;
+    const bool row_on = NCH == 1 || (c_row == 0 ? chan_on[0] : chan_on[NCH - 1]) != 0.f;
+    const bool on_blk = NCH == 1 || (row_on && c_row == c_out);
+    const bool on_k32 = NCH == 1 || (row_on && c_row == ((lane >> 4) & 1));
+    const int src = lane - 40 * c_row;          // FP32 and K = 16 operands
+    const int src32 = lane - 24 * c_row;        // K = 32 operand
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
 #pragma unroll
       for (int kt = 0; kt < RT; ++kt) {
         if constexpr (SPLIT) {
-          S.ga[i][kt] = *reinterpret_cast<const h8*>(G + ((i * RT + kt) * 64 + lane) * 4);
-          S.gb[i][kt] = *reinterpret_cast<const h4*>(G + RT * RT * 256 + ((i * RT + kt) * 64 + lane) * 2);
+          const h8 va = *reinterpret_cast<const h8*>(Gr + ((i * RT + kt) * 64 + (on_k32 ? src32 : lane)) * 4);
+          const h4 vb = *reinterpret_cast<const h4*>(Gr + RT * RT * 256 + ((i * RT + kt) * 64 + (on_blk ? src : lane)) * 2);
+          S.ga[i][kt] = on_k32 ? va : h8{};
+          S.gb[i][kt] = on_blk ? vb : h4{};
         } else {
-          S.gv[i][kt] = *reinterpret_cast<const f4*>(G + ((i * RT + kt) * 64 + lane) * 4);
+          const f4 v = *reinterpret_cast<const f4*>(Gr + ((i * RT + kt) * 64 + (on_blk ? src : lane)) * 4);
+          S.gv[i][kt] = on_blk ? v : f4{0.f, 0.f, 0.f, 0.f};
         }
       }
-      S.g1[i] = *reinterpret_cast<const f4*>(G + NMAT + 16 * i + 4 * (lane >> 4));
+      S.g1[i] = *reinterpret_cast<const f4*>(Go + NMAT + 16 * i + 4 * ((lane >> 4) - (D / 2) * c_out));
     }
   };
   auto step = [&](int t, const Step& S, Step& next) {
     const float2 q1 = S.q1, q2 = S.q2;
     const float th2 = S.th2;
-    const float* G = gco_at(t);
     // unconditional (the last step re-reads its own time) so that the waits
     // for this step's operands never cover the loads just issued
     load_step(next, min(t + 1, tr.y));
-    const float bm = beam_exp2(-th2 * kb);
-    const float x1 = reduced_cycles(dnu, q1);
-    const float x2 = reduced_cycles(dnu, q2);
-    float s1, c1, s2, c2;
-    sincos_rev(x1, s1, c1);
-    sincos_rev(x2, s2, c2);
-    // beta-axis terms of this lane's pixel: sum_n Re[omega(0, n) beta^n]
-    float zax = 0.f;
-    auto visit = [&](int n, float ar, float ai, float br, float bi) {
-      const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 16 * RT + 4 * n);
-      zax += ax[2] * br - ax[3] * bi;
-    };
+    float av[W], bv[SPLIT ? 1 : W];
+    uint32_t bh[SPLIT ? W / 2 : 1], bl[SPLIT ? W / 2 : 1];
+    float bm[NCH], zax[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const float* G = gco_at(t, c);
+      bm[c] = beam_exp2(-th2 * kb[c]);
+      const float x1 = reduced_cycles(dnu[c], q1);
+      const float x2 = reduced_cycles(dnu[c], q2);
+      float s1, c1, s2, c2;
+      sincos_rev(x1, s1, c1);
+      sincos_rev(x2, s2, c2);
+      // beta-axis terms of this lane's pixel: sum_n Re[omega(0, n) beta^n]
+      zax[c] = 0.f;
+      auto visit = [&](int n, float ar, float ai, float br, float bi) {
+        const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 16 * RT + 4 * n);
+        zax[c] += ax[2] * br - ax[3] * bi;
+      };
+      if constexpr (SPLIT) {
+        powers_split_adj<D>(av + 2 * D * c, bh + D * c, bl + D * c, c1, s1, c2, s2, visit);
+        // T comes out scaled by the coefficients' power of two: the weights undo it
+        const float isc = G[NMAT + 16 * RT + 4 * D];
+        BW[c][lane] = make_float2(bm[c] * isc, bm[c] * th2 * isc);
+      } else {
+        powers_f32<D>(av + 2 * D * c, bv + 2 * D * c, c1, s1, c2, s2, 1.0f, visit);
+        BW[c][lane] = make_float2(bm[c], bm[c] * th2);
+      }
+    }
     if constexpr (SPLIT) {
-      write_powers_split<D, W>(As, Bh, Bl, lane, c1, s1, c2, s2, visit);
-      // T comes out scaled by the coefficients' power of two: the weights undo it
-      const float isc = G[NMAT + 16 * RT + 4 * D];
-      BW[lane] = make_float2(bm * isc, bm * th2 * isc);
+#pragma unroll
+      for (int r = 2 * D * NCH; r < W; ++r) av[r] = 0.f;
+#pragma unroll
+      for (int n = D * NCH; n < W / 2; ++n) bh[n] = bl[n] = 0u;
+      store_rows_split_adj<W>(As, Bh, Bl, lane, av, bh, bl);
     } else {
-      write_powers<D, W>(As, Bs, lane, c1, s1, c2, s2, 1.0f, visit);
-      BW[lane] = make_float2(bm, bm * th2);
+#pragma unroll
+      for (int r = 2 * D * NCH; r < W; ++r) av[r] = bv[r] = 0.f;
+      store_rows<W>(As, Bs, lane, av, bv);
     }
     wave_sync();
     float2 bw[4];
 #pragma unroll
-    for (int pg = 0; pg < 4; ++pg) bw[pg] = BW[16 * pg + (lane & 15)];
+    for (int pg = 0; pg < 4; ++pg) bw[pg] = BW[NCH == 1 ? 0 : c_out][16 * pg + (lane & 15)];
     // T = G Bb + alpha-axis rows for the four 16-pixel groups: the four MFMA
     // chains are interleaved (pixel group innermost) so consecutive MFMAs are
     // independent
@@ -876,8 +1022,11 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
       }
     }
     wave_sync();
-    acc_i += bm * zax;
-    acc_f += bm * th2 * zax;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      acc_i[c] += bm[c] * zax[c];
+      acc_f[c] += bm[c] * th2 * zax[c];
+    }
   };
   Step sa, sb;
   load_step(sa, tr.x);
@@ -886,26 +1035,53 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
     if (t + 1 > tr.y) break;
     step(t + 1, sb, sa);
   }
-  // the four row groups of each pixel sit in lanes l, l ^ 16, l ^ 32, l ^ 48
-#pragma unroll
-  for (int pg = 0; pg < 4; ++pg) {
-    pz_i[pg] = sum_xor32(sum_xor16(pz_i[pg]));
-    pz_f[pg] = sum_xor32(sum_xor16(pz_f[pg]));
-  }
   const int own = lane >> 4;   // this lane's pixel is column lane & 15 of group lane >> 4
-  acc_i += own == 0 ? pz_i[0] : own == 1 ? pz_i[1] : own == 2 ? pz_i[2] : pz_i[3];
-  acc_f += own == 0 ? pz_f[0] : own == 1 ? pz_f[1] : own == 2 ? pz_f[2] : pz_f[3];
-  dimg[static_cast<size_t>(f) * nvp + k] = d_omega * acc_i;
-  float pf = acc_f * ival;
+  if constexpr (NCH == 1) {
+    // the four row groups of each pixel sit in lanes l, l ^ 16, l ^ 32, l ^ 48
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) pf += __shfl_xor(pf, o);
-  if (lane == 0) f_part[static_cast<size_t>(f) * nchunks + chunk] = d_omega * kappa * pf;
+    for (int pg = 0; pg < 4; ++pg) {
+      pz_i[pg] = sum_xor32(sum_xor16(pz_i[pg]));
+      pz_f[pg] = sum_xor32(sum_xor16(pz_f[pg]));
+    }
+    acc_i[0] += own == 0 ? pz_i[0] : own == 1 ? pz_i[1] : own == 2 ? pz_i[2] : pz_i[3];
+    acc_f[0] += own == 0 ? pz_f[0] : own == 1 ? pz_f[1] : own == 2 ? pz_f[2] : pz_f[3];
+  } else {
+    // channel c's two row groups sit in lanes 32 c + (l & 15) + {0, 16}: add
+    // them, then every lane fetches each channel's total for its own pixel
+#pragma unroll
+    for (int pg = 0; pg < 4; ++pg) {
+      pz_i[pg] = sum_xor16(pz_i[pg]);
+      pz_f[pg] = sum_xor16(pz_f[pg]);
+    }
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int from = 32 * c + (lane & 15);
+#pragma unroll
+      for (int pg = 0; pg < 4; ++pg) {
+        const float vi = __shfl(pz_i[pg], from), vf = __shfl(pz_f[pg], from);
+        if (pg == own) {
+          acc_i[c] += vi;
+          acc_f[c] += vf;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    if (NCH * fgrp + c >= nf) break;   // uniform over the wave
+    dimg[static_cast<size_t>(fch[c]) * nvp + k] = d_omega * acc_i[c];
+    float pf = acc_f[c] * ival[c];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) pf += __shfl_xor(pf, o);
+    if (lane == 0) f_part[static_cast<size_t>(fch[c]) * nchunks + chunk] = d_omega * kappa[c] * pf;
+  }
 }
 
 // ------------------------------------------------------------ launchers --
 template <int D>
 static void fwd_d(const vis_field* f, const float* img, const float* fwhm, float2* vu, hipStream_t st) {
-  const int nblk = static_cast<int>(round_up(static_cast<long>(f->n_freq) * f->n_time, 8));
+  constexpr int nch = fwd_channels_per_tile(D);
+  const int nblk = static_cast<int>(round_up(static_cast<long>((f->n_freq + nch - 1) / nch) * f->n_time, 8));
   const auto& T = f->tab;
   const bool split = fringe_split(f);
   if (split) {
@@ -926,7 +1102,8 @@ static void fwd_d(const vis_field* f, const float* img, const float* fwhm, float
 template <int D>
 static void adj_d(const vis_field* f, const float* img, const float* fwhm, const float* gco,
                   float* dimg, float* f_part, hipStream_t st) {
-  const int nblk = static_cast<int>(round_up(static_cast<long>(f->n_freq) * f->n_chunks, 8));
+  constexpr int nch = adj_channels_per_tile(D);
+  const int nblk = static_cast<int>(round_up(static_cast<long>((f->n_freq + nch - 1) / nch) * f->n_chunks, 8));
   const auto& T = f->tab;
   ProfScope ps(&f->prof, "k_fringe_adj", st);
   BV_REQUIRE(f->dtile == D, VIS_EINVAL, "internal: adjoint tile mismatch");
