@@ -399,7 +399,8 @@ __device__ __forceinline__ float chan_scale(const float* part, int f, float d_om
 }
 
 // ------------------------------------------------------------------ forward --
-// One block of kFwdWaves wavefronts per (t, nu); wave w takes every
+// One block of kFwdWaves wavefronts per (t, nu) (per (t, group of stacked
+// channels) for D <= 4, see fwd_channels_per_tile); wave w takes every
 // kFwdWaves-th pixel chunk visible at t, starting at chunk w, and the block
 // adds the waves' partial tiles in a fixed order at the end.  Splitting a
 // (t, nu) over the four SIMDs of a CU balances the SIMDs: with one wave per
@@ -757,8 +758,9 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
 }
 
 // ------------------------------------------------------------------ adjoint --
-// One wavefront per (nu, chunk of 64 visible pixels); loops over the times at
-// which the chunk is above the horizon.  gco[t][nu] holds the coefficient
+// One wavefront per (nu, chunk of 64 visible pixels) (per pair of channels
+// for D = 4, see adj_channels_per_tile); loops over the times at which the
+// chunk is above the horizon.  gco[t][nu] holds the coefficient
 // matrix in MFMA A-operand order, then the alpha-axis accumulator inputs of
 // every (row tile, lane group), then the axis coefficients (and, SPLIT, the
 // inverse of the power-of-two scale of the FP16 coefficients).
