@@ -96,9 +96,10 @@ typedef struct {
   int32_t max_batch;           /* requests per tick, >= 1 */
   int32_t batched;             /* 1: batched launches: every kernel of the evaluation
                                   sequence runs as one grid over all chains of the tick
-                                  (one grid per kernel instantiation and stage); each
-                                  chain's workgroups compute exactly what its own launch
-                                  would;
+                                  (chains with the same kernel sequence share each grid;
+                                  such groups run concurrently on streams of their own);
+                                  each chain's workgroups compute exactly what its own
+                                  launch would;
                                   2: each chain's sequence is launched on its own, the
                                   chains spread over several streams;
                                   0: one chain after another on the server stream */

@@ -1,7 +1,5 @@
 // Batched execution of recorded evaluation sequences (see batch.hpp).
 #include <algorithm>
-#include <map>
-#include <tuple>
 
 #include "batch.hpp"
 
@@ -14,12 +12,6 @@ Recorder*& thread_recorder() {
 
 namespace {
 
-struct Group {
-  int stage, pos;
-  const void* kid;
-  std::vector<const LaunchRec*> recs;   // one per evaluation that has this launch
-};
-
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
@@ -27,88 +19,87 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 void run_batched(Recorder& rec, unsigned char* host_stage, unsigned char* dev_stage,
                  size_t stage_bytes, hipStream_t st, int nsub, const hipStream_t* sub,
                  const hipEvent_t* ev) {
-  // groups keyed by (stage, position in stage, kernel), in first-seen order of
-  // the kernels within one (stage, position)
-  std::map<std::tuple<int, int, int>, Group> groups;
-  std::map<std::pair<int, int>, std::vector<const void*>> kid_order;
-  for (const auto& ev : rec.evals) {
-    for (const LaunchRec& L : ev) {
-      auto& order = kid_order[{L.stage, L.pos}];
-      int k = 0;
-      while (k < static_cast<int>(order.size()) && order[k] != L.kid) ++k;
-      if (k == static_cast<int>(order.size())) order.push_back(L.kid);
-      Group& g = groups[{L.stage, L.pos, k}];
-      g.stage = L.stage;
-      g.pos = L.pos;
-      g.kid = L.kid;
-      g.recs.push_back(&L);
+  // Classes: evaluations whose launch sequences are the same kernel
+  // instantiations in the same order (same lattice extent, precision and
+  // synthesis).  A class runs as one grid per launch position, in order, on a
+  // stream of its own; different classes share no data and overlap.
+  std::vector<std::vector<int>> classes;   // evaluation indices
+  std::vector<const std::vector<LaunchRec>*> reps;
+  auto same_seq = [](const std::vector<LaunchRec>& a, const std::vector<LaunchRec>& b) {
+    if (a.size() != b.size()) return false;
+    for (size_t k = 0; k < a.size(); ++k)
+      if (a[k].kid != b[k].kid || a[k].stage != b[k].stage || a[k].pos != b[k].pos) return false;
+    return true;
+  };
+  for (int e = 0; e < static_cast<int>(rec.evals.size()); ++e) {
+    const auto& seq = rec.evals[e];
+    if (seq.empty()) continue;
+    size_t c = 0;
+    while (c < classes.size() && !same_seq(*reps[c], seq)) ++c;
+    if (c == classes.size()) {
+      classes.emplace_back();
+      reps.push_back(&seq);
     }
+    classes[c].push_back(e);
   }
-  // pack every group's argument table and entries into the staging buffer
+  if (classes.empty()) return;
+  // pack every (class, launch position) table: the evaluations' arguments and
+  // their workgroup ranges
   struct Packed {
-    const Group* g;
+    const LaunchRec* rec0;
     size_t args_off, ent_off;
     int n, total;
     size_t lds;
   };
-  std::vector<Packed> packed;
+  std::vector<std::vector<Packed>> packed(classes.size());
   size_t used = 0;
-  for (const auto& kv : groups) {
-    const Group& g = kv.second;
-    const int n = static_cast<int>(g.recs.size());
-    const size_t asz = g.recs[0]->args_size;
-    Packed p{&g, 0, 0, n, 0, 0};
-    p.args_off = align_up(used, 256);
-    p.ent_off = align_up(p.args_off + asz * n, 64);
-    used = p.ent_off + sizeof(BatchEntry) * n;
-    BV_REQUIRE(used <= stage_bytes, VIS_ENOMEM, "batched launch tables exceed %zu bytes", stage_bytes);
-    BatchEntry* ent = reinterpret_cast<BatchEntry*>(host_stage + p.ent_off);
-    long start = 0;
-    for (int i = 0; i < n; ++i) {
-      const LaunchRec* L = g.recs[i];
-      std::memcpy(host_stage + p.args_off + asz * i, L->args, asz);
-      const long blocks = static_cast<long>(L->grid.x) * L->grid.y * L->grid.z;
-      ent[i] = BatchEntry{static_cast<int>(start), static_cast<int>(L->grid.x),
-                          static_cast<int>(L->grid.y), static_cast<int>(L->grid.z)};
-      start += round_up(blocks, 8);
-      p.lds = std::max(p.lds, L->lds);
+  for (size_t c = 0; c < classes.size(); ++c) {
+    const auto& members = classes[c];
+    const size_t nlaunch = reps[c]->size();
+    for (size_t k = 0; k < nlaunch; ++k) {
+      const int n = static_cast<int>(members.size());
+      const size_t asz = (*reps[c])[k].args_size;
+      Packed p{&(*reps[c])[k], 0, 0, n, 0, 0};
+      p.args_off = align_up(used, 256);
+      p.ent_off = align_up(p.args_off + asz * n, 64);
+      used = p.ent_off + sizeof(BatchEntry) * n;
+      BV_REQUIRE(used <= stage_bytes, VIS_ENOMEM, "batched launch tables exceed %zu bytes", stage_bytes);
+      BatchEntry* ent = reinterpret_cast<BatchEntry*>(host_stage + p.ent_off);
+      long start = 0;
+      for (int i = 0; i < n; ++i) {
+        const LaunchRec& L = rec.evals[members[i]][k];
+        std::memcpy(host_stage + p.args_off + asz * i, L.args, asz);
+        const long blocks = static_cast<long>(L.grid.x) * L.grid.y * L.grid.z;
+        ent[i] = BatchEntry{static_cast<int>(start), static_cast<int>(L.grid.x),
+                            static_cast<int>(L.grid.y), static_cast<int>(L.grid.z)};
+        start += round_up(blocks, 8);
+        p.lds = std::max(p.lds, L.lds);
+      }
+      BV_REQUIRE(start < (1L << 31), VIS_EINVAL, "batched launch of %ld workgroups", start);
+      p.total = static_cast<int>(start);
+      packed[c].push_back(p);
     }
-    BV_REQUIRE(start < (1L << 31), VIS_EINVAL, "batched launch of %ld workgroups", start);
-    p.total = static_cast<int>(start);
-    packed.push_back(p);
   }
-  if (packed.empty()) return;
   BV_HIP(hipMemcpyAsync(dev_stage, host_stage, used, hipMemcpyHostToDevice, st));
   auto launch = [&](const Packed& p, hipStream_t s) {
-    const LaunchRec* L0 = p.g->recs[0];
-    L0->many(dev_stage + p.args_off, reinterpret_cast<const BatchEntry*>(dev_stage + p.ent_off), p.n,
-             p.total, p.lds, s);
+    p.rec0->many(dev_stage + p.args_off, reinterpret_cast<const BatchEntry*>(dev_stage + p.ent_off),
+                 p.n, p.total, p.lds, s);
     check_launch("batched evaluation kernel");
   };
-  // levels: runs of groups with equal (stage, position); the map keeps them adjacent
-  for (size_t i = 0; i < packed.size();) {
-    size_t j = i + 1;
-    while (j < packed.size() && packed[j].g->stage == packed[i].g->stage &&
-           packed[j].g->pos == packed[i].g->pos)
-      ++j;
-    const int width = static_cast<int>(j - i);
-    if (nsub == 0 || width == 1) {
-      for (size_t k = i; k < j; ++k) launch(packed[k], st);
-    } else {
-      const int used_sub = std::min(nsub, width - 1);
-      BV_HIP(hipEventRecord(ev[nsub], st));
-      for (int q = 0; q < used_sub; ++q) BV_HIP(hipStreamWaitEvent(sub[q], ev[nsub], 0));
-      // the first group stays on the main stream, the others go round-robin
-      for (size_t k = i; k < j; ++k) {
-        const int q = static_cast<int>(k - i);
-        launch(packed[k], q == 0 ? st : sub[(q - 1) % used_sub]);
-      }
-      for (int q = 0; q < used_sub; ++q) {
-        BV_HIP(hipEventRecord(ev[q], sub[q]));
-        BV_HIP(hipStreamWaitEvent(st, ev[q], 0));
-      }
-    }
-    i = j;
+  const int nclass = static_cast<int>(classes.size());
+  const int used_sub = nsub == 0 ? 0 : std::min(nsub, nclass - 1);
+  if (used_sub > 0) {
+    BV_HIP(hipEventRecord(ev[nsub], st));   // the tables are on the device
+    for (int q = 0; q < used_sub; ++q) BV_HIP(hipStreamWaitEvent(sub[q], ev[nsub], 0));
+  }
+  // class 0 on the main stream, the others round-robin over the side streams
+  for (int c = 0; c < nclass; ++c) {
+    const hipStream_t s = (c == 0 || used_sub == 0) ? st : sub[(c - 1) % used_sub];
+    for (const Packed& p : packed[c]) launch(p, s);
+  }
+  for (int q = 0; q < used_sub; ++q) {
+    BV_HIP(hipEventRecord(ev[q], sub[q]));
+    BV_HIP(hipStreamWaitEvent(st, ev[q], 0));
   }
 }
 

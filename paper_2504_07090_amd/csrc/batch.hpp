@@ -15,9 +15,10 @@
 // launch would, whatever else shares the grid.
 //
 // The launchers record instead of launching while a Recorder is installed on
-// the calling thread; the recorder groups the launches of many evaluations by
-// (stage, position within the stage, kernel) and issues one batched launch per
-// group, stage by stage, in the order each evaluation needs.
+// the calling thread; run_batched sorts the recorded evaluations into classes
+// with the same launch sequence (same kernel instantiations in the same
+// order) and issues, per class, one batched launch per position of that
+// sequence, in order, each class on a stream of its own.
 #pragma once
 
 #include <cstring>
@@ -169,12 +170,12 @@ void launch_k(dim3 grid, size_t lds, const typename K::Args& a, hipStream_t st, 
 }
 
 // Batched execution of a recorder's evaluations on `st`.  The argument tables
-// and entries of all groups are packed into `host_stage` (pinned) and uploaded
-// with one copy to `dev_stage`; throws Failure{VIS_ENOMEM} when they do not
-// fit `stage_bytes`.  Groups at the same (stage, position) are independent
-// (different kernels or instantiations for different evaluations): with
-// `nsub` > 0 side streams they run concurrently, one level after another,
-// joined by events (`ev` holds nsub + 1 events).
+// and entries of all launches are packed into `host_stage` (pinned) and
+// uploaded with one copy to `dev_stage`; throws Failure{VIS_ENOMEM} when they
+// do not fit `stage_bytes`.  Different classes of evaluations share no data:
+// with `nsub` > 0 side streams they run concurrently (the first on `st`, the
+// others round-robin on `sub`), started after the upload and joined into `st`
+// by events (`ev` holds nsub + 1 events).
 void run_batched(Recorder& rec, unsigned char* host_stage, unsigned char* dev_stage,
                  size_t stage_bytes, hipStream_t st, int nsub = 0, const hipStream_t* sub = nullptr,
                  const hipEvent_t* ev = nullptr);

@@ -398,8 +398,9 @@ void hmc_server::enqueue(Tick& t) {
   if (nuts_tasks) launch_nuts_elem(S.dev_tasks, npre, S.dev_blk, bpre, stream);
   launch_hmc_gainblk(S.dev_tasks, npre, S.dev_blk + 3 * (nb + 1), cpre, stream);
   // evaluations.  Batched (cfg.batched == 1): every kernel of the evaluation
-  // sequence runs as one grid over all chains of the tick that need it (one
-  // grid per kernel instantiation, stage by stage).  Multi-stream
+  // sequence runs as one grid over all chains of the tick that need it (the
+  // chains grouped by their kernel sequence, one grid per launch of the
+  // sequence, each group on a stream of its own).  Multi-stream
   // (cfg.batched == 2): each chain's sequence is launched on its own, spread
   // over several streams so that kernels of different fields overlap.
   if (cfg.batched == 1 && !evs.empty()) {
