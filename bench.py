@@ -60,8 +60,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "6d2a6ee6280f02f452f74a54358b12d09685efa484fd77f2fb2a5263518aeeec",
-    "bytes_per_launch": {"k_fringe_adj": 199664428, "k_fringe_fwd": 273535542},
+    "sha256": "cefe8e87a51c140468708dcf82b44f91fad786ca11024ee06d25f8e2b55fd04b",
+    "bytes_per_launch": {"k_fringe_adj": 199023592, "k_fringe_fwd": 269417135},
 }
 
 

@@ -151,8 +151,9 @@ def test_forward_hex_sides(vis, side, prec):
     """Every lattice extent the fringe kernels instantiate: hex sides 2, 3, 4, 7
     and 9 have extents 2, 4, 6, 12 and 16 (the last two with two MFMA tiles per
     side; side 9 is 217 dishes, 408 unique baselines), forward, adjoint and the
-    chi^2 gradient, in FP32 and with split products (the adjoint fringe GEMM on
-    FP16 MFMA)."""
+    chi^2 gradient, in FP32 and with split products (both fringe GEMMs on FP16
+    MFMA).  Three channels: for extents 2 and 4 the kernels stack channels in
+    one tile, so the last group also holds a channel past the band."""
     cfg = w.scaled(w.C0, array="hex", array_size=side, n_freq=3, n_time=3,
                    freq_lo_hz=120e6, freq_hi_hz=130e6, grid_nz=32, grid_nphi=96, lmax=12)
     basis, fld, d = _setup(vis, cfg, precision=prec)
