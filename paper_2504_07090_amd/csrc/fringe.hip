@@ -215,12 +215,17 @@ __device__ __forceinline__ uint32_t split_lo2(float x0, float x1, uint32_t hi) {
   return r;
 }
 
-// LDS row strides (32-bit words) of the split B operand of the adjoint: rows
-// of W halves padded so that the 16-byte (hi) and 8-byte (lo) operand reads of
-// 16 consecutive pixel rows fall on distinct banks
+// LDS layout of the split B operand of the adjoint (32-bit words).  The hi
+// halves: rows of W halves padded to BH words, so that the 16-byte operand
+// reads of consecutive pixel rows fall on distinct banks.  The lo halves: W/4
+// planes of 64 rows x 8 bytes (plane q = halves 4q .. 4q + 3 of every row),
+// planes BLP words apart; a K = 16 operand read takes one plane per 16 lanes
+// (128 contiguous bytes), and BLP = 128 + 32 words puts the next plane on the
+// other half of the banks.
 template <int W> struct SplitRows {
   static constexpr int BH = W / 2 + 4;
-  static constexpr int BL = W / 2 + 2;
+  static constexpr int BLP = 64 * 2 + 32;
+  static constexpr int BL_WORDS = (W / 4) * BLP;
 };
 
 // Powers of one pixel for the split adjoint: alpha^n in FP32 into its As row
@@ -261,7 +266,7 @@ __device__ __forceinline__ void store_rows_split_adj(float* As, uint32_t* Bh, ui
     *reinterpret_cast<u4*>(Bh + px * R::BH + 4 * g) = u4{bh[4 * g], bh[4 * g + 1], bh[4 * g + 2], bh[4 * g + 3]};
 #pragma unroll
   for (int g = 0; g < W / 4; ++g)
-    *reinterpret_cast<u2*>(Bl + px * R::BL + 2 * g) = u2{bl[2 * g], bl[2 * g + 1]};
+    *reinterpret_cast<u2*>(Bl + g * R::BLP + 2 * px) = u2{bl[2 * g], bl[2 * g + 1]};
 }
 template <int D, int W, class Visit>
 __device__ __forceinline__ void write_powers_split(float* As, uint32_t* Bh, uint32_t* Bl, int px,
@@ -284,7 +289,18 @@ __device__ __forceinline__ void write_powers_split(float* As, uint32_t* Bh, uint
 // transposing operand reads below assume.
 template <int W>
 __device__ __forceinline__ int swz_h(int px) {
-  return W == 16 ? ((px >> 3) & 1) : ((px >> 2) & 3);
+  return W == 16 ? ((px >> 2) & 1) : ((px >> 2) & 3);
+}
+// Physical row of pixel row px.  A transposing operand read takes four whole
+// consecutive rows per 16 lanes; with 32-byte rows (W = 16) the next 16 lanes'
+// rows lie 256 bytes further, on the same banks.  Swapping the two halves of
+// every odd 8-row block puts those rows on the other half of the banks (for
+// W = 32 the swizzle above already separates them).  With it, the 16-byte
+// row writes of rows px and px + 4 (and of a row and its swapped partner)
+// land in different halves of their 32-byte rows through swz_h.
+template <int W>
+__device__ __forceinline__ int row_h(int px) {
+  return W == 16 ? (px ^ (((px >> 3) & 1) << 2)) : px;
 }
 
 // Powers of one pixel for the split forward: alpha^n and beta^m w as FP16
@@ -319,7 +335,7 @@ __device__ __forceinline__ void store_rows_split(uint32_t* Ah, uint32_t* Al, uin
   typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int g = 0; g < W / 8; ++g) {
-    const int o = px * (W / 2) + ((g ^ swz_h<W>(px)) << 2);
+    const int o = row_h<W>(px) * (W / 2) + ((g ^ swz_h<W>(px)) << 2);
     *reinterpret_cast<u4*>(Ah + o) = u4{ah[4 * g], ah[4 * g + 1], ah[4 * g + 2], ah[4 * g + 3]};
     *reinterpret_cast<u4*>(Al + o) = u4{al[4 * g], al[4 * g + 1], al[4 * g + 2], al[4 * g + 3]};
     *reinterpret_cast<u4*>(Bh + o) = u4{bh[4 * g], bh[4 * g + 1], bh[4 * g + 2], bh[4 * g + 3]};
@@ -346,7 +362,7 @@ __device__ __forceinline__ h8 tr_operand(const uint32_t* base, int pix0, int til
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int row = row0 + 4 * h;
-    const uint32_t* a = base + row * (W / 2) + ((grp ^ swz_h<W>(row)) << 2) + within;
+    const uint32_t* a = base + row_h<W>(row) * (W / 2) + ((grp ^ swz_h<W>(row)) << 2) + within;
     v[h] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
         (__attribute__((address_space(3))) s4*)(reinterpret_cast<uintptr_t>(a)));
   }
@@ -820,7 +836,7 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
   constexpr int NMAT = RT * RT * (SPLIT ? 384 : 256);
   __shared__ __attribute__((aligned(16))) float As[64 * W];
   // FP32 B operand rows, or (SPLIT) the hi rows followed by the lo rows
-  __shared__ __attribute__((aligned(16))) float Bs[SPLIT ? 64 * (R::BH + R::BL) : 64 * W];
+  __shared__ __attribute__((aligned(16))) float Bs[SPLIT ? 64 * R::BH + R::BL_WORDS : 64 * W];
   uint32_t* Bh = reinterpret_cast<uint32_t*>(Bs);
   uint32_t* Bl = Bh + 64 * R::BH;
   const int lane = threadIdx.x;
@@ -986,7 +1002,7 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
         const int px = 16 * pg + (lane & 15);
         if constexpr (SPLIT) {
           bh8[kt][pg] = *reinterpret_cast<const h8*>(Bh + px * R::BH + 8 * kt + 4 * ((lane >> 4) & 1));
-          bl4[kt][pg] = *reinterpret_cast<const h4*>(Bl + px * R::BL + 8 * kt + 2 * (lane >> 4));
+          bl4[kt][pg] = *reinterpret_cast<const h4*>(Bl + (4 * kt + (lane >> 4)) * R::BLP + 2 * px);
         } else {
           bq[kt][pg] = *reinterpret_cast<const f4*>(Bs + lds_at<W>(px, 16 * kt + 4 * (lane >> 4)));
         }
