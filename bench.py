@@ -60,7 +60,7 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "cefe8e87a51c140468708dcf82b44f91fad786ca11024ee06d25f8e2b55fd04b",
+    "sha256": "ab7d3080bfd325fb4e4b5f634c0467d7ef6d6e4d620e42f0ee0fed7cef383c6a",
     "bytes_per_launch": {"k_fringe_adj": 199023592, "k_fringe_fwd": 269417135},
 }
 
