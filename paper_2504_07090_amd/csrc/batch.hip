@@ -87,15 +87,31 @@ void run_batched(Recorder& rec, unsigned char* host_stage, unsigned char* dev_st
     check_launch("batched evaluation kernel");
   };
   const int nclass = static_cast<int>(classes.size());
-  const int used_sub = nsub == 0 ? 0 : std::min(nsub, nclass - 1);
-  if (used_sub > 0) {
-    BV_HIP(hipEventRecord(ev[nsub], st));   // the tables are on the device
-    for (int q = 0; q < used_sub; ++q) BV_HIP(hipStreamWaitEvent(sub[q], ev[nsub], 0));
+  if (nsub == 0 || nclass == 1) {
+    for (int c = 0; c < nclass; ++c)
+      for (const Packed& p : packed[c]) launch(p, st);
+    return;
   }
-  // class 0 on the main stream, the others round-robin over the side streams
-  for (int c = 0; c < nclass; ++c) {
-    const hipStream_t s = (c == 0 || used_sub == 0) ? st : sub[(c - 1) % used_sub];
-    for (const Packed& p : packed[c]) launch(p, s);
+  // Classes go to the side streams only: streams created one after another
+  // get distinct hardware queues (as many as the side streams, up to the
+  // queue count), while the caller's stream may share one with them, and two
+  // classes on one queue run one after the other.  Heaviest class first, each
+  // to the side stream with the least work so far.
+  std::vector<double> work(nclass, 0.0);
+  for (int c = 0; c < nclass; ++c)
+    for (int e : classes[c])
+      for (const LaunchRec& L : rec.evals[e]) work[c] += static_cast<double>(L.grid.x) * L.grid.y * L.grid.z;
+  std::vector<int> order(nclass);
+  for (int c = 0; c < nclass; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+  const int used_sub = std::min(nsub, nclass);
+  std::vector<double> load(used_sub, 0.0);
+  BV_HIP(hipEventRecord(ev[nsub], st));   // the tables are on the device
+  for (int q = 0; q < used_sub; ++q) BV_HIP(hipStreamWaitEvent(sub[q], ev[nsub], 0));
+  for (int c : order) {
+    const int q = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    load[q] += work[c];
+    for (const Packed& p : packed[c]) launch(p, sub[q]);
   }
   for (int q = 0; q < used_sub; ++q) {
     BV_HIP(hipEventRecord(ev[q], sub[q]));

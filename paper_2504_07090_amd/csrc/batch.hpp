@@ -173,9 +173,9 @@ void launch_k(dim3 grid, size_t lds, const typename K::Args& a, hipStream_t st, 
 // and entries of all launches are packed into `host_stage` (pinned) and
 // uploaded with one copy to `dev_stage`; throws Failure{VIS_ENOMEM} when they
 // do not fit `stage_bytes`.  Different classes of evaluations share no data:
-// with `nsub` > 0 side streams they run concurrently (the first on `st`, the
-// others round-robin on `sub`), started after the upload and joined into `st`
-// by events (`ev` holds nsub + 1 events).
+// with `nsub` > 0 side streams they run concurrently on `sub` (heaviest class
+// first, each to the least loaded side stream), started after the upload and
+// joined into `st` by events (`ev` holds nsub + 1 events).
 void run_batched(Recorder& rec, unsigned char* host_stage, unsigned char* dev_stage,
                  size_t stage_bytes, hipStream_t st, int nsub = 0, const hipStream_t* sub = nullptr,
                  const hipEvent_t* ev = nullptr);
