@@ -525,35 +525,36 @@ __device__ void KReduceGrads::run(const ReduceArgs& a, const Blk& B) {
   float* grad_fwhm = a.grad_fwhm;
   const int tid = threadIdx.x;
   if (B.x + 1 < B.nx) {
-    const int idx = B.x * 1024 + tid;
-    if (idx >= nf * nant || grad_gains == nullptr) return;
-    // eight independent partial sums (times t = q mod 8), combined in order:
-    // eight loads in flight per thread instead of one chain of nt
+    // eight lanes per output: lane j of the group sums the times t = j mod 8
+    // (two interleaved partial sums, so its loads are all in flight), then
+    // the group adds its lanes in a fixed butterfly order
+    const int idx = B.x * (1024 / 8) + (tid >> 3), j = tid & 7;
+    if (grad_gains == nullptr) return;   // uniform over the launch
+    const bool live = idx < nf * nant;
     const size_t stride = static_cast<size_t>(nf) * nant;
-    float2 p[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) p[q] = make_float2(0.f, 0.f);
-    int t = 0;
-    for (; t + 8 <= nt; t += 8) {
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const float2 v = g_part[static_cast<size_t>(t + q) * stride + idx];
-        p[q].x += v.x;
-        p[q].y += v.y;
+    float2 p0 = make_float2(0.f, 0.f), p1 = p0;
+    if (live) {
+      int t = j;
+      for (; t + 8 < nt; t += 16) {
+        const float2 v0 = g_part[static_cast<size_t>(t) * stride + idx];
+        const float2 v1 = g_part[static_cast<size_t>(t + 8) * stride + idx];
+        p0.x += v0.x;
+        p0.y += v0.y;
+        p1.x += v1.x;
+        p1.y += v1.y;
+      }
+      if (t < nt) {
+        const float2 v0 = g_part[static_cast<size_t>(t) * stride + idx];
+        p0.x += v0.x;
+        p0.y += v0.y;
       }
     }
-    for (int q = 0; t < nt; ++t, ++q) {
-      const float2 v = g_part[static_cast<size_t>(t) * stride + idx];
-      p[q].x += v.x;
-      p[q].y += v.y;
+    float2 s = make_float2(p0.x + p1.x, p0.y + p1.y);
+    for (int o = 1; o < 8; o <<= 1) {
+      s.x += __shfl_xor(s.x, o);
+      s.y += __shfl_xor(s.y, o);
     }
-    float2 s = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      s.x += p[q].x;
-      s.y += p[q].y;
-    }
-    grad_gains[idx] = s;
+    if (live && j == 0) grad_gains[idx] = s;
     return;
   }
   __shared__ double red[16];
@@ -628,7 +629,7 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
 void launch_reduce_grads(const vis_field* f, bool with_chi2, const double* chi_part, double* chi2,
                          const float2* g_part, float2* grad_gains, const float* f_part,
                          float* grad_fwhm, hipStream_t st) {
-  const int nblk = (grad_gains != nullptr ? ceil_div(static_cast<long>(f->n_freq) * f->n_ant, 1024) : 0) + 1;
+  const int nblk = (grad_gains != nullptr ? ceil_div(static_cast<long>(f->n_freq) * f->n_ant, 1024 / 8) : 0) + 1;
   ProfScope ps(&f->prof, "k_reduce_grads", st);
   const ReduceArgs a{f->n_time, f->n_freq, f->n_ant, f->n_freq * f->n_chunks, with_chi2 ? 1 : 0,
                      chi_part, chi2, g_part, grad_gains, f_part, grad_fwhm};
