@@ -199,7 +199,7 @@ vis_status chi2_and_grad(const vis_field* field, const vis_c64* data, float sigm
                          float* grad_fwhm, void* stream);
 
 /* ------------------------------------------------------------ map-making --
- * vis_make_map: the diagonally normalised map estimate of Sec. 6
+ * vis_make_map: the diagonally normalised map estimate of Sec. 4.3
  * (eq. vis_to_map, eq. map_psf) per channel,
  *     map_p = Re(A^H y)_p / (A^H A)_pp,
  * with A the beam-and-fringe response including the gains (eq. rime_matrix)

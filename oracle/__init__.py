@@ -20,7 +20,7 @@ follows.  Modules:
 ``hmc``        leapfrog / Hamiltonian, diagonal or block-dense mass  Sec. 4.2, App. B
 ``nuts``       No-U-Turn sampler, biased progressive sampling        Sec. 4.2 (Hoffman & Gelman 2014,
                Betancourt 2017)
-``mapmaking``  diagonally normalised dirty map                        Sec. 6
+``mapmaking``  diagonally normalised dirty map                        Sec. 4.3
 ``philox``     Philox-4x32-10 counter-based generator (Salmon et al. 2011)
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in

@@ -1,6 +1,6 @@
 """Map-making from visibilities (oracle).
 
-Sec. 6 (map-making, eq. map_to_vis, eq. vis_to_map, eq. map_psf): for one
+Sec. 4.3 (map-making, eq. map_to_vis, eq. vis_to_map, eq. map_psf): for one
 channel the visibilities are y = A x + n, with A the beam-and-fringe response
 of eq. rime_matrix stacked over times and baselines (here including the
 antenna gains, A[(t, ij)][p] = dOmega B(p, t) g_i conj(g_j)

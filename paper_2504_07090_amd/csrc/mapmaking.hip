@@ -1,4 +1,4 @@
-// Map-making: x_hat = D A^H N^-1 y (Sec. 6, eq. vis_to_map, eq. map_psf).
+// Map-making: x_hat = D A^H N^-1 y (Sec. 4.3, eq. vis_to_map, eq. map_psf).
 //
 // A is the beam-and-fringe response with gains (eq. rime_matrix), stacked
 // over times and baselines.  Re(A^H y) at the pixels above the horizon is the
