@@ -60,8 +60,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "ab7d3080bfd325fb4e4b5f634c0467d7ef6d6e4d620e42f0ee0fed7cef383c6a",
-    "bytes_per_launch": {"k_fringe_adj": 199023592, "k_fringe_fwd": 269417135},
+    "sha256": "7c6985893c210bf60b6fabb7639056df95c4de41ba6fa275a2ef4bf609c9d905",
+    "bytes_per_launch": {"k_fringe_adj": 202729612, "k_fringe_fwd": 269300921},
 }
 
 

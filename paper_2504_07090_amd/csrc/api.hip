@@ -30,9 +30,13 @@ void adjoint_tail(const vis_field* f, const float* fwhm, float* grad_alm, float2
     launch_reduce_grads(f, with_chi2, f->scr.chi_part, chi2, f->scr.g_part, grad_gains,
                         f->scr.f_part, nullptr, s);
   }
+  // separable fields: the adjoint fringe pass writes dL/dI straight into the
+  // full-grid layout that the azimuthal adjoint stage reads
+  const bool full = f->synthesis == VIS_SYNTH_SEPARABLE;
   {
     StageScope sc(kStageFringeAdj);
-    launch_fringe_adj(f, f->scr.img, fwhm, f->scr.gco, f->scr.dimg, f->scr.f_part, s);
+    launch_fringe_adj(f, f->scr.img, fwhm, f->scr.gco, full ? nullptr : f->scr.dimg, f->scr.f_part, s,
+                      full ? f->scr.sep_dfull : nullptr);
   }
   if (grad_fwhm != nullptr) {
     StageScope sc(kStageReduceF);
@@ -40,7 +44,7 @@ void adjoint_tail(const vis_field* f, const float* fwhm, float* grad_alm, float2
   }
   if (grad_alm != nullptr) {
     StageScope sc(kStageSynthAdj);
-    launch_synth_adj(f, f->scr.dimg, grad_alm, s);
+    launch_synth_adj(f, full ? nullptr : f->scr.dimg, grad_alm, s);
   }
 }
 

@@ -101,6 +101,7 @@ constexpr int kChunk = 64;        // pixels per fringe chunk (one wavefront)
 constexpr int kScaleParts = 16;   // row segments of the split forward's sky maxima
 constexpr int kMaxExtent = 16;    // max |lattice difference| supported
 constexpr int kSepPad = 4;        // zero azimuthal columns on each side of the separable T table
+constexpr int kSepStep = 32;      // columns per batch of the separable azimuthal stages
 // row length of the separable Legendre table's block for order m (l = m .. lmax, zero-padded)
 __host__ __device__ inline int sep_lpad(int lmax, int m) { return (lmax - m + 1 + 7) / 8 * 8; }
 constexpr float kBelowHorizon = 1e30f;  // theta^2 marker: beam exactly 0

@@ -368,6 +368,10 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
     S.sep_g = cv.take<float>(static_cast<size_t>(f->basis->nz) * f->kaz * nfq);
     S.sep_dfull = cv.take<float>(npix * nfq);
     S.sep_at = cv.take<float>(static_cast<size_t>(f->n_modes) * nfq);
+    T.sep_kb_off = cv.take<int>(f->basis->nz + 1);
+    const size_t nkb_max = static_cast<size_t>(f->basis->nz) * ceil_div(f->basis->nphi, kSepStep);
+    T.sep_kb = cv.take<int>(nkb_max);
+    T.sep_kb_ring = cv.take<int>(nkb_max);
   }
   if (f->precision != VIS_FP32) {
     const size_t nfp = static_cast<size_t>(round_up(f->n_freq, 64));
@@ -653,10 +657,33 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
     std::vector<int> vidx(basis->n_pix, -1);
     for (int k = 0; k < f->nv; ++k) vidx[g.vpix[k]] = k;
     up(T.vidx, vidx, s);
+    // named, like the tables above, until the stream is synchronised
+    std::vector<int> kb_off, kb, kb_ring;
     if (f->synthesis == VIS_SYNTH_SEPARABLE) {
       // rows of the Legendre stage beyond 2 lmax + 1 are never written: keep them zero
       BV_HIP(hipMemsetAsync(f->scr.sep_g, 0,
                             sizeof(float) * basis->nz * f->kaz * f->n_freq, s));
+      // the adjoint writes dL/dI only at pixels above the horizon at some time;
+      // the others stay zero
+      BV_HIP(hipMemsetAsync(f->scr.sep_dfull, 0, sizeof(float) * basis->n_pix * f->n_freq, s));
+      // the column batches of each ring that the azimuthal stages visit
+      kb_off.assign(1, 0);
+      for (int j = 0; j < basis->nz; ++j) {
+        for (int k0 = 0; k0 < basis->nphi; k0 += kSepStep) {
+          bool any = false;
+          for (int k = k0; k < std::min(basis->nphi, k0 + kSepStep); ++k)
+            any = any || vidx[static_cast<size_t>(j) * basis->nphi + k] >= 0;
+          if (any) {
+            kb.push_back(k0);
+            kb_ring.push_back(j);
+          }
+        }
+        kb_off.push_back(static_cast<int>(kb.size()));
+      }
+      f->sep_nkb = static_cast<int>(kb.size());
+      up(T.sep_kb_off, kb_off, s);
+      up(T.sep_kb, kb, s);
+      up(T.sep_kb_ring, kb_ring, s);
     }
     BV_HIP(hipStreamSynchronize(s));
     *out = f;

@@ -802,6 +802,11 @@ struct AdjArgs {
   const float* gco_lane;
   float* dimg;
   float* f_part;
+  // non-null: dL/dI goes to dfull[pixel][nu] (pixel vpix[k] of visible slot
+  // k < nv) for the separable adjoint synthesis, instead of dimg[nu][k]
+  float* dfull;
+  const int* vpix;
+  int nv;
 };
 
 // Channels that share one adjoint tile: for D = 4 two channels' coefficient
@@ -1087,7 +1092,11 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     if (NCH * fgrp + c >= nf) break;   // uniform over the wave
-    dimg[static_cast<size_t>(fch[c]) * nvp + k] = d_omega * acc_i[c];
+    if (args.dfull != nullptr) {        // uniform over the wave
+      if (k < args.nv) args.dfull[static_cast<size_t>(args.vpix[k]) * nf + fch[c]] = d_omega * acc_i[c];
+    } else {
+      dimg[static_cast<size_t>(fch[c]) * nvp + k] = d_omega * acc_i[c];
+    }
     float pf = acc_f[c] * ival[c];
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) pf += __shfl_xor(pf, o);
@@ -1119,15 +1128,16 @@ static void fwd_d(const vis_field* f, const float* img, const float* fwhm, float
 
 template <int D>
 static void adj_d(const vis_field* f, const float* img, const float* fwhm, const float* gco,
-                  float* dimg, float* f_part, hipStream_t st) {
+                  float* dimg, float* dfull, float* f_part, hipStream_t st) {
   constexpr int nch = adj_channels_per_tile(D);
   const int nblk = static_cast<int>(round_up(static_cast<long>((f->n_freq + nch - 1) / nch) * f->n_chunks, 8));
   const auto& T = f->tab;
   ProfScope ps(&f->prof, "k_fringe_adj", st);
   BV_REQUIRE(f->dtile == D, VIS_EINVAL, "internal: adjoint tile mismatch");
+  BV_REQUIRE((dimg == nullptr) != (dfull == nullptr), VIS_EINVAL, "internal: one adjoint output");
   const AdjArgs a{f->n_freq, f->n_time, f->nv_pad, f->n_chunks, f->gstride,
                   static_cast<float>(f->d_omega), T.dnu, T.sigr, T.q1, T.q2, T.th2,
-                  T.chunk_t, img, fwhm, gco, gco, dimg, f_part};
+                  T.chunk_t, img, fwhm, gco, gco, dimg, f_part, dfull, T.vpix, f->nv};
   if (fringe_split(f))
     launch_k<KFringeAdj<D, true>>(dim3(nblk), 0, a, st, "k_fringe_adj");
   else
@@ -1157,8 +1167,8 @@ int fringe_tile_extent(int e) {
 }
 
 void launch_fringe_adj(const vis_field* f, const float* img, const float* fwhm, const float* gco,
-                       float* dimg, float* f_part, hipStream_t st) {
-#define BV_CALL_ADJ(DD) adj_d<DD>(f, img, fwhm, gco, dimg, f_part, st)
+                       float* dimg, float* f_part, hipStream_t st, float* dfull) {
+#define BV_CALL_ADJ(DD) adj_d<DD>(f, img, fwhm, gco, dimg, dfull, f_part, st)
   BV_DISPATCH_EXTENT(f->extent, BV_CALL_ADJ);
 #undef BV_CALL_ADJ
 }

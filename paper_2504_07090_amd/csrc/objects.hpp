@@ -79,6 +79,7 @@ struct FieldScratch {
   float* sep_g = nullptr;          // separable fields: [nz][kaz][n_freq] Legendre stage output
                                    //   (forward) or azimuthal stage output (adjoint)
   float* sep_dfull = nullptr;      // separable fields: [n_pix][n_freq] dL/dI on the full grid
+                                   //   (zero at pixels never above the horizon)
   float* sep_at = nullptr;         // separable fields: [n_modes][n_freq] sky coefficients transposed
   float2* vu = nullptr;            // [n_time][n_freq][n_ubl] gain-free unique visibilities
   float* gco = nullptr;            // [n_time][n_freq][gstride] adjoint coefficients, MFMA layout
@@ -113,6 +114,11 @@ struct FieldTables {
   int2* ubl_nm = nullptr;          // [n_ubl] lattice (n1, n2), canonical
   int* ulut = nullptr;             // [(D+1) * (2D+1)] unique index of (n1, n2) or -1
   int4* cplan = nullptr;           // [gstride] source plan of each adjoint coefficient entry
+  // separable fields: per ring j, the first columns of the 32-column batches
+  // that hold a pixel above the horizon, sep_kb[sep_kb_off[j] .. sep_kb_off[j + 1])
+  int* sep_kb_off = nullptr;       // [nz + 1]
+  int* sep_kb = nullptr;           // [nz * ceil(nphi / 32)] at most
+  int* sep_kb_ring = nullptr;      // the ring of each sep_kb entry
 };
 
 }  // namespace bv
@@ -131,6 +137,7 @@ struct vis_field {
   int kaz = 0;                     // separable: rows per ring of sep_g, round_up(2 lmax + 1, 4)
   int asplit = 1;                  // split-K factor of the adjoint synthesis
   int fsplit = 1;                  // split-K factor of the FP32 forward synthesis
+  int sep_nkb = 0;                 // separable fields: entries of tab.sep_kb
   double d_omega = 0.0;
   double beam_ref_hz = 150e6;
   double fwd_macs = 0.0;
@@ -143,11 +150,15 @@ namespace bv {
 
 // ---- launchers (stream-ordered, no host sync) ----------------------------
 void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStream_t st);
+// Dense fields read dL/dI from dimg; separable fields take dimg == nullptr and
+// read it from the full-grid scratch, where the adjoint fringe pass put it.
 void launch_synth_adj(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st);
 void launch_fringe_fwd(const vis_field* f, const float* img, const float* fwhm, float2* vu,
                        hipStream_t st);
+// dL/dI goes to dimg ([n_freq][nv_pad]) or, for separable fields, with
+// dimg == nullptr, to the full-grid scratch dfull ([n_pix][n_freq]).
 void launch_fringe_adj(const vis_field* f, const float* img, const float* fwhm, const float* gco,
-                       float* dimg, float* f_part, hipStream_t st);
+                       float* dimg, float* f_part, hipStream_t st, float* dfull = nullptr);
 
 // Extent instantiated by the fringe kernels for a lattice extent D, and the
 // layout of the adjoint coefficient table that the gains pass writes.

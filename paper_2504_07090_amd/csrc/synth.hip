@@ -358,7 +358,7 @@ void launch_synth_fwd_split(const vis_field* f, const float* alm, float* dst, in
                             hipStream_t st);
 void launch_synth_adj_split(const vis_field* f, const float* dimg, int kps, hipStream_t st);
 void launch_synth_fwd_sep(const vis_field* f, const float* alm, float* img, hipStream_t st);
-void launch_synth_adj_sep(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st);
+void launch_synth_adj_sep(const vis_field* f, float* grad_alm, hipStream_t st);
 
 void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStream_t st) {
   if (f->synthesis == VIS_SYNTH_SEPARABLE) {
@@ -388,9 +388,11 @@ void launch_synth_fwd(const vis_field* f, const float* alm, float* img, hipStrea
 
 void launch_synth_adj(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st) {
   if (f->synthesis == VIS_SYNTH_SEPARABLE) {
-    launch_synth_adj_sep(f, dimg, grad_alm, st);
+    BV_REQUIRE(dimg == nullptr, VIS_EINVAL, "internal: separable synthesis adjoint reads the full-grid scratch");
+    launch_synth_adj_sep(f, grad_alm, st);
     return;
   }
+  BV_REQUIRE(dimg != nullptr, VIS_EINVAL, "internal: dense synthesis adjoint without dL/dI");
   const vis_basis* b = f->basis;
   const int nsplit = f->asplit;
   if (f->precision != VIS_FP32) {

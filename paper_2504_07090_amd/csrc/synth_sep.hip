@@ -12,8 +12,11 @@
 //     dL/da_lm(nu) = sum_j lambda_l|m|(z_j) H_m(j, nu).
 // At lmax 100 on 128 x 384 pixels and 64 channels this is ~0.7e9 MACs per
 // direction against 1.7e10 for the dense product with the visible rows of Y,
-// and the factor tables take ~3 MB instead of 2 GB.  All pixels of the grid
-// are synthesised (the visible ones are scattered into the sky scratch).
+// and the factor tables take ~3 MB instead of 2 GB.  The Legendre stages run
+// every ring; the azimuthal stages run only the 32-column batches of a ring
+// that hold a pixel above the horizon at some time.  The forward writes the
+// visible pixels into the sky scratch; the adjoint reads dL/dI on the full
+// grid, where the adjoint fringe pass writes it (zero at the other pixels).
 //
 // Every GEMM is a grid of 16 x 16 output tiles, one wavefront each, on
 // v_mfma_f32_16x16x4_f32: A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
@@ -67,7 +70,7 @@ __device__ __forceinline__ int3 sep_blocks_x_fastest(int L, const Blk& B) {
 }
 
 constexpr int kSepBatch = 8;              // MFMAs whose operand loads are issued together
-constexpr int kSepStep = 4 * kSepBatch;   // K covered per batch
+static_assert(kSepStep == 4 * kSepBatch, "K covered per batch");
 
 // at[mode][nu] = a[nu][mode]: the sky coefficients transposed through a
 // 16-mode x 64-channel LDS tile (one block per 16 modes, so the grid fills the
@@ -184,9 +187,10 @@ __device__ void KSepLegFwd::run(const SepLegFwdArgs& args_, const Blk& B_) {
 
 // img[nu][slot(j, k)] = sum_{c < nc} G[j][c][nu] Tt[c + toff][k] for visible pixels
 // (nc = 2 lmax + 1 rows of G per ring are used).
-// grid (ceil(nphi / 32), nz, ceil(nf / 32)); each wave computes a 2 x 2 block of
-// 16 x 16 tiles (rows = channels, columns = pixels), so every operand load
-// feeds two MFMAs.
+// grid (column batches that hold a pixel above the horizon at some time, 1,
+// ceil(nf / 32)): block x takes batch kb[x] of ring kb_ring[x] (a ring's
+// batches are consecutive); each wave computes a 2 x 2 block of 16 x 16 tiles
+// (rows = channels, columns = pixels), so every operand load feeds two MFMAs.
 struct SepAzFwdArgs {
   int nphi;
   int nf;
@@ -196,6 +200,8 @@ struct SepAzFwdArgs {
   const float* Tt;
   const float* G;
   const int* vidx;
+  const int* kb;
+  const int* kb_ring;
   int nvp;
   float* img;
 };
@@ -219,7 +225,7 @@ __device__ void KSepAzFwd::run(const SepAzFwdArgs& args_, const Blk& B_) {
   float* __restrict__ img = args_.img;
 
   const int3 bk = sep_blocks_x_fastest(sep_xcd_logical(B_), B_);
-  const int k0 = bk.x * 32, j = bk.y, f0 = bk.z * 32;
+  const int k0 = args_.kb[bk.x], j = args_.kb_ring[bk.x], f0 = bk.z * 32;
   const int lane = threadIdx.x, i = lane & 15, kk = lane >> 4;
   const float* grow[2];
   const float* tcol[2];
@@ -286,47 +292,6 @@ __device__ void KSepAzFwd::run(const SepAzFwdArgs& args_, const Blk& B_) {
   }
 }
 
-// dfull[p][nu] = dimg[nu][vidx[p]] (0 for pixels never above the horizon):
-// a 64 x 64 tile transposed through LDS so reads and writes are coalesced.
-struct SepScatterArgs {
-  int npix;
-  int nf;
-  int nvp;
-  const int* vidx;
-  const float* dimg;
-  float* dfull;
-};
-
-struct KSepScatter {
-  using Args = SepScatterArgs;
-  static constexpr int kThreads = 256, kWaves = 1;
-  static __device__ void run(const SepScatterArgs& args_, const Blk& B_);
-};
-
-__device__ void KSepScatter::run(const SepScatterArgs& args_, const Blk& B_) {
-  int npix = args_.npix;
-  int nf = args_.nf;
-  int nvp = args_.nvp;
-  const int* __restrict__ vidx = args_.vidx;
-  const float* __restrict__ dimg = args_.dimg;
-  float* __restrict__ dfull = args_.dfull;
-
-  __shared__ float tile[64][65];
-  const int p0 = B_.x * 64, f0 = B_.y * 64, tid = threadIdx.x;
-  const int tp = tid & 63, tr = tid >> 6;
-  const int p = p0 + tp;
-  const int slot = p < npix ? vidx[p] : -1;
-  for (int q = tr; q < 64; q += 4) {
-    const int f = f0 + q;
-    tile[q][tp] = (slot >= 0 && f < nf) ? dimg[static_cast<size_t>(f) * nvp + slot] : 0.f;
-  }
-  __syncthreads();
-  for (int q = tr; q < 64; q += 4) {
-    const int pp = p0 + q, f = f0 + tp;
-    if (pp < npix && f < nf) dfull[static_cast<size_t>(pp) * nf + f] = tile[tp][q];
-  }
-}
-
 // H[j][c][nu] = sum_k T[k][c + toff] dfull[j nphi + k][nu] for c < nc = 2 lmax + 1.
 // grid (ceil(nc / 32), nz, ceil(nf / 32)); each wave computes a 2 x 2 block of
 // 16 x 16 tiles (rows = c, columns = channels).
@@ -339,6 +304,8 @@ struct SepAzAdjArgs {
   int toff;
   const float* T;
   const float* dfull;
+  const int* kb_off;
+  const int* kb;
   float* H;
 };
 
@@ -400,16 +367,24 @@ __device__ void KSepAzAdj::run(const SepAzAdjArgs& args_, const Blk& B_) {
       }
     }
   };
-  Batch B0, B1;
-  load(0, B0);
-  for (int k0 = 0; k0 < nphi; k0 += 2 * kSepStep) {
-    load(k0 + kSepStep, B1);
-    __builtin_amdgcn_sched_barrier(0);
-    mma(k0, B0);
-    if (k0 + kSepStep >= nphi) break;
-    load(k0 + 2 * kSepStep, B0);
-    __builtin_amdgcn_sched_barrier(0);
-    mma(k0 + kSepStep, B1);
+  // the K loop visits only the ring's column batches that hold a pixel above
+  // the horizon at some time (dL/dI is zero elsewhere)
+  const int* kb = args_.kb + args_.kb_off[j];
+  const int nkb = args_.kb_off[j + 1] - args_.kb_off[j];
+  if (nkb > 0) {
+    // the batch after the last re-reads the last (always issued, never used)
+    auto kb_at = [&](int q) { return kb[min(q, nkb - 1)]; };
+    Batch B0, B1;
+    load(kb[0], B0);
+    for (int q = 0; q < nkb; q += 2) {
+      load(kb_at(q + 1), B1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(kb[q], B0);
+      if (q + 1 >= nkb) break;
+      load(kb_at(q + 2), B0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(kb[q + 1], B1);
+    }
   }
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
@@ -507,27 +482,25 @@ void launch_synth_fwd_sep(const vis_field* f, const float* alm, float* img, hipS
                                        f->scr.sep_at, f->scr.sep_g}, st, "k_sep_leg_fwd");
   }
   ProfScope ps(&f->prof, "k_sep_az_fwd", st);
-  dim3 grid(ceil_div(b->nphi, 32), b->nz, ceil_div(f->n_freq, 32));
+  dim3 grid(f->sep_nkb, 1, ceil_div(f->n_freq, 32));
   launch_k<KSepAzFwd>(grid, 0, SepAzFwdArgs{b->nphi, f->n_freq, f->kaz, 2 * L + 1, toff, b->sep_tt, f->scr.sep_g,
-                                    f->tab.vidx, f->nv_pad, img}, st, "k_sep_az_fwd");
+                                    f->tab.vidx, f->tab.sep_kb, f->tab.sep_kb_ring, f->nv_pad, img},
+                      st, "k_sep_az_fwd");
 }
 
-void launch_synth_adj_sep(const vis_field* f, const float* dimg, float* grad_alm, hipStream_t st) {
+// dL/dI comes in the full-grid scratch sep_dfull, written there by the
+// adjoint fringe pass (zero at pixels never above the horizon).
+void launch_synth_adj_sep(const vis_field* f, float* grad_alm, hipStream_t st) {
   const vis_basis* b = f->basis;
   BV_REQUIRE(b->sep_lam != nullptr, VIS_EINVAL, "basis has no separable factor tables");
   const int L = f->lmax;
   const int toff = b->lmax + kSepPad - L;
   {
-    ProfScope ps(&f->prof, "k_sep_scatter", st);
-    dim3 grid(ceil_div(b->n_pix, 64), ceil_div(f->n_freq, 64));
-    launch_k<KSepScatter>(grid, 0, SepScatterArgs{b->n_pix, f->n_freq, f->nv_pad, f->tab.vidx, dimg,
-                                        f->scr.sep_dfull}, st, "k_sep_scatter");
-  }
-  {
     ProfScope ps(&f->prof, "k_sep_az_adj", st);
     dim3 grid(ceil_div(2 * L + 1, 32), b->nz, ceil_div(f->n_freq, 32));
     launch_k<KSepAzAdj>(grid, 0, SepAzAdjArgs{b->nphi, f->n_freq, f->kaz, 2 * L + 1, b->kaz_t, toff, b->sep_t,
-                                      f->scr.sep_dfull, f->scr.sep_g}, st, "k_sep_az_adj");
+                                      f->scr.sep_dfull, f->tab.sep_kb_off, f->tab.sep_kb, f->scr.sep_g},
+                        st, "k_sep_az_adj");
   }
   ProfScope ps(&f->prof, "k_sep_leg_adj", st);
   dim3 grid(2 * L + 1, ceil_div(L + 1, 16), ceil_div(f->n_freq, 16));
