@@ -20,19 +20,24 @@
 
 namespace bv {
 
-// grad U at element i from the chi^2 gradient and the priors; adds the prior
-// part of U to acc_u.
-__device__ __forceinline__ float grad_potential(const HmcTask& T, int i, float q, double& acc_u) {
-  float g = 0.5f * T.gchi[i];
+// grad U at element i from its chi^2 gradient gchi and the priors (cvar: the
+// prior variance of a sky coefficient, unused for other elements); adds the
+// prior part of U to acc_u.
+__device__ __forceinline__ float grad_potential_v(const HmcTask& T, int i, float q, float gchi, float cvar,
+                                                  double& acc_u) {
+  float g = 0.5f * gchi;
   if (i < T.nalm) {
-    g += q / T.cvar[i];
-    acc_u += 0.5 * static_cast<double>(q) * q / T.cvar[i];
+    g += q / cvar;
+    acc_u += 0.5 * static_cast<double>(q) * q / cvar;
   } else if (i >= T.goff && i < T.goff + T.ngain) {
     const float dg = q - ((i - T.goff) % 2 == 0 ? 1.0f : 0.0f);
     g += dg * T.gvar_inv;
     acc_u += 0.5 * static_cast<double>(dg) * dg * T.gvar_inv;
   }
   return g;
+}
+__device__ __forceinline__ float grad_potential(const HmcTask& T, int i, float q, double& acc_u) {
+  return grad_potential_v(T, i, q, T.gchi[i], i < T.nalm ? T.cvar[i] : 1.f, acc_u);
 }
 
 // Sums N values over the block in a fixed order (wave butterflies, then the
@@ -284,7 +289,44 @@ k_nuts_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict_
   nuts_elem(T, lb, red_n, phase);
 }
 
-// One block handles kHmcPerBlock consecutive parameters of one chain.
+// One parameter's leapfrog work on register values: q, p and g come in as
+// stored (g = grad U at q) and go out updated; mi = minv, gchi and cvar are
+// its chi^2 gradient and prior variance (cvar read only for sky coefficients).
+__device__ __forceinline__ void hmc_elem_one(const HmcTask& T, int i, float eps, float z, float mi,
+                                             float gchi, float cvar, bool dense, float& q, float& p,
+                                             float& g, double& acc_u, double& acc_k, double& acc_k0) {
+  if ((T.op & kOpBegin) && !dense) {
+    p = z * rsqrtf(mi);
+    acc_k0 += 0.5 * static_cast<double>(mi) * p * p;
+  }
+  if ((T.op & kOpKickDrift) && !dense) {
+    p -= 0.5f * eps * g;
+    q += eps * mi * p;
+  }
+  if (T.op & (kOpPost | kOpInit)) {
+    // assemble grad U from the chi^2 gradient and the priors
+    g = grad_potential_v(T, i, q, gchi, cvar, acc_u);
+    if (T.op & kOpPost) {
+      p -= 0.5f * eps * g;
+      if (!dense) acc_k += 0.5 * static_cast<double>(mi) * p * p;
+    }
+  }
+}
+
+typedef float hv4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) hv4 ghv4;   // global, not flat
+__device__ __forceinline__ hv4 ld4(const float* a, int i) { return *(const ghv4*)(a + i); }
+__device__ __forceinline__ void st4(float* a, int i, hv4 v) { *(ghv4*)(a + i) = v; }
+
+// One block handles kHmcPerBlock consecutive parameters of one chain, a group
+// of four consecutive ones per thread.  A group that lies wholly among the
+// sky coefficients, or wholly among the gains, moves through 16-byte loads
+// and stores (the chain's vectors start 256-byte aligned); any other group
+// (a boundary, the last parameter) goes element by element, and groups in
+// the alignment padding between the two are never touched.  Either way each
+// element runs hmc_elem_one in index order, so the sums do not depend on the
+// path.
+static_assert(kHmcPerBlock == 4 * kHmcThreads, "one group of four parameters per thread");
 __global__ void __launch_bounds__(kHmcThreads)
 k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__ blk0) {
   __shared__ double red[4 * 3];   // block_sum_n<3> wave totals
@@ -294,49 +336,64 @@ k_hmc_elem(const HmcTask* __restrict__ tasks, int ntask, const int* __restrict__
   if (lb >= T.nblk || (T.op & kNutsOps)) return;
   HmcState* st = T.st;
   const float eps = st->eps;
-  const int beg = lb * kHmcPerBlock;
   double acc_u = 0.0, acc_k = 0.0, acc_k0 = 0.0;
   if ((T.op & kOpRestore) != 0 && st->restore == 0) return;
-  for (int i0 = beg + threadIdx.x * 4; i0 < beg + kHmcPerBlock; i0 += kHmcThreads * 4) {
-    float z[4];
+  const int i0 = lb * kHmcPerBlock + threadIdx.x * 4;
+  const bool in_alm = i0 + 4 <= T.nalm;
+  const bool in_gain = i0 >= T.goff && i0 + 4 <= T.goff + T.ngain;
+  const bool padding = i0 >= T.nalm && i0 + 4 <= T.goff;
+  if (i0 < T.len && !padding) {
+    float z[4] = {0.f, 0.f, 0.f, 0.f};
     if (T.op & kOpBegin) normals4(T.seed, T.stream, T.traj, static_cast<uint32_t>(i0 >> 2), z);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int i = i0 + e;
-      if (i >= T.len) break;
-      if (i >= T.nalm && i < T.goff) continue;  // alignment padding: never touched
+    if ((in_alm || in_gain) && i0 + 4 <= T.len) {
       if (T.op & kOpRestore) {
-        T.q[i] = T.q0[i];
-        T.grad[i] = T.grad0[i];
-        continue;
-      }
-      const float mi = T.minv[i];
-      // gains under a dense block mass: momentum draw, drift and kinetic
-      // energy belong to k_hmc_gainblk, which runs after this kernel
-      const bool dense = T.lrow != nullptr && i >= T.goff && i < T.goff + T.ngain;
-      float p = T.p[i];
-      if (T.op & kOpBegin) {
-        if (!dense) {
-          p = z[e] * rsqrtf(mi);
-          acc_k0 += 0.5 * static_cast<double>(mi) * p * p;
+        st4(T.q, i0, ld4(T.q0, i0));
+        st4(T.grad, i0, ld4(T.grad0, i0));
+      } else {
+        const bool dense = in_gain && T.lrow != nullptr;
+        const bool post = (T.op & (kOpPost | kOpInit)) != 0;
+        const hv4 q4 = ld4(T.q, i0), p4 = ld4(T.p, i0), mi = ld4(T.minv, i0), g4 = ld4(T.grad, i0);
+        const hv4 gc = post ? ld4(T.gchi, i0) : hv4{0.f, 0.f, 0.f, 0.f};
+        const hv4 cv = post && in_alm ? ld4(T.cvar, i0) : hv4{1.f, 1.f, 1.f, 1.f};
+        if (T.op & kOpBegin) {
+          st4(T.q0, i0, q4);
+          st4(T.grad0, i0, g4);
         }
-        T.q0[i] = T.q[i];
-        T.grad0[i] = T.grad[i];
+        float q[4] = {q4.x, q4.y, q4.z, q4.w}, p[4] = {p4.x, p4.y, p4.z, p4.w};
+        float g[4] = {g4.x, g4.y, g4.z, g4.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          hmc_elem_one(T, i0 + e, eps, z[e], mi[e], gc[e], cv[e], dense, q[e], p[e], g[e], acc_u, acc_k, acc_k0);
+        if (T.op & kOpKickDrift) st4(T.q, i0, hv4{q[0], q[1], q[2], q[3]});
+        if (post) st4(T.grad, i0, hv4{g[0], g[1], g[2], g[3]});
+        st4(T.p, i0, hv4{p[0], p[1], p[2], p[3]});
       }
-      if ((T.op & kOpKickDrift) && !dense) {
-        p -= 0.5f * eps * T.grad[i];
-        T.q[i] += eps * mi * p;
-      }
-      if (T.op & (kOpPost | kOpInit)) {
-        // assemble grad U from the chi^2 gradient and the priors
-        const float g = grad_potential(T, i, T.q[i], acc_u);
-        T.grad[i] = g;
-        if (T.op & kOpPost) {
-          p -= 0.5f * eps * g;
-          if (!dense) acc_k += 0.5 * static_cast<double>(mi) * p * p;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + e;
+        if (i >= T.len) break;
+        if (i >= T.nalm && i < T.goff) continue;  // alignment padding: never touched
+        if (T.op & kOpRestore) {
+          T.q[i] = T.q0[i];
+          T.grad[i] = T.grad0[i];
+          continue;
         }
+        // gains under a dense block mass: momentum draw, drift and kinetic
+        // energy belong to k_hmc_gainblk, which runs after this kernel
+        const bool dense = T.lrow != nullptr && i >= T.goff && i < T.goff + T.ngain;
+        const bool post = (T.op & (kOpPost | kOpInit)) != 0;
+        float q = T.q[i], p = T.p[i], g = T.grad[i];
+        if (T.op & kOpBegin) {
+          T.q0[i] = q;
+          T.grad0[i] = g;
+        }
+        hmc_elem_one(T, i, eps, z[e], T.minv[i], post ? T.gchi[i] : 0.f,
+                     post && i < T.nalm ? T.cvar[i] : 1.f, dense, q, p, g, acc_u, acc_k, acc_k0);
+        if (T.op & kOpKickDrift) T.q[i] = q;
+        if (post) T.grad[i] = g;
+        T.p[i] = p;
       }
-      T.p[i] = p;
     }
   }
   if (T.op & kOpRestore) return;
