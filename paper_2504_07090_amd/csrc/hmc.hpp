@@ -77,7 +77,7 @@ struct HmcTask {
   double* part_k;
   double* part_k0;
   HmcState* st;
-  HmcState* st_out;  // finalize copies the state here for the host read-back
+  HmcState* st_out;  // finalize copies the state here (pinned host memory) for the host
   // dense per-channel gain mass blocks M_f = L_f L_f^T (null: diagonal minv)
   const float* lrow;  // [n_freq][nb4][nb4] L row-major, padded with identity rows
   const float* lcol;  // the same blocks transposed (L column-major)

@@ -191,10 +191,11 @@ struct Slot {
   HmcTask* host_tasks = nullptr;     // [4][max_batch] task tables (owns the allocation)
   int* host_blk = nullptr;           // [kPrefixes][max_batch + 1] block prefixes (inside it)
   size_t table_bytes = 0;
-  HmcState* host_states = nullptr;   // pinned: [max_batch] read-back
+  // pinned, fine-grained: [max_batch] states, written by the finalize kernel
+  // straight over the bus (no read-back copy) and read after the tick's event
+  HmcState* host_states = nullptr;
   HmcTask* dev_tasks = nullptr;      // in the arena
   int* dev_blk = nullptr;
-  HmcState* dev_states = nullptr;    // finalize output, [max_batch]
   // argument tables and workgroup entries of the batched evaluation launches
   unsigned char* host_batch = nullptr;   // pinned
   unsigned char* dev_batch = nullptr;    // in the arena
@@ -326,7 +327,7 @@ void hmc_server::enqueue(Tick& t) {
     T.part_k = reinterpret_cast<double*>(c->base + c->L.off_pk);
     T.part_k0 = reinterpret_cast<double*>(c->base + c->L.off_pk0);
     T.st = c->st();
-    T.st_out = S.dev_states + npost;
+    T.st_out = S.host_states + npost;
     T.seed = c->seed;
     T.len = c->L.len;
     T.nalm = c->L.nalm;
@@ -458,9 +459,8 @@ void hmc_server::enqueue(Tick& t) {
     launch_hmc_elem(S.dev_tasks + 3 * nb, nrst, S.dev_blk + 2 * (nb + 1), rst_blk[nrst], stream);
   if (nuts_tasks)
     launch_nuts_elem(S.dev_tasks + 3 * nb, nrst, S.dev_blk + 2 * (nb + 1), rst_blk[nrst], stream);
-  // read back the state of every chain in the tick (gathered by the finalize kernel)
-  hip_or_throw(hipMemcpyAsync(S.host_states, S.dev_states, sizeof(HmcState) * npost,
-                              hipMemcpyDeviceToHost, stream), "state read-back");
+  // the finalize kernel has written every chain's state into host_states; the
+  // event orders the host's reads after it
   hip_or_throw(hipEventRecord(t.done, stream), "event record");
 }
 
@@ -600,9 +600,8 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
     const int nb = cfg->max_batch;
     const size_t task_bytes = round_up(sizeof(HmcTask) * 4 * nb, 256);
     const size_t blk_bytes = round_up(sizeof(int) * kPrefixes * (nb + 1), 256);
-    const size_t st_bytes = round_up(sizeof(HmcState) * nb, 256);
     const size_t bb = cfg->batched == 1 ? batch_stage_bytes(nb) : 0;
-    const size_t per = task_bytes + blk_bytes + st_bytes + bb;
+    const size_t per = task_bytes + blk_bytes + bb;
     const size_t reserve = kSlots * per;
     BV_REQUIRE(arena_bytes > reserve, VIS_ENOMEM, "arena smaller than the %zu-byte tick tables",
                reserve);
@@ -611,14 +610,14 @@ vis_status hmc_server_create(const hmc_server_config* cfg, void* arena_dev, size
       Slot& S = s->slots[i];
       S.dev_tasks = reinterpret_cast<HmcTask*>(base + i * per);
       S.dev_blk = reinterpret_cast<int*>(base + i * per + task_bytes);
-      S.dev_states = reinterpret_cast<HmcState*>(base + i * per + task_bytes + blk_bytes);
       S.table_bytes = task_bytes + blk_bytes;
       BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_tasks), S.table_bytes));
       S.host_blk = reinterpret_cast<int*>(reinterpret_cast<char*>(S.host_tasks) + task_bytes);
-      BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_states), sizeof(HmcState) * nb));
+      BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_states), sizeof(HmcState) * nb,
+                           hipHostMallocCoherent));
       std::memset(S.host_tasks, 0, S.table_bytes);
       if (bb > 0) {
-        S.dev_batch = reinterpret_cast<unsigned char*>(base + i * per + task_bytes + blk_bytes + st_bytes);
+        S.dev_batch = reinterpret_cast<unsigned char*>(base + i * per + task_bytes + blk_bytes);
         S.batch_bytes = bb;
         BV_HIP(hipHostMalloc(reinterpret_cast<void**>(&S.host_batch), bb));
       }
