@@ -98,6 +98,7 @@ constexpr double kFwhmToSigma = 0.42466090014400953;
 constexpr double kLn2 = 0.69314718055994531;
 
 constexpr int kChunk = 64;        // pixels per fringe chunk (one wavefront)
+constexpr int kAdjChunkTile = 32; // chunks per tile of the adjoint fringe grid (with 16 channel groups)
 constexpr int kScaleParts = 16;   // row segments of the split forward's sky maxima
 constexpr int kMaxExtent = 16;    // max |lattice difference| supported
 constexpr int kSepPad = 4;        // zero azimuthal columns on each side of the separable T table

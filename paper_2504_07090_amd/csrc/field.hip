@@ -311,6 +311,55 @@ static HostGeometry build_geometry(const vis_basis* basis, const vis_field_desc*
     });
     g.vpix.insert(g.vpix.end(), rest.begin(), rest.end());
   }
+  // The adjoint fringe grid deals tiles of kAdjChunkTile chunks (all
+  // channels) to the XCDs in contiguous ranges and a chunk costs one step per
+  // time in its range, so the chunks are regrouped into tiles of equal mean
+  // cost: longest first, each to the tile of lowest mean so far that has
+  // room.  The last, possibly partial chunk keeps its place (the padding
+  // slots stay at the end).
+  {
+    const int nv0 = static_cast<int>(g.vpix.size());
+    const int nck = (nv0 + kChunk - 1) / kChunk;
+    if (nck > 2) {
+      std::vector<int> cost(nck);
+      for (int c = 0; c < nck; ++c) {
+        int lo = nt, hi = -1;
+        for (int k = c * kChunk; k < std::min(nv0, (c + 1) * kChunk); ++k) {
+          lo = std::min(lo, first[g.vpix[k]]);
+          hi = std::max(hi, last[g.vpix[k]]);
+        }
+        cost[c] = hi - lo + 1;
+      }
+      const int ntile = (nck + kAdjChunkTile - 1) / kAdjChunkTile;
+      std::vector<int> room(ntile, kAdjChunkTile), size(ntile, kAdjChunkTile);
+      size[ntile - 1] = room[ntile - 1] = nck - (ntile - 1) * kAdjChunkTile;
+      std::vector<long> load(ntile, 0);
+      std::vector<std::vector<int>> tiles(ntile);
+      room[ntile - 1] -= 1;                      // the last chunk, placed at the end
+      load[ntile - 1] += cost[nck - 1];
+      std::vector<int> order(nck - 1);
+      for (int c = 0; c < nck - 1; ++c) order[c] = c;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+      for (int c : order) {
+        int best = -1;
+        for (int tt = 0; tt < ntile; ++tt) {
+          if (room[tt] == 0) continue;
+          // lower mean cost per chunk of the tile's capacity (cross-multiplied)
+          if (best < 0 || load[tt] * size[best] < load[best] * size[tt]) best = tt;
+        }
+        tiles[best].push_back(c);
+        load[best] += cost[c];
+        room[best] -= 1;
+      }
+      tiles[ntile - 1].push_back(nck - 1);
+      std::vector<int> vp;
+      vp.reserve(nv0);
+      for (const auto& tl : tiles)
+        for (int c : tl)
+          for (int k = c * kChunk; k < std::min(nv0, (c + 1) * kChunk); ++k) vp.push_back(g.vpix[k]);
+      g.vpix.swap(vp);
+    }
+  }
   BV_REQUIRE(!g.vpix.empty(), VIS_EINVAL, "no pixel is above the horizon at any time");
   const int nv = static_cast<int>(g.vpix.size());
   g.nv_pad = static_cast<int>(round_up(nv, kChunk));

@@ -851,7 +851,10 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
   const int L = xcd_logical(B.x, B.nx);
   if (L >= nfg * nchunks) return;
   int chunk, fgrp;
-  tile_map(L, nchunks, nfg, 32, 16, chunk, fgrp);   // 512 resident waves per XCD: 32 chunks x 16 channel groups
+  // 512 resident waves per XCD: 32 chunks x 16 channel groups (the field
+  // set-up orders the chunks so that every 32-chunk tile holds about the
+  // same number of (chunk, time) steps, so the XCDs' ranges balance)
+  tile_map(L, nchunks, nfg, kAdjChunkTile, 16, chunk, fgrp);
   const int k = chunk * kChunk + lane;
   const float fw = fwhm[0];
   // channel c of the group: f = NCH fgrp + c (one past the band, for an odd
