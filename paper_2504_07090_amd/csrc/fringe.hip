@@ -962,7 +962,8 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
       zax[c] = 0.f;
       auto visit = [&](int n, float ar, float ai, float br, float bi) {
         const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 16 * RT + 4 * n);
-        zax[c] += ax[2] * br - ax[3] * bi;
+        zax[c] = __builtin_fmaf(ax[2], br, zax[c]);   // two FMAs, no separate add
+        zax[c] = __builtin_fmaf(-ax[3], bi, zax[c]);
       };
       if constexpr (SPLIT) {
         powers_split_adj<D>(av + 2 * D * c, bh + D * c, bl + D * c, c1, s1, c2, s2, visit);
