@@ -60,8 +60,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "7c6985893c210bf60b6fabb7639056df95c4de41ba6fa275a2ef4bf609c9d905",
-    "bytes_per_launch": {"k_fringe_adj": 202729612, "k_fringe_fwd": 269300921},
+    "sha256": "d38288a928dfd978ac5c841394ca92595cad0b66d8c0456509b57155afd0bb9e",
+    "bytes_per_launch": {"k_fringe_adj": 185513761, "k_fringe_fwd": 236191551},
 }
 
 
