@@ -170,8 +170,7 @@ static void carve_basis(vis_basis* b, Carver& cv) {
     for (int m = 0; m <= b->lmax; ++m) nl += static_cast<size_t>(b->nz) * sep_lpad(b->lmax, m);
     b->sep_lam = cv.take<float>(nl);
     b->sep_loff = cv.take<int>(static_cast<size_t>(b->lmax) + 2);
-    b->sep_t = cv.take<float>(static_cast<size_t>(b->nphi) * b->kaz_t);
-    b->sep_tt = cv.take<float>(static_cast<size_t>(b->nphi) * b->kaz_t);
+    b->sep_tt = cv.take<float>(static_cast<size_t>(b->nphi_b) * b->kaz_t);
   }
 }
 
@@ -190,6 +189,7 @@ static void basis_shape(const vis_basis_desc* d, vis_basis* b) {
   b->kpad = static_cast<int>(round_up(b->n_modes, 64));
   b->storage = d->storage;
   b->kaz_t = static_cast<int>(round_up(2 * d->lmax + 1 + 2 * kSepPad, 4));
+  b->nphi_b = static_cast<int>(round_up(b->nphi, kSepStep));
 }
 
 // ---------------------------------------------------------------- field --
@@ -434,14 +434,14 @@ static void carve_field(vis_field* f, Carver& cv, int n_tchunk) {
   S.dimg = cv.take<float>(nfq * nvp);
   T.vidx = cv.take<int>(f->basis->n_pix);
   if (!dense) {
-    const size_t npix = f->basis->n_pix;
     S.sep_g = cv.take<float>(static_cast<size_t>(f->basis->nz) * f->kaz * nfq);
-    S.sep_dfull = cv.take<float>(npix * nfq);
+    S.sep_dfull = cv.take<float>(static_cast<size_t>(f->basis->nz) * nfq * f->basis->nphi_b);
     S.sep_at = cv.take<float>(static_cast<size_t>(f->n_modes) * nfq);
     T.sep_kb_off = cv.take<int>(f->basis->nz + 1);
     const size_t nkb_max = static_cast<size_t>(f->basis->nz) * ceil_div(f->basis->nphi, kSepStep);
     T.sep_kb = cv.take<int>(nkb_max);
     T.sep_kb_ring = cv.take<int>(nkb_max);
+    T.sep_voff = cv.take<int>(nvp);
   }
   if (f->precision != VIS_FP32) {
     const size_t nfp = static_cast<size_t>(round_up(f->n_freq, 64));
@@ -566,7 +566,7 @@ vis_status vis_basis_create(const vis_basis_desc* desc, void* ws, size_t bytes, 
                                         b->y32, b->ybh, b->ybl, b->yhh, b->yhl);
       check_launch("k_make_basis");
     }
-    std::vector<float> sl, st_, stt;   // host staging, alive until the stream synchronises
+    std::vector<float> sl, stt;   // host staging, alive until the stream synchronises
     std::vector<int> loff;
     if (b->storage & 8u) {
       // separable factors: Y(j, k; l, m) = lambda_l|m|(z_j) T_m(alpha_k)
@@ -580,20 +580,17 @@ vis_status vis_basis_create(const vis_basis_desc* desc, void* ws, size_t bytes, 
             sl[static_cast<size_t>(loff[m]) + static_cast<size_t>(j) * sep_lpad(b->lmax, m) + (l - m)] =
                 static_cast<float>(lam[static_cast<size_t>(j) * ntri + static_cast<size_t>(l) * (l + 1) / 2 + m]);
       BV_HIP(hipMemcpyAsync(b->sep_loff, loff.data(), loff.size() * sizeof(int), hipMemcpyHostToDevice, s));
-      st_.assign(static_cast<size_t>(b->nphi) * b->kaz_t, 0.f);
-      stt.assign(static_cast<size_t>(b->nphi) * b->kaz_t, 0.f);
+      stt.assign(static_cast<size_t>(b->nphi_b) * b->kaz_t, 0.f);
       for (int k = 0; k < b->nphi; ++k) {
         const double* tr = &trig[static_cast<size_t>(k) * 2 * (b->lmax + 1)];
         for (int m = -b->lmax; m <= b->lmax; ++m) {
           const int am = m < 0 ? -m : m;
           const double v = m == 0 ? 1.0 : m > 0 ? std::sqrt(2.0) * tr[2 * am] : std::sqrt(2.0) * tr[2 * am + 1];
           const int c = m + b->lmax + kSepPad;
-          st_[static_cast<size_t>(k) * b->kaz_t + c] = static_cast<float>(v);
-          stt[static_cast<size_t>(c) * b->nphi + k] = static_cast<float>(v);
+          stt[static_cast<size_t>(c) * b->nphi_b + k] = static_cast<float>(v);
         }
       }
       BV_HIP(hipMemcpyAsync(b->sep_lam, sl.data(), sl.size() * sizeof(float), hipMemcpyHostToDevice, s));
-      BV_HIP(hipMemcpyAsync(b->sep_t, st_.data(), st_.size() * sizeof(float), hipMemcpyHostToDevice, s));
       BV_HIP(hipMemcpyAsync(b->sep_tt, stt.data(), stt.size() * sizeof(float), hipMemcpyHostToDevice, s));
     }
     BV_HIP(hipStreamSynchronize(s));
@@ -728,14 +725,15 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
     for (int k = 0; k < f->nv; ++k) vidx[g.vpix[k]] = k;
     up(T.vidx, vidx, s);
     // named, like the tables above, until the stream is synchronised
-    std::vector<int> kb_off, kb, kb_ring;
+    std::vector<int> kb_off, kb, kb_ring, voff;
     if (f->synthesis == VIS_SYNTH_SEPARABLE) {
       // rows of the Legendre stage beyond 2 lmax + 1 are never written: keep them zero
       BV_HIP(hipMemsetAsync(f->scr.sep_g, 0,
                             sizeof(float) * basis->nz * f->kaz * f->n_freq, s));
       // the adjoint writes dL/dI only at pixels above the horizon at some time;
       // the others stay zero
-      BV_HIP(hipMemsetAsync(f->scr.sep_dfull, 0, sizeof(float) * basis->n_pix * f->n_freq, s));
+      BV_HIP(hipMemsetAsync(f->scr.sep_dfull, 0,
+                            sizeof(float) * basis->nz * f->n_freq * static_cast<size_t>(basis->nphi_b), s));
       // the column batches of each ring that the azimuthal stages visit
       kb_off.assign(1, 0);
       for (int j = 0; j < basis->nz; ++j) {
@@ -754,6 +752,15 @@ vis_status vis_field_create(const vis_basis* basis, const vis_field_desc* desc, 
       up(T.sep_kb_off, kb_off, s);
       up(T.sep_kb, kb, s);
       up(T.sep_kb_ring, kb_ring, s);
+      BV_REQUIRE(static_cast<double>(basis->nz) * f->n_freq * basis->nphi_b < 2147483647.0, VIS_EINVAL,
+                 "separable dL/dI rows of %d x %d x %d floats exceed 32-bit offsets", basis->nz, f->n_freq,
+                 basis->nphi_b);
+      voff.assign(f->nv_pad, 0);
+      for (int k = 0; k < f->nv; ++k) {
+        const int p = g.vpix[k];
+        voff[k] = (p / basis->nphi) * f->n_freq * basis->nphi_b + p % basis->nphi;
+      }
+      up(T.sep_voff, voff, s);
     }
     BV_HIP(hipStreamSynchronize(s));
     *out = f;

@@ -802,11 +802,11 @@ struct AdjArgs {
   const float* gco_lane;
   float* dimg;
   float* f_part;
-  // non-null: dL/dI goes to dfull[pixel][nu] (pixel vpix[k] of visible slot
-  // k < nv) for the separable adjoint synthesis, instead of dimg[nu][k]
+  // non-null: dL/dI of visible slot k < nv goes to dfull[voff[k] + nu fstride]
+  // (the full-grid rows of the separable adjoint synthesis), not dimg[nu][k]
   float* dfull;
-  const int* vpix;
-  int nv;
+  const int* voff;
+  int nv, fstride;
 };
 
 // Channels that share one adjoint tile: for D = 4 two channels' coefficient
@@ -1097,7 +1097,9 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
   for (int c = 0; c < NCH; ++c) {
     if (NCH * fgrp + c >= nf) break;   // uniform over the wave
     if (args.dfull != nullptr) {        // uniform over the wave
-      if (k < args.nv) args.dfull[static_cast<size_t>(args.vpix[k]) * nf + fch[c]] = d_omega * acc_i[c];
+      if (k < args.nv)
+        args.dfull[static_cast<size_t>(args.voff[k]) + static_cast<size_t>(fch[c]) * args.fstride] =
+            d_omega * acc_i[c];
     } else {
       dimg[static_cast<size_t>(fch[c]) * nvp + k] = d_omega * acc_i[c];
     }
@@ -1141,7 +1143,8 @@ static void adj_d(const vis_field* f, const float* img, const float* fwhm, const
   BV_REQUIRE((dimg == nullptr) != (dfull == nullptr), VIS_EINVAL, "internal: one adjoint output");
   const AdjArgs a{f->n_freq, f->n_time, f->nv_pad, f->n_chunks, f->gstride,
                   static_cast<float>(f->d_omega), T.dnu, T.sigr, T.q1, T.q2, T.th2,
-                  T.chunk_t, img, fwhm, gco, gco, dimg, f_part, dfull, T.vpix, f->nv};
+                  T.chunk_t, img, fwhm, gco, gco, dimg, f_part, dfull, T.sep_voff, f->nv,
+                  f->basis->nphi_b};
   if (fringe_split(f))
     launch_k<KFringeAdj<D, true>>(dim3(nblk), 0, a, st, "k_fringe_adj");
   else

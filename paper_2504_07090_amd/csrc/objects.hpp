@@ -55,11 +55,12 @@ struct vis_basis {
   //   sep_lam: per m >= 0 a block of nz rows of sep_lpad(m) = round_up(lmax - m + 1, 8)
   //   floats, row j holding lambda_lm(z_j) for l = m .. lmax then zeros; block m
   //   starts at sep_loff[m] (so both Legendre stages read consecutive l)
-  //   sep_t[k][c], sep_tt[c][k] = T_m(alpha_k) with c = m + lmax + kSepPad, zero for |m| > lmax
-  int kaz_t = 0;                   // columns of sep_t: round_up(2 lmax + 1 + 2 kSepPad, 4)
+  //   sep_tt[c][k] = T_m(alpha_k) with c = m + lmax + kSepPad, zero for |m| > lmax; its
+  //   rows hold nphi_b columns, zero beyond nphi
+  int kaz_t = 0;                   // rows of sep_tt: round_up(2 lmax + 1 + 2 kSepPad, 4)
+  int nphi_b = 0;                  // nphi rounded up to whole 32-column batches
   float* sep_lam = nullptr;
   int* sep_loff = nullptr;         // [lmax + 2] block offsets of sep_lam (floats)
-  float* sep_t = nullptr;
   float* sep_tt = nullptr;
 };
 
@@ -78,8 +79,8 @@ struct FieldScratch {
                                    //   which the forward fringe scales the weighted sky
   float* sep_g = nullptr;          // separable fields: [nz][kaz][n_freq] Legendre stage output
                                    //   (forward) or azimuthal stage output (adjoint)
-  float* sep_dfull = nullptr;      // separable fields: [n_pix][n_freq] dL/dI on the full grid
-                                   //   (zero at pixels never above the horizon)
+  float* sep_dfull = nullptr;      // separable fields: [nz][n_freq][nphi_b] dL/dI on the full grid
+                                   //   (zero at pixels never above the horizon and beyond nphi)
   float* sep_at = nullptr;         // separable fields: [n_modes][n_freq] sky coefficients transposed
   float2* vu = nullptr;            // [n_time][n_freq][n_ubl] gain-free unique visibilities
   float* gco = nullptr;            // [n_time][n_freq][gstride] adjoint coefficients, MFMA layout
@@ -119,6 +120,8 @@ struct FieldTables {
   int* sep_kb_off = nullptr;       // [nz + 1]
   int* sep_kb = nullptr;           // [nz * ceil(nphi / 32)] at most
   int* sep_kb_ring = nullptr;      // the ring of each sep_kb entry
+  int* sep_voff = nullptr;         // [nv_pad] offset of visible slot k's pixel in sep_dfull at
+                                   //   channel 0: ring * n_freq * nphi_b + column
 };
 
 }  // namespace bv

@@ -197,6 +197,7 @@ struct SepAzFwdArgs {
   int kaz;
   int nc;
   int toff;
+  int tstride;        // row length of Tt (nphi rounded up to whole batches)
   const float* Tt;
   const float* G;
   const int* vidx;
@@ -232,7 +233,7 @@ __device__ void KSepAzFwd::run(const SepAzFwdArgs& args_, const Blk& B_) {
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     grow[h] = G + static_cast<size_t>(j) * kaz * nf + min(f0 + 16 * h + i, nf - 1);
-    tcol[h] = Tt + static_cast<size_t>(toff) * nphi + min(k0 + 16 * h + i, nphi - 1);
+    tcol[h] = Tt + static_cast<size_t>(toff) * args_.tstride + min(k0 + 16 * h + i, nphi - 1);
   }
   f4 acc[2][2];
 #pragma unroll
@@ -249,7 +250,7 @@ __device__ void KSepAzFwd::run(const SepAzFwdArgs& args_, const Blk& B_) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         B.a[q][h] = grow[h][static_cast<size_t>(c) * nf];
-        B.b[q][h] = tcol[h][static_cast<size_t>(c) * nphi];
+        B.b[q][h] = tcol[h][static_cast<size_t>(c) * args_.tstride];
       }
     }
   };
@@ -292,17 +293,22 @@ __device__ void KSepAzFwd::run(const SepAzFwdArgs& args_, const Blk& B_) {
   }
 }
 
-// H[j][c][nu] = sum_k T[k][c + toff] dfull[j nphi + k][nu] for c < nc = 2 lmax + 1.
-// grid (ceil(nc / 32), nz, ceil(nf / 32)); each wave computes a 2 x 2 block of
-// 16 x 16 tiles (rows = c, columns = channels).
+// H[j][c][nu] = sum_k T[k][c + toff] dL/dI[j][nu][k] for c < nc = 2 lmax + 1,
+// over the ring's column batches that hold a pixel above the horizon at some
+// time (dL/dI is zero elsewhere).  grid (ceil(nc / 32), nz, ceil(nf / 32));
+// each wave computes a 2 x 2 block of 16 x 16 tiles (rows = c, columns =
+// channels).  In a group of four MFMA steps, lane group kk supplies columns
+// k0 + 4 kk .. + 3 (one per step): the transposed table Tt[c][k] and the
+// channel's dL/dI row are both contiguous in k, so each operand value of the
+// four steps comes with one 16-byte load.  Rows are tstride (whole batches)
+// long and zero beyond nphi in both, so no column needs masking.
 struct SepAzAdjArgs {
-  int nphi;
   int nf;
   int kaz;
   int nc;
-  int kaz_t;
+  int tstride;
   int toff;
-  const float* T;
+  const float* Tt;
   const float* dfull;
   const int* kb_off;
   const int* kb;
@@ -316,14 +322,7 @@ struct KSepAzAdj {
 };
 
 __device__ void KSepAzAdj::run(const SepAzAdjArgs& args_, const Blk& B_) {
-  int nphi = args_.nphi;
-  int nf = args_.nf;
-  int kaz = args_.kaz;
-  int nc = args_.nc;
-  int kaz_t = args_.kaz_t;
-  int toff = args_.toff;
-  const float* T = args_.T;
-  const float* dfull = args_.dfull;
+  const int nf = args_.nf, kaz = args_.kaz, nc = args_.nc, tstride = args_.tstride;
   float* __restrict__ H = args_.H;
 
   const int3 bk = sep_blocks_x_fastest(sep_xcd_logical(B_), B_);
@@ -333,42 +332,38 @@ __device__ void KSepAzAdj::run(const SepAzAdjArgs& args_, const Blk& B_) {
   const float* drow[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    trow[h] = T + toff + min(c0 + 16 * h + i, nc - 1);
-    drow[h] = dfull + static_cast<size_t>(j) * nphi * nf + min(f0 + 16 * h + i, nf - 1);
+    trow[h] = args_.Tt + static_cast<size_t>(min(c0 + 16 * h + i, nc - 1) + args_.toff) * tstride + 4 * kk;
+    drow[h] = args_.dfull + (static_cast<size_t>(j) * nf + min(f0 + 16 * h + i, nf - 1)) * tstride + 4 * kk;
   }
   f4 acc[2][2];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int g = 0; g < 2; ++g) acc[h][g] = f4{0.f, 0.f, 0.f, 0.f};
+  // one batch: two groups of 16 columns, per group a 16-byte load of each row
+  // (h) and each channel (g)
   struct Batch {
-    float a[kSepBatch][2], b[kSepBatch][2];
+    f4 a[2][2], b[2][2];
   };
   auto load = [&](int k0, Batch& B) {
 #pragma unroll
-    for (int q = 0; q < kSepBatch; ++q) {
-      const int k = min(k0 + 4 * q + kk, nphi - 1);
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        B.a[q][h] = trow[h][static_cast<size_t>(k) * kaz_t];
-        B.b[q][h] = drow[h][static_cast<size_t>(k) * nf];
+        B.a[s][h] = *reinterpret_cast<const f4*>(trow[h] + k0 + 16 * s);
+        B.b[s][h] = *reinterpret_cast<const f4*>(drow[h] + k0 + 16 * s);
       }
-    }
   };
-  auto mma = [&](int k0, const Batch& B) {
+  auto mma = [&](const Batch& B) {
 #pragma unroll
-    for (int q = 0; q < kSepBatch; ++q) {
-      const bool ok = k0 + 4 * q + kk < nphi;
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const float av = ok ? B.a[q][h] : 0.f;
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int g = 0; g < 2; ++g) acc[h][g] = sep_mfma(av, B.b[q][g], acc[h][g]);
-      }
-    }
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int g = 0; g < 2; ++g) acc[h][g] = sep_mfma(B.a[s][h][q], B.b[s][g][q], acc[h][g]);
   };
-  // the K loop visits only the ring's column batches that hold a pixel above
-  // the horizon at some time (dL/dI is zero elsewhere)
   const int* kb = args_.kb + args_.kb_off[j];
   const int nkb = args_.kb_off[j + 1] - args_.kb_off[j];
   if (nkb > 0) {
@@ -379,11 +374,11 @@ __device__ void KSepAzAdj::run(const SepAzAdjArgs& args_, const Blk& B_) {
     for (int q = 0; q < nkb; q += 2) {
       load(kb_at(q + 1), B1);
       __builtin_amdgcn_sched_barrier(0);
-      mma(kb[q], B0);
+      mma(B0);
       if (q + 1 >= nkb) break;
       load(kb_at(q + 2), B0);
       __builtin_amdgcn_sched_barrier(0);
-      mma(kb[q + 1], B1);
+      mma(B1);
     }
   }
 #pragma unroll
@@ -483,7 +478,7 @@ void launch_synth_fwd_sep(const vis_field* f, const float* alm, float* img, hipS
   }
   ProfScope ps(&f->prof, "k_sep_az_fwd", st);
   dim3 grid(f->sep_nkb, 1, ceil_div(f->n_freq, 32));
-  launch_k<KSepAzFwd>(grid, 0, SepAzFwdArgs{b->nphi, f->n_freq, f->kaz, 2 * L + 1, toff, b->sep_tt, f->scr.sep_g,
+  launch_k<KSepAzFwd>(grid, 0, SepAzFwdArgs{b->nphi, f->n_freq, f->kaz, 2 * L + 1, toff, b->nphi_b, b->sep_tt, f->scr.sep_g,
                                     f->tab.vidx, f->tab.sep_kb, f->tab.sep_kb_ring, f->nv_pad, img},
                       st, "k_sep_az_fwd");
 }
@@ -498,7 +493,7 @@ void launch_synth_adj_sep(const vis_field* f, float* grad_alm, hipStream_t st) {
   {
     ProfScope ps(&f->prof, "k_sep_az_adj", st);
     dim3 grid(ceil_div(2 * L + 1, 32), b->nz, ceil_div(f->n_freq, 32));
-    launch_k<KSepAzAdj>(grid, 0, SepAzAdjArgs{b->nphi, f->n_freq, f->kaz, 2 * L + 1, b->kaz_t, toff, b->sep_t,
+    launch_k<KSepAzAdj>(grid, 0, SepAzAdjArgs{f->n_freq, f->kaz, 2 * L + 1, b->nphi_b, toff, b->sep_tt,
                                       f->scr.sep_dfull, f->tab.sep_kb_off, f->tab.sep_kb, f->scr.sep_g},
                         st, "k_sep_az_adj");
   }
