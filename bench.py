@@ -60,8 +60,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "d38288a928dfd978ac5c841394ca92595cad0b66d8c0456509b57155afd0bb9e",
-    "bytes_per_launch": {"k_fringe_adj": 185513761, "k_fringe_fwd": 236191551},
+    "sha256": "5c8257b981cb9d922cd62a60d7e1822e000cd3484daffcbd06be881154e95118",
+    "bytes_per_launch": {"k_fringe_adj": 195679240, "k_fringe_fwd": 235158301},
 }
 
 
