@@ -25,11 +25,6 @@ void forward_core(const vis_field* f, const float* alm, const float* fwhm, hipSt
 
 void adjoint_tail(const vis_field* f, const float* fwhm, float* grad_alm, float2* grad_gains,
                   float* grad_fwhm, bool with_chi2, double* chi2, hipStream_t s) {
-  {
-    StageScope sc(kStageReduce);
-    launch_reduce_grads(f, with_chi2, f->scr.chi_part, chi2, f->scr.g_part, grad_gains,
-                        f->scr.f_part, nullptr, s);
-  }
   // separable fields: the adjoint fringe pass writes dL/dI straight into the
   // full-grid layout that the azimuthal adjoint stage reads
   const bool full = f->synthesis == VIS_SYNTH_SEPARABLE;
@@ -38,9 +33,12 @@ void adjoint_tail(const vis_field* f, const float* fwhm, float* grad_alm, float2
     launch_fringe_adj(f, f->scr.img, fwhm, f->scr.gco, full ? nullptr : f->scr.dimg, f->scr.f_part, s,
                       full ? f->scr.sep_dfull : nullptr);
   }
-  if (grad_fwhm != nullptr) {
-    StageScope sc(kStageReduceF);
-    launch_reduce_grads(f, false, nullptr, nullptr, nullptr, nullptr, f->scr.f_part, grad_fwhm, s);
+  {
+    // one launch for the gain gradient, chi^2 and dL/dF (the gains pass's
+    // partials are complete before the fringe pass, dL/dF's after it)
+    StageScope sc(kStageReduce);
+    launch_reduce_grads(f, with_chi2, f->scr.chi_part, chi2, f->scr.g_part, grad_gains, f->scr.f_part,
+                        grad_fwhm, s);
   }
   if (grad_alm != nullptr) {
     StageScope sc(kStageSynthAdj);

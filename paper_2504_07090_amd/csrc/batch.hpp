@@ -89,8 +89,8 @@ k_many(const typename K::Args* __restrict__ args, const BatchEntry* __restrict__
 
 // Stages of one evaluation, in execution order.
 enum Stage : int {
-  kStageSynthFwd = 0, kStageFringeFwd = 1, kStageGains = 2, kStageReduce = 3,
-  kStageFringeAdj = 4, kStageReduceF = 5, kStageSynthAdj = 6, kNumStages = 7
+  kStageSynthFwd = 0, kStageFringeFwd = 1, kStageGains = 2, kStageFringeAdj = 3,
+  kStageReduce = 4, kStageSynthAdj = 5, kNumStages = 6
 };
 
 // One recorded launch (type-erased).
