@@ -452,6 +452,13 @@ struct FwdArgs {
 // (the off-diagonal blocks pair one channel's alpha with another's beta and
 // are not read).  The MFMA work is shared; the generation is per channel.
 __host__ __device__ constexpr int fwd_channels_per_tile(int D) { return 2 * D <= 8 ? 16 / (2 * D) : 1; }
+// Extents whose 2 D operand rows leave a one-channel tile a free row and
+// column (D = 6, 12): a row of ones in A and a column of the pixel weight w in
+// B make the tile form the axis sums sum_p w beta^m (row 2 D) and
+// sum_p w alpha^n (column 2 D) in the padding the MFMAs compute anyway.
+__host__ __device__ constexpr bool fwd_axis_in_tile(int D) {
+  return fwd_channels_per_tile(D) == 1 && 2 * D < 16 * ((2 * D + 15) / 16);
+}
 
 // SPLIT: the P tile runs on FP16 MFMA (K = 32) as three products of hi + lo
 // pairs, A_hi B_hi + A_lo B_hi + A_hi B_lo, accumulated in FP32; the beam-
@@ -491,6 +498,7 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
   uint32_t* Bl = Bh + 32 * W;
   constexpr int NCH = fwd_channels_per_tile(D);
   static_assert(NCH == 1 || RT == 1, "stacked channels share one 16 x 16 tile");
+  constexpr bool AXT = fwd_axis_in_tile(D);
   const int nfg = (nf + NCH - 1) / NCH;   // channel groups
   const int L = xcd_logical(B.x, B.nx);
   if (L >= nfg * nt) return;   // uniform over the block
@@ -521,12 +529,14 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
     for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < RT; ++j) acc[h][i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  // per-lane partial sums of alpha^n S and beta^m S (the axis baselines)
-  float axr[NCH][D], axi[NCH][D], bxr[NCH][D], bxi[NCH][D];
+  // per-lane partial sums of alpha^n S and beta^m S (the axis baselines;
+  // unused where they ride in the tile)
+  constexpr int DX = AXT ? 1 : D;
+  float axr[NCH][DX], axi[NCH][DX], bxr[NCH][DX], bxi[NCH][DX];
 #pragma unroll
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
-    for (int n = 0; n < D; ++n) axr[c][n] = axi[c][n] = bxr[c][n] = bxi[c][n] = 0.f;
+    for (int n = 0; n < DX; ++n) axr[c][n] = axi[c][n] = bxr[c][n] = bxi[c][n] = 0.f;
 
   const int cbeg = tchunk_off[t], cend = tchunk_off[t + 1];
   const float2* q1t = Q1 + static_cast<size_t>(t) * nvp;
@@ -549,6 +559,7 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
   auto generate = [&](const G& g, float live) {
     float av[SPLIT ? 1 : W], bv[SPLIT ? 1 : W];
     uint32_t ah[SPLIT ? W / 2 : 1], al[SPLIT ? W / 2 : 1], bh[SPLIT ? W / 2 : 1], bl[SPLIT ? W / 2 : 1];
+    float wlast = 0.f;   // the weight (times its scale) of the last channel
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
       const float x1 = reduced_cycles(dnu[c], g.q1);
@@ -558,24 +569,36 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
       sincos_rev(x1, s1, c1);
       sincos_rev(x2, s2, c2);
       auto visit = [&](int n, float ar, float ai, float br, float bi) {
-        axr[c][n] += ar * s;
-        axi[c][n] += ai * s;
-        bxr[c][n] += br;   // SPLIT: scaled by csc, undone after the loop
-        bxi[c][n] += bi;
+        if constexpr (!AXT) {
+          axr[c][n] += ar * s;
+          axi[c][n] += ai * s;
+          bxr[c][n] += br;   // SPLIT: scaled by csc, undone after the loop
+          bxi[c][n] += bi;
+        }
       };
+      wlast = SPLIT ? s * csc[c] : s;
       if constexpr (SPLIT)
         powers_split_fwd<D>(ah + D * c, al + D * c, bh + D * c, bl + D * c, c1, s1, c2, s2,
-                            s * csc[c], visit);
+                            wlast, visit);
       else
         powers_f32<D>(av + 2 * D * c, bv + 2 * D * c, c1, s1, c2, s2, s, visit);
     }
     if constexpr (SPLIT) {
 #pragma unroll
       for (int n = NCH * D; n < W / 2; ++n) ah[n] = al[n] = bh[n] = bl[n] = 0u;
+      if constexpr (AXT) {   // row 2 D: (1, 0); column 2 D: (w, 0), as hi + lo
+        ah[D] = split_hi2(1.f, 0.f);
+        bh[D] = split_hi2(wlast, 0.f);
+        bl[D] = split_lo2(wlast, 0.f, bh[D]);
+      }
       store_rows_split<W>(Ah, Al, Bh, Bl, lane, ah, al, bh, bl);
     } else {
 #pragma unroll
       for (int r = 2 * NCH * D; r < W; ++r) av[r] = bv[r] = 0.f;
+      if constexpr (AXT) {
+        av[2 * D] = 1.f;
+        bv[2 * D] = wlast;
+      }
       store_rows<W>(As, Bs, lane, av, bv);
     }
   };
@@ -682,18 +705,20 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     inv_csc[c] = 1.0f / csc[c];   // exact: a power of two
+    if constexpr (!AXT) {
 #pragma unroll
-    for (int n = 0; n < D; ++n) {
+      for (int n = 0; n < D; ++n) {
 #pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        axr[c][n] += __shfl_xor(axr[c][n], o);
-        axi[c][n] += __shfl_xor(axi[c][n], o);
-        bxr[c][n] += __shfl_xor(bxr[c][n], o);
-        bxi[c][n] += __shfl_xor(bxi[c][n], o);
-      }
-      if constexpr (SPLIT) {
-        bxr[c][n] *= inv_csc[c];
-        bxi[c][n] *= inv_csc[c];
+        for (int o = 32; o >= 1; o >>= 1) {
+          axr[c][n] += __shfl_xor(axr[c][n], o);
+          axi[c][n] += __shfl_xor(axi[c][n], o);
+          bxr[c][n] += __shfl_xor(bxr[c][n], o);
+          bxi[c][n] += __shfl_xor(bxi[c][n], o);
+        }
+        if constexpr (SPLIT) {
+          bxr[c][n] *= inv_csc[c];
+          bxi[c][n] *= inv_csc[c];
+        }
       }
     }
   }
@@ -721,11 +746,11 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
           Pw[(16 * i + 4 * (lane >> 4) + r) * W + 16 * j + (lane & 15)] = sum;
         }
     float* AXw = Bs;  // [NCH][D][4]: axr, axi, bxr, bxi
-    if (lane == 0) {
+    if (!AXT && lane == 0) {
 #pragma unroll
       for (int c = 0; c < NCH; ++c)
 #pragma unroll
-        for (int n = 0; n < D; ++n) {
+        for (int n = 0; n < DX; ++n) {
           AXw[4 * (D * c + n)] = axr[c][n];
           AXw[4 * (D * c + n) + 1] = axi[c][n];
           AXw[4 * (D * c + n) + 2] = bxr[c][n];
@@ -736,7 +761,7 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
   __syncthreads();
   // the block's totals, waves added in index order, into the last wave's
   // rows beyond the tiles (W x W + 4 D NCH floats fit in one wave's 64 W)
-  constexpr int NAX = 4 * D * NCH;
+  constexpr int NAX = AXT ? 0 : 4 * D * NCH;
   float* P = Bs_all[kFwdWaves - 1] + NAX;
   float* AX = Bs_all[kFwdWaves - 1] + NAX + W * W;
   static_assert(2 * NAX + W * W <= 64 * W, "tile totals exceed one wave's rows");
@@ -757,7 +782,11 @@ __device__ void KFringeFwd<D, SPLIT>::run(const FwdArgs& args, const Blk& B) {
     for (int u = threadIdx.x; u < nubl; u += 64 * kFwdWaves) {
       const int2 nm = ubl_nm[u];
       float2 v;
-      if (nm.x == 0) {
+      if (AXT && nm.x == 0) {   // row 2 D: sum_p of the B columns of beta^m w
+        v = make_float2(P[2 * D * W + 2 * (nm.y - 1)], P[2 * D * W + 2 * (nm.y - 1) + 1]);
+      } else if (AXT && nm.y == 0) {   // column 2 D: sum_p of alpha^n w
+        v = make_float2(P[2 * (nm.x - 1) * W + 2 * D], P[(2 * (nm.x - 1) + 1) * W + 2 * D]);
+      } else if (nm.x == 0) {
         v = make_float2(AXc[4 * (nm.y - 1) + 2], AXc[4 * (nm.y - 1) + 3]);
       } else if (nm.y == 0) {
         v = make_float2(AXc[4 * (nm.x - 1)], AXc[4 * (nm.x - 1) + 1]);
@@ -809,11 +838,6 @@ struct AdjArgs {
   int nv, fstride;
 };
 
-// Channels that share one adjoint tile: for D = 4 two channels' coefficient
-// matrices sit on the diagonal blocks of the 16 x 16 tile (the gains pass
-// writes each channel's slice as usual; the kernel places them).
-__host__ __device__ constexpr int adj_channels_per_tile(int D) { return D == 4 ? 2 : 1; }
-
 template <int D, bool SPLIT>
 struct KFringeAdj {
   using Args = AdjArgs;
@@ -847,6 +871,9 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
   const int lane = threadIdx.x;
   constexpr int NCH = adj_channels_per_tile(D);
   static_assert(NCH == 1 || (D == 4 && RT == 1), "two stacked channels: D = 4 only");
+  // beta-axis terms in the tile's row 2 D (the gains pass put omega(0, m)
+  // there) against a row of ones in the pixel operand
+  constexpr bool AXT = adj_axis_in_tile(D);
   const int nfg = (nf + NCH - 1) / NCH;   // channel groups
   const int L = xcd_logical(B.x, B.nx);
   if (L >= nfg * nchunks) return;
@@ -961,9 +988,11 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
       // beta-axis terms of this lane's pixel: sum_n Re[omega(0, n) beta^n]
       zax[c] = 0.f;
       auto visit = [&](int n, float ar, float ai, float br, float bi) {
-        const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 16 * RT + 4 * n);
-        zax[c] = __builtin_fmaf(ax[2], br, zax[c]);   // two FMAs, no separate add
-        zax[c] = __builtin_fmaf(-ax[3], bi, zax[c]);
+        if constexpr (!AXT) {
+          const f4 ax = *reinterpret_cast<const f4*>(G + NMAT + 16 * RT + 4 * n);
+          zax[c] = __builtin_fmaf(ax[2], br, zax[c]);   // two FMAs, no separate add
+          zax[c] = __builtin_fmaf(-ax[3], bi, zax[c]);
+        }
       };
       if constexpr (SPLIT) {
         powers_split_adj<D>(av + 2 * D * c, bh + D * c, bl + D * c, c1, s1, c2, s2, visit);
@@ -980,10 +1009,12 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
       for (int r = 2 * D * NCH; r < W; ++r) av[r] = 0.f;
 #pragma unroll
       for (int n = D * NCH; n < W / 2; ++n) bh[n] = bl[n] = 0u;
+      if constexpr (AXT) av[2 * D] = 1.f;
       store_rows_split_adj<W>(As, Bh, Bl, lane, av, bh, bl);
     } else {
 #pragma unroll
       for (int r = 2 * D * NCH; r < W; ++r) av[r] = bv[r] = 0.f;
+      if constexpr (AXT) av[2 * D] = 1.f;
       store_rows<W>(As, Bs, lane, av, bv);
     }
     wave_sync();
@@ -1049,10 +1080,12 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
       }
     }
     wave_sync();
+    if constexpr (!AXT) {
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      acc_i[c] += bm[c] * zax[c];
-      acc_f[c] += bm[c] * th2 * zax[c];
+      for (int c = 0; c < NCH; ++c) {
+        acc_i[c] += bm[c] * zax[c];
+        acc_f[c] += bm[c] * th2 * zax[c];
+      }
     }
   };
   Step sa, sb;

@@ -100,7 +100,9 @@ __device__ __forceinline__ float2 lds_sum4(const float2* x, int2 r, int w) {
 // The coefficient matrix G[r][c], r = 16 i + (row in tile) = 2 (n - 1) + (Re /
 // Im of alpha^n), c = 16 kt + (column in tile) = 2 (m - 1) + (Re / Im of beta^m):
 //   G = w+r + w-r (Re Re), w-r - w+r (Im Im), w-i - w+i (Re Im), -w+i - w-i (Im Re),
-// w+- = omega(n, +-m).
+// w+- = omega(n, +-m).  Where the tile has a free row (adj_axis_in_tile), row
+// r = 2 dtile holds the beta-axis coefficients: omega(0, m).re in column
+// 2 (m - 1) and -omega(0, m).im in column 2 (m - 1) + 1.
 //
 // FP32 layout: entry ((i * rt + kt) * 64 + l) * 4 + s holds G[r][c] with
 // r = 16 i + (l & 15), c = 16 kt + 4 (l >> 4) + s (lane l's A operand of the
@@ -149,9 +151,18 @@ std::vector<int4> coef_plan(const std::vector<int>& ulut, int extent, int dtile,
     const int u = ulut[n1 * lw + n2 + extent];
     return u >= 0 ? u + 1 : 0;
   };
+  const bool axis_row = adj_axis_in_tile(dtile);
   auto gterm = [&](int r, int c) {   // G[r][c] as +-omega(n, m).comp +- omega(n, -m).comp
     CoefTerm t;
     const int n = (r >> 1) + 1, m = (c >> 1) + 1;
+    if (axis_row && r == 2 * dtile && m <= dtile) {
+      // beta-axis row, against the pixel operand's row of ones: Re(omega(0, m)
+      // beta^m) = omega.re Re(beta^m) - omega.im Im(beta^m)
+      t.a = src(0, m);
+      t.comp = c & 1;
+      t.na = c & 1;
+      return t;
+    }
     if (n > dtile || m > dtile) return t;
     t.a = src(n, m);
     t.b = src(n, -m);

@@ -167,6 +167,16 @@ void launch_fringe_adj(const vis_field* f, const float* img, const float* fwhm, 
 // layout of the adjoint coefficient table that the gains pass writes.
 int fringe_tile_extent(int extent);
 inline int fringe_tiles(int dtile) { return (2 * dtile + 15) / 16; }
+// Channels that share one adjoint tile: for D = 4 two channels' coefficient
+// matrices sit on the diagonal blocks of the 16 x 16 tile (the gains pass
+// writes each channel's slice as usual; the kernel places them).
+__host__ __device__ constexpr int adj_channels_per_tile(int D) { return D == 4 ? 2 : 1; }
+// Extents whose 2 D coefficient rows leave a one-channel tile a free row
+// (D = 2, 6, 12): the beta-axis coefficients omega(0, m) fill row 2 D, and the
+// pixel operand's row 2 D of ones picks them up inside the tile product.
+__host__ __device__ constexpr bool adj_axis_in_tile(int D) {
+  return adj_channels_per_tile(D) == 1 && 2 * D < 16 * ((2 * D + 15) / 16);
+}
 // Split-precision fields run the fringe products as FP16 hi + lo pairs.
 inline bool fringe_split(const vis_field* f) { return f->precision != VIS_FP32; }
 inline int adj_coef_stride(int dtile, bool split) {
