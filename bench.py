@@ -60,8 +60,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "5c8257b981cb9d922cd62a60d7e1822e000cd3484daffcbd06be881154e95118",
-    "bytes_per_launch": {"k_fringe_adj": 195679240, "k_fringe_fwd": 235158301},
+    "sha256": "17f97dff2487efbf3edc429e0cf3106f3b203cf5acb64a6bf6189ba2100bab9a",
+    "bytes_per_launch": {"k_fringe_adj": 196021259, "k_fringe_fwd": 235267318},
 }
 
 
