@@ -237,8 +237,12 @@ __device__ __forceinline__ float coef_term(const float2* om, int src, int comp, 
   return neg ? -v : v;
 }
 
+// Plan entries a thread of a 256-thread block holds in registers for a whole
+// slab (entries tid and tid + 256); the rest are read per slice.
+constexpr int kPlanRegs = 2;
+
 __device__ __forceinline__ void write_coefficients(const GainArgs& a, const float2* om, size_t slice,
-                                                   int tid) {
+                                                   int tid, const int4* plan_r) {
   // split layout: power-of-two scale from the largest |omega| component
   // (|G| <= 2 max |omega|), found by the whole block
   float scale = 1.0f;
@@ -258,8 +262,7 @@ __device__ __forceinline__ void write_coefficients(const GainArgs& a, const floa
     }
   }
   float* G = a.gco + slice * a.gstride;
-  for (int e = tid; e < a.gstride; e += blockDim.x) {
-    const int4 p = a.cplan[e];
+  auto entry = [&](int e, const int4 p) {
     const int kind = p.z & 15;
     const float g0 = coef_term(om, p.x & 0xffff, (p.z >> 4) & 1, (p.z >> 5) & 1) +
                      coef_term(om, p.x >> 16, (p.z >> 4) & 1, (p.z >> 6) & 1);
@@ -279,7 +282,13 @@ __device__ __forceinline__ void write_coefficients(const GainArgs& a, const floa
       val = 1.0f / scale;
     }
     G[e] = val;
+  };
+#pragma unroll
+  for (int q = 0; q < kPlanRegs; ++q) {
+    const int e = tid + 256 * q;
+    if (e < a.gstride) entry(e, plan_r[q]);
   }
+  for (int e = tid + 256 * kPlanRegs; e < a.gstride; e += 256) entry(e, a.cplan[e]);
 }
 
 // Gains pass over (t, nu) slices.  Pass 1 walks the physical baselines in
@@ -331,6 +340,13 @@ __device__ void KGains<SORTED, MODE>::run(const GainArgs& a, const Blk& B) {
         pos_r[q] = a.bl_pos[k];
       }
     }
+  }
+  // this thread's first plan entries, the same for every slice
+  int4 plan_r[kPlanRegs];
+#pragma unroll
+  for (int q = 0; q < kPlanRegs; ++q) {
+    const int e = tid + 256 * q;
+    plan_r[q] = e < a.gstride ? a.cplan[e] : int4{0, 0, 0, 0};
   }
   // SORTED: the lane group of each unique baseline and antenna, and its list's
   // range, are the same for every slice of the slab (one list per group:
@@ -480,7 +496,7 @@ __device__ void KGains<SORTED, MODE>::run(const GainArgs& a, const Blk& B) {
       }
     }
     __syncthreads();
-    write_coefficients(a, om, slice, tid);
+    write_coefficients(a, om, slice, tid, plan_r);
   }
 }
 
