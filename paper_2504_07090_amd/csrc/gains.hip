@@ -455,21 +455,61 @@ __device__ void KGains<SORTED, MODE>::run(const GainArgs& a, const Blk& B) {
       }
     } else {
       double unused = 0.0;
+      // One list entry's baseline data: the list code and the gathered data,
+      // antenna pair and unique-baseline code of its baseline.  The walks
+      // below gather kWalk entries at once (the gathers depend on the list
+      // read, so one entry at a time would wait out two memory latencies per
+      // entry) and then add their terms in list order.
+      struct Ent { int code; float2 d; int2 ij; int uc; };
+      constexpr int kWalk = 4;
+      auto gather = [&](const int* list, int e) {
+        Ent x;
+        x.code = list[e];
+        const int k = x.code >> 1;
+        x.d = din[k];
+        x.ij = a.bl_ant[k];
+        x.uc = a.bl_u[k];
+        return x;
+      };
+      auto vis_e = [&](const Ent& x) { return x.uc >= 0 ? v[x.uc] : conjf2(v[~x.uc]); };
+      auto gprod_e = [&](const Ent& x) { return cmul(g[x.ij.x], conjf2(g[x.ij.y])); };
+      auto uterm = [&](const Ent& x) {
+        const float2 G = gprod_e(x);
+        const float2 c = cot_from(x.d, kCot ? make_float2(0.f, 0.f) : cmul(G, vis_e(x)), unused);
+        return omega_term(x.code & 1, c, G);
+      };
+      auto aterm = [&](const Ent& x) {
+        const float2 vk = vis_e(x);
+        const float2 c = cot_from(x.d, kCot ? make_float2(0.f, 0.f) : cmul(gprod_e(x), vk), unused);
+        return ant_term(x.code & 1, x.ij, cmul(c, conjf2(vk)));
+      };
+      // sum of term(entry) over list[e0], list[e0 + w], ... < list[e1], in order
+      auto walk = [&](const int* list, int e0, int e1, int w, auto term) {
+        float2 o = make_float2(0.f, 0.f);
+        int e = e0;
+        for (; e + (kWalk - 1) * w < e1; e += kWalk * w) {
+          Ent x[kWalk];
+#pragma unroll
+          for (int q = 0; q < kWalk; ++q) x[q] = gather(list, e + q * w);
+#pragma unroll
+          for (int q = 0; q < kWalk; ++q) {
+            const float2 tq = term(x[q]);
+            o.x += tq.x;
+            o.y += tq.y;
+          }
+        }
+        for (; e < e1; e += w) {
+          const float2 tq = term(gather(list, e));
+          o.x += tq.x;
+          o.y += tq.y;
+        }
+        return o;
+      };
       const int w = lanes_per_item(a.nubl), sub = tid & (w - 1);
       for (int base = 0; base < a.nubl; base += 256 / w) {
         const int u = base + tid / w;
         float2 o = make_float2(0.f, 0.f);
-        if (u < a.nubl) {
-          for (int e = a.u_off[u] + sub; e < a.u_off[u + 1]; e += w) {
-            const int code = a.u_list[e];
-            const int k = code >> 1;
-            const float2 G = gprod(k);
-            const float2 c = cot_from(din[k], kCot ? make_float2(0.f, 0.f) : cmul(G, vis_of(k)), unused);
-            const float2 term = omega_term(code & 1, c, G);
-            o.x += term.x;
-            o.y += term.y;
-          }
-        }
+        if (u < a.nubl) o = walk(a.u_list, a.u_off[u] + sub, a.u_off[u + 1], w, uterm);
         o = group_sum(o, w);
         if (u < a.nubl && sub == 0) om[u] = o;
       }
@@ -478,18 +518,7 @@ __device__ void KGains<SORTED, MODE>::run(const GainArgs& a, const Blk& B) {
         for (int base = 0; base < a.nant; base += 256 / w2) {
           const int ant = base + tid / w2;
           float2 sg = make_float2(0.f, 0.f);
-          if (ant < a.nant) {
-            for (int e = a.a_off[ant] + sub2; e < a.a_off[ant + 1]; e += w2) {
-              const int code = a.a_list[e];
-              const int k = code >> 1;
-              const int2 ij = a.bl_ant[k];
-              const float2 vk = vis_of(k);
-              const float2 c = cot_from(din[k], kCot ? make_float2(0.f, 0.f) : cmul(gprod(k), vk), unused);
-              const float2 term = ant_term(code & 1, ij, cmul(c, conjf2(vk)));
-              sg.x += term.x;
-              sg.y += term.y;
-            }
-          }
+          if (ant < a.nant) sg = walk(a.a_list, a.a_off[ant] + sub2, a.a_off[ant + 1], w2, aterm);
           sg = group_sum(sg, w2);
           if (ant < a.nant && sub2 == 0) a.g_part[slice * a.nant + ant] = sg;
         }
