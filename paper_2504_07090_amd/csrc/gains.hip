@@ -435,7 +435,27 @@ __device__ void KGains<SORTED, MODE>::run(const GainArgs& a, const Blk& B) {
         }
       }
     } else if (MODE == kGainChi2) {
-      for (int k = tid; k < a.nbl; k += 256) cot_from(din[k], cmul(gprod(k), vis_of(k)), acc);
+      // four baselines' global loads at once, then their terms, added in
+      // baseline order
+      int k = tid;
+      for (; k + 3 * 256 < a.nbl; k += 4 * 256) {
+        float2 d4[4];
+        int2 ij4[4];
+        int uc4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          d4[q] = din[k + 256 * q];
+          ij4[q] = a.bl_ant[k + 256 * q];
+          uc4[q] = a.bl_u[k + 256 * q];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float2 G = cmul(g[ij4[q].x], conjf2(g[ij4[q].y]));
+          const float2 vk = uc4[q] >= 0 ? v[uc4[q]] : conjf2(v[~uc4[q]]);
+          cot_from(d4[q], cmul(G, vk), acc);
+        }
+      }
+      for (; k < a.nbl; k += 256) cot_from(din[k], cmul(gprod(k), vis_of(k)), acc);
     }
     if (MODE == kGainChi2) {
       for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
@@ -461,7 +481,7 @@ __device__ void KGains<SORTED, MODE>::run(const GainArgs& a, const Blk& B) {
       // read, so one entry at a time would wait out two memory latencies per
       // entry) and then add their terms in list order.
       struct Ent { int code; float2 d; int2 ij; int uc; };
-      constexpr int kWalk = 4;
+      constexpr int kWalk = 8;
       auto gather = [&](const int* list, int e) {
         Ent x;
         x.code = list[e];
