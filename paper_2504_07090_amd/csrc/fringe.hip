@@ -916,11 +916,8 @@ __device__ void KFringeAdj<D, SPLIT>::run(const AdjArgs& args, const Blk& B) {
   // gco feeds the wave-uniform (scalar) loads of the axis coefficients;
   // gco_lane, the same table, the per-lane loads of the prefetch below: a
   // pointer not marked read-only-unaliased keeps the optimizer from moving
-  // those loads to their use in the next step (as it does for P1, P2, TH2)
+  // those loads to their use in the next step (as it does for Q1, Q2, TH2)
   auto gco_at = [&](int t, int c) { return gco + t * gst + static_cast<size_t>(fch[c]) * gstride; };
-  auto gco_lane_at = [&](int t, int c) {
-    return gco_lane + t * gst + static_cast<size_t>(fch[c]) * gstride;
-  };
   // Software pipeline over t, unrolled by two so that the two register sets
   // swap roles without copies: the geometry and this lane's coefficients of
   // time t + 1 load while time t is processed.
