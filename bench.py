@@ -60,8 +60,8 @@ EPS = 0.02   # leapfrog step in units of the diagonal-Hessian scale
 TRAFFIC = {
     "sources": ["paper_2504_07090_amd/csrc/fringe.hip", "paper_2504_07090_amd/csrc/common.hpp",
                 "paper_2504_07090_amd/build.py"],
-    "sha256": "17f97dff2487efbf3edc429e0cf3106f3b203cf5acb64a6bf6189ba2100bab9a",
-    "bytes_per_launch": {"k_fringe_adj": 196021259, "k_fringe_fwd": 235267318},
+    "sha256": "4a70a4f9bdfaf8239f323f3e473f87d5a2f626af547bdf4b32b4be21f49b12d5",
+    "bytes_per_launch": {"k_fringe_adj": 195683636, "k_fringe_fwd": 235222678},
 }
 
 
