@@ -573,8 +573,8 @@ __device__ double block_sum(const T* __restrict__ x, int n, double* red) {
   return tot;
 }
 
-// grad_gains[f][a] = sum_t g_part[t][f][a]; block (nblk-1) also totals chi^2
-// and dL/dF in FP64.
+// grad_gains[f][a] = sum_t g_part[t][f][a]; block nblk - 2 totals chi^2 and
+// block nblk - 1 dL/dF, in FP64.
 struct ReduceArgs {
   int nt, nf, nant, nfpart, with_chi2;
   const double* chi_part;
@@ -600,7 +600,7 @@ __device__ void KReduceGrads::run(const ReduceArgs& a, const Blk& B) {
   const float* __restrict__ f_part = a.f_part;
   float* grad_fwhm = a.grad_fwhm;
   const int tid = threadIdx.x;
-  if (B.x + 1 < B.nx) {
+  if (B.x + 2 < B.nx) {
     // eight lanes per output: lane j of the group sums the times t = j mod 8
     // (two interleaved partial sums, so its loads are all in flight), then
     // the group adds its lanes in a fixed butterfly order
@@ -633,12 +633,14 @@ __device__ void KReduceGrads::run(const ReduceArgs& a, const Blk& B) {
     if (live && j == 0) grad_gains[idx] = s;
     return;
   }
+  // the last two blocks: chi^2 and dL/dF, side by side
   __shared__ double red[16];
-  if (with_chi2) {
-    const double tot = block_sum(chi_part, nt * nf, red);
-    if (tid == 0) *chi2 = tot;
-  }
-  if (grad_fwhm != nullptr) {
+  if (B.x + 2 == B.nx) {
+    if (with_chi2) {
+      const double tot = block_sum(chi_part, nt * nf, red);
+      if (tid == 0) *chi2 = tot;
+    }
+  } else if (grad_fwhm != nullptr) {
     const double tot = block_sum(f_part, nfpart, red);
     if (tid == 0) *grad_fwhm = static_cast<float>(tot);
   }
@@ -705,7 +707,7 @@ void launch_gains(const vis_field* f, GainMode mode, const float2* vu, const flo
 void launch_reduce_grads(const vis_field* f, bool with_chi2, const double* chi_part, double* chi2,
                          const float2* g_part, float2* grad_gains, const float* f_part,
                          float* grad_fwhm, hipStream_t st) {
-  const int nblk = (grad_gains != nullptr ? ceil_div(static_cast<long>(f->n_freq) * f->n_ant, 1024 / 8) : 0) + 1;
+  const int nblk = (grad_gains != nullptr ? ceil_div(static_cast<long>(f->n_freq) * f->n_ant, 1024 / 8) : 0) + 2;
   ProfScope ps(&f->prof, "k_reduce_grads", st);
   const ReduceArgs a{f->n_time, f->n_freq, f->n_ant, f->n_freq * f->n_chunks, with_chi2 ? 1 : 0,
                      chi_part, chi2, g_part, grad_gains, f_part, grad_fwhm};
